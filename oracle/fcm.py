@@ -1,0 +1,378 @@
+"""Finite cell discretisation on a uniform Cartesian grid (oracle, FP64).
+
+Implements, in the plainest form:
+  * the FCM weak form with indicator alpha (Section 2.1, eq. weakform) for the
+    Poisson equation (-kappa Lap u = f) and isotropic linear elasticity;
+  * the tensor-product integrated Legendre basis (Section 2.1);
+  * cut-cell integration by recursive bisection of cut cells to a fixed depth,
+    with a (p+1)^d Gauss rule on every leaf sub-cell and alpha evaluated per
+    point (quadtree/octree integration, Section 4.4);
+  * strong homogeneous Dirichlet conditions on grid-aligned box faces
+    (DOFs on those faces are removed), Neumann tractions on box faces;
+  * elements entirely outside the physical domain are dropped, and so are the
+    DOFs supported only on them;
+  * the hierarchical DOF ordering of eq. hierarchicalFunctions: all DOFs of
+    degree <= q come before any DOF of degree q+1, so the level-q unknowns are
+    a prefix of the vector (eq. restrictionoperation) and the level-q matrix is
+    the leading principal block (eq. hierarchicalMatrices).
+
+A global DOF is identified by a canonical integer key built from its per-axis
+topological entity (vertex at node i, or the bubble of degree j in cell i) and
+its field component:
+    code_ax = i*p            for a vertex at node i
+    code_ax = i*p + (j - 1)  for the degree-j bubble of cell i
+    key     = code_0 + S_0*(code_1 + S_1*(code_2 + S_2*c)),   S_ax = (n_ax+1)*p
+The GPU library exports the same keys for its own layout, so the two numberings
+can be matched in tests without sharing code.
+"""
+from __future__ import annotations
+
+import itertools
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import basis
+from .geometry import CUT, PHYS, VOID, alpha_at, classify_box
+
+
+def local_modes(p: int, dim: int):
+    """All per-axis mode tuples (a_0, ..., a_{d-1}), a_ax in 0..p, axis 0 fastest."""
+    return [tuple(reversed(t)) for t in itertools.product(range(p + 1), repeat=dim)]
+
+
+def source(desc, x):
+    """Scalar source f(x) = f_const + sum_k A_k exp(-|x - c_k|^2 / w_k^2)."""
+    if callable(desc.get("source_fn")):          # test hook: manufactured solutions
+        return np.asarray(desc["source_fn"](x), dtype=np.float64)
+    f = np.full(x.shape[0], float(desc.get("f_const", 0.0)))
+    for A, w, c in desc.get("gauss", []):
+        d2 = np.sum((x - np.asarray(c)) ** 2, axis=1)
+        f += A * np.exp(-d2 / (w * w))
+    return f
+
+
+def elasticity_C(dim, E, nu):
+    """Isotropic elasticity matrix in Voigt notation (3D, or plane strain in 2D)."""
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    mu = E / (2.0 * (1.0 + nu))
+    if dim == 3:
+        C = np.zeros((6, 6))
+        C[:3, :3] = lam
+        C[np.arange(3), np.arange(3)] = lam + 2 * mu
+        C[3, 3] = C[4, 4] = C[5, 5] = mu
+        return C
+    C = np.array([[lam + 2 * mu, lam, 0.0], [lam, lam + 2 * mu, 0.0], [0.0, 0.0, mu]])
+    return C
+
+
+class Discretization:
+    """Uniform-grid FCM discretisation of one problem descriptor."""
+
+    def __init__(self, desc, assemble: bool = True):
+        self.desc = desc
+        self.dim = d = int(desc["dim"])
+        self.n = np.array(desc["n"][:d], dtype=np.int64)
+        self.p = p = int(desc["p"])
+        self.nf = int(desc.get("n_fields", 1))
+        self.lo = np.array(desc["lo"][:d], dtype=np.float64)
+        self.hi = np.array(desc["hi"][:d], dtype=np.float64)
+        self.h = (self.hi - self.lo) / self.n
+        self.depth = int(desc.get("quad_depth", 3))
+        self.modes = local_modes(p, d)                    # scalar mode tuples
+        self.m_scalar = len(self.modes)
+        self.m = self.m_scalar * self.nf                  # local index = mode*nf + comp
+        self.mode_deg = np.array([max(basis.mode_degree(a) for a in t) for t in self.modes])
+        self.local_deg = np.repeat(self.mode_deg, self.nf)
+        self._classify()
+        self._number_dofs()
+        self._kref = None
+        if assemble:
+            self.assemble()
+
+    # ------------------------------------------------------------------ geometry
+    def elem_box(self, e):
+        lo = self.lo + np.asarray(e) * self.h
+        return lo, lo + self.h
+
+    def _classify(self):
+        d = self.dim
+        shape = tuple(int(v) for v in self.n)
+        state = np.empty(shape[::-1], dtype=np.int8)   # indexed [e_{d-1},...,e_0]
+        for e in itertools.product(*[range(s) for s in shape[::-1]]):
+            idx = tuple(reversed(e))
+            lo, hi = self.elem_box(idx)
+            state[e] = classify_box(self.desc, lo, hi)
+        self.state = state
+        flat = state.reshape(-1)                         # axis 0 fastest
+        self.kept = np.nonzero(flat != VOID)[0]
+        self.kept_state = flat[self.kept]
+        # multi-index of kept elements, axis 0 first
+        idx = np.zeros((self.kept.size, d), dtype=np.int64)
+        rem = self.kept.copy()
+        for ax in range(d):
+            idx[:, ax] = rem % self.n[ax]
+            rem //= self.n[ax]
+        self.kept_idx = idx
+
+    # ---------------------------------------------------------------------- DOFs
+    def _entity_codes(self, e_idx):
+        """codes[e, mode, ax] and vertex-node-on-Dirichlet-face mask for elements e_idx."""
+        p, d = self.p, self.dim
+        T = np.array(self.modes, dtype=np.int64)          # (ms, d)
+        E = e_idx[:, None, :]                            # (ne, 1, d)
+        A = T[None, :, :]
+        node = E + (A == 1)
+        code = np.where(A <= 1, node * p, E * p + (A - 1))
+        faces = int(self.desc.get("dirichlet_faces", 0))
+        dir_mask = np.zeros(code.shape[:2], dtype=bool)
+        for ax in range(d):
+            vert = A[..., ax] <= 1
+            if faces & (1 << (2 * ax)):
+                dir_mask |= vert & (node[..., ax] == 0)
+            if faces & (1 << (2 * ax + 1)):
+                dir_mask |= vert & (node[..., ax] == self.n[ax])
+        return code, dir_mask
+
+    def keys_from_codes(self, code, comp):
+        S = (self.n + 1) * self.p
+        key = comp.astype(np.int64)
+        for ax in reversed(range(self.dim)):
+            key = key * S[ax] + code[..., ax]
+        return key
+
+    def _number_dofs(self):
+        nf = self.nf
+        code, dmask = self._entity_codes(self.kept_idx)   # (ne, ms, d)
+        ne, ms = code.shape[:2]
+        code = np.repeat(code, nf, axis=1)                  # (ne, m, d) local = mode*nf+c
+        dmask = np.repeat(dmask, nf, axis=1)
+        comp = np.tile(np.arange(nf), ms)[None, :].repeat(ne, axis=0)
+        keys = self.keys_from_codes(code, comp)
+        deg = np.broadcast_to(self.local_deg[None, :], keys.shape)
+        valid = ~dmask
+        uk, first = np.unique(keys[valid], return_index=True)
+        udeg = deg[valid][first]
+        ucomp = comp[valid][first]
+        # hierarchical order: degree shell first, then component, then key
+        order = np.lexsort((uk, ucomp, udeg))
+        self.dof_keys = uk[order]
+        self.dof_deg = udeg[order]
+        self.n_dofs = self.dof_keys.size
+        pos = np.empty(uk.size, dtype=np.int64)
+        pos[order] = np.arange(uk.size)
+        elem_dofs = np.full(keys.shape, -1, dtype=np.int64)
+        elem_dofs[valid] = pos[np.searchsorted(uk, keys[valid])]
+        self.elem_dofs = elem_dofs                           # (n_kept, m), -1 = Dirichlet
+        self.level_orders = list(range(1, self.p + 1))      # level l <-> order q = l+1
+        self.level_sizes = [int(np.sum(self.dof_deg <= q)) for q in self.level_orders]
+
+    # --------------------------------------------------------------- integration
+    def _leaves(self, lo, hi, depth):
+        st = classify_box(self.desc, lo, hi)
+        if st == CUT and depth < self.depth:
+            mid = 0.5 * (lo + hi)
+            for bits in itertools.product((0, 1), repeat=self.dim):
+                b = np.array(bits)
+                clo = np.where(b == 0, lo, mid)
+                chi = np.where(b == 0, mid, hi)
+                yield from self._leaves(clo, chi, depth + 1)
+        else:
+            yield lo, hi
+
+    def _points(self, boxes):
+        """Tensor Gauss points (p+1 per axis) on each box: x (npts,d), weights (npts,)."""
+        d = self.dim
+        gx, gw = basis.gauss(int(self.desc.get("quad_points", 0)) or self.p + 1)
+        xs, ws = [], []
+        for lo, hi in boxes:
+            half = 0.5 * (hi - lo)
+            mid = 0.5 * (hi + lo)
+            grids = [mid[ax] + half[ax] * gx for ax in range(d)]
+            wts = [half[ax] * gw for ax in range(d)]
+            mesh = np.meshgrid(*grids, indexing="ij")
+            wmesh = np.meshgrid(*wts, indexing="ij")
+            xs.append(np.stack([m.reshape(-1) for m in mesh], axis=1))
+            ws.append(np.prod(np.stack([m.reshape(-1) for m in wmesh], axis=1), axis=1))
+        return np.concatenate(xs), np.concatenate(ws)
+
+    def _shape(self, e_lo, x):
+        """Values (npts, ms) and gradients (npts, ms, d) of the element's scalar modes."""
+        d, p = self.dim, self.p
+        xi = 2.0 * (x - e_lo) / self.h - 1.0
+        V = [basis.modes_1d(p, xi[:, ax]) for ax in range(d)]     # (p+1, npts)
+        D = [basis.dmodes_1d(p, xi[:, ax]) * (2.0 / self.h[ax]) for ax in range(d)]
+        T = np.array(self.modes)
+        val = np.ones((x.shape[0], len(self.modes)))
+        for ax in range(d):
+            val *= V[ax][T[:, ax]].T
+        grad = np.ones((x.shape[0], len(self.modes), d))
+        for k in range(d):
+            for ax in range(d):
+                src = D[ax] if ax == k else V[ax]
+                grad[:, :, k] *= src[T[:, ax]].T
+        return val, grad
+
+    def _stiffness(self, grad, wa):
+        """sum_q w_q alpha_q B^T C B over points (Poisson or elasticity)."""
+        d, nf = self.dim, self.nf
+        if nf == 1:
+            kappa = float(self.desc.get("kappa", 1.0))
+            G = grad * np.sqrt(wa)[:, None, None]
+            K = kappa * np.einsum("qak,qbk->ab", G, G)
+            return K
+        C = elasticity_C(d, float(self.desc["E"]), float(self.desc["nu"]))
+        npts, ms = grad.shape[:2]
+        nv = 6 if d == 3 else 3
+        B = np.zeros((npts, nv, ms * nf))
+        for a in range(ms):
+            gx = grad[:, a, :]
+            for c in range(nf):
+                col = a * nf + c
+                B[:, c, col] = gx[:, c]                     # normal strains
+            if d == 3:
+                # gamma_yz, gamma_xz, gamma_xy
+                B[:, 3, a * nf + 1] = gx[:, 2]
+                B[:, 3, a * nf + 2] = gx[:, 1]
+                B[:, 4, a * nf + 0] = gx[:, 2]
+                B[:, 4, a * nf + 2] = gx[:, 0]
+                B[:, 5, a * nf + 0] = gx[:, 1]
+                B[:, 5, a * nf + 1] = gx[:, 0]
+            else:
+                B[:, 2, a * nf + 0] = gx[:, 1]
+                B[:, 2, a * nf + 1] = gx[:, 0]
+        CB = np.einsum("ij,qjb->qib", C, B)
+        K = np.einsum("q,qia,qib->ab", wa, B, CB)
+        return K
+
+    def _load(self, val, x, wa):
+        nf = self.nf
+        if nf == 1:
+            return val.T @ (wa * source(self.desc, x))
+        bf = np.asarray(self.desc.get("body_force", [0.0] * self.dim), dtype=np.float64)
+        out = np.zeros(val.shape[1] * nf)
+        for c in range(nf):
+            out[c::nf] = bf[c] * (val.T @ wa)
+        return out
+
+    def element_quadrature(self, e):
+        """Leaf Gauss points of element e: physical points, weights, alpha."""
+        lo, hi = self.elem_box(e)
+        leaves = list(self._leaves(lo, hi, 0))
+        x, w = self._points(leaves)
+        return lo, x, w, alpha_at(self.desc, x), len(leaves)
+
+    def element_system(self, e):
+        """(K_e, b_e) of element e in the oracle's local order (mode*nf + comp)."""
+        lo, x, w, a, _ = self.element_quadrature(e)
+        val, grad = self._shape(lo, x)
+        wa = w * a
+        return self._stiffness(grad, wa), self._load(val, x, wa)
+
+    def reference_stiffness(self):
+        """K_e of an uncut element (alpha = 1 everywhere): one Gauss rule per element."""
+        if self._kref is None:
+            lo = self.lo.copy()
+            x, w = self._points([(lo, lo + self.h)])
+            val, grad = self._shape(lo, x)
+            self._kref = self._stiffness(grad, w)
+        return self._kref
+
+    def phys_load(self, e):
+        lo, hi = self.elem_box(e)
+        x, w = self._points([(lo, hi)])
+        val, _ = self._shape(lo, x)
+        return self._load(val, x, w)
+
+    def traction_load(self, e):
+        """Neumann traction of box faces touching element e: vector over local dofs."""
+        d, nf, p = self.dim, self.nf, self.p
+        out = np.zeros(self.m)
+        for fbit, t in self.desc.get("tractions", []):
+            ax, side = fbit // 2, fbit % 2
+            if e[ax] != (self.n[ax] - 1 if side else 0):
+                continue
+            gx, gw = basis.gauss(p + 1)
+            others = [k for k in range(d) if k != ax]
+            lo, hi = self.elem_box(e)
+            grids, wts = [], []
+            for k in range(d):
+                if k == ax:
+                    grids.append(np.array([hi[k] if side else lo[k]]))
+                    wts.append(np.array([1.0]))
+                else:
+                    half = 0.5 * self.h[k]
+                    grids.append(lo[k] + half * (gx + 1.0))
+                    wts.append(half * gw)
+            mesh = np.meshgrid(*grids, indexing="ij")
+            wmesh = np.meshgrid(*wts, indexing="ij")
+            xq = np.stack([m.reshape(-1) for m in mesh], axis=1)
+            wq = np.prod(np.stack([m.reshape(-1) for m in wmesh], axis=1), axis=1)
+            val, _ = self._shape(lo, xq)
+            base = val.T @ wq
+            for c in range(nf):
+                out[c::nf] += float(t[c]) * base
+            del others
+        return out
+
+    # ------------------------------------------------------------------ assembly
+    def assemble(self):
+        m = self.m
+        kref = self.reference_stiffness()
+        ne = self.kept.size
+        Ks = np.empty((ne, m, m))
+        bs = np.empty((ne, m))
+        const_f = (self.nf == 1 and not self.desc.get("gauss")
+                   and not callable(self.desc.get("source_fn"))) or self.nf > 1
+        phys_b = None
+        self.cut_elems = []
+        for k in range(ne):
+            e = tuple(self.kept_idx[k])
+            if self.kept_state[k] == PHYS:
+                Ks[k] = kref
+                if const_f:
+                    if phys_b is None:
+                        phys_b = self.phys_load(e)
+                    bs[k] = phys_b
+                else:
+                    bs[k] = self.phys_load(e)
+            else:
+                Ks[k], bs[k] = self.element_system(e)
+                self.cut_elems.append(k)
+            if self.desc.get("tractions"):
+                bs[k] = bs[k] + self.traction_load(e)
+        self.Ke = Ks
+        self.be = bs
+        ed = self.elem_dofs
+        rows = np.repeat(ed[:, :, None], m, axis=2)
+        cols = np.repeat(ed[:, None, :], m, axis=1)
+        ok = (rows >= 0) & (cols >= 0)
+        N = self.n_dofs
+        A = sp.coo_matrix((Ks[ok], (rows[ok], cols[ok])), shape=(N, N)).tocsr()
+        A.sum_duplicates()
+        self.A = A
+        b = np.zeros(N)
+        okb = ed >= 0
+        np.add.at(b, ed[okb], bs[okb])
+        self.b = b
+        return A, b
+
+    # ------------------------------------------------------------------ helpers
+    def evaluate(self, u, pts):
+        """Evaluate the FE field with coefficients u (oracle order) at points (npts, d)."""
+        pts = np.atleast_2d(np.asarray(pts, dtype=np.float64))
+        d, nf = self.dim, self.nf
+        out = np.zeros((pts.shape[0], nf))
+        eidx = np.minimum(((pts - self.lo) / self.h).astype(np.int64), self.n - 1)
+        lookup = {tuple(self.kept_idx[k]): k for k in range(self.kept.size)}
+        for i in range(pts.shape[0]):
+            k = lookup.get(tuple(eidx[i]))
+            if k is None:
+                continue
+            lo, _ = self.elem_box(eidx[i])
+            val, _ = self._shape(lo, pts[i:i + 1])
+            dofs = self.elem_dofs[k]
+            coef = np.where(dofs >= 0, u[np.maximum(dofs, 0)], 0.0)
+            for c in range(nf):
+                out[i, c] = val[0] @ coef[c::nf]
+        return out
