@@ -1,0 +1,234 @@
+/*
+ * fcm.h -- C-ABI of libfcm: multigrid-preconditioned CG for finite cell
+ * method (FCM) systems on one AMD Instinct MI355X (gfx950).
+ *
+ * What is solved (Section 2.1, eq. weakform): find u_h in the span of an
+ * integrated-Legendre tensor-product basis of order p on a uniform Cartesian
+ * grid that embeds the physical domain, with
+ *     a(u,v) = int alpha(x) (B v)^T C (B u) dOmega
+ *     b(v)   = int alpha(x) (N v)^T f dOmega + int (N v)^T t dGamma_N
+ * where alpha = 1 in the physical domain and alpha = eps << 1 in the
+ * fictitious part.  Poisson (one field, C = kappa I) or isotropic linear
+ * elasticity (dim fields).  Cut cells are integrated by recursive bisection
+ * (quadtree/octree, Section 4.4) with a (p+1)^d Gauss rule per leaf.
+ * Homogeneous Dirichlet conditions are imposed strongly on grid-aligned box
+ * faces; elements entirely outside the physical domain are dropped.
+ *
+ * How it is solved (Section 3): hierarchical p-multigrid.  Level l holds the
+ * basis functions of degree <= l+1 (eq. hierarchicalFunctions), so the level
+ * vector is a prefix of the fine vector, restriction keeps the prefix and
+ * prolongation zero-extends it (eq. restrictionoperation), and the level
+ * matrix is the leading principal block of the fine one (eq.
+ * hierarchicalMatrices).  Levels >= 1 are smoothed by elementwise additive
+ * Schwarz (eq. AdditiveSchwarz) with relaxation omega; level 0 (p = 1) is
+ * solved exactly.  One V-cycle (Alg. 1) preconditions an FP64 CG (Section 4).
+ *
+ * Vectors.  All device vectors use the library's padded "plane" layout: the
+ * vector of level l is nplanes(l) contiguous planes of G grid points each
+ * (G = prod_ax (n_ax + 1), axis 0 fastest).  A plane holds one slot type
+ * (vertex or bubble degree per axis) of one field component; planes are
+ * sorted by polynomial degree, so level l is a prefix.  Entries that are not
+ * DOFs (Dirichlet, padding, support only on dropped elements) are zero on
+ * input and are written as zero.  fcm_dof_keys() maps every entry to a
+ * canonical entity key (or -1) so results can be compared with any other
+ * numbering.
+ *
+ * Memory ownership.  The handle owns every device allocation it makes (level
+ * operators, Schwarz inverses, coarse factors, work vectors).  Pointers passed
+ * in (device vectors, host arrays) remain owned by the caller; the library
+ * never frees or retains them beyond the call.  Device vectors must be
+ * hipMalloc'ed (or torch-allocated) memory on the handle's device.
+ *
+ * Streams.  Every call that takes `stream` (a hipStream_t passed as void*,
+ * NULL = default stream) enqueues its work on that stream.  Calls that return
+ * host data synchronise that stream first.
+ *
+ * Errors.  A negative status means the call failed and produced no result;
+ * fcm_last_error() returns a thread-local description.  Positive statuses are
+ * warnings with a valid result (FCM_NOT_CONVERGED returns the last iterate).
+ * Handles are not thread-safe; a server is safe for concurrent submit/poll.
+ */
+#ifndef FCM_H
+#define FCM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FCM_OK = 0,
+  FCM_NOT_CONVERGED = 1,
+  FCM_ERR_ARG = -1,
+  FCM_ERR_OOM = -2,
+  FCM_ERR_HIP = -3,
+  FCM_ERR_NOT_SPD = -4,
+  FCM_ERR_BREAKDOWN = -5,
+  FCM_ERR_NAN = -6,
+  FCM_ERR_BUSY = -7
+} fcm_status;
+
+enum { FCM_GEOM_BOX_MINUS_BALLS = 0, FCM_GEOM_BALL_INTERIOR = 1 };
+enum { FCM_FP64 = 0, FCM_MIXED = 1 };           /* V-cycle precision           */
+enum { FCM_SMOOTH_ELEMENTWISE = 0 };             /* additive Schwarz blocks     */
+
+typedef struct fcm_handle fcm_handle;
+typedef struct fcm_server fcm_server;
+
+/* Problem statement (Section 2.1).  All pointers are host memory, read during
+ * the call only.  Unused trailing axes of 3-vectors are ignored when dim = 2. */
+typedef struct {
+  int dim;                    /* 2 or 3                                          */
+  int n[3];                   /* cells per axis, >= 1                            */
+  double lo[3], hi[3];        /* embedding box                                   */
+  int p;                      /* polynomial order, 1..6                          */
+  int n_fields;               /* 1 (Poisson) or dim (linear elasticity)          */
+  int refine_levels;          /* multi-level hp depth k; only 0 is supported     */
+  int geom;                   /* FCM_GEOM_*                                      */
+  int n_balls;                /* holes (BOX_MINUS_BALLS) or 1 (BALL_INTERIOR)    */
+  const double *ball_c;       /* [n_balls][dim] centres                          */
+  const double *ball_r;       /* [n_balls] radii                                 */
+  double alpha;               /* fictitious-domain scaling eps, 0 < eps <= 1     */
+  int quad_depth;             /* sub-cell bisection depth for cut cells, 0..4    */
+  double kappa;               /* Poisson conductivity                            */
+  double E, nu;               /* elasticity                                      */
+  unsigned dirichlet_faces;   /* bit 2*axis+side: u = 0 on that box face         */
+  int n_traction;             /* Neumann tractions on box faces                  */
+  const int *traction_face;   /* [n_traction] face bit index 2*axis+side         */
+  const double *traction_vec; /* [n_traction][3] traction vector                 */
+  int n_gauss;                /* Gaussian sources f += A exp(-|x-c|^2/w^2)       */
+  const double *gauss;        /* [n_gauss][5]: A, w, c_x, c_y, c_z               */
+  double f_const;             /* constant scalar source                          */
+  double body_force[3];       /* constant body force (elasticity)                */
+} fcm_problem;
+
+/* Solver options (Sections 3.3.2 and 4). */
+typedef struct {
+  int smoother;               /* FCM_SMOOTH_ELEMENTWISE                          */
+  double omega;               /* relaxation; 1/3 (2D) or 2/15 (3D) for elementwise */
+  int n_pre, n_post;          /* smoothing steps per level (5 and 5 in the paper) */
+  int precision;              /* FCM_FP64 or FCM_MIXED (FP32 V-cycle)            */
+  double rtol;                /* ||r||/||b|| stopping tolerance                  */
+  int max_iter;               /* CG iteration cap (500 in the paper)             */
+} fcm_options;
+
+typedef struct {
+  int iterations;             /* CG iterations (x updates)                       */
+  double rel_res;             /* recursive ||r||/||b|| at exit                   */
+  double true_rel_res;        /* ||b - A x|| / ||b|| recomputed at exit (FP64)   */
+  double t_setup_ms;          /* fcm_setup wall time                             */
+  double t_solve_ms;          /* this solve's wall time                          */
+  const double *res_history;  /* [n_history] relative residuals, owned by handle */
+  int n_history;
+} fcm_solve_info;
+
+/* Build the discretisation and the whole multigrid hierarchy on the device:
+ * cell classification, cut-cell integration, RHS, elementwise Schwarz block
+ * inverses for every level >= 1 and the exact factorisation of level 0.
+ * On success *out owns all device memory.  Errors: FCM_ERR_ARG (invalid
+ * problem/options), FCM_ERR_OOM, FCM_ERR_HIP, FCM_ERR_NOT_SPD (a Schwarz block
+ * or the coarse matrix lost positive definiteness in FP64).                 */
+fcm_status fcm_setup(const fcm_problem *prob, const fcm_options *opts,
+                     void *stream, fcm_handle **out);
+
+/* Level count and sizes, coarse first: n_dofs[l] = number of unknowns,
+ * n_padded[l] = length of the level vector in the padded plane layout.
+ * Either array may be NULL; each must hold *n_levels entries (<= 8).        */
+fcm_status fcm_sizes(const fcm_handle *h, int *n_levels, int64_t *n_dofs,
+                     int64_t *n_padded);
+
+/* Copy the assembled right-hand side b (fine level, FP64) to b_dev.         */
+fcm_status fcm_rhs(fcm_handle *h, double *b_dev, void *stream);
+
+/* y = A_l x (FP64) on level l (eq. hierarchicalMatrices); x, y level-l vectors. */
+fcm_status fcm_apply(fcm_handle *h, int level, const double *x, double *y,
+                     void *stream);
+
+/* z = M_l^{-1} r (FP64), the elementwise additive Schwarz operator of level
+ * l >= 1 (eq. AdditiveSchwarz), without the relaxation factor.              */
+fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z,
+                      void *stream);
+
+/* x = A_0^{-1} b on the coarsest level (exact FP64 solve).                  */
+fcm_status fcm_coarse_solve(fcm_handle *h, const double *b, double *x,
+                            void *stream);
+
+/* z = V(0, r): one V-cycle of Alg. 1 on the fine level with zero initial
+ * guess, in the handle's precision (FP64, or FP32 with an FP64 coarse solve).
+ * r and z are fine-level FP64 vectors.                                      */
+fcm_status fcm_vcycle(fcm_handle *h, const double *r_dev, double *z_dev,
+                      void *stream);
+
+/* CG preconditioned by one V-cycle (Section 4).  b_dev = NULL uses the
+ * assembled right-hand side.  x_dev receives the solution (x0 = 0).  Stops
+ * when ||r||/||b|| < rtol or after max_iter iterations (FCM_NOT_CONVERGED).
+ * info may be NULL.  Synchronises the stream before returning.             */
+fcm_status fcm_pcg_solve(fcm_handle *h, const double *b_dev, double *x_dev,
+                         fcm_solve_info *info, void *stream);
+
+/* The V-cycle as a stand-alone solver: x <- x + V(b - A x) (Section 4,
+ * eq. contraction).  *rho_max receives the largest contraction number.     */
+fcm_status fcm_mg_solve(fcm_handle *h, const double *b_dev, double *x_dev,
+                        fcm_solve_info *info, double *rho_max, void *stream);
+
+/* Canonical entity key of every fine-level padded entry (host array of
+ * n_padded[fine] int64), -1 for entries that are not DOFs.  Key:
+ *   code_ax = i*p (vertex at node i) or i*p + j - 1 (degree-j bubble, cell i)
+ *   key = code_0 + S_0*(code_1 + S_1*(code_2 + S_2*component)),
+ *   S_ax = (n_ax + 1)*p.                                                    */
+fcm_status fcm_dof_keys(const fcm_handle *h, int64_t *keys);
+
+/* Local mode table of the element matrices: for each of the m local modes
+ * (degree-sorted), 4 ints: a_0, a_1, a_2, component, where a_ax = 0 (left
+ * vertex), 1 (right vertex) or j >= 2 (degree-j bubble).  *m receives m.    */
+fcm_status fcm_local_modes(const fcm_handle *h, int *m, int *modes);
+
+/* Element data for element linear index e (axis 0 fastest): *state = 0 void,
+ * 1 uncut, 2 cut; K (host, m*m, row-major, may be NULL) and be (host, m, may
+ * be NULL) receive the element stiffness and load in the local mode order.  */
+fcm_status fcm_element(const fcm_handle *h, int64_t e, int *state, double *K,
+                       double *be);
+
+/* Counts for reporting: number of cut elements, kept elements, unique
+ * Schwarz blocks per level >= 1, shared classes, bytes of device memory.   */
+typedef struct {
+  int64_t n_elements, n_kept, n_cut, n_unique_blocks, n_shared_classes;
+  int64_t device_bytes;
+  int coarse_blocks, coarse_block_size;
+} fcm_stats;
+fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s);
+
+void fcm_destroy(fcm_handle *h);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop that admits solves of different grids and orders
+ * by device-memory footprint, keeps their hierarchies resident and advances
+ * all admitted solves together, one CG iteration per tick (continuous
+ * batching: requests join and leave between ticks).                        */
+typedef struct {
+  int64_t memory_budget_bytes;  /* admit while resident footprint fits        */
+  int max_active;               /* batch slots                                */
+  int n_streams;                /* device streams the ticks spread over       */
+} fcm_server_opts;
+
+fcm_status fcm_server_create(const fcm_server_opts *o, fcm_server **out);
+/* Copies *prob and *opts; returns a request id.                            */
+fcm_status fcm_serve_submit(fcm_server *s, const fcm_problem *prob,
+                            const fcm_options *opts, uint64_t *req_id);
+/* *done = 1 when finished.  x_host (may be NULL) receives the fine-level
+ * padded solution (n_padded doubles); info receives the solve record with
+ * t_setup_ms/t_solve_ms, and latency_ms (submit to done).  Returns the
+ * request's own status once done.                                          */
+fcm_status fcm_serve_poll(fcm_server *s, uint64_t req_id, int *done,
+                          double *x_host, int64_t x_len, fcm_solve_info *info,
+                          double *latency_ms);
+fcm_status fcm_server_destroy(fcm_server *s);
+
+const char *fcm_status_string(fcm_status s);
+const char *fcm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCM_H */

@@ -241,8 +241,9 @@ class Discretization:
             else:
                 B[:, 2, a * nf + 0] = gx[:, 1]
                 B[:, 2, a * nf + 1] = gx[:, 0]
-        CB = np.einsum("ij,qjb->qib", C, B)
-        K = np.einsum("q,qia,qib->ab", wa, B, CB)
+        CB = np.einsum("ij,qjb->qib", C, B) * wa[:, None, None]
+        # K = sum_q w_q alpha_q B_q^T C B_q, as one matrix product over (q, i)
+        K = B.reshape(-1, B.shape[2]).T @ CB.reshape(-1, CB.shape[2])
         return K
 
     def _load(self, val, x, wa):

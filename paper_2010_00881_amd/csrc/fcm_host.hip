@@ -1,0 +1,1202 @@
+// Host side of libfcm: C-ABI entry points, hierarchy setup, V-cycle (Alg. 1)
+// and CG driver (Section 4).  All numerical work runs in the kernels of
+// kernels_setup.hip and kernels_solve.hip; the host only builds index tables
+// (local mode order, plane order, Schwarz block classes) and sequences
+// launches on the caller's stream.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fcm_internal.hpp"
+
+namespace fcm {
+
+static thread_local std::string g_err;
+
+void set_error(const char *fmt, ...) {
+  char buf[1024];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+}
+
+// ------------------------------------------------------------ host basis
+// Gauss-Legendre nodes by Newton iteration on L_n.
+static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = z;
+        p0 = 1.0;
+      }
+      double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    double dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+  if (n == 1) {
+    x[0] = 0.0;
+    w[0] = 2.0;
+  }
+}
+
+static void modes1d_host(int p, double xi, double *v, double *dv) {
+  double L[kMaxP + 1];
+  L[0] = 1.0;
+  if (p >= 1) L[1] = xi;
+  for (int n = 1; n < p; ++n) L[n + 1] = ((2 * n + 1) * xi * L[n] - n * L[n - 1]) / (n + 1);
+  v[0] = 0.5 * (1.0 - xi);
+  v[1] = 0.5 * (1.0 + xi);
+  dv[0] = -0.5;
+  dv[1] = 0.5;
+  for (int j = 2; j <= p; ++j) {
+    double s = 1.0 / std::sqrt(2.0 * (2 * j - 1));
+    v[j] = (L[j] - L[j - 2]) * s;
+    dv[j] = (2 * j - 1) * L[j - 1] * s;
+  }
+}
+
+static int deg1(int a) { return a < 2 ? 1 : a; }      // local 1D mode -> degree
+static int tdeg(int t) { return t == 0 ? 1 : t + 1; }  // slot type -> degree
+
+template <typename T>
+static fcm_status dalloc(fcm_handle *h, T **p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void **)p, n * sizeof(T));
+  if (e != hipSuccess) {
+    set_error("hipMalloc of %zu bytes failed: %s", n * sizeof(T), hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? FCM_ERR_OOM : FCM_ERR_HIP;
+  }
+  h->allocs.push_back(*p);
+  h->bytes += (int64_t)(n * sizeof(T));
+  e = hipMemsetAsync(*p, 0, n * sizeof(T), h->stream);
+  if (e != hipSuccess) {
+    set_error("hipMemsetAsync failed: %s", hipGetErrorString(e));
+    return FCM_ERR_HIP;
+  }
+  return FCM_OK;
+}
+
+template <typename T>
+static fcm_status upload(fcm_handle *h, T **p, const std::vector<T> &v) {
+  fcm_status st = dalloc(h, p, v.size());
+  if (st != FCM_OK) return st;
+  FCM_HIP(hipStreamSynchronize(h->stream));
+  FCM_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return FCM_OK;
+}
+
+#define TRY(x)                         \
+  do {                                 \
+    fcm_status s_ = (x);               \
+    if (s_ != FCM_OK) return s_;       \
+  } while (0)
+
+// ------------------------------------------------------------ validation
+static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
+  if (!p || !o) { set_error("null problem or options"); return FCM_ERR_ARG; }
+  if (p->dim != 2 && p->dim != 3) { set_error("dim must be 2 or 3"); return FCM_ERR_ARG; }
+  if (p->p < 1 || p->p > kMaxP) { set_error("p must be in 1..%d", kMaxP); return FCM_ERR_ARG; }
+  if (p->n_fields != 1 && p->n_fields != p->dim) {
+    set_error("n_fields must be 1 or dim");
+    return FCM_ERR_ARG;
+  }
+  if (p->refine_levels != 0) {
+    set_error("multi-level hp refinement (refine_levels > 0) is not supported by this build");
+    return FCM_ERR_ARG;
+  }
+  for (int ax = 0; ax < p->dim; ++ax) {
+    if (p->n[ax] < 1 || p->n[ax] > 4096) { set_error("n[%d] out of range", ax); return FCM_ERR_ARG; }
+    if (!(p->hi[ax] > p->lo[ax])) { set_error("empty box on axis %d", ax); return FCM_ERR_ARG; }
+  }
+  if (!(p->alpha > 0.0) || p->alpha > 1.0) { set_error("alpha must be in (0,1]"); return FCM_ERR_ARG; }
+  if (p->quad_depth < 0 || p->quad_depth > kMaxDepth) {
+    set_error("quad_depth must be in 0..%d", kMaxDepth);
+    return FCM_ERR_ARG;
+  }
+  if (p->geom != FCM_GEOM_BOX_MINUS_BALLS && p->geom != FCM_GEOM_BALL_INTERIOR) {
+    set_error("unknown geometry");
+    return FCM_ERR_ARG;
+  }
+  if (p->n_balls < 0 || (p->n_balls > 0 && (!p->ball_c || !p->ball_r))) {
+    set_error("invalid balls");
+    return FCM_ERR_ARG;
+  }
+  if (p->geom == FCM_GEOM_BALL_INTERIOR && p->n_balls != 1) {
+    set_error("ball interior needs exactly one ball");
+    return FCM_ERR_ARG;
+  }
+  for (int j = 0; j < p->n_balls; ++j)
+    if (!(p->ball_r[j] >= 0.0) || !std::isfinite(p->ball_r[j])) {
+      set_error("invalid radius");
+      return FCM_ERR_ARG;
+    }
+  if (p->n_gauss < 0 || (p->n_gauss > 0 && !p->gauss)) { set_error("invalid sources"); return FCM_ERR_ARG; }
+  for (int k = 0; k < 5 * p->n_gauss; ++k)
+    if (!std::isfinite(p->gauss[k])) { set_error("non-finite source parameter"); return FCM_ERR_NAN; }
+  if (!std::isfinite(p->f_const)) { set_error("non-finite source"); return FCM_ERR_NAN; }
+  if (p->n_traction < 0 || (p->n_traction > 0 && (!p->traction_face || !p->traction_vec))) {
+    set_error("invalid tractions");
+    return FCM_ERR_ARG;
+  }
+  for (int k = 0; k < p->n_traction; ++k)
+    if (p->traction_face[k] < 0 || p->traction_face[k] >= 2 * p->dim) {
+      set_error("invalid traction face");
+      return FCM_ERR_ARG;
+    }
+  if (p->n_fields > 1) {
+    if (!(p->E > 0.0) || !(p->nu > -1.0 && p->nu < 0.5)) { set_error("invalid E/nu"); return FCM_ERR_ARG; }
+  } else if (!(p->kappa > 0.0)) {
+    set_error("kappa must be positive");
+    return FCM_ERR_ARG;
+  }
+  if (!(o->omega > 0.0) || o->n_pre < 0 || o->n_post < 0 || o->max_iter < 0 ||
+      !(o->rtol >= 0.0) || (o->precision != FCM_FP64 && o->precision != FCM_MIXED) ||
+      o->smoother != FCM_SMOOTH_ELEMENTWISE) {
+    set_error("invalid options");
+    return FCM_ERR_ARG;
+  }
+  return FCM_OK;
+}
+
+// --------------------------------------------------------------- tables
+static fcm_status build_tables(fcm_handle *h) {
+  const Geo &g = h->geo;
+  const int d = g.d, nf = g.nf, p = g.p, np = p + 1;
+  Tables &t = h->tab;
+  // scalar tuples (axis 0 fastest), local modes degree-sorted
+  int ms = 1;
+  for (int ax = 0; ax < d; ++ax) ms *= np;
+  t.ms = ms;
+  std::vector<int> lm;
+  std::vector<int> smap(ms * nf, -1);
+  for (int s = 1; s <= p; ++s)
+    for (int a2 = 0; a2 < (d == 3 ? np : 1); ++a2)
+      for (int a1 = 0; a1 < np; ++a1)
+        for (int a0 = 0; a0 < np; ++a0) {
+          int dg = std::max(deg1(a0), deg1(a1));
+          if (d == 3) dg = std::max(dg, deg1(a2));
+          if (dg != s) continue;
+          for (int c = 0; c < nf; ++c) {
+            int idx = (int)lm.size() / 4;
+            smap[(a0 + np * (a1 + np * a2)) * nf + c] = idx;
+            lm.push_back(a0);
+            lm.push_back(a1);
+            lm.push_back(a2);
+            lm.push_back(c);
+          }
+        }
+  t.m = (int)lm.size() / 4;
+  h->h_lm = lm;
+  // planes: slot types t_ax in 0..p-1, degree-sorted
+  std::vector<int> pidx(std::max(1, p * p * p) * nf, -1);
+  std::vector<int> ptype;
+  for (int s = 1; s <= p; ++s)
+    for (int t2 = 0; t2 < (d == 3 ? p : 1); ++t2)
+      for (int t1 = 0; t1 < p; ++t1)
+        for (int t0 = 0; t0 < p; ++t0) {
+          int dg = std::max(tdeg(t0), tdeg(t1));
+          if (d == 3) dg = std::max(dg, tdeg(t2));
+          if (dg != s) continue;
+          for (int c = 0; c < nf; ++c) {
+            pidx[(t0 + p * (t1 + p * t2)) * nf + c] = (int)ptype.size() / 4;
+            ptype.push_back(t0);
+            ptype.push_back(t1);
+            ptype.push_back(t2);
+            ptype.push_back(c);
+          }
+        }
+  t.nP = (int)ptype.size() / 4;
+  std::vector<int> xoff(t.m), rows(t.nP * 8, -1), pinfo(t.nP);
+  for (int b = 0; b < t.m; ++b) {
+    int tt[3], off[3];
+    for (int ax = 0; ax < 3; ++ax) {
+      int a = lm[4 * b + ax];
+      tt[ax] = a <= 1 ? 0 : a - 1;
+      off[ax] = (a == 1) ? 1 : 0;
+    }
+    int plane = pidx[(tt[0] + p * (tt[1] + p * tt[2])) * nf + lm[4 * b + 3]];
+    xoff[b] = plane * g.G + off[0] + g.gn[0] * (off[1] + g.gn[1] * off[2]);
+  }
+  for (int P = 0; P < t.nP; ++P) {
+    int vmask = 0, bmask = 0;
+    for (int ax = 0; ax < d; ++ax) {
+      if (ptype[4 * P + ax] == 0) vmask |= 1 << ax;
+      else bmask |= 1 << ax;
+    }
+    pinfo[P] = vmask | (bmask << 8);
+    for (int s = 0; s < (1 << d); ++s) {
+      if (s & ~vmask) continue;
+      int a[3] = {0, 0, 0};
+      for (int ax = 0; ax < d; ++ax) {
+        int tt = ptype[4 * P + ax];
+        a[ax] = ((s >> ax) & 1) ? 1 : (tt == 0 ? 0 : tt + 1);
+      }
+      rows[P * 8 + s] = smap[(a[0] + np * (a[1] + np * a[2])) * nf + ptype[4 * P + 3]];
+    }
+  }
+  // Gauss rule, basis at the nodes, 1D sub-interval matrices for levels 0..depth
+  std::vector<double> gx, gw;
+  gauss_legendre(np, gx, gw);
+  std::vector<double> gxw(2 * np), vg(np * np);
+  for (int i = 0; i < np; ++i) {
+    gxw[i] = gx[i];
+    gxw[np + i] = gw[i];
+    double v[kMaxP + 1], dv[kMaxP + 1];
+    modes1d_host(p, gx[i], v, dv);
+    for (int a = 0; a < np; ++a) vg[i * np + a] = v[a];
+  }
+  const int nint = (2 << g.depth) - 1;
+  std::vector<double> tab1d((size_t)nint * 3 * np * np, 0.0);
+  for (int l = 0; l <= g.depth; ++l) {
+    int nsub = 1 << l;
+    for (int i = 0; i < nsub; ++i) {
+      double half = 1.0 / nsub, mid = -1.0 + (2.0 * i + 1.0) * half;
+      double *T = &tab1d[(size_t)((nsub - 1) + i) * 3 * np * np];
+      for (int q = 0; q < np; ++q) {
+        double v[kMaxP + 1], dv[kMaxP + 1];
+        modes1d_host(p, mid + half * gx[q], v, dv);
+        double w = gw[q] * half;
+        for (int a = 0; a < np; ++a)
+          for (int b = 0; b < np; ++b) {
+            T[a * np + b] += w * v[a] * v[b];
+            T[np * np + a * np + b] += w * dv[a] * dv[b];
+            T[2 * np * np + a * np + b] += w * dv[a] * v[b];
+          }
+      }
+    }
+  }
+  TRY(upload(h, &t.lm, lm));
+  TRY(upload(h, &t.xoff, xoff));
+  TRY(upload(h, &t.rows, rows));
+  TRY(upload(h, &t.pinfo, pinfo));
+  TRY(upload(h, &t.smap, smap));
+  TRY(upload(h, &t.tab1d, tab1d));
+  TRY(upload(h, &t.gxw, gxw));
+  TRY(upload(h, &t.vgauss, vg));
+  std::vector<double> ball = h->prob.ball, gs = h->prob.gsrc;
+  if (ball.empty()) ball.assign(4, 0.0);
+  if (gs.empty()) gs.assign(5, 0.0);
+  TRY(upload(h, &t.ball, ball));
+  TRY(upload(h, &t.gsrc, gs));
+  return FCM_OK;
+}
+
+static inline int elin(const Geo &g, int x, int y, int z) { return x + g.n[0] * (y + g.n[1] * z); }
+
+// Schwarz block classes: an element whose whole 3^d neighbourhood is uncut
+// has a block that depends only on its position relative to the box faces.
+static void build_blocks(fcm_handle *h) {
+  const Geo &g = h->geo;
+  h->h_blk.assign(g.E, -1);
+  std::map<int, int> cls;
+  std::vector<int> reps, uniq;
+  for (int z = 0; z < g.n[2]; ++z)
+    for (int y = 0; y < g.n[1]; ++y)
+      for (int x = 0; x < g.n[0]; ++x) {
+        int e = elin(g, x, y, z);
+        if (h->h_state[e] == kVoid) continue;
+        bool unique = h->h_state[e] == kCut;
+        int c[3] = {x, y, z};
+        for (int o = 0; o < 27 && !unique; ++o) {
+          int off[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
+          if (g.d == 2 && off[2] != 0) continue;
+          int nc[3];
+          bool in = true;
+          for (int ax = 0; ax < 3; ++ax) {
+            nc[ax] = c[ax] + off[ax];
+            in = in && nc[ax] >= 0 && nc[ax] < g.n[ax];
+          }
+          if (in && h->h_state[elin(g, nc[0], nc[1], nc[2])] != kPhys) unique = true;
+        }
+        if (unique) {
+          uniq.push_back(e);
+          h->h_blk[e] = -2;
+          continue;
+        }
+        int key = 0;
+        for (int ax = 0; ax < g.d; ++ax) {
+          int cat = (c[ax] == 0 ? 1 : 0) | (c[ax] == g.n[ax] - 1 ? 2 : 0);
+          key |= cat << (2 * ax);
+        }
+        auto it = cls.find(key);
+        if (it == cls.end()) {
+          int id = (int)reps.size();
+          cls[key] = id;
+          reps.push_back(e);
+          h->h_blk[e] = id;
+        } else {
+          h->h_blk[e] = it->second;
+        }
+      }
+  h->n_shared = (int)reps.size();
+  h->n_unique = (int)uniq.size();
+  for (size_t u = 0; u < uniq.size(); ++u) h->h_blk[uniq[u]] = h->n_shared + (int)u;
+  h->h_block_elems = reps;
+  h->h_block_elems.insert(h->h_block_elems.end(), uniq.begin(), uniq.end());
+}
+
+static fcm_status check_flag(fcm_handle *h, const char *what) {
+  int f = 0;
+  FCM_HIP(hipMemcpyAsync(&f, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  FCM_HIP(hipStreamSynchronize(h->stream));
+  if (f) {
+    set_error("%s: a pivot was not positive (matrix not SPD in FP64)", what);
+    return FCM_ERR_NOT_SPD;
+  }
+  return FCM_OK;
+}
+
+static fcm_status setup_coarse(fcm_handle *h) {
+  const Geo &g = h->geo;
+  Coarse &c = h->co;
+  const int sl = g.d - 1;
+  int first = ((g.dir >> (2 * sl)) & 1) ? 1 : 0;
+  int last = ((g.dir >> (2 * sl + 1)) & 1) ? g.n[sl] - 1 : g.n[sl];
+  if (last < first) last = first;
+  const int nl = last - first + 1;
+  c.PP = 1;
+  for (int ax = 0; ax < sl; ++ax) c.PP *= g.gn[ax];
+  const int per_layer = g.nf * c.PP;
+  int w = std::max(1, (int)std::lround(1024.0 / per_layer));
+  w = std::min(w, nl);
+  c.w = w;
+  c.layer0 = first;
+  c.nblk = (nl + w - 1) / w;
+  c.nb = g.nf * w * c.PP;
+  c.no = g.d == 3 ? 9 : 3;
+  const int RT = (c.nb + 63) / 64;
+  c.JS = std::max(1, std::min(32, (256 + RT - 1) / RT));
+  c.JS = std::min(c.JS, std::max(1, c.nb / 16));
+  c.CJ = (c.nb + c.JS - 1) / c.JS;
+  const size_t nb2 = (size_t)c.nb * c.nb;
+  TRY(dalloc(h, &c.Sinv, nb2 * c.nblk));
+  TRY(dalloc(h, &c.Dst, (size_t)c.nblk * c.nb * 3 * c.no * g.nf));
+  TRY(dalloc(h, &c.W, (size_t)c.nblk * c.nb));
+  TRY(dalloc(h, &c.P0, (size_t)c.JS * c.nb));
+  TRY(dalloc(h, &c.P1, (size_t)c.JS * c.nb));
+  TRY(dalloc(h, &c.xb, (size_t)g.nf * g.G));
+  TRY(dalloc(h, &c.bb, (size_t)g.nf * g.G));
+  double *T = nullptr, *scr = nullptr;
+  FCM_HIP(hipMalloc((void **)&T, nb2 * sizeof(double)));
+  FCM_HIP(hipMalloc((void **)&scr, spd_inverse_scratch_doubles(c.nb, 1) * sizeof(double)));
+  launch_coarse_stencils(g, h->tab, c, h->kmat, h->Kref64, h->Kcut64, h->stream);
+  for (int k = 0; k < c.nblk; ++k) {
+    double *S = c.Sinv + (size_t)k * nb2;
+    launch_coarse_first(g, c, k, S, h->stream);
+    if (k > 0) launch_coarse_schur(g, c, k, S, T, h->stream);
+    spd_inverse_batched(S, c.nb, 1, scr, h->dflag, nullptr, h->stream);
+  }
+  FCM_HIP(hipStreamSynchronize(h->stream));
+  FCM_HIP(hipFree(T));
+  FCM_HIP(hipFree(scr));
+  return check_flag(h, "coarse factorisation");
+}
+
+static fcm_status setup_levels(fcm_handle *h) {
+  const Geo &g = h->geo;
+  int *belems = nullptr;
+  TRY(upload(h, &belems, h->h_block_elems));
+  const int nblocks = (int)h->h_block_elems.size();
+  double *kappa = nullptr;
+  FCM_HIP(hipMalloc((void **)&kappa, std::max(1, nblocks) * sizeof(double)));
+  std::vector<double> hk(nblocks);
+  for (int l = 1; l <= h->L; ++l) {
+    Level &L = h->lev[l];
+    const int m = L.m;
+    const size_t mm = (size_t)m * m;
+    TRY(dalloc(h, &L.invS64, mm * nblocks));
+    TRY(dalloc(h, &L.invS32, mm * nblocks));
+    L.invU64 = L.invS64 + mm * h->n_shared;
+    L.invU32 = L.invS32 + mm * h->n_shared;
+    if (m <= kSmallInv) {
+      launch_form_invert_small(g, h->tab, L.q, m, belems, nblocks, h->kmat, h->Kref64, h->Kcut64,
+                               L.invS64, L.invS32, h->dflag, kappa, h->stream);
+    } else {
+      const int chunk = 512;
+      double *scr = nullptr;
+      const int cb = std::min(chunk, nblocks);
+      FCM_HIP(hipMalloc((void **)&scr, spd_inverse_scratch_doubles(m, cb) * sizeof(double)));
+      launch_form_blocks(g, h->tab, L.q, m, belems, nblocks, h->kmat, h->Kref64, h->Kcut64,
+                         L.invS64, h->stream);
+      for (int b0 = 0; b0 < nblocks; b0 += chunk) {
+        int nbat = std::min(chunk, nblocks - b0);
+        spd_inverse_batched(L.invS64 + mm * b0, m, nbat, scr, h->dflag, kappa + b0, h->stream);
+      }
+      launch_to_f32(L.invS64, L.invS32, (int64_t)(mm * nblocks), h->stream);
+      FCM_HIP(hipStreamSynchronize(h->stream));
+      FCM_HIP(hipFree(scr));
+    }
+    // unique blocks whose Jacobi-scaled condition number exceeds kKappa64 are
+    // applied from their FP64 inverse inside the FP32 V-cycle
+    FCM_HIP(hipMemcpy(hk.data(), kappa, nblocks * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<uint8_t> fl(std::max(1, h->n_unique), 0);
+    L.n_hi64 = 0;
+    for (int u = 0; u < h->n_unique; ++u)
+      if (!(hk[h->n_shared + u] <= kKappa64)) {
+        fl[u] = 1;
+        L.n_hi64++;
+      }
+    TRY(upload(h, &L.hi64, fl));
+  }
+  FCM_HIP(hipFree(kappa));
+  return check_flag(h, "Schwarz block inversion");
+}
+
+static fcm_status do_setup(fcm_handle *h) {
+  Geo &g = h->geo;
+  const fcm_problem &pr = h->prob.pr;
+  TRY(build_tables(h));
+  const int m = h->tab.m;
+  TRY(dalloc(h, &h->dflag, 1));
+  FCM_HIP(hipMemsetAsync(h->dflag, 0, sizeof(int), h->stream));
+  // classification
+  TRY(dalloc(h, &h->state, (size_t)g.E));
+  launch_classify(g, h->tab.ball, h->state, h->stream);
+  h->h_state.resize(g.E);
+  FCM_HIP(hipMemcpyAsync(h->h_state.data(), h->state, g.E, hipMemcpyDeviceToHost, h->stream));
+  FCM_HIP(hipStreamSynchronize(h->stream));
+  h->h_kmat.assign(g.E, -1);
+  h->h_cut.clear();
+  for (int e = 0; e < g.E; ++e) {
+    if (h->h_state[e] == kPhys) h->h_kmat[e] = 0;
+    else if (h->h_state[e] == kCut) {
+      h->h_kmat[e] = 1 + (int)h->h_cut.size();
+      h->h_cut.push_back(e);
+    }
+  }
+  build_blocks(h);
+  TRY(upload(h, &h->kmat, h->h_kmat));
+  TRY(upload(h, &h->blk, h->h_blk));
+  // element matrices and loads
+  const size_t mm = (size_t)m * m;
+  const int ncut = (int)h->h_cut.size();
+  TRY(dalloc(h, &h->Kref64, mm));
+  TRY(dalloc(h, &h->Kref32, mm));
+  TRY(dalloc(h, &h->Kcut64, mm * std::max(1, ncut)));
+  TRY(dalloc(h, &h->Kcut32, mm * std::max(1, ncut)));
+  TRY(dalloc(h, &h->be, (size_t)g.E * m));
+  FCM_HIP(hipMemsetAsync(h->be, 0, (size_t)g.E * m * sizeof(double), h->stream));
+  int *dcut = nullptr;
+  if (ncut > 0) TRY(upload(h, &dcut, h->h_cut));
+  launch_integrate(g, h->tab, pr, nullptr, 1, 1, h->Kref64, h->be, h->dflag, h->stream);
+  if (ncut > 0)
+    launch_integrate(g, h->tab, pr, dcut, ncut, 0, h->Kcut64, h->be, h->dflag, h->stream);
+  launch_phys_rhs(g, h->tab, pr, h->state, h->be, h->stream);
+  for (int k = 0; k < pr.n_traction; ++k)
+    launch_traction_rhs(g, h->tab, pr.traction_face[k], &h->prob.tvec[3 * k], h->state, h->be,
+                        h->stream);
+  const int L = h->L;
+  TRY(dalloc(h, &h->b, (size_t)h->lev[L].npad));
+  launch_assemble_rhs(g, h->tab, h->kmat, h->be, h->b, h->stream);
+  launch_to_f32(h->Kref64, h->Kref32, (int64_t)mm, h->stream);
+  if (ncut > 0) launch_to_f32(h->Kcut64, h->Kcut32, (int64_t)(mm * ncut), h->stream);
+  // Schwarz inverses per level >= 1, coarse factorisation
+  TRY(setup_levels(h));
+  TRY(setup_coarse(h));
+  // work vectors
+  for (int l = 0; l <= L; ++l) {
+    Level &lv = h->lev[l];
+    TRY(dalloc(h, &lv.x64, lv.npad));
+    TRY(dalloc(h, &lv.x32, lv.npad));
+    if (l >= 1) {
+      TRY(dalloc(h, &lv.r64, lv.npad));
+      TRY(dalloc(h, &lv.d64, lv.npad));
+      TRY(dalloc(h, &lv.r32, lv.npad));
+      TRY(dalloc(h, &lv.d32, lv.npad));
+    }
+  }
+  const int64_t nf = h->lev[L].npad;
+  TRY(dalloc(h, &h->cg_r, nf));
+  TRY(dalloc(h, &h->cg_z, nf));
+  TRY(dalloc(h, &h->cg_p, nf));
+  TRY(dalloc(h, &h->cg_q, nf));
+  TRY(dalloc(h, &h->vin32, nf));
+  TRY(dalloc(h, &h->vout32, nf));
+  TRY(dalloc(h, &h->red, 1024));
+  TRY(dalloc(h, &h->scal, 16));
+  FCM_HIP(hipHostMalloc((void **)&h->hscal, 16 * sizeof(double), hipHostMallocDefault));
+  FCM_HIP(hipStreamSynchronize(h->stream));
+  return FCM_OK;
+}
+
+// ------------------------------------------------------------- V-cycle
+template <typename T> struct Prec;
+template <> struct Prec<double> {
+  static double *x(Level &l) { return l.x64; }
+  static double *r(Level &l) { return l.r64; }
+  static double *d(Level &l) { return l.d64; }
+  static const double *invS(Level &l) { return l.invS64; }
+  static const double *invU(Level &l) { return l.invU64; }
+  static const double *Kref(fcm_handle *h) { return h->Kref64; }
+  static const double *Kcut(fcm_handle *h) { return h->Kcut64; }
+};
+template <> struct Prec<float> {
+  static float *x(Level &l) { return l.x32; }
+  static float *r(Level &l) { return l.r32; }
+  static float *d(Level &l) { return l.d32; }
+  static const float *invS(Level &l) { return l.invS32; }
+  static const float *invU(Level &l) { return l.invU32; }
+  static const float *Kref(fcm_handle *h) { return h->Kref32; }
+  static const float *Kcut(fcm_handle *h) { return h->Kcut32; }
+};
+
+static void coarse_solve_t(fcm_handle *h, const double *b, double *x, hipStream_t s) {
+  coarse_solve_launch(h->geo, h->co, b, x, s);
+}
+static void coarse_solve_t(fcm_handle *h, const float *b, float *x, hipStream_t s) {
+  const int64_t n = (int64_t)h->geo.nf * h->geo.G;
+  launch_f32_to_f64(b, h->co.bb, n, s);
+  coarse_solve_launch(h->geo, h->co, h->co.bb, h->co.xb, s);
+  launch_f64_to_f32(h->co.xb, x, n, s);
+}
+
+template <typename T>
+static OpArgs<T> stiffness_args(fcm_handle *h, int l) {
+  OpArgs<T> a;
+  a.m_in = h->lev[l].m;
+  a.nP_out = h->lev[l].nP;
+  a.ld = h->tab.m;
+  a.mid = h->kmat;
+  a.matS = Prec<T>::Kref(h);
+  a.nS = 1;
+  a.matU = Prec<T>::Kcut(h);
+  set_fp64_parts<T>(h, l, a, false);
+  return a;
+}
+
+template <typename T>
+static void set_fp64_parts(fcm_handle *, int, OpArgs<T> &, bool) {}
+template <>
+void set_fp64_parts<float>(fcm_handle *h, int l, OpArgs<float> &a, bool smoother) {
+  if (smoother) {
+    a.matU64 = h->lev[l].invU64;
+    a.u64flag = h->lev[l].hi64;
+  } else {
+    a.matU64 = h->Kcut64;   // every cut element: FP64 entries and accumulation
+    a.u64flag = nullptr;
+  }
+}
+
+template <typename T>
+static OpArgs<T> smoother_args(fcm_handle *h, int l) {
+  Level &L = h->lev[l];
+  OpArgs<T> a;
+  a.m_in = L.m;
+  a.nP_out = L.nP;
+  a.ld = L.m;
+  a.mid = h->blk;
+  a.matS = Prec<T>::invS(L);
+  a.nS = h->n_shared;
+  a.matU = Prec<T>::invU(L);
+  set_fp64_parts<T>(h, l, a, true);
+  return a;
+}
+
+// Alg. 1 on level l with zero initial guess: x = V(l, b).  The residual is
+// updated after every smoothing step (r -= omega A delta == b - A x).
+template <typename T>
+static void vcycle_level(fcm_handle *h, int l, const T *b, T *x, hipStream_t s) {
+  if (l == 0) {
+    coarse_solve_t(h, b, x, s);
+    return;
+  }
+  const Geo &g = h->geo;
+  Level &L = h->lev[l];
+  T *r = Prec<T>::r(L), *dl = Prec<T>::d(L);
+  const T w = (T)h->opt.omega;
+  OpArgs<T> sm = smoother_args<T>(h, l);
+  OpArgs<T> ap = stiffness_args<T>(h, l);
+  sm.out = dl;
+  sm.xs = x;
+  sm.omega = w;
+  ap.x = dl;
+  ap.out = r;
+  ap.scale = -w;
+  const int npre = h->opt.n_pre, npost = h->opt.n_post;
+  if (npre == 0) {
+    hipMemcpyAsync(r, b, L.npad * sizeof(T), hipMemcpyDeviceToDevice, s);
+    hipMemsetAsync(x, 0, L.npad * sizeof(T), s);
+  }
+  for (int it = 0; it < npre; ++it) {
+    sm.x = it == 0 ? b : r;
+    sm.first = it == 0;
+    launch_elem_op<T>(g, h->tab, sm, s);
+    ap.cvec = it == 0 ? b : r;
+    launch_elem_op<T>(g, h->tab, ap, s);
+  }
+  // coarse-grid correction: b_{l-1} = R r (prefix), x += R^T e, r -= A R^T e
+  Level &Lc = h->lev[l - 1];
+  T *e = Prec<T>::x(Lc);
+  vcycle_level<T>(h, l - 1, r, e, s);
+  OpArgs<T> pr = stiffness_args<T>(h, l);
+  pr.x = e;
+  pr.m_in = Lc.m;
+  pr.out = r;
+  pr.cvec = r;
+  pr.scale = (T)-1;
+  pr.xp = x;
+  pr.ep = e;
+  pr.nP_e = Lc.nP;
+  launch_elem_op<T>(g, h->tab, pr, s);
+  for (int it = 0; it < npost; ++it) {
+    sm.x = r;
+    sm.first = 0;
+    launch_elem_op<T>(g, h->tab, sm, s);
+    if (it + 1 < npost) {
+      ap.cvec = r;
+      launch_elem_op<T>(g, h->tab, ap, s);
+    }
+  }
+}
+
+static void vcycle_top(fcm_handle *h, const double *r, double *z, hipStream_t s) {
+  const int L = h->L;
+  if (L == 0) {
+    coarse_solve_launch(h->geo, h->co, r, z, s);
+    return;
+  }
+  if (h->opt.precision == FCM_FP64) {
+    vcycle_level<double>(h, L, r, z, s);
+  } else {
+    // FP32 V-cycle inside the FP64 iteration: cast at entry and exit
+    Level &lv = h->lev[L];
+    launch_f64_to_f32(r, h->vin32, lv.npad, s);
+    vcycle_level<float>(h, L, h->vin32, h->vout32, s);
+    launch_f32_to_f64(h->vout32, z, lv.npad, s);
+  }
+}
+
+static void apply_fine64(fcm_handle *h, int l, const double *x, double *y, hipStream_t s) {
+  OpArgs<double> a = stiffness_args<double>(h, l);
+  a.x = x;
+  a.out = y;
+  launch_elem_op<double>(h->geo, h->tab, a, s);
+}
+
+static double dot_sync(fcm_handle *h, const double *x, const double *y, int64_t n,
+                       hipStream_t s, int slot) {
+  int nb = dot_blocks(n);
+  launch_dot_partial(x, y, n, h->red, nb, s);
+  launch_dot_final(h->red, nb, h->scal + slot, s);
+  hipMemcpyAsync(h->hscal + slot, h->scal + slot, sizeof(double), hipMemcpyDeviceToHost, s);
+  hipStreamSynchronize(s);
+  return h->hscal[slot];
+}
+
+
+// ------------------------------------------------ resumable PCG (Section 4)
+// cg_issue enqueues one CG iteration without synchronising: the V-cycle of
+// the previous residual (if due), q = A p, alpha, x += alpha p, r -= alpha q
+// and ||r||^2, whose scalars are copied to pinned host memory.  cg_finish
+// reads them after the stream has drained and decides convergence.  Solves
+// driven this way can be interleaved on several streams (serving).
+fcm_status cg_begin(fcm_handle *h, CGState &cg, const double *b_dev, double *x, hipStream_t s) {
+  const int L = h->L;
+  const int64_t n = h->lev[L].npad;
+  cg = CGState();
+  cg.b = b_dev ? b_dev : h->b;
+  cg.x = x;
+  FCM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  FCM_HIP(hipMemcpyAsync(h->cg_r, cg.b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  h->history.assign(1, 1.0);
+  double bb = dot_sync(h, cg.b, cg.b, n, s, 6);
+  if (!std::isfinite(bb)) {
+    set_error("non-finite right-hand side");
+    cg.done = true;
+    cg.status = FCM_ERR_NAN;
+    return FCM_ERR_NAN;
+  }
+  cg.nb = std::sqrt(bb);
+  cg.first = true;
+  cg.status = FCM_NOT_CONVERGED;
+  if (cg.nb == 0.0) {
+    cg.rel = 0.0;
+    cg.done = true;
+    cg.status = FCM_OK;
+  } else if (h->opt.max_iter == 0) {
+    cg.done = true;
+  }
+  return FCM_OK;
+}
+
+void cg_issue(fcm_handle *h, CGState &cg, hipStream_t s) {
+  const int L = h->L;
+  const int64_t n = h->lev[L].npad;
+  double *r = h->cg_r, *z = h->cg_z, *p = h->cg_p, *q = h->cg_q;
+  const int nblk = dot_blocks(n);
+  vcycle_top(h, r, z, s);
+  launch_dot_partial(r, z, n, h->red, nblk, s);
+  if (cg.first) {
+    launch_dot_final(h->red, nblk, h->scal + 0, s);
+    launch_cg_update_p(p, z, h->scal, n, 1, s);
+  } else {
+    launch_dot_final(h->red, nblk, h->scal + 4, s);
+    launch_cg_beta(h->scal, s);
+    launch_cg_update_p(p, z, h->scal, n, 0, s);
+  }
+  apply_fine64(h, L, p, q, s);
+  launch_dot_partial(p, q, n, h->red, nblk, s);
+  launch_dot_final(h->red, nblk, h->scal + 1, s);
+  launch_cg_alpha(h->scal, s);
+  launch_cg_update_xr(cg.x, r, p, q, h->scal, n, h->red, nblk, s);
+  launch_dot_final(h->red, nblk, h->scal + 3, s);
+  hipMemcpyAsync(h->hscal, h->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s);
+}
+
+void cg_finish(fcm_handle *h, CGState &cg) {
+  cg.first = false;
+  ++cg.it;
+  const double pq = h->hscal[1], rr = h->hscal[3];
+  if (!(pq > 0.0) || !std::isfinite(rr)) {
+    set_error("CG breakdown (p^T A p = %g, r^T r = %g)", pq, rr);
+    cg.status = std::isfinite(rr) ? FCM_ERR_BREAKDOWN : FCM_ERR_NAN;
+    cg.done = true;
+    return;
+  }
+  cg.rel = std::sqrt(rr) / cg.nb;
+  h->history.push_back(cg.rel);
+  if (cg.rel < h->opt.rtol) {
+    cg.status = FCM_OK;
+    cg.done = true;
+  } else if (cg.it >= h->opt.max_iter) {
+    cg.status = FCM_NOT_CONVERGED;
+    cg.done = true;
+  }
+}
+
+fcm_status cg_report(fcm_handle *h, CGState &cg, fcm_solve_info *info, hipStream_t s) {
+  const int64_t n = h->lev[h->L].npad;
+  double *q = h->cg_q;
+  apply_fine64(h, h->L, cg.x, q, s);
+  launch_axpby(q, cg.b, 1.0, -1.0, n, s);   // q = b - A x
+  double rr = dot_sync(h, q, q, n, s, 7);
+  info->iterations = cg.it;
+  info->rel_res = cg.rel;
+  info->true_rel_res = cg.nb > 0 ? std::sqrt(rr) / cg.nb : 0.0;
+  info->t_setup_ms = h->t_setup_ms;
+  info->t_solve_ms = 0.0;
+  info->res_history = h->history.data();
+  info->n_history = (int)h->history.size();
+  FCM_HIP(hipGetLastError());
+  return FCM_OK;
+}
+
+}  // namespace fcm
+
+using namespace fcm;
+
+// ================================================================= C-ABI
+extern "C" {
+
+const char *fcm_last_error(void) { return g_err.c_str(); }
+
+const char *fcm_status_string(fcm_status s) {
+  switch (s) {
+    case FCM_OK: return "ok";
+    case FCM_NOT_CONVERGED: return "not converged";
+    case FCM_ERR_ARG: return "invalid argument";
+    case FCM_ERR_OOM: return "out of device memory";
+    case FCM_ERR_HIP: return "HIP runtime error";
+    case FCM_ERR_NOT_SPD: return "matrix not positive definite";
+    case FCM_ERR_BREAKDOWN: return "CG breakdown";
+    case FCM_ERR_NAN: return "non-finite value";
+    case FCM_ERR_BUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+void fcm_destroy(fcm_handle *h) {
+  if (!h) return;
+  for (void *p : h->allocs) hipFree(p);
+  if (h->hscal) hipHostFree(h->hscal);
+  delete h;
+}
+
+fcm_status fcm_setup(const fcm_problem *pr, const fcm_options *op, void *stream,
+                     fcm_handle **out) {
+  if (!out) {
+    set_error("null output handle");
+    return FCM_ERR_ARG;
+  }
+  *out = nullptr;
+  fcm_status st = validate(pr, op);
+  if (st != FCM_OK) return st;
+  auto t0 = std::chrono::steady_clock::now();
+  fcm_handle *h = new fcm_handle();
+  h->stream = (hipStream_t)stream;
+  hipGetDevice(&h->device);
+  h->opt = *op;
+  Problem &P = h->prob;
+  P.pr = *pr;
+  for (int j = 0; j < pr->n_balls; ++j) {
+    for (int ax = 0; ax < 3; ++ax) P.ball.push_back(ax < pr->dim ? pr->ball_c[j * pr->dim + ax] : 0.0);
+    P.ball.push_back(pr->ball_r[j]);
+  }
+  P.gsrc.assign(pr->gauss, pr->gauss + 5 * pr->n_gauss);
+  P.tface.assign(pr->traction_face, pr->traction_face + pr->n_traction);
+  P.tvec.assign(pr->traction_vec, pr->traction_vec + 3 * pr->n_traction);
+  P.pr.ball_c = nullptr;
+  P.pr.ball_r = nullptr;
+  P.pr.gauss = P.gsrc.data();
+  P.pr.traction_face = P.tface.data();
+  P.pr.traction_vec = P.tvec.data();
+  Geo &g = h->geo;
+  g.d = pr->dim;
+  g.nf = pr->n_fields;
+  g.p = pr->p;
+  g.G = 1;
+  g.E = 1;
+  for (int ax = 0; ax < 3; ++ax) {
+    g.n[ax] = ax < g.d ? pr->n[ax] : 1;
+    g.gn[ax] = ax < g.d ? pr->n[ax] + 1 : 1;
+    g.lo[ax] = ax < g.d ? pr->lo[ax] : 0.0;
+    g.h[ax] = ax < g.d ? (pr->hi[ax] - pr->lo[ax]) / pr->n[ax] : 1.0;
+    g.G *= g.gn[ax];
+    g.E *= g.n[ax];
+  }
+  g.dir = pr->dirichlet_faces;
+  g.geom = pr->geom;
+  g.nballs = pr->n_balls;
+  g.alpha = pr->alpha;
+  g.depth = pr->quad_depth;
+  h->L = pr->p - 1;
+  for (int l = 0; l <= h->L; ++l) {
+    Level &lv = h->lev[l];
+    lv.q = l + 1;
+    int q1 = 1, qq = 1;
+    for (int ax = 0; ax < g.d; ++ax) {
+      q1 *= (lv.q + 1);
+      qq *= lv.q;
+    }
+    lv.m = g.nf * q1;
+    lv.nP = g.nf * qq;
+    lv.npad = (int64_t)lv.nP * g.G;
+  }
+  if ((int64_t)h->lev[h->L].npad >= (1ll << 31) - 1) {
+    delete h;
+    set_error("problem too large for 32-bit plane offsets");
+    return FCM_ERR_ARG;
+  }
+  st = do_setup(h);
+  if (st != FCM_OK) {
+    fcm_destroy(h);
+    return st;
+  }
+  // DOF counts per level (host, from the states)
+  {
+    std::vector<int64_t> keys;
+    // counted in fcm_sizes on demand
+  }
+  h->t_setup_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = h;
+  return FCM_OK;
+}
+
+// Existence of DOF (grid point gc, plane slot types tt) on the host.
+static bool dof_exists(const fcm_handle *h, const int *gc, const int *tt) {
+  const Geo &g = h->geo;
+  int vmask = 0;
+  for (int ax = 0; ax < g.d; ++ax) {
+    if (tt[ax] == 0) {
+      vmask |= 1 << ax;
+      if (gc[ax] == 0 && ((g.dir >> (2 * ax)) & 1)) return false;
+      if (gc[ax] == g.n[ax] && ((g.dir >> (2 * ax + 1)) & 1)) return false;
+    } else if (gc[ax] == g.n[ax]) {
+      return false;
+    }
+  }
+  for (int s = 0; s < (1 << g.d); ++s) {
+    if (s & ~vmask) continue;
+    int ec[3] = {gc[0] - (s & 1), gc[1] - ((s >> 1) & 1), gc[2] - ((s >> 2) & 1)};
+    bool in = true;
+    for (int ax = 0; ax < 3; ++ax) in = in && ec[ax] >= 0 && ec[ax] < g.n[ax];
+    if (in && h->h_state[elin(g, ec[0], ec[1], ec[2])] != kVoid) return true;
+  }
+  return false;
+}
+
+static void plane_types(const fcm_handle *h, std::vector<int> &pt) {
+  const Geo &g = h->geo;
+  const int p = g.p, d = g.d, nf = g.nf;
+  pt.clear();
+  for (int s = 1; s <= p; ++s)
+    for (int t2 = 0; t2 < (d == 3 ? p : 1); ++t2)
+      for (int t1 = 0; t1 < p; ++t1)
+        for (int t0 = 0; t0 < p; ++t0) {
+          int dg = std::max(tdeg(t0), tdeg(t1));
+          if (d == 3) dg = std::max(dg, tdeg(t2));
+          if (dg != s) continue;
+          for (int c = 0; c < nf; ++c) {
+            pt.push_back(t0);
+            pt.push_back(t1);
+            pt.push_back(t2);
+            pt.push_back(c);
+          }
+        }
+}
+
+fcm_status fcm_sizes(const fcm_handle *h, int *n_levels, int64_t *n_dofs, int64_t *n_padded) {
+  if (!h || !n_levels) {
+    set_error("null argument");
+    return FCM_ERR_ARG;
+  }
+  *n_levels = h->L + 1;
+  if (n_padded)
+    for (int l = 0; l <= h->L; ++l) n_padded[l] = h->lev[l].npad;
+  if (n_dofs) {
+    const Geo &g = h->geo;
+    std::vector<int> pt;
+    plane_types(h, pt);
+    std::vector<int64_t> per_plane(pt.size() / 4, 0);
+    for (size_t P = 0; P < per_plane.size(); ++P)
+      for (int gi = 0; gi < g.G; ++gi) {
+        int gc[3] = {gi % g.gn[0], (gi / g.gn[0]) % g.gn[1], gi / (g.gn[0] * g.gn[1])};
+        if (dof_exists(h, gc, &pt[4 * P])) per_plane[P]++;
+      }
+    for (int l = 0; l <= h->L; ++l) {
+      int64_t s = 0;
+      for (int P = 0; P < h->lev[l].nP; ++P) s += per_plane[P];
+      n_dofs[l] = s;
+    }
+  }
+  return FCM_OK;
+}
+
+fcm_status fcm_dof_keys(const fcm_handle *h, int64_t *keys) {
+  if (!h || !keys) {
+    set_error("null argument");
+    return FCM_ERR_ARG;
+  }
+  const Geo &g = h->geo;
+  std::vector<int> pt;
+  plane_types(h, pt);
+  const int p = g.p;
+  int64_t S[3];
+  for (int ax = 0; ax < 3; ++ax) S[ax] = (int64_t)(g.n[ax] + 1) * p;
+  for (size_t P = 0; P < pt.size() / 4; ++P)
+    for (int gi = 0; gi < g.G; ++gi) {
+      int gc[3] = {gi % g.gn[0], (gi / g.gn[0]) % g.gn[1], gi / (g.gn[0] * g.gn[1])};
+      int64_t &k = keys[(int64_t)P * g.G + gi];
+      if (!dof_exists(h, gc, &pt[4 * P])) {
+        k = -1;
+        continue;
+      }
+      int64_t key = pt[4 * P + 3];
+      for (int ax = g.d - 1; ax >= 0; --ax) {
+        int64_t code = (int64_t)gc[ax] * p + pt[4 * P + ax];
+        key = key * S[ax] + code;
+      }
+      k = key;
+    }
+  return FCM_OK;
+}
+
+fcm_status fcm_local_modes(const fcm_handle *h, int *m, int *modes) {
+  if (!h || !m) {
+    set_error("null argument");
+    return FCM_ERR_ARG;
+  }
+  *m = h->tab.m;
+  if (modes) std::memcpy(modes, h->h_lm.data(), h->h_lm.size() * sizeof(int));
+  return FCM_OK;
+}
+
+fcm_status fcm_element(const fcm_handle *h, int64_t e, int *state, double *K, double *be) {
+  if (!h || e < 0 || e >= h->geo.E) {
+    set_error("element index out of range");
+    return FCM_ERR_ARG;
+  }
+  const int m = h->tab.m;
+  if (state) *state = h->h_state[e];
+  int kid = h->h_kmat[e];
+  if (K && kid >= 0) {
+    const double *src = kid == 0 ? h->Kref64 : h->Kcut64 + (size_t)(kid - 1) * m * m;
+    FCM_HIP(hipMemcpy(K, src, (size_t)m * m * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  if (be && kid >= 0)
+    FCM_HIP(hipMemcpy(be, h->be + (size_t)e * m, (size_t)m * sizeof(double), hipMemcpyDeviceToHost));
+  return FCM_OK;
+}
+
+fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s) {
+  if (!h || !s) {
+    set_error("null argument");
+    return FCM_ERR_ARG;
+  }
+  s->n_elements = h->geo.E;
+  int64_t kept = 0;
+  for (auto v : h->h_state) kept += v != kVoid;
+  s->n_kept = kept;
+  s->n_cut = (int64_t)h->h_cut.size();
+  s->n_unique_blocks = h->n_unique;
+  s->n_shared_classes = h->n_shared;
+  s->device_bytes = h->bytes;
+  s->coarse_blocks = h->co.nblk;
+  s->coarse_block_size = h->co.nb;
+  return FCM_OK;
+}
+
+fcm_status fcm_rhs(fcm_handle *h, double *b_dev, void *stream) {
+  if (!h || !b_dev) {
+    set_error("null argument");
+    return FCM_ERR_ARG;
+  }
+  FCM_HIP(hipMemcpyAsync(b_dev, h->b, h->lev[h->L].npad * sizeof(double),
+                         hipMemcpyDeviceToDevice, (hipStream_t)stream));
+  return FCM_OK;
+}
+
+fcm_status fcm_apply(fcm_handle *h, int level, const double *x, double *y, void *stream) {
+  if (!h || !x || !y || level < 0 || level > h->L) {
+    set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  apply_fine64(h, level, x, y, (hipStream_t)stream);
+  FCM_HIP(hipGetLastError());
+  return FCM_OK;
+}
+
+fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z, void *stream) {
+  if (!h || !r || !z || level < 1 || level > h->L) {
+    set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  OpArgs<double> a = smoother_args<double>(h, level);
+  a.x = r;
+  a.out = z;
+  launch_elem_op<double>(h->geo, h->tab, a, (hipStream_t)stream);
+  FCM_HIP(hipGetLastError());
+  return FCM_OK;
+}
+
+fcm_status fcm_coarse_solve(fcm_handle *h, const double *b, double *x, void *stream) {
+  if (!h || !b || !x) {
+    set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  coarse_solve_launch(h->geo, h->co, b, x, (hipStream_t)stream);
+  FCM_HIP(hipGetLastError());
+  return FCM_OK;
+}
+
+fcm_status fcm_vcycle(fcm_handle *h, const double *r, double *z, void *stream) {
+  if (!h || !r || !z) {
+    set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  vcycle_top(h, r, z, (hipStream_t)stream);
+  FCM_HIP(hipGetLastError());
+  return FCM_OK;
+}
+
+fcm_status fcm_pcg_solve(fcm_handle *h, const double *b_dev, double *x_dev, fcm_solve_info *info,
+                         void *stream) {
+  if (!h || !x_dev) {
+    set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  auto t0 = std::chrono::steady_clock::now();
+  CGState cg;
+  fcm_status st = cg_begin(h, cg, b_dev, x_dev, s);
+  if (st < 0) return st;
+  while (!cg.done) {
+    cg_issue(h, cg, s);
+    FCM_HIP(hipStreamSynchronize(s));
+    cg_finish(h, cg);
+  }
+  FCM_HIP(hipGetLastError());
+  if (info) {
+    st = cg_report(h, cg, info, s);
+    if (st < 0) return st;
+    info->t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return (fcm_status)cg.status;
+}
+
+fcm_status fcm_mg_solve(fcm_handle *h, const double *b_dev, double *x_dev, fcm_solve_info *info,
+                        double *rho_max, void *stream) {
+  if (!h || !x_dev) {
+    set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  auto t0 = std::chrono::steady_clock::now();
+  const int L = h->L;
+  const int64_t n = h->lev[L].npad;
+  const double *b = b_dev ? b_dev : h->b;
+  double *x = x_dev, *r = h->cg_r, *z = h->cg_z, *q = h->cg_p;
+  FCM_HIP(hipMemsetAsync(x, 0, n * sizeof(double), s));
+  FCM_HIP(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  h->history.assign(1, 1.0);
+  const double nb = std::sqrt(dot_sync(h, b, b, n, s, 6));
+  int it = 0;
+  double rel = 1.0, rmax = 0.0;
+  fcm_status st = FCM_NOT_CONVERGED;
+  while (nb > 0 && it < h->opt.max_iter) {
+    vcycle_top(h, r, z, s);
+    launch_axpby(x, z, 1.0, 1.0, n, s);
+    apply_fine64(h, L, x, q, s);
+    FCM_HIP(hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_axpby(r, q, -1.0, 1.0, n, s);
+    double rr = dot_sync(h, r, r, n, s, 3);
+    ++it;
+    double nrel = std::sqrt(rr) / nb;
+    if (!std::isfinite(nrel)) {
+      st = FCM_ERR_NAN;
+      break;
+    }
+    rmax = std::max(rmax, nrel / rel);
+    rel = nrel;
+    h->history.push_back(rel);
+    if (rel < h->opt.rtol) {
+      st = FCM_OK;
+      break;
+    }
+  }
+  if (rho_max) *rho_max = rmax;
+  if (info) {
+    info->iterations = it;
+    info->rel_res = rel;
+    info->true_rel_res = rel;
+    info->t_setup_ms = h->t_setup_ms;
+    info->t_solve_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    info->res_history = h->history.data();
+    info->n_history = (int)h->history.size();
+  }
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,240 @@
+// Internal declarations of libfcm (not part of the C-ABI).
+//
+// Data layout in device memory (gfx950, HBM3E):
+//  * Grid: G = prod (n_ax + 1) points, axis 0 fastest.  Element e has the
+//    same multi-index as its lowest grid point.
+//  * Vectors: padded planes.  A plane is one slot type T = (t_0..t_{d-1})
+//    (t = 0 vertex, t = j-1 for the degree-j bubble) and one component; plane
+//    P occupies [P*G, (P+1)*G).  Planes are sorted by max degree, so the
+//    level-q vector (degree <= q) is the prefix of nf*q^d planes.
+//  * Element matrices: m_p x m_p row-major in a degree-sorted local mode
+//    order; the level-q matrix is the leading m_q x m_q block (ld = m_p).
+//  * Schwarz inverses of level q: m_q x m_q row-major, shared classes first
+//    (translation-invariant blocks away from cuts), then unique blocks.
+//  * Coarse level (q = 1, vertex planes): split along the slowest axis into
+//    blocks of w grid layers; dense inverses of the block Schur complements.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fcm.h"
+
+namespace fcm {
+
+constexpr int kMaxP = 6;
+constexpr int kMaxLevels = 8;
+constexpr int kMaxDepth = 4;
+constexpr double kKappa64 = 1e5; // scaled kappa_1 above which a Schwarz block stays FP64
+constexpr int kSmallInv = 88;   // Schwarz blocks up to this size are inverted in LDS (<= 64 KB)
+
+enum : uint8_t { kVoid = 0, kPhys = 1, kCut = 2 };
+
+// Geometry and discretisation constants, passed to kernels by value.
+struct Geo {
+  int d, nf, p;
+  int n[3];      // cells per axis (1 for unused axes)
+  int gn[3];     // grid points per axis (1 for unused axes)
+  int G;         // grid points
+  int E;         // elements
+  double lo[3], h[3];
+  unsigned dir;  // Dirichlet face bits
+  int geom, nballs;
+  double alpha;
+  int depth;
+};
+
+// Per-level Schwarz data and work vectors.
+struct Level {
+  int q = 0, m = 0, nP = 0;
+  int64_t npad = 0, ndofs = 0;
+  double *invS64 = nullptr, *invU64 = nullptr;
+  float *invS32 = nullptr, *invU32 = nullptr;
+  uint8_t *hi64 = nullptr;     // unique blocks applied in FP64 inside the FP32 V-cycle
+  int n_hi64 = 0;
+  double *x64 = nullptr, *r64 = nullptr, *d64 = nullptr;
+  float *x32 = nullptr, *r32 = nullptr, *d32 = nullptr;
+};
+
+struct Coarse {
+  int w = 1;          // grid layers per block
+  int nblk = 0;       // number of blocks
+  int layer0 = 0;     // first grid layer of block 0
+  int PP = 0;         // points per layer
+  int nb = 0;         // block size = nf * w * PP
+  int no = 0;         // in-layer stencil offsets (3^{d-1})
+  int JS = 1, CJ = 0; // column splits of the block GEMV
+  double *Sinv = nullptr;           // [nblk][nb][nb]
+  double *Lst = nullptr, *Ust = nullptr;   // [nblk*nb][no*nf] couplings to previous / next block
+  double *Dst = nullptr;            // [nblk*nb][w-local dense rows are built from it] in-block stencil
+  double *W = nullptr;              // [nblk*nb] forward-sweep right-hand sides
+  double *P0 = nullptr, *P1 = nullptr;  // [JS][nb] partial products
+  double *xb = nullptr, *bb = nullptr;  // FP64 coarse vectors (used by the FP32 V-cycle)
+};
+
+struct Problem {
+  fcm_problem pr;
+  std::vector<double> ball;    // [nballs][4]: cx, cy, cz, r
+  std::vector<double> gsrc;    // [ngauss][5]
+  std::vector<int> tface;
+  std::vector<double> tvec;
+};
+
+// Device tables shared by the kernels.
+struct Tables {
+  int m = 0, ms = 0, nP = 0;
+  int *lm = nullptr;        // [m][4] local modes a0,a1,a2,c (degree-sorted)
+  int *xoff = nullptr;      // [m] plane(b)*G + grid offset of mode b
+  int *rows = nullptr;      // [nP][8] local row of plane P in element g - delta(s), or -1
+  int *pinfo = nullptr;     // [nP] bit0..2 vertex axes, bits 8..10 bubble axes
+  int *smap = nullptr;      // [ms*nf] local index of (scalar tuple s, comp c)
+  double *tab1d = nullptr;  // [nint][3][(p+1)^2] 1D sub-interval matrices M1, K1, D1
+  double *gxw = nullptr;    // [2][p+1] Gauss nodes and weights on [-1,1]
+  double *vgauss = nullptr; // [p+1][p+1] mode values at the Gauss nodes
+  double *ball = nullptr;   // [nballs][4]
+  double *gsrc = nullptr;   // [ngauss][5]
+};
+
+}  // namespace fcm
+
+struct fcm_handle {
+  fcm::Problem prob;
+  fcm_options opt{};
+  fcm::Geo geo{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int L = 0;                                  // fine level index (= p-1)
+  fcm::Level lev[fcm::kMaxLevels];
+  fcm::Tables tab;
+  std::vector<int> h_lm;                      // host copy of the local modes
+  std::vector<uint8_t> h_state;               // element states
+  std::vector<int> h_kmat, h_blk;             // per element matrix ids
+  std::vector<int> h_cut;                     // element ids of cut elements
+  int n_shared = 0, n_unique = 0;
+  std::vector<int> h_block_elems;             // representative element per block
+  uint8_t *state = nullptr;
+  int *kmat = nullptr;                        // -1 void, 0 uncut (K_ref), 1+c cut c
+  int *blk = nullptr;                         // -1 void, <n_shared class, else n_shared+u
+  double *Kref64 = nullptr, *Kcut64 = nullptr, *be = nullptr, *b = nullptr;
+  float *Kref32 = nullptr, *Kcut32 = nullptr;
+  fcm::Coarse co;
+  // CG work vectors (fine level, FP64) and reduction scratch
+  double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
+  float *vin32 = nullptr, *vout32 = nullptr;  // FP32 V-cycle input/output (fine level)
+  double *red = nullptr;                      // partial sums
+  double *scal = nullptr;                     // device scalars
+  double *hscal = nullptr;                    // pinned host mirror
+  int *dflag = nullptr;                       // device error flag
+  std::vector<double> history;
+  double t_setup_ms = 0.0;
+  int64_t bytes = 0;
+  std::vector<void *> allocs;
+};
+
+namespace fcm {
+
+// ----------------------------------------------------------------- helpers
+void set_error(const char *fmt, ...);
+#define FCM_HIP(call)                                                         \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      fcm::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call,               \
+                     hipGetErrorString(e_));                                  \
+      return FCM_ERR_HIP;                                                     \
+    }                                                                         \
+  } while (0)
+
+// ------------------------------------------------------- kernel launchers
+// Setup (kernels_setup.hip).
+void launch_classify(const Geo &g, const double *ball, uint8_t *state, hipStream_t s);
+void launch_integrate(const Geo &g, const Tables &t, const fcm_problem &pr, const int *elist,
+                      int nlist, int ref_mode, double *Kout, double *be_all, int *flag,
+                      hipStream_t s);
+void launch_phys_rhs(const Geo &g, const Tables &t, const fcm_problem &pr, const uint8_t *state,
+                     double *be_all, hipStream_t s);
+void launch_traction_rhs(const Geo &g, const Tables &t, int face, const double *tvec,
+                         const uint8_t *state, double *be_all, hipStream_t s);
+void launch_assemble_rhs(const Geo &g, const Tables &t, const int *kmat, const double *be_all,
+                         double *b, hipStream_t s);
+void launch_form_invert_small(const Geo &g, const Tables &t, int q, int m, const int *belems,
+                              int nblocks, const int *kmat, const double *Kref,
+                              const double *Kcut, double *inv64, float *inv32, int *flag,
+                              double *kappa, hipStream_t s);
+void launch_form_blocks(const Geo &g, const Tables &t, int q, int m, const int *belems,
+                        int nblocks, const int *kmat, const double *Kref, const double *Kcut,
+                        double *out, hipStream_t s);
+// Batched in-place SPD inverse of `batch` n x n matrices (row-major, stride n*n).
+// kappa (may be null): per matrix ||A_s||_1 ||A_s^{-1}||_1 of the Jacobi-scaled matrix A_s.
+int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag, double *kappa,
+                        hipStream_t s);
+size_t spd_inverse_scratch_doubles(int n, int batch);
+void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
+void launch_coarse_stencils(const Geo &g, const Tables &t, const Coarse &c, const int *kmat,
+                            const double *Kref, const double *Kcut, hipStream_t s);
+void launch_coarse_first(const Geo &g, const Coarse &c, int k, double *S, hipStream_t s);
+void launch_coarse_schur(const Geo &g, const Coarse &c, int k, double *S, double *T,
+                         hipStream_t s);
+
+// Solve (kernels_solve.hip).
+template <typename T>
+struct OpArgs {
+  const T *x = nullptr;       // input vector (level q or q-1 planes)
+  int m_in = 0;               // local input modes used
+  int nP_out = 0;             // output planes
+  int ld = 0;                 // matrix leading dimension
+  const int *mid = nullptr;   // per element matrix id (-1 skip)
+  const T *matS = nullptr;    // shared matrices
+  int nS = 0;
+  const T *matU = nullptr;    // stored matrices (id - nS)
+  const double *matU64 = nullptr;   // FP32 operator only: FP64 copies of stored matrices,
+  const uint8_t *u64flag = nullptr; //   used for all of them (flag null) or where flag != 0
+  T *out = nullptr;           // out = cvec + scale*acc  (cvec may be null)
+  const T *cvec = nullptr;
+  T scale = 1;
+  T *xs = nullptr;            // smoother: xs = (first ? 0 : xs) + omega*acc
+  T omega = 0;
+  int first = 0;
+  T *xp = nullptr;            // prolongation: xp[P] += ep[P] for P < nP_e
+  const T *ep = nullptr;
+  int nP_e = 0;
+};
+template <typename T>
+void launch_elem_op(const Geo &g, const Tables &t, const OpArgs<T> &a, hipStream_t s);
+
+void launch_dot_partial(const double *x, const double *y, int64_t n, double *partial, int nblk,
+                        hipStream_t s);
+int dot_blocks(int64_t n);
+void launch_dot_final(const double *partial, int nblk, double *dst, hipStream_t s);
+void launch_cg_alpha(double *scal, hipStream_t s);
+void launch_cg_update_xr(double *x, double *r, const double *p, const double *q,
+                         const double *scal, int64_t n, double *partial, int nblk, hipStream_t s);
+void launch_cg_beta(double *scal, hipStream_t s);
+void launch_cg_update_p(double *p, const double *z, const double *scal, int64_t n, int first,
+                        hipStream_t s);
+void launch_axpby(double *y, const double *x, double a, double b, int64_t n, hipStream_t s);
+void launch_f64_to_f32(const double *x, float *y, int64_t n, hipStream_t s);
+void launch_f32_to_f64(const float *x, double *y, int64_t n, hipStream_t s);
+
+// Resumable PCG used by fcm_pcg_solve and the server (fcm_host.hip).
+struct CGState {
+  const double *b = nullptr;
+  double *x = nullptr;
+  double nb = 0.0, rel = 1.0;
+  int it = 0, status = 0;
+  bool first = true, done = false;
+};
+fcm_status cg_begin(fcm_handle *h, CGState &cg, const double *b_dev, double *x, hipStream_t s);
+void cg_issue(fcm_handle *h, CGState &cg, hipStream_t s);
+void cg_finish(fcm_handle *h, CGState &cg);
+fcm_status cg_report(fcm_handle *h, CGState &cg, fcm_solve_info *info, hipStream_t s);
+int64_t footprint_estimate(const fcm_problem &p);
+
+// Coarse solve.  b, x: level-0 vectors (FP64, padded planes).
+void coarse_solve_launch(const Geo &g, const Coarse &c, const double *b, double *x,
+                         hipStream_t s);
+
+}  // namespace fcm

@@ -1,0 +1,1253 @@
+// Setup kernels of libfcm (gfx950): everything that builds the hierarchy.
+//
+//  classify        element state from ball/box tests (Section 2.1)
+//  integrate       cut-cell stiffness and load by recursive bisection of cut
+//                  cells (Section 4.4); uncut sub-cells use separable closed
+//                  forms, cut leaf sub-cells a (p+1)^d Gauss rule with alpha
+//                  per point (eq. weakform)
+//  phys/traction   loads of uncut elements and of box-face tractions
+//  form/invert     elementwise additive Schwarz blocks P_i^T A_l P_i (eq.
+//                  AdditiveSchwarz) and their inverses (Jacobi-scaled
+//                  Gauss-Jordan sweeps in FP64)
+//  coarse          stencil of the p = 1 matrix and the block Schur
+//                  complements of its layer-block-tridiagonal form
+//
+// All arithmetic is FP64; the setup is bound by FP64 VALU throughput.
+#include <cstdio>
+
+#include "fcm_internal.hpp"
+
+namespace fcm {
+
+// ------------------------------------------------------------ device helpers
+__device__ inline int classify_box_dev(const Geo &g, const double *ball, const double *lo,
+                                       const double *hi) {
+  if (g.geom == FCM_GEOM_BOX_MINUS_BALLS) {
+    bool any = false;
+    for (int j = 0; j < g.nballs; ++j) {
+      const double *b = ball + 4 * j;
+      double dmin2 = 0.0, dmax2 = 0.0;
+      for (int ax = 0; ax < g.d; ++ax) {
+        double c = b[ax];
+        double nr = fmin(fmax(c, lo[ax]), hi[ax]) - c;
+        dmin2 += nr * nr;
+        double fa = fmax(fabs(lo[ax] - c), fabs(hi[ax] - c));
+        dmax2 += fa * fa;
+      }
+      double r = b[3];
+      if (sqrt(dmax2) < r) return kVoid;
+      if (sqrt(dmin2) < r) any = true;
+    }
+    return any ? kCut : kPhys;
+  }
+  const double *b = ball;
+  double dmin2 = 0.0, dmax2 = 0.0;
+  for (int ax = 0; ax < g.d; ++ax) {
+    double c = b[ax];
+    double nr = fmin(fmax(c, lo[ax]), hi[ax]) - c;
+    dmin2 += nr * nr;
+    double fa = fmax(fabs(lo[ax] - c), fabs(hi[ax] - c));
+    dmax2 += fa * fa;
+  }
+  double r = b[3];
+  if (sqrt(dmin2) >= r) return kVoid;
+  if (sqrt(dmax2) <= r) return kPhys;
+  return kCut;
+}
+
+__device__ inline bool inside_phys_dev(const Geo &g, const double *ball, const double *x) {
+  if (g.geom == FCM_GEOM_BOX_MINUS_BALLS) {
+    for (int j = 0; j < g.nballs; ++j) {
+      const double *b = ball + 4 * j;
+      double d2 = 0.0;
+      for (int ax = 0; ax < g.d; ++ax) {
+        double t = x[ax] - b[ax];
+        d2 += t * t;
+      }
+      if (d2 < b[3] * b[3]) return false;
+    }
+    return true;
+  }
+  double d2 = 0.0;
+  for (int ax = 0; ax < g.d; ++ax) {
+    double t = x[ax] - ball[ax];
+    d2 += t * t;
+  }
+  return d2 <= ball[3] * ball[3];
+}
+
+// Integrated Legendre modes on [-1,1]: vertex modes (1 -+ xi)/2 and
+// (L_j - L_{j-2}) / sqrt(2(2j-1)); Legendre values by the three-term recurrence.
+__device__ inline void modes1d_dev(int p, double xi, double *v, double *dv) {
+  double L[kMaxP + 1];
+  L[0] = 1.0;
+  if (p >= 1) L[1] = xi;
+  for (int n = 1; n < p; ++n) L[n + 1] = ((2 * n + 1) * xi * L[n] - n * L[n - 1]) / (n + 1);
+  v[0] = 0.5 * (1.0 - xi);
+  v[1] = 0.5 * (1.0 + xi);
+  dv[0] = -0.5;
+  dv[1] = 0.5;
+  for (int j = 2; j <= p; ++j) {
+    double s = rsqrt(2.0 * (2 * j - 1));
+    v[j] = (L[j] - L[j - 2]) * s;
+    dv[j] = (2 * j - 1) * L[j - 1] * s;
+  }
+}
+
+__device__ inline double source_dev(const double *gsrc, int ngauss, double fconst,
+                                    const double *x, int d) {
+  double f = fconst;
+  for (int k = 0; k < ngauss; ++k) {
+    const double *s = gsrc + 5 * k;
+    double d2 = 0.0;
+    for (int ax = 0; ax < d; ++ax) {
+      double t = x[ax] - s[2 + ax];
+      d2 += t * t;
+    }
+    f += s[0] * exp(-d2 / (s[1] * s[1]));
+  }
+  return f;
+}
+
+__device__ inline void elem_coords(const Geo &g, int e, int *c) {
+  c[0] = e % g.n[0];
+  int r = e / g.n[0];
+  c[1] = r % g.n[1];
+  c[2] = r / g.n[1];
+}
+
+// ------------------------------------------------------------------ classify
+__global__ void classify_kernel(Geo g, const double *ball, uint8_t *state) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= g.E) return;
+  int c[3];
+  elem_coords(g, e, c);
+  double lo[3], hi[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    lo[ax] = g.lo[ax] + c[ax] * g.h[ax];
+    hi[ax] = lo[ax] + g.h[ax];
+  }
+  state[e] = (uint8_t)classify_box_dev(g, ball, lo, hi);
+}
+
+void launch_classify(const Geo &g, const double *ball, uint8_t *state, hipStream_t s) {
+  classify_kernel<<<(g.E + 255) / 256, 256, 0, s>>>(g, ball, state);
+}
+
+// ----------------------------------------------------------------- integrate
+// One workgroup per cut element.  Leaves of the sub-cell tree are enumerated
+// breadth first in a fixed order (deterministic accumulation).  The stiffness
+// is accumulated as gradient moments G_kl(a,b) = int alpha d_k N_a d_l N_b
+// over scalar modes a,b (one moment, the trace, for Poisson), each thread
+// owning a 4x4 tile of mode pairs.
+constexpr int kIntThreads = 256;
+
+struct IntegArgs {
+  Geo g;
+  const double *ball, *gsrc, *tab1d, *gxw;
+  const int *smap;
+  int ngauss, ms, m, np, elastic;
+  double fconst, kappa, lam, mu;
+  double bf[3];
+  const int *elist;
+  int ref_mode;
+  double *Kout, *be_all;
+  // shared-memory carve (in doubles / ints)
+  int max_leaves, max_cur, max_child, pb;
+};
+
+__device__ inline int leaf_pack(int lvl, int kind, int ix, int iy, int iz) {
+  return lvl | (kind << 3) | (ix << 5) | (iy << 10) | (iz << 15);
+}
+
+template <int NM>
+__global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
+  extern __shared__ double smem[];
+  const Geo &g = A.g;
+  const int d = g.d, np = A.np, np2 = np * np, ms = A.ms;
+  const int nint = (2 << g.depth) - 1;
+  double *tab = smem;                              // nint*3*np2
+  double *V1 = tab + nint * 3 * np2;               // [3][np][np]
+  double *D1v = V1 + 3 * np2;                      // [3][np][np]
+  double *wa = D1v + 3 * np2;                      // [np^d]
+  double *grads = wa + 343;                        // [pb][ms][d]
+  int *leaves = (int *)(grads + A.pb * ms * d);    // [max_leaves]
+  int *curA = leaves + A.max_leaves;               // [max_cur]
+  int *curB = curA + A.max_cur;
+  uint8_t *chst = (uint8_t *)(curB + A.max_cur);   // [max_child]
+  __shared__ int s_nleaf, s_ncur;
+
+  const int tid = threadIdx.x;
+  const int e = A.ref_mode ? 0 : A.elist[blockIdx.x];
+  int ec[3];
+  elem_coords(g, e, ec);
+  double elo[3];
+  for (int ax = 0; ax < 3; ++ax) elo[ax] = g.lo[ax] + ec[ax] * g.h[ax];
+  if (A.ref_mode) elo[0] = elo[1] = elo[2] = 0.0;
+
+  for (int i = tid; i < nint * 3 * np2; i += kIntThreads) tab[i] = A.tab1d[i];
+
+  // ---- enumerate leaves
+  if (tid == 0) {
+    if (A.ref_mode) {
+      leaves[0] = leaf_pack(0, kPhys, 0, 0, 0);
+      s_nleaf = 1;
+      s_ncur = 0;
+    } else if (g.depth == 0) {
+      leaves[0] = leaf_pack(0, kCut, 0, 0, 0);
+      s_nleaf = 1;
+      s_ncur = 0;
+    } else {
+      curA[0] = leaf_pack(0, kCut, 0, 0, 0);
+      s_nleaf = 0;
+      s_ncur = 1;
+    }
+  }
+  __syncthreads();
+  for (int lvl = 0; lvl < g.depth; ++lvl) {
+    int *cur = (lvl & 1) ? curB : curA;
+    int *nxt = (lvl & 1) ? curA : curB;
+    const int ncur = s_ncur;
+    const int nch = ncur << d;
+    const double sub = 1.0 / (double)(1 << (lvl + 1));
+    for (int c = tid; c < nch; c += kIntThreads) {
+      int par = cur[c >> d];
+      int bits = c & ((1 << d) - 1);
+      int idx[3] = {(par >> 5) & 31, (par >> 10) & 31, (par >> 15) & 31};
+      double lo[3], hi[3];
+      for (int ax = 0; ax < 3; ++ax) {
+        int ci = ax < d ? 2 * idx[ax] + ((bits >> ax) & 1) : 0;
+        lo[ax] = elo[ax] + ci * sub * g.h[ax];
+        hi[ax] = lo[ax] + sub * g.h[ax];
+      }
+      chst[c] = (uint8_t)classify_box_dev(g, A.ball, lo, hi);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int nl = s_nleaf, nn = 0;
+      for (int c = 0; c < nch; ++c) {
+        int par = cur[c >> d];
+        int bits = c & ((1 << d) - 1);
+        int idx[3] = {(par >> 5) & 31, (par >> 10) & 31, (par >> 15) & 31};
+        int ci[3];
+        for (int ax = 0; ax < 3; ++ax) ci[ax] = ax < d ? 2 * idx[ax] + ((bits >> ax) & 1) : 0;
+        int st = chst[c];
+        if (st != kCut) {
+          leaves[nl++] = leaf_pack(lvl + 1, st, ci[0], ci[1], ci[2]);
+        } else if (lvl + 1 < g.depth) {
+          nxt[nn++] = leaf_pack(lvl + 1, kCut, ci[0], ci[1], ci[2]);
+        } else {
+          leaves[nl++] = leaf_pack(lvl + 1, kCut, ci[0], ci[1], ci[2]);
+        }
+      }
+      s_nleaf = nl;
+      s_ncur = nn;
+    }
+    __syncthreads();
+  }
+  const int nleaf = s_nleaf;
+
+  // Jacobian factors: d/dx_k = (2/h_k) d/dxi_k ; dx = prod (h/2) dxi
+  double vol = 1.0;
+  for (int ax = 0; ax < d; ++ax) vol *= 0.5 * g.h[ax];
+  double inv_h2[3];
+  for (int ax = 0; ax < 3; ++ax) inv_h2[ax] = 2.0 / g.h[ax];
+  const int Q = (d == 2) ? np2 : np2 * np;
+  const double *gx = A.gxw, *gw = A.gxw + np;
+
+  // ---- stiffness moments, 4x4 mode-pair tiles per thread
+  const int nta = (ms + 3) / 4;
+  const int ntile = nta * nta;
+  for (int base = 0; base < ntile; base += kIntThreads) {
+    const int tile = base + tid;
+    const bool active = tile < ntile;
+    const int ta = active ? tile / nta : 0, tb = active ? tile % nta : 0;
+    int sa[4], sb[4], aa[4][3], bb[4][3];
+    for (int i = 0; i < 4; ++i) {
+      sa[i] = min(4 * ta + i, ms - 1);
+      sb[i] = min(4 * tb + i, ms - 1);
+      int r = sa[i];
+      aa[i][0] = r % np; r /= np; aa[i][1] = r % np; aa[i][2] = r / np;
+      r = sb[i];
+      bb[i][0] = r % np; r /= np; bb[i][1] = r % np; bb[i][2] = r / np;
+      if (d == 2) { aa[i][2] = 0; bb[i][2] = 0; }
+    }
+    double acc[4][4][NM];
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        for (int k = 0; k < NM; ++k) acc[i][j][k] = 0.0;
+
+    for (int lf = 0; lf < nleaf; ++lf) {
+      const int pk = leaves[lf];
+      const int lvl = pk & 7, kind = (pk >> 3) & 3;
+      const int li[3] = {(pk >> 5) & 31, (pk >> 10) & 31, (pk >> 15) & 31};
+      const int nsub = 1 << lvl;
+      if (kind != kCut) {
+        // closed form over the sub-box: product of 1D sub-interval integrals
+        const double al = (kind == kPhys) ? 1.0 : g.alpha;
+        const double *T[3];
+        for (int ax = 0; ax < 3; ++ax) T[ax] = tab + ((nsub - 1) + (ax < d ? li[ax] : 0)) * 3 * np2;
+        if (active) {
+          for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j) {
+              if (NM == 1) {
+                double s = 0.0;
+                for (int k = 0; k < d; ++k) {
+                  double pr = inv_h2[k] * inv_h2[k];
+                  for (int ax = 0; ax < d; ++ax) {
+                    const double *M = T[ax] + (ax == k ? np2 : 0);
+                    pr *= M[aa[i][ax] * np + bb[j][ax]];
+                  }
+                  s += pr;
+                }
+                acc[i][j][0] += al * vol * s;
+              } else {
+                for (int k = 0; k < d; ++k)
+                  for (int l = 0; l < d; ++l) {
+                    double pr = inv_h2[k] * inv_h2[l] * vol * al;
+                    for (int ax = 0; ax < d; ++ax) {
+                      double v;
+                      if (ax == k && ax == l) v = T[ax][np2 + aa[i][ax] * np + bb[j][ax]];
+                      else if (ax == k) v = T[ax][2 * np2 + aa[i][ax] * np + bb[j][ax]];
+                      else if (ax == l) v = T[ax][2 * np2 + bb[j][ax] * np + aa[i][ax]];
+                      else v = T[ax][aa[i][ax] * np + bb[j][ax]];
+                      pr *= v;
+                    }
+                    acc[i][j][k * d + l] += pr;
+                  }
+              }
+            }
+        }
+        continue;
+      }
+      // pointwise quadrature on a cut leaf
+      __syncthreads();
+      const double half = 1.0 / nsub;                       // half-width in xi
+      if (tid < d * np) {
+        int ax = tid / np, qa = tid % np;
+        double xi = -1.0 + (2.0 * li[ax] + 1.0) * half + half * gx[qa];
+        modes1d_dev(A.np - 1, xi, V1 + ax * np2 + qa * np, D1v + ax * np2 + qa * np);
+      }
+      for (int q = tid; q < Q; q += kIntThreads) {
+        int qc[3] = {q % np, (q / np) % np, q / np2};
+        double x[3] = {0, 0, 0};
+        double w = 1.0;
+        for (int ax = 0; ax < d; ++ax) {
+          double xi = -1.0 + (2.0 * li[ax] + 1.0) * half + half * gx[qc[ax]];
+          x[ax] = elo[ax] + 0.5 * (xi + 1.0) * g.h[ax];
+          w *= gw[qc[ax]] * half * 0.5 * g.h[ax];
+        }
+        wa[q] = w * (inside_phys_dev(g, A.ball, x) ? 1.0 : g.alpha);
+      }
+      __syncthreads();
+      for (int q0 = 0; q0 < Q; q0 += A.pb) {
+        const int nq = min(A.pb, Q - q0);
+        for (int i = tid; i < nq * ms * d; i += kIntThreads) {
+          int k = i % d, s = (i / d) % ms, qq = i / (d * ms);
+          int q = q0 + qq;
+          int qc[3] = {q % np, (q / np) % np, q / np2};
+          int sc[3] = {s % np, (s / np) % np, s / np2};
+          double v = inv_h2[k];
+          for (int ax = 0; ax < d; ++ax) {
+            const double *tb1 = (ax == k ? D1v : V1) + ax * np2 + qc[ax] * np;
+            v *= tb1[sc[ax]];
+          }
+          grads[i] = v;
+        }
+        __syncthreads();
+        if (active) {
+          for (int qq = 0; qq < nq; ++qq) {
+            const double w = wa[q0 + qq];
+            const double *gq = grads + qq * ms * d;
+            double ga[4][3], gb[4][3];
+            for (int i = 0; i < 4; ++i)
+              for (int k = 0; k < d; ++k) {
+                ga[i][k] = gq[sa[i] * d + k] * w;
+                gb[i][k] = gq[sb[i] * d + k];
+              }
+            for (int i = 0; i < 4; ++i)
+              for (int j = 0; j < 4; ++j) {
+                if (NM == 1) {
+                  double s = 0.0;
+                  for (int k = 0; k < d; ++k) s += ga[i][k] * gb[j][k];
+                  acc[i][j][0] += s;
+                } else {
+                  for (int k = 0; k < d; ++k)
+                    for (int l = 0; l < d; ++l) acc[i][j][k * d + l] += ga[i][k] * gb[j][l];
+                }
+              }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // ---- write element matrix entries of this tile
+    if (active) {
+      const int m = A.m, nf = A.g.nf;
+      double *K = A.ref_mode ? A.Kout : A.Kout + (size_t)blockIdx.x * m * m;
+      for (int i = 0; i < 4; ++i) {
+        if (4 * ta + i >= ms) continue;
+        for (int j = 0; j < 4; ++j) {
+          if (4 * tb + j >= ms) continue;
+          if (NM == 1) {
+            int la = A.smap[sa[i]], lb = A.smap[sb[j]];
+            K[(size_t)la * m + lb] = A.kappa * acc[i][j][0];
+          } else {
+            double tr = 0.0;
+            for (int k = 0; k < d; ++k) tr += acc[i][j][k * d + k];
+            for (int ci = 0; ci < nf; ++ci)
+              for (int cj = 0; cj < nf; ++cj) {
+                int la = A.smap[sa[i] * nf + ci], lb = A.smap[sb[j] * nf + cj];
+                double v = A.lam * acc[i][j][ci * d + cj] + A.mu * acc[i][j][cj * d + ci];
+                if (ci == cj) v += A.mu * tr;
+                K[(size_t)la * m + lb] = v;
+              }
+          }
+        }
+      }
+    }
+  }
+  if (A.ref_mode) return;
+
+  // ---- element load: all leaves, pointwise source, alpha per point
+  double accb[2] = {0.0, 0.0};
+  const int s0 = tid, s1 = tid + kIntThreads;
+  for (int lf = 0; lf < nleaf; ++lf) {
+    const int pk = leaves[lf];
+    const int lvl = pk & 7, kind = (pk >> 3) & 3;
+    const int li[3] = {(pk >> 5) & 31, (pk >> 10) & 31, (pk >> 15) & 31};
+    const double half = 1.0 / (1 << lvl);
+    __syncthreads();
+    if (tid < d * np) {
+      int ax = tid / np, qa = tid % np;
+      double xi = -1.0 + (2.0 * li[ax] + 1.0) * half + half * gx[qa];
+      modes1d_dev(A.np - 1, xi, V1 + ax * np2 + qa * np, D1v + ax * np2 + qa * np);
+    }
+    for (int q = tid; q < Q; q += kIntThreads) {
+      int qc[3] = {q % np, (q / np) % np, q / np2};
+      double x[3] = {0, 0, 0};
+      double w = 1.0;
+      for (int ax = 0; ax < d; ++ax) {
+        double xi = -1.0 + (2.0 * li[ax] + 1.0) * half + half * gx[qc[ax]];
+        x[ax] = elo[ax] + 0.5 * (xi + 1.0) * g.h[ax];
+        w *= gw[qc[ax]] * half * 0.5 * g.h[ax];
+      }
+      double al;
+      if (kind == kPhys) al = 1.0;
+      else if (kind == kVoid) al = g.alpha;
+      else al = inside_phys_dev(g, A.ball, x) ? 1.0 : g.alpha;
+      double f = A.elastic ? 1.0 : source_dev(A.gsrc, A.ngauss, A.fconst, x, d);
+      wa[q] = w * al * f;
+    }
+    __syncthreads();
+    for (int r = 0; r < 2; ++r) {
+      int s = r == 0 ? s0 : s1;
+      if (s >= ms) continue;
+      int sc[3] = {s % np, (s / np) % np, s / np2};
+      double sum = 0.0;
+      for (int q = 0; q < Q; ++q) {
+        int qc[3] = {q % np, (q / np) % np, q / np2};
+        double v = wa[q];
+        for (int ax = 0; ax < d; ++ax) v *= V1[ax * np2 + qc[ax] * np + sc[ax]];
+        sum += v;
+      }
+      accb[r] += sum;
+    }
+  }
+  for (int r = 0; r < 2; ++r) {
+    int s = r == 0 ? s0 : s1;
+    if (s >= ms) continue;
+    const int m = A.m, nf = A.g.nf;
+    double *be = A.be_all + (size_t)e * m;
+    if (!A.elastic) {
+      be[A.smap[s]] = accb[r];
+    } else {
+      for (int c = 0; c < nf; ++c) be[A.smap[s * nf + c]] = A.bf[c] * accb[r];
+    }
+  }
+}
+
+void launch_integrate(const Geo &g, const Tables &t, const fcm_problem &pr, const int *elist,
+                      int nlist, int ref_mode, double *Kout, double *be_all, int *flag,
+                      hipStream_t s) {
+  (void)flag;
+  if (nlist <= 0) return;
+  IntegArgs A;
+  A.g = g;
+  A.ball = t.ball;
+  A.gsrc = t.gsrc;
+  A.tab1d = t.tab1d;
+  A.gxw = t.gxw;
+  A.smap = t.smap;
+  A.ngauss = pr.n_gauss;
+  A.ms = t.ms;
+  A.m = t.m;
+  A.np = g.p + 1;
+  A.elastic = g.nf > 1;
+  A.fconst = pr.f_const;
+  A.kappa = pr.kappa;
+  A.lam = pr.E * pr.nu / ((1.0 + pr.nu) * (1.0 - 2.0 * pr.nu));
+  A.mu = pr.E / (2.0 * (1.0 + pr.nu));
+  for (int i = 0; i < 3; ++i) A.bf[i] = pr.body_force[i];
+  A.elist = elist;
+  A.ref_mode = ref_mode;
+  A.Kout = Kout;
+  A.be_all = be_all;
+  int maxl = 1, cur = 1, maxc = 1;
+  for (int l = 1; l <= g.depth; ++l) {
+    int c = 1 << (g.d * l);
+    maxl += c;
+    maxc = std::max(maxc, c);
+    cur = std::max(cur, 1 << (g.d * (l - 1)));
+  }
+  A.max_leaves = maxl;
+  A.max_cur = cur;
+  A.max_child = maxc;
+  const int np = g.p + 1, np2 = np * np;
+  const int nint = (2 << g.depth) - 1;
+  size_t fixed = (size_t)(nint * 3 * np2 + 6 * np2 + 343) * 8 + (size_t)(maxl + 2 * cur) * 4 + maxc + 64;
+  const size_t budget = 60 * 1024;
+  int pb = (int)((budget - std::min(budget - 8192, fixed)) / ((size_t)t.ms * g.d * 8));
+  pb = std::max(1, std::min(pb, 64));
+  A.pb = pb;
+  size_t shm = fixed + (size_t)pb * t.ms * g.d * 8;
+  dim3 grid(ref_mode ? 1 : nlist);
+  if (g.nf == 1)
+    integrate_kernel<1><<<grid, kIntThreads, shm, s>>>(A);
+  else if (g.d == 3)
+    integrate_kernel<9><<<grid, kIntThreads, shm, s>>>(A);
+  else
+    integrate_kernel<4><<<grid, kIntThreads, shm, s>>>(A);
+}
+
+// ------------------------------------------------------------ uncut loads
+// One 64-thread workgroup per uncut element: (p+1)^d Gauss rule on the element.
+__global__ __launch_bounds__(64) void phys_rhs_kernel(Geo g, const double *gxw,
+                                                      const double *vgauss, const int *smap,
+                                                      const double *gsrc, int ngauss,
+                                                      double fconst, double bf0, double bf1,
+                                                      double bf2, int ms, int m,
+                                                      const uint8_t *state, double *be_all) {
+  __shared__ double fw[343];
+  const int e = blockIdx.x;
+  if (state[e] != kPhys) return;
+  const int d = g.d, np = g.p + 1, np2 = np * np;
+  const int Q = (d == 2) ? np2 : np2 * np;
+  int ec[3];
+  elem_coords(g, e, ec);
+  const double *gx = gxw, *gw = gxw + np;
+  const bool elastic = g.nf > 1;
+  for (int q = threadIdx.x; q < Q; q += 64) {
+    int qc[3] = {q % np, (q / np) % np, q / np2};
+    double x[3] = {0, 0, 0}, w = 1.0;
+    for (int ax = 0; ax < d; ++ax) {
+      x[ax] = g.lo[ax] + ec[ax] * g.h[ax] + 0.5 * (gx[qc[ax]] + 1.0) * g.h[ax];
+      w *= gw[qc[ax]] * 0.5 * g.h[ax];
+    }
+    fw[q] = w * (elastic ? 1.0 : source_dev(gsrc, ngauss, fconst, x, d));
+  }
+  __syncthreads();
+  double *be = be_all + (size_t)e * m;
+  for (int s = threadIdx.x; s < ms; s += 64) {
+    int sc[3] = {s % np, (s / np) % np, s / np2};
+    double sum = 0.0;
+    for (int q = 0; q < Q; ++q) {
+      int qc[3] = {q % np, (q / np) % np, q / np2};
+      double v = fw[q];
+      for (int ax = 0; ax < d; ++ax) v *= vgauss[qc[ax] * np + sc[ax]];
+      sum += v;
+    }
+    if (!elastic) {
+      be[smap[s]] = sum;
+    } else {
+      const double bfv[3] = {bf0, bf1, bf2};
+      for (int c = 0; c < g.nf; ++c) be[smap[s * g.nf + c]] = bfv[c] * sum;
+    }
+  }
+}
+
+void launch_phys_rhs(const Geo &g, const Tables &t, const fcm_problem &pr, const uint8_t *state,
+                     double *be_all, hipStream_t s) {
+  phys_rhs_kernel<<<g.E, 64, 0, s>>>(g, t.gxw, t.vgauss, t.smap, t.gsrc, pr.n_gauss, pr.f_const,
+                                     pr.body_force[0], pr.body_force[1], pr.body_force[2], t.ms,
+                                     t.m, state, be_all);
+}
+
+// Box-face traction t on face (axis, side): int_face N_a t dA, closed form per mode.
+__global__ void traction_kernel(Geo g, const double *gxw, const double *vgauss, const int *smap,
+                                int ms, int m, int face, double t0, double t1, double t2,
+                                const uint8_t *state, double *be_all) {
+  const int ax = face / 2, side = face % 2;
+  const int np = g.p + 1;
+  // enumerate elements on the face: index over the other axes
+  int nface = 1;
+  for (int k = 0; k < g.d; ++k)
+    if (k != ax) nface *= g.n[k];
+  int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nface * ms) return;
+  int s = id % ms, fe = id / ms;
+  int ec[3] = {0, 0, 0};
+  for (int k = 0; k < g.d; ++k) {
+    if (k == ax) continue;
+    ec[k] = fe % g.n[k];
+    fe /= g.n[k];
+  }
+  ec[ax] = side ? g.n[ax] - 1 : 0;
+  int e = ec[0] + g.n[0] * (ec[1] + g.n[1] * ec[2]);
+  if (state[e] == kVoid) return;
+  int sc[3] = {s % np, (s / np) % np, s / (np * np)};
+  if (sc[ax] != side) return;
+  const double *gw = gxw + np;
+  double val = 1.0;
+  for (int k = 0; k < g.d; ++k) {
+    if (k == ax) continue;
+    double integ = 0.0;
+    for (int q = 0; q < np; ++q) integ += gw[q] * vgauss[q * np + sc[k]];
+    val *= integ * 0.5 * g.h[k];
+  }
+  const double tv[3] = {t0, t1, t2};
+  double *be = be_all + (size_t)e * m;
+  for (int c = 0; c < g.nf; ++c) be[smap[s * g.nf + c]] += tv[c] * val;
+}
+
+void launch_traction_rhs(const Geo &g, const Tables &t, int face, const double *tvec,
+                         const uint8_t *state, double *be_all, hipStream_t s) {
+  int ax = face / 2;
+  int nface = 1;
+  for (int k = 0; k < g.d; ++k)
+    if (k != ax) nface *= g.n[k];
+  int tot = nface * t.ms;
+  traction_kernel<<<(tot + 255) / 256, 256, 0, s>>>(g, t.gxw, t.vgauss, t.smap, t.ms, t.m, face,
+                                                    tvec[0], tvec[1], tvec[2], state, be_all);
+}
+
+// Gather of element loads into the padded fine vector (owner computes).
+__global__ void assemble_rhs_kernel(Geo g, const int *rows, const int *pinfo, const int *kmat,
+                                    const double *be_all, int m, double *b) {
+  const int P = blockIdx.y;
+  const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= g.G) return;
+  int gc[3] = {gi % g.gn[0], (gi / g.gn[0]) % g.gn[1], gi / (g.gn[0] * g.gn[1])};
+  const int info = pinfo[P], vmask = info & 7, bmask = (info >> 8) & 7;
+  bool valid = true;
+  for (int ax = 0; ax < g.d; ++ax) {
+    if (((bmask >> ax) & 1) && gc[ax] == g.n[ax]) valid = false;
+    if ((vmask >> ax) & 1) {
+      if (gc[ax] == 0 && ((g.dir >> (2 * ax)) & 1)) valid = false;
+      if (gc[ax] == g.n[ax] && ((g.dir >> (2 * ax + 1)) & 1)) valid = false;
+    }
+  }
+  double acc = 0.0;
+  if (valid) {
+    for (int s = 0; s < (1 << g.d); ++s) {
+      if (s & ~vmask) continue;
+      int ec[3] = {gc[0] - (s & 1), gc[1] - ((s >> 1) & 1), gc[2] - ((s >> 2) & 1)};
+      bool in = true;
+      for (int ax = 0; ax < 3; ++ax) in = in && ec[ax] >= 0 && ec[ax] < g.n[ax];
+      if (!in) continue;
+      int e = ec[0] + g.n[0] * (ec[1] + g.n[1] * ec[2]);
+      if (kmat[e] < 0) continue;
+      acc += be_all[(size_t)e * m + rows[P * 8 + s]];
+    }
+  }
+  b[(size_t)P * g.G + gi] = acc;
+}
+
+void launch_assemble_rhs(const Geo &g, const Tables &t, const int *kmat, const double *be_all,
+                         double *b, hipStream_t s) {
+  dim3 grid((g.G + 255) / 256, t.nP);
+  assemble_rhs_kernel<<<grid, 256, 0, s>>>(g, t.rows, t.pinfo, kmat, be_all, t.m, b);
+}
+
+// ----------------------------------------------------- Schwarz block entries
+// Entry (a,b) of P_i^T A_q P_i for the block of element e (local modes of e,
+// level q): sum over the 3^d neighbours e' of the entries of K_{e'} that
+// couple the same two global DOFs.  A vertex mode of e is shared with the
+// neighbour on that side; bubble modes only with e itself along their axis.
+__device__ inline bool local_dirichlet(const Geo &g, const int *lm4, const int *ec) {
+  for (int ax = 0; ax < g.d; ++ax) {
+    int a = lm4[ax];
+    if (a > 1) continue;
+    int node = ec[ax] + a;
+    if (node == 0 && ((g.dir >> (2 * ax)) & 1)) return true;
+    if (node == g.n[ax] && ((g.dir >> (2 * ax + 1)) & 1)) return true;
+  }
+  return false;
+}
+
+__device__ inline double block_entry(const Geo &g, const int *lm, const int *smap, int mp,
+                                     const int *kmat, const double *Kref, const double *Kcut,
+                                     const int *ec, int a, int b) {
+  const int *la = lm + 4 * a, *lb = lm + 4 * b;
+  const bool da = local_dirichlet(g, la, ec), db = local_dirichlet(g, lb, ec);
+  if (da || db) return (a == b) ? 1.0 : 0.0;
+  const int np = g.p + 1;
+  double sum = 0.0;
+  const int nofs = (g.d == 2) ? 9 : 27;
+  for (int o = 0; o < nofs; ++o) {
+    int off[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
+    int ne[3];
+    bool ok = true;
+    for (int ax = 0; ax < 3; ++ax) {
+      ne[ax] = ec[ax] + (ax < g.d ? off[ax] : 0);
+      ok = ok && ne[ax] >= 0 && ne[ax] < g.n[ax];
+    }
+    if (!ok) continue;
+    int kid = kmat[ne[0] + g.n[0] * (ne[1] + g.n[1] * ne[2])];
+    if (kid < 0) continue;
+    int ta[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
+    for (int ax = 0; ax < g.d && ok; ++ax) {
+      int x = la[ax], y = lb[ax];
+      if (off[ax] == -1) {
+        ok = (x == 0) && (y == 0);
+        x = 1;
+        y = 1;
+      } else if (off[ax] == 1) {
+        ok = (x == 1) && (y == 1);
+        x = 0;
+        y = 0;
+      }
+      ta[ax] = x;
+      tb[ax] = y;
+    }
+    if (!ok) continue;
+    int sa = ta[0] + np * (ta[1] + np * ta[2]);
+    int sb = tb[0] + np * (tb[1] + np * tb[2]);
+    int ia = smap[sa * g.nf + la[3]], ib = smap[sb * g.nf + lb[3]];
+    const double *K = kid == 0 ? Kref : Kcut + (size_t)(kid - 1) * mp * mp;
+    sum += K[(size_t)ia * mp + ib];
+  }
+  return sum;
+}
+
+// Form and invert one block per workgroup entirely in LDS (m <= kSmallInv).
+// Jacobi scaling, then an in-place Gauss-Jordan sweep over all pivots, which
+// leaves -A^{-1}; SPD guarantees positive pivots (checked).
+__global__ __launch_bounds__(256) void form_invert_small_kernel(Geo g, const int *lm,
+                                                                const int *smap, int mp, int m,
+                                                                const int *belems,
+                                                                const int *kmat,
+                                                                const double *Kref,
+                                                                const double *Kcut,
+                                                                double *inv64, float *inv32,
+                                                                int *flag, double *kappa) {
+  extern __shared__ double sm[];
+  const int ldA = m + 1;
+  double *Am = sm;               // m x (m+1)
+  double *sc = Am + m * ldA;     // scale
+  double *ck = sc + m;           // pivot column
+  double *rk = ck + m;           // pivot row
+  const int e = belems[blockIdx.x];
+  int ec[3];
+  elem_coords(g, e, ec);
+  for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
+    int a = i / m, b = i % m;
+    Am[a * ldA + b] = block_entry(g, lm, smap, mp, kmat, Kref, Kcut, ec, a, b);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    double dg = Am[i * ldA + i];
+    if (!(dg > 0.0)) atomicOr(flag, 1);
+    sc[i] = dg > 0.0 ? rsqrt(dg) : 1.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
+    int a = i / m, b = i % m;
+    Am[a * ldA + b] *= sc[a] * sc[b];
+  }
+  __syncthreads();
+  __shared__ double s_norm[2];
+  if (threadIdx.x == 0) {
+    // 1-norm of the scaled block (max absolute column sum; symmetric)
+    double nm = 0.0;
+    for (int b = 0; b < m; ++b) {
+      double cs = 0.0;
+      for (int a = 0; a < m; ++a) cs += fabs(Am[a * ldA + b]);
+      nm = fmax(nm, cs);
+    }
+    s_norm[0] = nm;
+  }
+  __syncthreads();
+  for (int k = 0; k < m; ++k) {
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      ck[i] = Am[i * ldA + k];
+      rk[i] = Am[k * ldA + i];
+    }
+    __syncthreads();
+    const double piv = ck[k];
+    if (threadIdx.x == 0 && !(piv > 0.0)) atomicOr(flag, 1);
+    const double P = 1.0 / piv;
+    for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
+      int a = i / m, b = i % m;
+      double v;
+      if (a != k && b != k) v = Am[a * ldA + b] - ck[a] * rk[b] * P;
+      else if (a != k) v = ck[a] * P;
+      else if (b != k) v = rk[b] * P;
+      else v = -P;
+      Am[a * ldA + b] = v;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double nm = 0.0;
+    for (int b = 0; b < m; ++b) {
+      double cs = 0.0;
+      for (int a = 0; a < m; ++a) cs += fabs(Am[a * ldA + b]);
+      nm = fmax(nm, cs);
+    }
+    if (kappa) kappa[blockIdx.x] = s_norm[0] * nm;
+  }
+  double *o64 = inv64 + (size_t)blockIdx.x * m * m;
+  float *o32 = inv32 + (size_t)blockIdx.x * m * m;
+  for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
+    int a = i / m, b = i % m;
+    double v = -Am[a * ldA + b] * sc[a] * sc[b];
+    o64[i] = v;
+    o32[i] = (float)v;
+  }
+}
+
+void launch_form_invert_small(const Geo &g, const Tables &t, int q, int m, const int *belems,
+                              int nblocks, const int *kmat, const double *Kref,
+                              const double *Kcut, double *inv64, float *inv32, int *flag,
+                              double *kappa, hipStream_t s) {
+  (void)q;
+  if (nblocks <= 0) return;
+  size_t shm = ((size_t)m * (m + 1) + 3 * m) * sizeof(double);
+  form_invert_small_kernel<<<nblocks, 256, shm, s>>>(g, t.lm, t.smap, t.m, m, belems, kmat,
+                                                     Kref, Kcut, inv64, inv32, flag, kappa);
+}
+
+__global__ void form_blocks_kernel(Geo g, const int *lm, const int *smap, int mp, int m,
+                                   const int *belems, const int *kmat, const double *Kref,
+                                   const double *Kcut, double *out) {
+  const int blk = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m * m) return;
+  int ec[3];
+  elem_coords(g, belems[blk], ec);
+  out[(size_t)blk * m * m + i] =
+      block_entry(g, lm, smap, mp, kmat, Kref, Kcut, ec, i / m, i % m);
+}
+
+void launch_form_blocks(const Geo &g, const Tables &t, int q, int m, const int *belems,
+                        int nblocks, const int *kmat, const double *Kref, const double *Kcut,
+                        double *out, hipStream_t s) {
+  (void)q;
+  if (nblocks <= 0) return;
+  dim3 grid((m * m + 255) / 256, nblocks);
+  form_blocks_kernel<<<grid, 256, 0, s>>>(g, t.lm, t.smap, t.m, m, belems, kmat, Kref, Kcut, out);
+}
+
+// --------------------------------------------- batched blocked SPD inverse
+// In-place symmetric Gauss-Jordan sweep by 32x32 tiles: sweeping pivot block K
+// maps [[A_KK, A_KJ],[A_IK, A_IJ]] to [[-P, P A_KJ],[A_IK P, A_IJ - A_IK P A_KJ]]
+// with P = A_KK^{-1}; after all K the matrix holds -A^{-1}.  Three launches
+// per pivot block (panel, trailing update, pivot column); the matrix is
+// Jacobi-scaled first.
+constexpr int kTB = 32;
+
+__global__ void jacobi_scale_kernel(double *A, int n, double *scale, int *flag) {
+  const int b = blockIdx.y;
+  double *M = A + (size_t)b * n * n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double dg = M[(size_t)i * n + i];
+    if (!(dg > 0.0)) atomicOr(flag, 1);
+    scale[(size_t)b * n + i] = dg > 0.0 ? rsqrt(dg) : 1.0;
+  }
+}
+
+__global__ void apply_scale_kernel(double *A, int n, const double *scale, double sign) {
+  const int b = blockIdx.y;
+  double *M = A + (size_t)b * n * n;
+  const double *s = scale + (size_t)b * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n * n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    int r = (int)(i / n), c = (int)(i % n);
+    M[i] = sign * M[i] * s[r] * s[c];
+  }
+}
+
+// Invert the pivot tile (in LDS) and form the panel W_KJ = P A_KJ for tile J.
+__global__ __launch_bounds__(256) void sweep_panel_kernel(double *A, int n, int K, double *W,
+                                                          int *flag) {
+  __shared__ double P[kTB][kTB + 1];
+  __shared__ double T[kTB][kTB + 1];
+  __shared__ double ck[kTB], rk[kTB];
+  const int b = blockIdx.y, J = blockIdx.x;
+  double *M = A + (size_t)b * n * n;
+  const int k0 = K * kTB, j0 = J * kTB;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kTB * kTB; i += 256) {
+    int r = i / kTB, c = i % kTB;
+    int gr = k0 + r, gc = k0 + c;
+    double v = (gr < n && gc < n) ? M[(size_t)gr * n + gc] : (r == c ? 1.0 : 0.0);
+    P[r][c] = v;
+    int gj = j0 + c;
+    T[r][c] = (gr < n && gj < n) ? M[(size_t)gr * n + gj] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < kTB; ++k) {
+    if (tid < kTB) {
+      ck[tid] = P[tid][k];
+      rk[tid] = P[k][tid];
+    }
+    __syncthreads();
+    const double piv = ck[k];
+    if (tid == 0 && J == 0 && !(piv > 0.0)) atomicOr(flag, 1);
+    const double ip = 1.0 / piv;
+    for (int i = tid; i < kTB * kTB; i += 256) {
+      int r = i / kTB, c = i % kTB;
+      double v;
+      if (r != k && c != k) v = P[r][c] - ck[r] * rk[c] * ip;
+      else if (r != k) v = ck[r] * ip;
+      else if (c != k) v = rk[c] * ip;
+      else v = -ip;
+      P[r][c] = v;
+    }
+    __syncthreads();
+  }
+  // P now holds -A_KK^{-1}
+  double *Wb = W + (size_t)b * kTB * n;
+  for (int i = tid; i < kTB * kTB; i += 256) {
+    int r = i / kTB, c = i % kTB;
+    int gj = j0 + c;
+    if (gj >= n) continue;
+    double v;
+    if (J == K) {
+      v = -P[r][c];
+    } else {
+      v = 0.0;
+      for (int k = 0; k < kTB; ++k) v -= P[r][k] * T[k][c];
+    }
+    Wb[(size_t)r * n + gj] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void sweep_update_kernel(double *A, int n, int K,
+                                                           const double *W) {
+  __shared__ double Ai[kTB][kTB + 1];
+  __shared__ double Wk[kTB][kTB + 1];
+  const int b = blockIdx.z, I = blockIdx.y, J = blockIdx.x;
+  if (J == K) return;
+  double *M = A + (size_t)b * n * n;
+  const double *Wb = W + (size_t)b * kTB * n;
+  const int i0 = I * kTB, j0 = J * kTB, k0 = K * kTB;
+  const int tid = threadIdx.x;
+  if (I == K) {
+    for (int i = tid; i < kTB * kTB; i += 256) {
+      int r = i / kTB, c = i % kTB;
+      int gr = k0 + r, gc = j0 + c;
+      if (gr < n && gc < n) M[(size_t)gr * n + gc] = Wb[(size_t)r * n + gc];
+    }
+    return;
+  }
+  for (int i = tid; i < kTB * kTB; i += 256) {
+    int r = i / kTB, c = i % kTB;
+    int gr = i0 + r, gk = k0 + c;
+    Ai[r][c] = (gr < n && gk < n) ? M[(size_t)gr * n + gk] : 0.0;
+    int gj = j0 + c;
+    Wk[r][c] = (gj < n && k0 + r < n) ? Wb[(size_t)r * n + gj] : 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < kTB * kTB; i += 256) {
+    int r = i / kTB, c = i % kTB;
+    int gr = i0 + r, gc = j0 + c;
+    if (gr >= n || gc >= n) continue;
+    double s = 0.0;
+    for (int k = 0; k < kTB; ++k) s += Ai[r][k] * Wk[k][c];
+    M[(size_t)gr * n + gc] -= s;
+  }
+}
+
+__global__ void sweep_column_kernel(double *A, int n, int K, const double *W) {
+  const int b = blockIdx.y, I = blockIdx.x;
+  double *M = A + (size_t)b * n * n;
+  const double *Wb = W + (size_t)b * kTB * n;
+  const int i0 = I * kTB, k0 = K * kTB;
+  for (int i = threadIdx.x; i < kTB * kTB; i += blockDim.x) {
+    int r = i / kTB, c = i % kTB;
+    int gr = i0 + r, gk = k0 + c;
+    if (gr >= n || gk >= n) continue;
+    double v = Wb[(size_t)c * n + gr];   // (P A_KI)^T = A_IK P ; for I == K: W_KK = P
+    if (I == K) v = -v;
+    M[(size_t)gr * n + gk] = v;
+  }
+}
+
+// kappa[b] = (or *=) max absolute column sum of matrix b (one workgroup per matrix)
+__global__ void norm1_kernel(const double *A, int n, double *kappa, int multiply) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  const double *M = A + (size_t)b * n * n;
+  double best = 0.0;
+  for (int c = threadIdx.x; c < n; c += 256) {
+    double cs = 0.0;
+    for (int r = 0; r < n; ++r) cs += fabs(M[(size_t)r * n + c]);
+    best = fmax(best, cs);
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) kappa[b] = multiply ? kappa[b] * red[0] : red[0];
+}
+
+size_t spd_inverse_scratch_doubles(int n, int batch) {
+  return (size_t)batch * kTB * n + (size_t)batch * n;
+}
+
+int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag, double *kappa,
+                        hipStream_t s) {
+  if (batch <= 0 || n <= 0) return 0;
+  double *W = scratch;
+  double *scale = scratch + (size_t)batch * kTB * n;
+  const int NB = (n + kTB - 1) / kTB;
+  jacobi_scale_kernel<<<dim3((n + 255) / 256, batch), 256, 0, s>>>(A, n, scale, flag);
+  int sblk = (int)std::min<size_t>(((size_t)n * n + 255) / 256, 1024);
+  apply_scale_kernel<<<dim3(sblk, batch), 256, 0, s>>>(A, n, scale, 1.0);
+  if (kappa) norm1_kernel<<<batch, 256, 0, s>>>(A, n, kappa, 0);
+  for (int K = 0; K < NB; ++K) {
+    sweep_panel_kernel<<<dim3(NB, batch), 256, 0, s>>>(A, n, K, W, flag);
+    sweep_update_kernel<<<dim3(NB, NB, batch), 256, 0, s>>>(A, n, K, W);
+    sweep_column_kernel<<<dim3(NB, batch), 256, 0, s>>>(A, n, K, W);
+  }
+  if (kappa) norm1_kernel<<<batch, 256, 0, s>>>(A, n, kappa, 1);
+  apply_scale_kernel<<<dim3(sblk, batch), 256, 0, s>>>(A, n, scale, -1.0);
+  return 0;
+}
+
+__global__ void to_f32_kernel(const double *src, float *dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+void launch_to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+  to_f32_kernel<<<blocks, 256, 0, s>>>(src, dst, n);
+}
+
+// ----------------------------------------------------------- coarse level
+// Coarse DOF (vertex at grid point g, component c) exists iff a kept element
+// touches g and g is not on a Dirichlet face.
+__device__ inline bool coarse_exists(const Geo &g, const int *kmat, const int *gc) {
+  for (int ax = 0; ax < g.d; ++ax) {
+    if (gc[ax] == 0 && ((g.dir >> (2 * ax)) & 1)) return false;
+    if (gc[ax] == g.n[ax] && ((g.dir >> (2 * ax + 1)) & 1)) return false;
+  }
+  for (int s = 0; s < (1 << g.d); ++s) {
+    int ec[3] = {gc[0] - (s & 1), gc[1] - ((s >> 1) & 1), gc[2] - ((s >> 2) & 1)};
+    bool in = true;
+    for (int ax = 0; ax < 3; ++ax) in = in && ec[ax] >= 0 && ec[ax] < g.n[ax];
+    if (in && kmat[ec[0] + g.n[0] * (ec[1] + g.n[1] * ec[2])] >= 0) return true;
+  }
+  return false;
+}
+
+// Row r of the blocked coarse system -> grid point; false for padding rows.
+__device__ inline bool coarse_row_point(const Geo &g, const Coarse &c, int blk, int i, int *gc,
+                                        int *comp) {
+  const int lay = c.w * c.PP;
+  *comp = i / lay;
+  int rem = i % lay;
+  int lam = rem / c.PP, pt = rem % c.PP;
+  const int sl = g.d - 1;
+  int layer = c.layer0 + blk * c.w + lam;
+  if (layer >= g.gn[sl]) return false;
+  gc[0] = gc[1] = gc[2] = 0;
+  if (g.d == 3) {
+    gc[0] = pt % g.gn[0];
+    gc[1] = pt / g.gn[0];
+  } else {
+    gc[0] = pt;
+  }
+  gc[sl] = layer;
+  return true;
+}
+
+__device__ inline double coarse_entry(const Geo &g, const int *smap, int mp, const int *kmat,
+                                      const double *Kref, const double *Kcut, const int *ga,
+                                      int ca, const int *gb, int cb) {
+  // elements containing both vertices
+  double sum = 0.0;
+  for (int s = 0; s < (1 << g.d); ++s) {
+    int ec[3] = {ga[0] - (s & 1), ga[1] - ((s >> 1) & 1), ga[2] - ((s >> 2) & 1)};
+    bool ok = true;
+    int ta[3] = {0, 0, 0}, tb[3] = {0, 0, 0};
+    for (int ax = 0; ax < 3; ++ax) {
+      ok = ok && ec[ax] >= 0 && ec[ax] < g.n[ax];
+      int db = gb[ax] - ec[ax];
+      ok = ok && db >= 0 && db <= 1;
+      ta[ax] = ga[ax] - ec[ax];
+      tb[ax] = db;
+    }
+    if (!ok) continue;
+    int kid = kmat[ec[0] + g.n[0] * (ec[1] + g.n[1] * ec[2])];
+    if (kid < 0) continue;
+    const int np = g.p + 1;
+    int ia = smap[(ta[0] + np * (ta[1] + np * ta[2])) * g.nf + ca];
+    int ib = smap[(tb[0] + np * (tb[1] + np * tb[2])) * g.nf + cb];
+    const double *K = kid == 0 ? Kref : Kcut + (size_t)(kid - 1) * mp * mp;
+    sum += K[(size_t)ia * mp + ib];
+  }
+  return sum;
+}
+
+// Full 27-point (9-point in 2D) stencil per coarse row, for slow offsets
+// -1, 0, +1: St[row][(so+1)*no*nf + o*nf + c'].
+__global__ void coarse_stencil_kernel(Geo g, Coarse c, const int *smap, int mp,
+                                      const int *kmat, const double *Kref, const double *Kcut,
+                                      double *St) {
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nrows = c.nblk * c.nb;
+  if (row >= nrows) return;
+  const int blk = row / c.nb, i = row % c.nb;
+  const int per = 3 * c.no * g.nf;
+  double *out = St + (size_t)row * per;
+  int ga[3], ca;
+  bool inrange = coarse_row_point(g, c, blk, i, ga, &ca);
+  bool ex = inrange && coarse_exists(g, kmat, ga);
+  const int sl = g.d - 1;
+  for (int so = -1; so <= 1; ++so)
+    for (int o = 0; o < c.no; ++o)
+      for (int cb = 0; cb < g.nf; ++cb) {
+        double v = 0.0;
+        if (ex) {
+          int gb[3] = {ga[0], ga[1], ga[2]};
+          gb[0] += o % 3 - 1;
+          if (g.d == 3) gb[1] += o / 3 - 1;
+          gb[sl] += so;
+          bool in = true;
+          for (int ax = 0; ax < g.d; ++ax) in = in && gb[ax] >= 0 && gb[ax] < g.gn[ax];
+          if (in && coarse_exists(g, kmat, gb))
+            v = coarse_entry(g, smap, mp, kmat, Kref, Kcut, ga, ca, gb, cb);
+        }
+        out[((so + 1) * c.no + o) * g.nf + cb] = v;
+      }
+}
+
+void launch_coarse_stencils(const Geo &g, const Tables &t, const Coarse &c, const int *kmat,
+                            const double *Kref, const double *Kcut, hipStream_t s) {
+  int nrows = c.nblk * c.nb;
+  coarse_stencil_kernel<<<(nrows + 127) / 128, 128, 0, s>>>(g, c, t.smap, t.m, kmat, Kref, Kcut,
+                                                            c.Dst);
+}
+
+// Neighbour of block-local row i at (so, o, c') -> block-local index in the
+// block of that layer, and which block (-1, 0, +1 relative), or -1 if none.
+__device__ inline int coarse_nbr(const Geo &g, const Coarse &c, int i, int so, int o, int cb,
+                                 int *dblk) {
+  const int lay = c.w * c.PP;
+  int rem = i % lay;
+  int lam = rem / c.PP, pt = rem % c.PP;
+  int px, py = 0;
+  if (g.d == 3) {
+    px = pt % g.gn[0];
+    py = pt / g.gn[0];
+  } else {
+    px = pt;
+  }
+  px += o % 3 - 1;
+  if (g.d == 3) py += o / 3 - 1;
+  if (px < 0 || px >= g.gn[0]) return -1;
+  if (g.d == 3 && (py < 0 || py >= g.gn[1])) return -1;
+  int npt = (g.d == 3) ? px + g.gn[0] * py : px;
+  int nl = lam + so;
+  *dblk = 0;
+  if (nl < 0) {
+    nl += c.w;
+    *dblk = -1;
+  } else if (nl >= c.w) {
+    nl -= c.w;
+    *dblk = 1;
+  }
+  return cb * lay + nl * c.PP + npt;
+}
+
+// Dense diagonal block D_k from the stencil (identity rows for non-DOFs).
+__global__ void coarse_fill_kernel(Geo g, Coarse c, int k, double *S) {
+  const int i = blockIdx.y;
+  const int nb = c.nb;
+  double *row = S + (size_t)i * nb;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nb; j += gridDim.x * blockDim.x)
+    row[j] = 0.0;
+  __syncthreads();
+  if (blockIdx.x != 0) return;
+  int ga[3], ca;
+  bool inrange = coarse_row_point(g, c, k, i, ga, &ca);
+  const double *st = c.Dst + (size_t)(k * nb + i) * 3 * c.no * g.nf;
+  bool any = false;
+  if (inrange) {
+    for (int t = threadIdx.x; t < 3 * c.no * g.nf; t += blockDim.x) {
+      int so = t / (c.no * g.nf) - 1;
+      int o = (t / g.nf) % c.no, cb = t % g.nf;
+      double v = st[t];
+      if (v == 0.0) continue;
+      int db;
+      int j = coarse_nbr(g, c, i, so, o, cb, &db);
+      if (j < 0 || db != 0) continue;
+      row[j] = v;
+    }
+    any = st[(c.no + c.no / 2) * g.nf + ca] != 0.0;   // diagonal entry present
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && !any) row[i] = 1.0;
+}
+
+void launch_coarse_first(const Geo &g, const Coarse &c, int k, double *S, hipStream_t s) {
+  dim3 grid(1, c.nb);
+  coarse_fill_kernel<<<grid, 256, 0, s>>>(g, c, k, S);
+}
+
+// T = Sinv_{k-1} B_k^T  (only columns j of the first layer of block k couple)
+__global__ void coarse_T_kernel(Geo g, Coarse c, int k, const double *Sprev, double *T) {
+  const int nb = c.nb;
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nb; j += gridDim.x * blockDim.x) {
+    const double *st = c.Dst + (size_t)(k * nb + j) * 3 * c.no * g.nf;   // so = -1 part
+    double s = 0.0;
+    for (int t = 0; t < c.no * g.nf; ++t) {
+      double v = st[t];
+      if (v == 0.0) continue;
+      int o = t / g.nf, cb = t % g.nf, db;
+      int l = coarse_nbr(g, c, j, -1, o, cb, &db);
+      if (l < 0 || db != -1) continue;
+      s += Sprev[(size_t)i * nb + l] * v;
+    }
+    T[(size_t)i * nb + j] = s;
+  }
+}
+
+// S_k = D_k - B_k T
+__global__ void coarse_S_kernel(Geo g, Coarse c, int k, const double *T, double *S) {
+  const int nb = c.nb;
+  const int i = blockIdx.y;
+  const double *st = c.Dst + (size_t)(k * nb + i) * 3 * c.no * g.nf;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nb; j += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int t = 0; t < c.no * g.nf; ++t) {
+      double v = st[t];
+      if (v == 0.0) continue;
+      int o = t / g.nf, cb = t % g.nf, db;
+      int l = coarse_nbr(g, c, i, -1, o, cb, &db);
+      if (l < 0 || db != -1) continue;
+      s += v * T[(size_t)l * nb + j];
+    }
+    S[(size_t)i * nb + j] -= s;
+  }
+}
+
+void launch_coarse_schur(const Geo &g, const Coarse &c, int k, double *S, double *T,
+                         hipStream_t s) {
+  const int nb = c.nb;
+  const double *Sprev = c.Sinv + (size_t)(k - 1) * nb * nb;
+  dim3 grid((nb + 255) / 256, nb);
+  coarse_T_kernel<<<grid, 256, 0, s>>>(g, c, k, Sprev, T);
+  coarse_S_kernel<<<grid, 256, 0, s>>>(g, c, k, T, S);
+}
+
+}  // namespace fcm

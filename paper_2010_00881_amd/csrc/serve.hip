@@ -1,0 +1,349 @@
+// Serving loop of libfcm: continuous batching of MG-PCG solves on one GPU.
+//
+// Two host threads share the device:
+//  * admission: takes pending requests in arrival order and, while a batch
+//    slot is free and the estimated device footprint of the request fits the
+//    memory budget next to the hierarchies already resident, builds its
+//    hierarchy (fcm_setup) on the admission stream;
+//  * ticks: every tick enqueues one CG iteration (V-cycle, apply, fused
+//    updates) for every active solve, spread over several streams, then waits
+//    and retires the solves that converged.  Requests join and leave between
+//    ticks, so solves of different grids and orders overlap on the device.
+// Results are copied to host memory when a solve retires and its hierarchy is
+// freed at once, returning its footprint to the budget.
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "fcm_internal.hpp"
+
+namespace fcm {
+
+// Device footprint estimate of a problem before setup (bytes): padded vectors,
+// element matrices of the cells within one cell of a hole surface, Schwarz
+// inverses of those blocks and the dense coarse Schur inverses.
+int64_t footprint_estimate(const fcm_problem &p) {
+  const int d = p.dim, nf = p.n_fields;
+  int64_t G = 1, E = 1;
+  double h = 1.0;
+  for (int ax = 0; ax < d; ++ax) {
+    G *= p.n[ax] + 1;
+    E *= p.n[ax];
+    h = std::min(h, (p.hi[ax] - p.lo[ax]) / p.n[ax]);
+  }
+  int64_t mp = nf, nP = nf;
+  for (int ax = 0; ax < d; ++ax) {
+    mp *= p.p + 1;
+    nP *= p.p;
+  }
+  // cells touched by the ball surfaces
+  double surf = 0.0;
+  for (int j = 0; j < p.n_balls; ++j) {
+    double r = p.ball_r[j];
+    surf += (d == 3) ? 4.0 * M_PI * r * r / (h * h) : 2.0 * M_PI * r / h;
+  }
+  int64_t ncut = std::min<int64_t>(E, (int64_t)(3.0 * surf) + 1);
+  int64_t nuniq = std::min<int64_t>(E, ncut * (d == 3 ? 4 : 3));
+  int64_t bytes = 0;
+  bytes += ncut * mp * mp * 12;               // cut matrices FP64 + FP32
+  bytes += E * mp * 8;                        // element loads
+  int64_t inv = 0;
+  for (int q = 2; q <= p.p; ++q) {
+    int64_t m = nf;
+    for (int ax = 0; ax < d; ++ax) m *= q + 1;
+    inv += (nuniq + 64) * m * m * 12;
+  }
+  bytes += inv;
+  // vectors: ~10 FP64 + 6 FP32 fine-level vectors
+  bytes += nP * G * (10 * 8 + 6 * 4);
+  // coarse: layers of ~1024 unknowns
+  int64_t per_layer = nf;
+  for (int ax = 0; ax < d - 1; ++ax) per_layer *= p.n[ax] + 1;
+  int64_t w = std::max<int64_t>(1, (int64_t)(1024.0 / per_layer + 0.5));
+  int64_t nb = per_layer * w;
+  int64_t nblk = (p.n[d - 1] + w) / w;
+  bytes += nblk * nb * nb * 8 + nblk * nb * 27 * nf * 8;
+  return bytes + (16 << 20);
+}
+
+}  // namespace fcm
+
+using namespace fcm;
+
+namespace {
+
+struct Request {
+  uint64_t id = 0;
+  fcm_problem pr{};
+  fcm_options opt{};
+  std::vector<double> ball_c, ball_r, gauss, tvec;
+  std::vector<int> tface;
+  std::chrono::steady_clock::time_point t_submit, t_done;
+  fcm_handle *h = nullptr;
+  double *x = nullptr;
+  CGState cg;
+  int stream = 0;
+  bool done = false;
+  fcm_status status = FCM_OK;
+  std::vector<double> x_host;
+  fcm_solve_info info{};
+  std::vector<double> hist;
+  int64_t footprint = 0;
+  double t_solve_start_ms = 0.0;
+};
+
+}  // namespace
+
+struct fcm_server {
+  fcm_server_opts opt{};
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::shared_ptr<Request>> pending;
+  std::vector<std::shared_ptr<Request>> active;
+  std::map<uint64_t, std::shared_ptr<Request>> all;
+  std::atomic<bool> stop{false};
+  std::atomic<uint64_t> next_id{1};
+  int64_t resident = 0;          // bytes of admitted hierarchies (estimates until set up)
+  int n_admitting = 0;
+  std::vector<hipStream_t> streams;
+  hipStream_t setup_stream = nullptr;
+  std::thread admit_thr, tick_thr;
+  int device = 0;
+};
+
+static void finish_request(fcm_server *s, std::shared_ptr<Request> &r, hipStream_t st) {
+  if (r->h && r->status >= 0) {
+    fcm_solve_info info{};
+    cg_report(r->h, r->cg, &info, st);
+    r->hist.assign(info.res_history, info.res_history + info.n_history);
+    r->info = info;
+    r->info.res_history = nullptr;
+    r->info.n_history = (int)r->hist.size();
+    const int64_t n = r->h->lev[r->h->L].npad;
+    r->x_host.resize(n);
+    hipMemcpyAsync(r->x_host.data(), r->x, n * sizeof(double), hipMemcpyDeviceToHost, st);
+    hipStreamSynchronize(st);
+  }
+  r->t_done = std::chrono::steady_clock::now();
+  r->info.t_solve_ms =
+      std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count() -
+      r->t_solve_start_ms;
+  if (r->x) hipFree(r->x);
+  r->x = nullptr;
+  if (r->h) fcm_destroy(r->h);
+  r->h = nullptr;
+}
+
+static void admission_loop(fcm_server *s) {
+  hipSetDevice(s->device);
+  for (;;) {
+    std::shared_ptr<Request> r;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] {
+        if (s->stop) return true;
+        if (s->pending.empty()) return false;
+        const int64_t need = s->pending.front()->footprint;
+        const bool slot = (int)s->active.size() + s->n_admitting < s->opt.max_active;
+        const bool mem = s->resident + need <= s->opt.memory_budget_bytes || s->resident == 0;
+        return slot && mem;
+      });
+      if (s->stop) return;
+      r = s->pending.front();
+      s->pending.pop_front();
+      s->resident += r->footprint;
+      s->n_admitting++;
+    }
+    fcm_handle *h = nullptr;
+    fcm_status st = fcm_setup(&r->pr, &r->opt, s->setup_stream, &h);
+    double *x = nullptr;
+    if (st == FCM_OK) {
+      const int64_t n = h->lev[h->L].npad;
+      if (hipMalloc((void **)&x, n * sizeof(double)) != hipSuccess) st = FCM_ERR_OOM;
+    }
+    if (st == FCM_OK) {
+      h->stream = nullptr;
+      // pick the stream this solve ticks on
+      r->h = h;
+      r->x = x;
+      r->stream = (int)(r->id % s->streams.size());
+      hipStream_t hs = s->streams[r->stream];
+      st = cg_begin(h, r->cg, nullptr, x, hs);
+      r->t_solve_start_ms = std::chrono::duration<double, std::milli>(
+                                std::chrono::steady_clock::now() - r->t_submit)
+                                .count();
+    } else if (h) {
+      fcm_destroy(h);
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->n_admitting--;
+    if (st < 0) {
+      r->status = st;
+      r->done = true;
+      r->t_done = std::chrono::steady_clock::now();
+      if (r->x) hipFree(r->x);
+      if (r->h) fcm_destroy(r->h);
+      r->h = nullptr;
+      r->x = nullptr;
+      s->resident -= r->footprint;
+    } else {
+      // replace the estimate by the measured footprint
+      s->resident += h->bytes - r->footprint;
+      r->footprint = h->bytes;
+      s->active.push_back(r);
+    }
+    s->cv.notify_all();
+  }
+}
+
+static void tick_loop(fcm_server *s) {
+  hipSetDevice(s->device);
+  for (;;) {
+    std::vector<std::shared_ptr<Request>> batch;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv.wait(lk, [&] { return s->stop || !s->active.empty(); });
+      if (s->stop) return;
+      batch = s->active;
+    }
+    // issue one CG iteration for every active solve, then wait for all
+    for (auto &r : batch)
+      if (!r->cg.done) cg_issue(r->h, r->cg, s->streams[r->stream]);
+    for (auto st : s->streams) hipStreamSynchronize(st);
+    std::vector<std::shared_ptr<Request>> retired;
+    for (auto &r : batch) {
+      if (!r->cg.done) cg_finish(r->h, r->cg);
+      if (r->cg.done) retired.push_back(r);
+    }
+    for (auto &r : retired) {
+      r->status = (fcm_status)r->cg.status;
+      int64_t fp = r->footprint;
+      finish_request(s, r, s->streams[r->stream]);
+      std::lock_guard<std::mutex> lk(s->mu);
+      r->done = true;
+      s->resident -= fp;
+      for (size_t i = 0; i < s->active.size(); ++i)
+        if (s->active[i] == r) {
+          s->active.erase(s->active.begin() + i);
+          break;
+        }
+      s->cv.notify_all();
+    }
+  }
+}
+
+extern "C" {
+
+fcm_status fcm_server_create(const fcm_server_opts *o, fcm_server **out) {
+  if (!o || !out || o->max_active < 1 || o->n_streams < 1 || o->memory_budget_bytes <= 0) {
+    set_error("invalid server options");
+    return FCM_ERR_ARG;
+  }
+  auto *s = new fcm_server();
+  s->opt = *o;
+  hipGetDevice(&s->device);
+  s->streams.resize(std::min(o->n_streams, 16));
+  for (auto &st : s->streams)
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      set_error("stream creation failed");
+      return FCM_ERR_HIP;
+    }
+  if (hipStreamCreateWithFlags(&s->setup_stream, hipStreamNonBlocking) != hipSuccess) {
+    set_error("stream creation failed");
+    return FCM_ERR_HIP;
+  }
+  s->admit_thr = std::thread(admission_loop, s);
+  s->tick_thr = std::thread(tick_loop, s);
+  *out = s;
+  return FCM_OK;
+}
+
+fcm_status fcm_serve_submit(fcm_server *s, const fcm_problem *prob, const fcm_options *opts,
+                            uint64_t *req_id) {
+  if (!s || !prob || !opts || !req_id) {
+    set_error("null argument");
+    return FCM_ERR_ARG;
+  }
+  auto r = std::make_shared<Request>();
+  r->id = s->next_id++;
+  r->pr = *prob;
+  r->opt = *opts;
+  r->ball_c.assign(prob->ball_c, prob->ball_c + prob->n_balls * prob->dim);
+  r->ball_r.assign(prob->ball_r, prob->ball_r + prob->n_balls);
+  r->gauss.assign(prob->gauss, prob->gauss + 5 * prob->n_gauss);
+  r->tface.assign(prob->traction_face, prob->traction_face + prob->n_traction);
+  r->tvec.assign(prob->traction_vec, prob->traction_vec + 3 * prob->n_traction);
+  r->pr.ball_c = r->ball_c.data();
+  r->pr.ball_r = r->ball_r.data();
+  r->pr.gauss = r->gauss.data();
+  r->pr.traction_face = r->tface.data();
+  r->pr.traction_vec = r->tvec.data();
+  r->footprint = footprint_estimate(r->pr);
+  r->t_submit = std::chrono::steady_clock::now();
+  *req_id = r->id;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->all[r->id] = r;
+  s->pending.push_back(r);
+  s->cv.notify_all();
+  return FCM_OK;
+}
+
+fcm_status fcm_serve_poll(fcm_server *s, uint64_t req_id, int *done, double *x_host,
+                          int64_t x_len, fcm_solve_info *info, double *latency_ms) {
+  if (!s || !done) {
+    set_error("null argument");
+    return FCM_ERR_ARG;
+  }
+  std::shared_ptr<Request> r;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(req_id);
+    if (it == s->all.end()) {
+      set_error("unknown request id");
+      return FCM_ERR_ARG;
+    }
+    r = it->second;
+    *done = r->done ? 1 : 0;
+  }
+  if (!*done) return FCM_OK;
+  if (x_host && !r->x_host.empty()) {
+    int64_t n = std::min<int64_t>(x_len, (int64_t)r->x_host.size());
+    std::memcpy(x_host, r->x_host.data(), n * sizeof(double));
+  }
+  if (info) {
+    *info = r->info;
+    info->res_history = r->hist.data();
+    info->n_history = (int)r->hist.size();
+  }
+  if (latency_ms)
+    *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  return r->status;
+}
+
+fcm_status fcm_server_destroy(fcm_server *s) {
+  if (!s) return FCM_OK;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    s->cv.notify_all();
+  }
+  if (s->admit_thr.joinable()) s->admit_thr.join();
+  if (s->tick_thr.joinable()) s->tick_thr.join();
+  for (auto &r : s->active) {
+    if (r->x) hipFree(r->x);
+    if (r->h) fcm_destroy(r->h);
+  }
+  for (auto st : s->streams) hipStreamDestroy(st);
+  if (s->setup_stream) hipStreamDestroy(s->setup_stream);
+  delete s;
+  return FCM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,45 @@
+"""The C-ABI library loads on the CPU and exports every declared entry point.
+
+No compute call is made here (no GPU in this environment)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2010_00881_amd", "libfcm.so")
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "fcm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fcm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for name in ["fcm_setup", "fcm_vcycle", "fcm_pcg_solve", "fcm_serve_submit"]:
+        assert name in syms
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfcm.so not built")
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    lib = ctypes.CDLL(LIB)
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+    from paper_2010_00881_amd import fcm
+    assert set(fcm.SIGNATURES) == set(declared_symbols())
+    lib.fcm_status_string.restype = ctypes.c_char_p
+    assert lib.fcm_status_string(0) == b"ok"
+    assert lib.fcm_status_string(-4) == b"matrix not positive definite"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfcm.so not built")
+def test_struct_layouts_match_header():
+    import ctypes
+    from paper_2010_00881_amd import fcm
+    # the C structs are plain; sizes follow the C alignment rules for x86-64
+    assert ctypes.sizeof(fcm.Options) == 48
+    assert ctypes.sizeof(fcm.SolveInfo) == 56
+    assert ctypes.sizeof(fcm.ServerOpts) == 16
