@@ -1,0 +1,169 @@
+#!/usr/bin/env python3
+"""MG-PCG throughput of the FCM p-multigrid solver on one MI355X.
+
+Workload: 3D Poisson on the unit cube minus 8 seeded spherical voids, 32^3
+cells, integrated-Legendre tensor basis p = 3 (848k unknowns for seed 0),
+alpha = 1e-10, octree depth 3, u = 0 on the box faces, f = 1; FP32 V-cycle
+inside FP64 CG (rtol 1e-10).  One step = one complete solve of a fresh
+seeded problem: classification, cut-cell integration, loads, Schwarz
+inverses, coarse factorisation (setup) and the MG-preconditioned CG.  Step k
+uses generator seed k; warm-up steps use seeds 1000+.
+
+Prints one JSON line.  `value` is solves/s over the timed steps; p50/p99 are
+per-solve latencies; the V-cycle throughput and the roofline of the dominant
+kernel (the finest-level Schwarz smoother) are timed with HIP events on the
+stream the library launches on, after the timed region.
+"""
+import argparse
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MG-PCG solves/s + V-cycle DOF/s (%HBM roofline) at rel. err 1e-8; p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(n_sample=8):
+    """Oracle (FP64 NumPy/SciPy) MG-PCG, setup + solve, on the workload's geometry
+    at a reduced grid; scaled to the full workload by the ratio of fine DOFs."""
+    import fcm_inputs as fi
+    from oracle import fcm, mg
+    desc, opts = fi.voided_cube_poisson(0, n=n_sample, p=3)
+    t0 = time.perf_counter()
+    disc = fcm.Discretization(desc)
+    hier = mg.Hierarchy(disc, opts)
+    _, it, _ = hier.pcg(disc.b)
+    t = time.perf_counter() - t0
+    full = 848071
+    scale = full / disc.n_dofs
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": (f"oracle setup+MG-PCG of the same seeded voided cube at {n_sample}^3 cells, "
+                       f"p=3 ({disc.n_dofs} DOFs, {it} iterations, {t:.1f} s), scaled by fine DOFs "
+                       f"x{scale:.1f} to the 32^3 workload")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="also time the plain FP64 form one problem at a time")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        return 2
+
+    import torch
+    import fcm_inputs as fi
+    from paper_2010_00881_amd import Solver
+
+    def problem(seed, precision):
+        d, o = fi.voided_cube_poisson(seed, n=args.n, p=3)
+        return d, dict(o, precision=precision)
+
+    def run_steps(seeds, precision, keep_last=False):
+        lat, its, setup, solve, errs = [], [], [], [], []
+        last = None
+        for sd in seeds:
+            t = time.perf_counter()
+            s = Solver(*problem(sd, precision))
+            x, info = s.pcg()
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t) * 1e3)
+            its.append(info["iterations"])
+            setup.append(info["t_setup_ms"])
+            solve.append(info["t_solve_ms"])
+            errs.append(info["true_rel_res"])
+            if info["status"] != 0:
+                raise RuntimeError(f"solve of seed {sd} did not converge: {info}")
+            if keep_last and sd == seeds[-1]:
+                last = s
+            else:
+                s.close()
+            del x
+        return lat, its, setup, solve, errs, last
+
+    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    run_steps([1000 + w for w in range(args.warmup)], args.precision)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    lat, its, setup, solve, errs, s = run_steps(list(range(args.steps)), args.precision,
+                                                keep_last=True)
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t0
+    value = args.steps / T
+
+    # V-cycle throughput and dominant kernel (finest-level smoother), HIP events
+    L = s.n_levels - 1
+    n_fine = s.n_dofs[-1]
+    ms_v, bytes_v = s.time_op("vcycle", reps=10)
+    ms_k, bytes_k = s.time_op("smooth", level=L, reps=50)
+    ms_r, bytes_r = s.time_op("residual", level=L, reps=50)
+    ms_c, bytes_c = s.time_op("coarse", reps=10)
+    achieved = bytes_k / (ms_k * 1e-3) / 1e9
+    st = s.stats()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic (seeded voided cube, seeds 0..steps-1)",
+        "config": {"workload": f"cube_voids_poisson_{args.n}^3_p3", "n": args.n, "p": 3,
+                   "dofs": n_fine, "precision": args.precision, "alpha": 1e-10,
+                   "quad_depth": 3, "rtol": 1e-10, "parallelism": "none (1 GPU)"},
+        "p50_ms": statistics.median(lat),
+        "p99_ms": sorted(lat)[max(0, int(round(0.99 * len(lat))) - 1)],
+        "setup_ms_median": statistics.median(setup),
+        "solve_ms_median": statistics.median(solve),
+        "iterations": its,
+        "max_true_rel_res": max(errs),
+        "vcycle_ms": ms_v,
+        "vcycle_gdof_s": n_fine / (ms_v * 1e-3) / 1e9,
+        "vcycle_hbm_frac": bytes_v / (ms_v * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "kernels": {
+            "smooth_fine": {"ms": ms_k, "bytes": bytes_k},
+            "residual_fine": {"ms": ms_r, "bytes": bytes_r,
+                              "gbs": bytes_r / (ms_r * 1e-3) / 1e9},
+            "coarse_solve": {"ms": ms_c, "bytes": bytes_c,
+                             "gbs": bytes_c / (ms_c * 1e-3) / 1e9},
+        },
+        "problem": {k: st[k] for k in ("n_cut", "n_unique_blocks", "n_fp64_blocks",
+                                        "coarse_blocks", "coarse_block_size", "device_bytes")},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    s.close()
+    if args.compare_fp64:
+        print("[bench] plain FP64 form, one problem at a time", file=sys.stderr, flush=True)
+        t1 = time.perf_counter()
+        lat64, *_ = run_steps(list(range(args.steps)), "fp64")
+        torch.cuda.synchronize()
+        out["fp64_form_solves_s"] = args.steps / (time.perf_counter() - t1)
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -196,8 +196,22 @@ typedef struct {
   int64_t n_elements, n_kept, n_cut, n_unique_blocks, n_shared_classes;
   int64_t device_bytes;
   int coarse_blocks, coarse_block_size;
+  int64_t n_fp64_blocks;      /* Schwarz blocks kept in FP64 in the FP32 V-cycle */
 } fcm_stats;
 fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s);
+
+/* Benchmark hook: launch one operator of the solve `reps` times between two
+ * HIP events recorded on `stream` and report the average time per launch and
+ * the algorithmic bytes one launch must move (inputs read once, outputs
+ * written once, matrices streamed once; see the design notes).
+ * op: FCM_OP_SMOOTH (Schwarz smoother of `level`, handle precision),
+ *     FCM_OP_RESIDUAL (residual update r -= omega A delta of `level`),
+ *     FCM_OP_COARSE (one exact coarse solve), FCM_OP_VCYCLE (one V-cycle,
+ *     bytes = sum over its launches).  Work vectors of the handle are used;
+ * their contents are overwritten.                                          */
+enum { FCM_OP_SMOOTH = 0, FCM_OP_RESIDUAL = 1, FCM_OP_COARSE = 2, FCM_OP_VCYCLE = 3 };
+fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
+                       double *ms_per_launch, double *bytes_per_launch);
 
 void fcm_destroy(fcm_handle *h);
 

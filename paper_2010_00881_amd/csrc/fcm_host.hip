@@ -1063,6 +1063,8 @@ fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s) {
   s->device_bytes = h->bytes;
   s->coarse_blocks = h->co.nblk;
   s->coarse_block_size = h->co.nb;
+  s->n_fp64_blocks = 0;
+  for (int l = 1; l <= h->L; ++l) s->n_fp64_blocks += h->lev[l].n_hi64;
   return FCM_OK;
 }
 
@@ -1197,6 +1199,99 @@ fcm_status fcm_mg_solve(fcm_handle *h, const double *b_dev, double *x_dev, fcm_s
     info->n_history = (int)h->history.size();
   }
   return st;
+}
+
+// Algorithmic bytes of one smoother / residual launch on level l.
+static double op_bytes(const fcm_handle *h, int op, int l) {
+  const bool mixed = h->opt.precision == FCM_MIXED;
+  const double sv = mixed ? 4.0 : 8.0;
+  const fcm::Level &L = h->lev[l];
+  const double mm = (double)L.m * L.m;
+  const double E = h->geo.E;
+  if (op == FCM_OP_SMOOTH) {
+    double nhi = mixed ? L.n_hi64 : 0;
+    double mats = (h->n_shared + h->n_unique - nhi) * mm * sv + nhi * mm * 8.0;
+    return 4.0 * L.npad * sv + mats + 4.0 * E;
+  }
+  // residual update: delta, r read, r written; cut matrices (FP64 when mixed)
+  double mats = (double)h->h_cut.size() * mm * 8.0 / (mixed ? 1.0 : 1.0) + mm * sv;
+  return 3.0 * L.npad * sv + mats + 4.0 * E;
+}
+
+static double coarse_bytes(const fcm_handle *h) {
+  const fcm::Coarse &c = h->co;
+  // each block inverse is read in the forward and in the backward sweep
+  return 2.0 * (double)c.nblk * c.nb * c.nb * 8.0 + 4.0 * (double)c.nblk * c.nb * 8.0;
+}
+
+fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
+                       double *ms_per_launch, double *bytes_per_launch) {
+  if (!h || reps < 1 || (op != FCM_OP_COARSE && op != FCM_OP_VCYCLE && (level < 1 || level > h->L))) {
+    set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const bool mixed = h->opt.precision == FCM_MIXED;
+  hipEvent_t e0, e1;
+  FCM_HIP(hipEventCreate(&e0));
+  FCM_HIP(hipEventCreate(&e1));
+  double bytes = 0.0;
+  auto launch = [&]() {
+    if (op == FCM_OP_SMOOTH || op == FCM_OP_RESIDUAL) {
+      fcm::Level &L = h->lev[level];
+      if (mixed) {
+        OpArgs<float> a = op == FCM_OP_SMOOTH ? smoother_args<float>(h, level)
+                                              : stiffness_args<float>(h, level);
+        a.x = op == FCM_OP_SMOOTH ? L.r32 : L.d32;
+        a.out = op == FCM_OP_SMOOTH ? L.d32 : L.r32;
+        if (op == FCM_OP_SMOOTH) {
+          a.xs = L.x32;
+          a.omega = (float)h->opt.omega;
+        } else {
+          a.cvec = L.r32;
+          a.scale = -(float)h->opt.omega;
+        }
+        launch_elem_op<float>(h->geo, h->tab, a, s);
+      } else {
+        OpArgs<double> a = op == FCM_OP_SMOOTH ? smoother_args<double>(h, level)
+                                               : stiffness_args<double>(h, level);
+        a.x = op == FCM_OP_SMOOTH ? L.r64 : L.d64;
+        a.out = op == FCM_OP_SMOOTH ? L.d64 : L.r64;
+        if (op == FCM_OP_SMOOTH) {
+          a.xs = L.x64;
+          a.omega = h->opt.omega;
+        } else {
+          a.cvec = L.r64;
+          a.scale = -h->opt.omega;
+        }
+        launch_elem_op<double>(h->geo, h->tab, a, s);
+      }
+    } else if (op == FCM_OP_COARSE) {
+      coarse_solve_launch(h->geo, h->co, h->b, h->lev[0].x64, s);
+    } else {
+      vcycle_top(h, h->b, h->cg_z, s);
+    }
+  };
+  if (op == FCM_OP_SMOOTH || op == FCM_OP_RESIDUAL) bytes = op_bytes(h, op, level);
+  else if (op == FCM_OP_COARSE) bytes = coarse_bytes(h);
+  else {
+    for (int l = 1; l <= h->L; ++l)
+      bytes += (h->opt.n_pre + h->opt.n_post) * op_bytes(h, FCM_OP_SMOOTH, l) +
+               (h->opt.n_pre + h->opt.n_post) * op_bytes(h, FCM_OP_RESIDUAL, l);
+    bytes += coarse_bytes(h);
+  }
+  launch();  // warm-up
+  FCM_HIP(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; ++i) launch();
+  FCM_HIP(hipEventRecord(e1, s));
+  FCM_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  FCM_HIP(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (ms_per_launch) *ms_per_launch = ms / reps;
+  if (bytes_per_launch) *bytes_per_launch = bytes;
+  return FCM_OK;
 }
 
 }  // extern "C"

@@ -67,7 +67,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("n_elements", ctypes.c_int64), ("n_kept", ctypes.c_int64),
                 ("n_cut", ctypes.c_int64), ("n_unique_blocks", ctypes.c_int64),
                 ("n_shared_classes", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
-                ("coarse_blocks", ctypes.c_int), ("coarse_block_size", ctypes.c_int)]
+                ("coarse_blocks", ctypes.c_int), ("coarse_block_size", ctypes.c_int),
+                ("n_fp64_blocks", ctypes.c_int64)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -94,6 +95,8 @@ SIGNATURES = {
     "fcm_element": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "fcm_get_stats": ([_P, ctypes.POINTER(Stats)], ctypes.c_int),
+    "fcm_time_op": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double),
+                     ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "fcm_destroy": ([_P], None),
     "fcm_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)], ctypes.c_int),
     "fcm_serve_submit": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Options),
@@ -219,12 +222,21 @@ class Solver:
                                ctypes.byref(h)), allow=(0,))
         self.h = h
         n = ctypes.c_int()
-        nd = (ctypes.c_int64 * 8)()
         npd = (ctypes.c_int64 * 8)()
-        _check(lib().fcm_sizes(self.h, ctypes.byref(n), nd, npd))
+        _check(lib().fcm_sizes(self.h, ctypes.byref(n), None, npd))
         self.n_levels = n.value
-        self.n_dofs = [nd[i] for i in range(n.value)]
         self.n_padded = [npd[i] for i in range(n.value)]
+        self._n_dofs = None
+
+    @property
+    def n_dofs(self):
+        """Unknowns per level, coarse first (counted on the host on first use)."""
+        if self._n_dofs is None:
+            n = ctypes.c_int()
+            nd = (ctypes.c_int64 * 8)()
+            _check(lib().fcm_sizes(self.h, ctypes.byref(n), nd, None))
+            self._n_dofs = [nd[i] for i in range(n.value)]
+        return self._n_dofs
 
     def close(self):
         if getattr(self, "h", None):
@@ -309,6 +321,17 @@ class Solver:
         st = ctypes.c_int()
         _check(lib().fcm_element(self.h, int(e), ctypes.byref(st), _dptr(K), _dptr(be)))
         return st.value, K, be
+
+    OPS = {"smooth": 0, "residual": 1, "coarse": 2, "vcycle": 3}
+
+    def time_op(self, op, level=None, reps=20):
+        """(ms per launch, algorithmic bytes per launch) timed with HIP events."""
+        lv = self.n_levels - 1 if level is None else level
+        ms = ctypes.c_double()
+        by = ctypes.c_double()
+        _check(lib().fcm_time_op(self.h, self.OPS[op], lv, int(reps), _stream(), ctypes.byref(ms),
+                                 ctypes.byref(by)))
+        return ms.value, by.value
 
     def stats(self):
         s = Stats()

@@ -42,4 +42,5 @@ def test_struct_layouts_match_header():
     # the C structs are plain; sizes follow the C alignment rules for x86-64
     assert ctypes.sizeof(fcm.Options) == 48
     assert ctypes.sizeof(fcm.SolveInfo) == 56
+    assert ctypes.sizeof(fcm.Stats) == 64
     assert ctypes.sizeof(fcm.ServerOpts) == 16
