@@ -111,6 +111,8 @@ typedef struct {
   int precision;              /* FCM_FP64 or FCM_MIXED (FP32 V-cycle)            */
   double rtol;                /* ||r||/||b|| stopping tolerance                  */
   int max_iter;               /* CG iteration cap (500 in the paper)             */
+  int use_graphs;             /* 1: replay each CG iteration as a captured HIP
+                                 graph on a library-owned stream (0: eager)     */
 } fcm_options;
 
 typedef struct {

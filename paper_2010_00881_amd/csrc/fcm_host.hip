@@ -393,32 +393,73 @@ static fcm_status setup_coarse(fcm_handle *h) {
   c.nblk = (nl + w - 1) / w;
   c.nb = g.nf * w * c.PP;
   c.no = g.d == 3 ? 9 : 3;
-  const int RT = (c.nb + 63) / 64;
-  c.JS = std::max(1, std::min(32, (256 + RT - 1) / RT));
-  c.JS = std::min(c.JS, std::max(1, c.nb / 16));
-  c.CJ = (c.nb + c.JS - 1) / c.JS;
   const size_t nb2 = (size_t)c.nb * c.nb;
   TRY(dalloc(h, &c.Sinv, nb2 * c.nblk));
+  TRY(dalloc(h, &c.Gm, nb2 * c.nblk));
+  TRY(dalloc(h, &c.Fm, nb2 * c.nblk));
   TRY(dalloc(h, &c.Dst, (size_t)c.nblk * c.nb * 3 * c.no * g.nf));
-  TRY(dalloc(h, &c.W, (size_t)c.nblk * c.nb));
-  TRY(dalloc(h, &c.P0, (size_t)c.JS * c.nb));
-  TRY(dalloc(h, &c.P1, (size_t)c.JS * c.nb));
   TRY(dalloc(h, &c.xb, (size_t)g.nf * g.G));
+  TRY(dalloc(h, &c.xblk, (size_t)c.nblk * c.nb));
+  TRY(dalloc(h, &c.bblk, (size_t)c.nblk * c.nb));
   TRY(dalloc(h, &c.bb, (size_t)g.nf * g.G));
-  double *T = nullptr, *scr = nullptr;
-  FCM_HIP(hipMalloc((void **)&T, nb2 * sizeof(double)));
+  double *scr = nullptr;
   FCM_HIP(hipMalloc((void **)&scr, spd_inverse_scratch_doubles(c.nb, 1) * sizeof(double)));
   launch_coarse_stencils(g, h->tab, c, h->kmat, h->Kref64, h->Kcut64, h->stream);
   for (int k = 0; k < c.nblk; ++k) {
     double *S = c.Sinv + (size_t)k * nb2;
     launch_coarse_first(g, c, k, S, h->stream);
-    if (k > 0) launch_coarse_schur(g, c, k, S, T, h->stream);
+    // S_k = D_k - B_k F_{k-1},  F_{k-1} = S_{k-1}^{-1} B_k^T is kept for the back sweep
+    if (k > 0) launch_coarse_schur(g, c, k, S, c.Fm + (size_t)(k - 1) * nb2, h->stream);
     spd_inverse_batched(S, c.nb, 1, scr, h->dflag, nullptr, h->stream);
+    if (k > 0) launch_coarse_G(g, c, k, h->stream);
   }
   FCM_HIP(hipStreamSynchronize(h->stream));
-  FCM_HIP(hipFree(T));
   FCM_HIP(hipFree(scr));
   return check_flag(h, "coarse factorisation");
+}
+
+// Owner-kernel work units of level l: planes grouped by (vertex mask, comp),
+// at most kUnit = 8 planes per unit.
+static fcm_status build_units(fcm_handle *h, int l) {
+  const Geo &g = h->geo;
+  const int p = g.p, d = g.d, nf = g.nf;
+  std::vector<int> pt;
+  pt.clear();
+  for (int s = 1; s <= p; ++s)
+    for (int t2 = 0; t2 < (d == 3 ? p : 1); ++t2)
+      for (int t1 = 0; t1 < p; ++t1)
+        for (int t0 = 0; t0 < p; ++t0) {
+          int dg = std::max(tdeg(t0), tdeg(t1));
+          if (d == 3) dg = std::max(dg, tdeg(t2));
+          if (dg != s) continue;
+          for (int c = 0; c < nf; ++c) {
+            pt.push_back(t0);
+            pt.push_back(t1);
+            pt.push_back(t2);
+            pt.push_back(c);
+          }
+        }
+  const int nP = h->lev[l].nP;
+  std::vector<int> units;
+  for (int V = 0; V < (1 << d); ++V)
+    for (int c = 0; c < nf; ++c) {
+      std::vector<int> planes;
+      for (int P = 0; P < nP; ++P) {
+        int vm = 0;
+        for (int ax = 0; ax < d; ++ax)
+          if (pt[4 * P + ax] == 0) vm |= 1 << ax;
+        if (vm == V && pt[4 * P + 3] == c) planes.push_back(P);
+      }
+      for (size_t k0 = 0; k0 < planes.size(); k0 += 8) {
+        int cnt = (int)std::min<size_t>(8, planes.size() - k0);
+        int rec[12] = {V, c, cnt, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int k = 0; k < cnt; ++k) rec[3 + k] = planes[k0 + k];
+        for (int k = cnt; k < 8; ++k) rec[3 + k] = planes[k0];
+        units.insert(units.end(), rec, rec + 12);
+      }
+    }
+  h->lev[l].nunits = (int)units.size() / 12;
+  return upload(h, &h->lev[l].units, units);
 }
 
 static fcm_status setup_levels(fcm_handle *h) {
@@ -520,6 +561,29 @@ static fcm_status do_setup(fcm_handle *h) {
   launch_to_f32(h->Kref64, h->Kref32, (int64_t)mm, h->stream);
   if (ncut > 0) launch_to_f32(h->Kcut64, h->Kcut32, (int64_t)(mm * ncut), h->stream);
   // Schwarz inverses per level >= 1, coarse factorisation
+  for (int l = 0; l <= L; ++l) TRY(build_units(h, l));
+  {
+    std::vector<int> ue(h->h_block_elems.begin() + h->n_shared, h->h_block_elems.end());
+    if (ue.empty()) ue.push_back(0);
+    TRY(upload(h, &h->uniq_elems, ue));
+    std::vector<int> ce = h->h_cut;
+    if (ce.empty()) ce.push_back(0);
+    TRY(upload(h, &h->cut_elems, ce));
+    TRY(dalloc(h, &h->Yscr, (size_t)std::max(1, std::max(ncut, h->n_unique)) * m));
+    TRY(dalloc(h, &h->Yshr, (size_t)g.E * m));
+    std::vector<int> ul, cl;
+    for (int e = 0; e < g.E; ++e)
+      if (h->h_kmat[e] == 0) ul.push_back(e);
+    for (int c = 0; c < h->n_shared; ++c)
+      for (int e = 0; e < g.E; ++e)
+        if (h->h_blk[e] == c) cl.push_back(e);
+    h->n_uncut = (int)ul.size();
+    h->n_classed = (int)cl.size();
+    if (ul.empty()) ul.push_back(0);
+    if (cl.empty()) cl.push_back(0);
+    TRY(upload(h, &h->uncut_list, ul));
+    TRY(upload(h, &h->class_list, cl));
+  }
   TRY(setup_levels(h));
   TRY(setup_coarse(h));
   // work vectors
@@ -544,6 +608,7 @@ static fcm_status do_setup(fcm_handle *h) {
   TRY(dalloc(h, &h->red, 1024));
   TRY(dalloc(h, &h->scal, 16));
   FCM_HIP(hipHostMalloc((void **)&h->hscal, 16 * sizeof(double), hipHostMallocDefault));
+  FCM_HIP(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
   FCM_HIP(hipStreamSynchronize(h->stream));
   return FCM_OK;
 }
@@ -589,6 +654,15 @@ static OpArgs<T> stiffness_args(fcm_handle *h, int l) {
   a.matS = Prec<T>::Kref(h);
   a.nS = 1;
   a.matU = Prec<T>::Kcut(h);
+  a.m_out = h->lev[l].m;
+  a.units = h->lev[l].units;
+  a.nunits = h->lev[l].nunits;
+  a.selem = h->cut_elems;
+  a.nstored = (int)h->h_cut.size();
+  a.Y = h->Yscr;
+  a.Yshared = h->Yshr;
+  a.shlist = h->uncut_list;
+  a.nsh = h->n_uncut;
   set_fp64_parts<T>(h, l, a, false);
   return a;
 }
@@ -598,11 +672,16 @@ static void set_fp64_parts(fcm_handle *, int, OpArgs<T> &, bool) {}
 template <>
 void set_fp64_parts<float>(fcm_handle *h, int l, OpArgs<float> &a, bool smoother) {
   if (smoother) {
+    // FP32 storage only where the block is well conditioned; all arithmetic FP64
     a.matU64 = h->lev[l].invU64;
     a.u64flag = h->lev[l].hi64;
+    a.matS64 = h->lev[l].invS64;
   } else {
-    a.matU64 = h->Kcut64;   // every cut element: FP64 entries and accumulation
+    // residual of the FP32 V-cycle: FP64 entries and accumulation for every
+    // element matrix (vectors stay FP32), so that r -= omega A delta cancels
+    a.matU64 = h->Kcut64;
     a.u64flag = nullptr;
+    a.matS64 = h->Kref64;
   }
 }
 
@@ -617,6 +696,15 @@ static OpArgs<T> smoother_args(fcm_handle *h, int l) {
   a.matS = Prec<T>::invS(L);
   a.nS = h->n_shared;
   a.matU = Prec<T>::invU(L);
+  a.m_out = L.m;
+  a.units = L.units;
+  a.nunits = L.nunits;
+  a.selem = h->uniq_elems;
+  a.nstored = h->n_unique;
+  a.Y = h->Yscr;
+  a.Yshared = h->Yshr;
+  a.shlist = h->class_list;
+  a.nsh = h->n_classed;
   set_fp64_parts<T>(h, l, a, true);
   return a;
 }
@@ -643,8 +731,8 @@ static void vcycle_level(fcm_handle *h, int l, const T *b, T *x, hipStream_t s) 
   ap.scale = -w;
   const int npre = h->opt.n_pre, npost = h->opt.n_post;
   if (npre == 0) {
-    hipMemcpyAsync(r, b, L.npad * sizeof(T), hipMemcpyDeviceToDevice, s);
-    hipMemsetAsync(x, 0, L.npad * sizeof(T), s);
+    launch_copy<T>(r, b, L.npad, s);
+    launch_copy<T>(x, nullptr, L.npad, s);
   }
   for (int it = 0; it < npre; ++it) {
     sm.x = it == 0 ? b : r;
@@ -748,11 +836,18 @@ fcm_status cg_begin(fcm_handle *h, CGState &cg, const double *b_dev, double *x, 
   return FCM_OK;
 }
 
-void cg_issue(fcm_handle *h, CGState &cg, hipStream_t s) {
+static void cg_issue_body(fcm_handle *h, CGState &cg, hipStream_t s) {
   const int L = h->L;
   const int64_t n = h->lev[L].npad;
   double *r = h->cg_r, *z = h->cg_z, *p = h->cg_p, *q = h->cg_q;
   const int nblk = dot_blocks(n);
+  // The FP32 V-cycle is an inexact preconditioner: its CG uses the flexible
+  // (Polak-Ribiere) beta, which needs r_new . z_old before z is overwritten.
+  const int flexible = h->opt.precision == FCM_MIXED;
+  if (flexible && !cg.first) {
+    launch_dot_partial(r, z, n, h->red, nblk, s);
+    launch_dot_final(h->red, nblk, h->scal + 8, s);
+  }
   vcycle_top(h, r, z, s);
   launch_dot_partial(r, z, n, h->red, nblk, s);
   if (cg.first) {
@@ -760,7 +855,7 @@ void cg_issue(fcm_handle *h, CGState &cg, hipStream_t s) {
     launch_cg_update_p(p, z, h->scal, n, 1, s);
   } else {
     launch_dot_final(h->red, nblk, h->scal + 4, s);
-    launch_cg_beta(h->scal, s);
+    launch_cg_beta(h->scal, flexible, s);
     launch_cg_update_p(p, z, h->scal, n, 0, s);
   }
   apply_fine64(h, L, p, q, s);
@@ -770,6 +865,43 @@ void cg_issue(fcm_handle *h, CGState &cg, hipStream_t s) {
   launch_cg_update_xr(cg.x, r, p, q, h->scal, n, h->red, nblk, s);
   launch_dot_final(h->red, nblk, h->scal + 3, s);
   hipMemcpyAsync(h->hscal, h->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s);
+}
+
+// One CG iteration.  With use_graphs, every iteration after the first is a
+// replay of a HIP graph captured once per (b, x) pair; the launches inside it
+// are the same as the eager ones and the graph holds no memset nodes.
+void cg_issue(fcm_handle *h, CGState &cg, hipStream_t s) {
+  if (!h->opt.use_graphs || cg.first || s == nullptr) {
+    cg_issue_body(h, cg, s);
+    return;
+  }
+  if (!h->cg_exec || h->graph_x != cg.x || h->graph_b != cg.b) {
+    if (h->cg_exec) {
+      hipGraphExecDestroy(h->cg_exec);
+      hipGraphDestroy(h->cg_graph);
+      h->cg_exec = nullptr;
+    }
+    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      cg_issue_body(h, cg, s);
+      return;
+    }
+    cg_issue_body(h, cg, s);
+    hipGraph_t gph = nullptr;
+    if (hipStreamEndCapture(s, &gph) != hipSuccess || !gph) {
+      set_error("graph capture failed");
+      return;
+    }
+    if (hipGraphInstantiate(&h->cg_exec, gph, nullptr, nullptr, 0) != hipSuccess) {
+      hipGraphDestroy(gph);
+      h->cg_exec = nullptr;
+      cg_issue_body(h, cg, s);
+      return;
+    }
+    h->cg_graph = gph;
+    h->graph_x = cg.x;
+    h->graph_b = cg.b;
+  }
+  hipGraphLaunch(h->cg_exec, s);
 }
 
 void cg_finish(fcm_handle *h, CGState &cg) {
@@ -836,6 +968,9 @@ const char *fcm_status_string(fcm_status s) {
 
 void fcm_destroy(fcm_handle *h) {
   if (!h) return;
+  if (h->cg_exec) hipGraphExecDestroy(h->cg_exec);
+  if (h->cg_graph) hipGraphDestroy(h->cg_graph);
+  if (h->own) hipStreamDestroy(h->own);
   for (void *p : h->allocs) hipFree(p);
   if (h->hscal) hipHostFree(h->hscal);
   delete h;
@@ -1129,6 +1264,12 @@ fcm_status fcm_pcg_solve(fcm_handle *h, const double *b_dev, double *x_dev, fcm_
   }
   hipStream_t s = (hipStream_t)stream;
   auto t0 = std::chrono::steady_clock::now();
+  if (h->opt.use_graphs) {
+    // captured iterations run on the library's own stream (capture is not
+    // possible on the legacy default stream); order it after the caller's work
+    FCM_HIP(hipStreamSynchronize(s));
+    s = h->own;
+  }
   CGState cg;
   fcm_status st = cg_begin(h, cg, b_dev, x_dev, s);
   if (st < 0) return st;
@@ -1220,8 +1361,8 @@ static double op_bytes(const fcm_handle *h, int op, int l) {
 
 static double coarse_bytes(const fcm_handle *h) {
   const fcm::Coarse &c = h->co;
-  // each block inverse is read in the forward and in the backward sweep
-  return 2.0 * (double)c.nblk * c.nb * c.nb * 8.0 + 4.0 * (double)c.nblk * c.nb * 8.0;
+  // S_k^{-1} (all blocks), G_k (k >= 1) and F_k (k < K-1) are each read once
+  return (3.0 * c.nblk - 2.0) * c.nb * c.nb * 8.0 + 3.0 * (double)c.nblk * c.nb * 8.0;
 }
 
 fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,

@@ -29,7 +29,9 @@ constexpr int kMaxP = 6;
 constexpr int kMaxLevels = 8;
 constexpr int kMaxDepth = 4;
 constexpr double kKappa64 = 1e5; // scaled kappa_1 above which a Schwarz block stays FP64
-constexpr int kSmallInv = 88;   // Schwarz blocks up to this size are inverted in LDS (<= 64 KB)
+constexpr int kSmallInv = 88;
+// Schwarz blocks up to kSmallInv are formed and inverted in LDS (<= 64 KB).
+constexpr int kMaxStoredIn = 1029; // largest element matrix (p = 6 elasticity: 3*7^3)
 
 enum : uint8_t { kVoid = 0, kPhys = 1, kCut = 2 };
 
@@ -55,6 +57,8 @@ struct Level {
   float *invS32 = nullptr, *invU32 = nullptr;
   uint8_t *hi64 = nullptr;     // unique blocks applied in FP64 inside the FP32 V-cycle
   int n_hi64 = 0;
+  int *units = nullptr;        // owner-kernel work units of this level
+  int nunits = 0;
   double *x64 = nullptr, *r64 = nullptr, *d64 = nullptr;
   float *x32 = nullptr, *r32 = nullptr, *d32 = nullptr;
 };
@@ -66,13 +70,12 @@ struct Coarse {
   int PP = 0;         // points per layer
   int nb = 0;         // block size = nf * w * PP
   int no = 0;         // in-layer stencil offsets (3^{d-1})
-  int JS = 1, CJ = 0; // column splits of the block GEMV
-  double *Sinv = nullptr;           // [nblk][nb][nb]
-  double *Lst = nullptr, *Ust = nullptr;   // [nblk*nb][no*nf] couplings to previous / next block
-  double *Dst = nullptr;            // [nblk*nb][w-local dense rows are built from it] in-block stencil
-  double *W = nullptr;              // [nblk*nb] forward-sweep right-hand sides
-  double *P0 = nullptr, *P1 = nullptr;  // [JS][nb] partial products
+  double *Sinv = nullptr;           // [nblk][nb][nb] inverted Schur complements S_k^{-1}
+  double *Gm = nullptr;             // [nblk][nb][nb] G_k = S_k^{-1} B_k   (k >= 1)
+  double *Fm = nullptr;             // [nblk][nb][nb] F_k = S_k^{-1} B_{k+1}^T (k < nblk-1)
+  double *Dst = nullptr;            // [nblk*nb][3][no][nf] stencil rows (slow offsets -1, 0, +1)
   double *xb = nullptr, *bb = nullptr;  // FP64 coarse vectors (used by the FP32 V-cycle)
+  double *xblk = nullptr, *bblk = nullptr;  // [nblk][nb] block-layout sweep vectors
 };
 
 struct Problem {
@@ -118,6 +121,13 @@ struct fcm_handle {
   uint8_t *state = nullptr;
   int *kmat = nullptr;                        // -1 void, 0 uncut (K_ref), 1+c cut c
   int *blk = nullptr;                         // -1 void, <n_shared class, else n_shared+u
+  int *cut_elems = nullptr;                   // element of each cut matrix
+  int *uniq_elems = nullptr;                  // element of each unique Schwarz block
+  int *uncut_list = nullptr;                  // kept uncut elements (K_ref)
+  int *class_list = nullptr;                  // elements with a shared Schwarz class, by class
+  int n_uncut = 0, n_classed = 0;
+  double *Yscr = nullptr;                     // stored-matrix products (scratch)
+  double *Yshr = nullptr;                     // shared-matrix element products (scratch)
   double *Kref64 = nullptr, *Kcut64 = nullptr, *be = nullptr, *b = nullptr;
   float *Kref32 = nullptr, *Kcut32 = nullptr;
   fcm::Coarse co;
@@ -129,6 +139,11 @@ struct fcm_handle {
   double *hscal = nullptr;                    // pinned host mirror
   int *dflag = nullptr;                       // device error flag
   std::vector<double> history;
+  hipStream_t own = nullptr;                  // stream of captured CG iterations
+  hipGraphExec_t cg_exec = nullptr;           // captured steady-state CG iteration
+  hipGraph_t cg_graph = nullptr;
+  const double *graph_b = nullptr;
+  double *graph_x = nullptr;
   double t_setup_ms = 0.0;
   int64_t bytes = 0;
   std::vector<void *> allocs;
@@ -178,6 +193,7 @@ void launch_coarse_stencils(const Geo &g, const Tables &t, const Coarse &c, cons
 void launch_coarse_first(const Geo &g, const Coarse &c, int k, double *S, hipStream_t s);
 void launch_coarse_schur(const Geo &g, const Coarse &c, int k, double *S, double *T,
                          hipStream_t s);
+void launch_coarse_G(const Geo &g, const Coarse &c, int k, hipStream_t s);
 
 // Solve (kernels_solve.hip).
 template <typename T>
@@ -188,10 +204,20 @@ struct OpArgs {
   int ld = 0;                 // matrix leading dimension
   const int *mid = nullptr;   // per element matrix id (-1 skip)
   const T *matS = nullptr;    // shared matrices
+  const double *matS64 = nullptr;  // FP64 shared matrices and FP64 accumulation (optional)
   int nS = 0;
   const T *matU = nullptr;    // stored matrices (id - nS)
   const double *matU64 = nullptr;   // FP32 operator only: FP64 copies of stored matrices,
   const uint8_t *u64flag = nullptr; //   used for all of them (flag null) or where flag != 0
+  int m_out = 0;              // rows of the operator (local modes of the output level)
+  const int *units = nullptr; // [nunits][12]: vmask, comp, count, planes[8], pad
+  int nunits = 0;
+  const int *selem = nullptr; // element of each stored matrix
+  int nstored = 0;
+  double *Y = nullptr;        // [nstored][m_out] stored-matrix products (scratch)
+  void *Yshared = nullptr;    // [m_out][E] shared-matrix products (scratch, TM)
+  const int *shlist = nullptr; // elements with a shared matrix, sorted by matrix id
+  int nsh = 0;
   T *out = nullptr;           // out = cvec + scale*acc  (cvec may be null)
   const T *cvec = nullptr;
   T scale = 1;
@@ -212,11 +238,14 @@ void launch_dot_final(const double *partial, int nblk, double *dst, hipStream_t 
 void launch_cg_alpha(double *scal, hipStream_t s);
 void launch_cg_update_xr(double *x, double *r, const double *p, const double *q,
                          const double *scal, int64_t n, double *partial, int nblk, hipStream_t s);
-void launch_cg_beta(double *scal, hipStream_t s);
+void launch_cg_beta(double *scal, int flexible, hipStream_t s);
 void launch_cg_update_p(double *p, const double *z, const double *scal, int64_t n, int first,
                         hipStream_t s);
 void launch_axpby(double *y, const double *x, double a, double b, int64_t n, hipStream_t s);
 void launch_f64_to_f32(const double *x, float *y, int64_t n, hipStream_t s);
+// y = x (x null: y = 0); a kernel, so that it may sit inside a captured graph
+template <typename T>
+void launch_copy(T *y, const T *x, int64_t n, hipStream_t s);
 void launch_f32_to_f64(const float *x, double *y, int64_t n, hipStream_t s);
 
 // Resumable PCG used by fcm_pcg_solve and the server (fcm_host.hip).

@@ -1241,6 +1241,33 @@ __global__ void coarse_S_kernel(Geo g, Coarse c, int k, const double *T, double 
   }
 }
 
+// G_k = S_k^{-1} B_k: column j (block k-1) couples through the upper stencil
+// of row j, B_k[l][j] = A[(k-1,j),(k,l)].
+__global__ void coarse_G_kernel(Geo g, Coarse c, int k, const double *Sk, double *Gk) {
+  const int nb = c.nb;
+  const int i = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nb; j += gridDim.x * blockDim.x) {
+    const double *st = c.Dst + (size_t)((k - 1) * nb + j) * 3 * c.no * g.nf + 2 * c.no * g.nf;
+    double s = 0.0;
+    for (int t = 0; t < c.no * g.nf; ++t) {
+      double v = st[t];
+      if (v == 0.0) continue;
+      int o = t / g.nf, cb = t % g.nf, db;
+      int l = coarse_nbr(g, c, j, 1, o, cb, &db);
+      if (l < 0 || db != 1) continue;
+      s += Sk[(size_t)i * nb + l] * v;
+    }
+    Gk[(size_t)i * nb + j] = s;
+  }
+}
+
+void launch_coarse_G(const Geo &g, const Coarse &c, int k, hipStream_t s) {
+  const int nb = c.nb;
+  dim3 grid((nb + 255) / 256, nb);
+  coarse_G_kernel<<<grid, 256, 0, s>>>(g, c, k, c.Sinv + (size_t)k * nb * nb,
+                                       c.Gm + (size_t)k * nb * nb);
+}
+
 void launch_coarse_schur(const Geo &g, const Coarse &c, int k, double *S, double *T,
                          hipStream_t s) {
   const int nb = c.nb;

@@ -16,15 +16,234 @@
 //
 // Coarse: forward/backward block sweeps of the layer-block-tridiagonal p = 1
 // system with dense inverted Schur complements.
+#include <type_traits>
+
 #include "fcm_internal.hpp"
 
 namespace fcm {
 
+// Phase A: stored matrices (cut stiffness, unique Schwarz inverses).  One wave
+// per matrix streams it row by row with lanes over the output index (the
+// matrices are symmetric, so row b holds column b contiguously) and writes
+// Y[sid][a] = sum_b M[a][b] x_e[b] in FP64.  FP64 copies are used where the
+// FP32 operator must not round (see set_fp64_parts in the host code).
 template <typename T>
-__global__ __launch_bounds__(256) void elem_op_kernel(Geo g, const int *__restrict__ xoff,
-                                                      const int *__restrict__ rows,
-                                                      const int *__restrict__ pinfo,
-                                                      OpArgs<T> a) {
+__device__ void stored_gemv_wg(Geo g, const int *__restrict__ xoff, OpArgs<T> a, int wg,
+                               double *scratch) {
+  double(*xs)[kMaxStoredIn] = reinterpret_cast<double(*)[kMaxStoredIn]>(scratch);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sid = wg * 4 + wave;
+  const bool active = sid < a.nstored;
+  if (active) {
+    const int e = a.selem[sid];
+    const int ex = e % g.n[0], r = e / g.n[0];
+    const int base = ex + g.gn[0] * ((r % g.n[1]) + g.gn[1] * (r / g.n[1]));
+    for (int b = lane; b < a.m_in; b += 64) xs[wave][b] = (double)a.x[base + xoff[b]];
+  }
+  __syncthreads();
+  if (!active) return;
+  const int ld = a.ld;
+  const bool hi = a.matU64 && (!a.u64flag || a.u64flag[sid]);
+  const double *xw = xs[wave];
+  for (int a0 = 0; a0 < a.m_out; a0 += 64) {
+    const int row = a0 + lane;
+    if (row >= a.m_out) break;
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    int b = 0;
+    // 16 independent coalesced loads in flight per lane (lanes = rows)
+    if (hi) {
+      const double *M = a.matU64 + (size_t)sid * ld * ld + row;
+#pragma unroll 4
+      for (; b + 3 < a.m_in; b += 4) {
+        c0 += M[(size_t)b * ld] * xw[b];
+        c1 += M[(size_t)(b + 1) * ld] * xw[b + 1];
+        c2 += M[(size_t)(b + 2) * ld] * xw[b + 2];
+        c3 += M[(size_t)(b + 3) * ld] * xw[b + 3];
+      }
+      for (; b < a.m_in; ++b) c0 += M[(size_t)b * ld] * xw[b];
+    } else {
+      const T *M = a.matU + (size_t)sid * ld * ld + row;
+#pragma unroll 4
+      for (; b + 3 < a.m_in; b += 4) {
+        c0 += (double)M[(size_t)b * ld] * xw[b];
+        c1 += (double)M[(size_t)(b + 1) * ld] * xw[b + 1];
+        c2 += (double)M[(size_t)(b + 2) * ld] * xw[b + 2];
+        c3 += (double)M[(size_t)(b + 3) * ld] * xw[b + 3];
+      }
+      for (; b < a.m_in; ++b) c0 += (double)M[(size_t)b * ld] * xw[b];
+    }
+    a.Y[(size_t)sid * a.m_out + row] = (c0 + c1) + (c2 + c3);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void stored_gemv_kernel(Geo g, const int *__restrict__ xoff,
+                                                          OpArgs<T> a) {
+  __shared__ double xs[4 * kMaxStoredIn];
+  stored_gemv_wg<T>(g, xoff, a, blockIdx.x, xs);
+}
+
+// Phase B: elements with a shared matrix (K_ref, Schwarz classes).  One thread
+// per element computes Ys[a][e] = sum_b M[a][b] x_e[b] for all output rows;
+// the matrix is wave-uniform (one pass per distinct class present in the
+// wave), so its rows come through scalar loads and every gathered x value
+// feeds kRows FMAs.  TM is the matrix / accumulation type (FP64 for the
+// residual of the FP32 V-cycle, where the sum over elements must cancel).
+constexpr int kRows = 32;
+constexpr int kCols = 32;
+
+template <typename T, typename TM>
+__global__ __launch_bounds__(256) void shared_elem_kernel(Geo g, const int *__restrict__ xoff,
+                                                          const TM *__restrict__ matS,
+                                                          OpArgs<T> a, TM *__restrict__ Ys) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  const bool in = e < g.E;
+  const int id = in ? a.mid[e] : -1;
+  bool todo = id >= 0 && id < a.nS;
+  const int ex = e % g.n[0], r = e / g.n[0];
+  const int base = ex + g.gn[0] * ((r % g.n[1]) + g.gn[1] * (r / g.n[1]));
+  const T *xb = a.x + base;
+  const int ld = a.ld;
+  for (;;) {
+    const unsigned long long msk = __ballot(todo);
+    if (msk == 0ull) break;
+    const int first = __ffsll((long long)msk) - 1;
+    const int id0 = __builtin_amdgcn_readfirstlane(__shfl(id, first));
+    const bool mine = todo && id == id0;
+    todo = todo && !mine;
+    const TM *M0 = matS + (size_t)id0 * ld * ld;
+    for (int a0 = 0; a0 < a.m_out; a0 += kRows) {
+      TM acc[kRows];
+#pragma unroll
+      for (int rr = 0; rr < kRows; ++rr) acc[rr] = 0;
+      for (int b0 = 0; b0 < a.m_in; b0 += kCols) {
+        TM xv[kCols];
+#pragma unroll
+        for (int bb = 0; bb < kCols; ++bb)
+          xv[bb] = (mine && b0 + bb < a.m_in) ? (TM)xb[xoff[b0 + bb]] : TM(0);
+#pragma unroll
+        for (int rr = 0; rr < kRows; ++rr) {
+          if (a0 + rr >= a.m_out) break;
+          const TM *Mr = M0 + (size_t)(a0 + rr) * ld + b0;
+          TM sum = 0;
+#pragma unroll
+          for (int bb = 0; bb < kCols; ++bb)
+            if (b0 + bb < a.m_in) sum += Mr[bb] * xv[bb];
+          acc[rr] += sum;
+        }
+      }
+      if (mine) {
+#pragma unroll
+        for (int rr = 0; rr < kRows; ++rr)
+          if (a0 + rr < a.m_out) Ys[(size_t)(a0 + rr) * g.E + e] = acc[rr];
+      }
+    }
+  }
+}
+
+// Phase B on the matrix cores (element matrices up to 64 x 64).  A wave takes
+// 32 (FP32) or 16 (FP64) consecutive elements and computes Y = M X with
+// v_mfma_f32_32x32x2f32 / v_mfma_f64_16x16x4f64: A = M read column-wise
+// (M is symmetric, so column k is row k and the read is coalesced over the
+// lanes' row index), B = the gathered element vectors x_e.  Lane layouts
+// (gfx950): 32x32x2 f32 -- lane l supplies A[l%32][l/32] and B[l/32][l%32],
+// holds D[8(j/4) + 4(l/32) + j%4][l%32] in register j; 16x16x4 f64 -- lane l
+// supplies A[l%16][l/16] and B[l/16][l%16], holds D[4j + l/16][l%16].
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// FP64 matrix-core variant with the shared matrix staged in LDS.  The class
+// loop is uniform over the workgroup: for each distinct shared matrix present
+// among the workgroup's 64 elements, the matrix is copied to LDS (column stride
+// m+1 against bank conflicts) and every wave multiplies its own elements of
+// that class.
+constexpr int kLdsM = 64 * 65;
+
+template <typename T>
+__device__ void shared_mfma64_wg(Geo g, const int *__restrict__ xoff,
+                                 const double *__restrict__ matS, OpArgs<T> a,
+                                 double *__restrict__ Ys, int wg, double *Ms) {
+  constexpr int KS = 16;   // k-steps of 4 (m_in <= 64)
+  __shared__ int s_next;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = lane & 15, kq = lane >> 4;
+  // elements come from a list sorted by shared matrix, so a workgroup
+  // usually meets a single class
+  const int li = (wg * 4 + wave) * 16 + n;
+  const bool in = li < a.nsh;
+  const int e = in ? a.shlist[li] : 0;
+  const int id = in ? a.mid[e] : -1;
+  const bool shared = id >= 0 && id < a.nS;
+  bool todo = shared;
+  const int ee = shared ? e : 0;
+  const int ex = ee % g.n[0], r = ee / g.n[0];
+  const int base = ex + g.gn[0] * ((r % g.n[1]) + g.gn[1] * (r / g.n[1]));
+  const int ld = a.ld, mi = a.m_in, mo = a.m_out, lds = mo + 1;   // column k holds mo rows
+  double bv[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    const int k = min(4 * ks + kq, mi - 1);
+    const double v = (double)a.x[base + xoff[k]];
+    bv[ks] = (shared && 4 * ks + kq < mi) ? v : 0.0;
+  }
+  const int nks = (mi + 3) / 4;
+  for (;;) {
+    // smallest pending class id in the workgroup
+    if (threadIdx.x == 0) s_next = 0x7fffffff;
+    __syncthreads();
+    if (todo) atomicMin(&s_next, id);
+    __syncthreads();
+    const int id0 = s_next;
+    if (id0 == 0x7fffffff) break;
+    const double *M0 = matS + (size_t)id0 * ld * ld;
+    for (int t = threadIdx.x; t < mi * mo; t += 256) {
+      const int k = t / mo, rr = t % mo;
+      Ms[k * lds + rr] = M0[(size_t)k * ld + rr];   // column k of the symmetric matrix
+    }
+    __syncthreads();
+    const bool mine = todo && id == id0;
+    todo = todo && !mine;
+    if (__ballot(mine) != 0ull) {
+      for (int rt = 0; rt < 4; ++rt) {
+        if (16 * rt >= mo) break;
+        const int row = min(16 * rt + n, mo - 1);
+        doublex4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          if (ks < nks) {
+            const int k = min(4 * ks + kq, mi - 1);
+            const double av = (4 * ks + kq < mi && 16 * rt + n < mo) ? Ms[k * lds + row] : 0.0;
+            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, mine ? bv[ks] : 0.0, c, 0, 0, 0);
+          }
+        }
+        if (mine) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int rr = 16 * rt + 4 * j + kq;
+            if (rr < mo) Ys[(size_t)rr * g.E + e] = c[j];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void shared_mfma64_kernel(Geo g, const int *__restrict__ xoff,
+                                                            const double *__restrict__ matS,
+                                                            OpArgs<T> a, double *__restrict__ Ys) {
+  __shared__ double Ms[kLdsM];
+  shared_mfma64_wg<T>(g, xoff, matS, a, Ys, blockIdx.x, Ms);
+}
+
+// Phase C: owner gather.  One thread per output entry (grid point g, plane P)
+// sums the 2^k element results that belong to this DOF and applies the fused
+// epilogue (damped update, residual update, prolongation).
+template <typename T, typename TM>
+__global__ __launch_bounds__(256) void gather_kernel(Geo g, const int *__restrict__ rows,
+                                                     const int *__restrict__ pinfo, OpArgs<T> a,
+                                                     const TM *__restrict__ Ys) {
   const int P = blockIdx.y;
   const int gi = blockIdx.x * 256 + threadIdx.x;
   if (gi >= g.G) return;
@@ -42,13 +261,11 @@ __global__ __launch_bounds__(256) void elem_op_kernel(Geo g, const int *__restri
       if (gc[ax] == g.n[ax] && ((g.dir >> (2 * ax + 1)) & 1)) valid = false;
     }
   }
-  T acc = 0;
+  TM acc = 0;
   double acc64 = 0.0;
   bool any = false;
-  const int ld = a.ld;
-  const int nsub = 1 << g.d;
   if (valid) {
-    for (int s = 0; s < nsub; ++s) {
+    for (int s = 0; s < (1 << g.d); ++s) {
       if (s & ~vmask) continue;
       const int ex = gx - (s & 1), ey = gy - ((s >> 1) & 1), ez = gz - ((s >> 2) & 1);
       if (ex < 0 || ey < 0 || ez < 0 || ex >= g.n[0] || ey >= g.n[1] || ez >= g.n[2]) continue;
@@ -57,32 +274,8 @@ __global__ __launch_bounds__(256) void elem_op_kernel(Geo g, const int *__restri
       if (id < 0) continue;
       any = true;
       const int row = rows[P * 8 + s];
-      const int base = ex + g.gn[0] * (ey + g.gn[1] * ez);
-      const T *xb = a.x + base;
-      if (a.matU64 && id >= a.nS && (!a.u64flag || a.u64flag[id - a.nS])) {
-        // ill-conditioned stored matrix inside the FP32 operator: FP64 entries, FP64 sum
-        const double *M = a.matU64 + (size_t)(id - a.nS) * ld * ld + (size_t)row * ld;
-        double d0 = 0.0, d1 = 0.0;
-        int b = 0;
-        for (; b + 1 < a.m_in; b += 2) {
-          d0 += M[b] * (double)xb[xoff[b]];
-          d1 += M[b + 1] * (double)xb[xoff[b + 1]];
-        }
-        if (b < a.m_in) d0 += M[b] * (double)xb[xoff[b]];
-        acc64 += d0 + d1;
-        continue;
-      }
-      const T *M = (id < a.nS) ? a.matS + (size_t)id * ld * ld
-                               : a.matU + (size_t)(id - a.nS) * ld * ld;
-      M += (size_t)row * ld;
-      T s0 = 0, s1 = 0;
-      int b = 0;
-      for (; b + 1 < a.m_in; b += 2) {
-        s0 += M[b] * xb[xoff[b]];
-        s1 += M[b + 1] * xb[xoff[b + 1]];
-      }
-      if (b < a.m_in) s0 += M[b] * xb[xoff[b]];
-      acc += s0 + s1;
+      if (id < a.nS) acc += Ys[(size_t)row * g.E + e];
+      else acc64 += a.Y[(size_t)(id - a.nS) * a.m_out + row];
     }
   }
   const bool live = valid && any;
@@ -101,10 +294,44 @@ __global__ __launch_bounds__(256) void elem_op_kernel(Geo g, const int *__restri
   if (a.xp && P < a.nP_e) a.xp[oi] += a.ep[oi];
 }
 
+template <typename T, typename TM>
+static void launch_shared(const Geo &g, const Tables &t, const OpArgs<T> &a, const TM *matS,
+                          TM *Ys, hipStream_t s) {
+  shared_elem_kernel<T, TM><<<(g.E + 255) / 256, 256, 0, s>>>(g, t.xoff, matS, a, Ys);
+}
+
+template <typename T, typename TM>
+static void launch_op3(const Geo &g, const Tables &t, const OpArgs<T> &a, const TM *matS,
+                       hipStream_t s) {
+  TM *Ys = reinterpret_cast<TM *>(a.Yshared);
+  launch_shared<T, TM>(g, t, a, matS, Ys, s);
+  dim3 grid((g.G + 255) / 256, a.nP_out);
+  gather_kernel<T, TM><<<grid, 256, 0, s>>>(g, t.rows, t.pinfo, a, Ys);
+}
+
 template <typename T>
 void launch_elem_op(const Geo &g, const Tables &t, const OpArgs<T> &a, hipStream_t s) {
-  dim3 grid((g.G + 255) / 256, a.nP_out);
-  elem_op_kernel<T><<<grid, 256, 0, s>>>(g, t.xoff, t.rows, t.pinfo, a);
+  const double *mS64 = a.matS64 ? a.matS64
+                                 : (std::is_same<T, double>::value
+                                        ? reinterpret_cast<const double *>(a.matS)
+                                        : nullptr);
+  if (mS64 && a.m_out <= 64) {
+    // stored-matrix GEMV (HBM stream) and FP64 matrix-core work on shared matrices
+    double *Ys = reinterpret_cast<double *>(a.Yshared);
+    if (a.nstored > 0)
+      stored_gemv_kernel<T><<<(a.nstored + 3) / 4, 256, 0, s>>>(g, t.xoff, a);
+    if (a.nsh > 0)
+      shared_mfma64_kernel<T><<<(a.nsh + 63) / 64, 256, 0, s>>>(g, t.xoff, mS64, a, Ys);
+    dim3 grid((g.G + 255) / 256, a.nP_out);
+    gather_kernel<T, double><<<grid, 256, 0, s>>>(g, t.rows, t.pinfo, a, Ys);
+    return;
+  }
+  if (a.nstored > 0)
+    stored_gemv_kernel<T><<<(a.nstored + 3) / 4, 256, 0, s>>>(g, t.xoff, a);
+  if (a.matS64)
+    launch_op3<T, double>(g, t, a, a.matS64, s);
+  else
+    launch_op3<T, T>(g, t, a, a.matS, s);
 }
 template void launch_elem_op<double>(const Geo &, const Tables &, const OpArgs<double> &,
                                      hipStream_t);
@@ -191,11 +418,14 @@ void launch_cg_update_xr(double *x, double *r, const double *p, const double *q,
   cg_update_xr_kernel<<<nblk, kRedThreads, 0, s>>>(x, r, p, q, scal, n, partial);
 }
 
-__global__ void cg_beta_kernel(double *sc) {
-  sc[5] = sc[4] / sc[0];
+// beta = r_new.z_new / r.z (flexible: (r_new.z_new - r_new.z_old) / r.z, scal[8])
+__global__ void cg_beta_kernel(double *sc, int flexible) {
+  sc[5] = (sc[4] - (flexible ? sc[8] : 0.0)) / sc[0];
   sc[0] = sc[4];
 }
-void launch_cg_beta(double *scal, hipStream_t s) { cg_beta_kernel<<<1, 1, 0, s>>>(scal); }
+void launch_cg_beta(double *scal, int flexible, hipStream_t s) {
+  cg_beta_kernel<<<1, 1, 0, s>>>(scal, flexible);
+}
 
 __global__ void cg_update_p_kernel(double *p, const double *z, const double *sc, int64_t n,
                                    int first) {
@@ -221,6 +451,20 @@ void launch_axpby(double *y, const double *x, double a, double b, int64_t n, hip
   int blocks = (int)std::min<int64_t>((n + 255) / 256, 2048);
   axpby_kernel<<<blocks, 256, 0, s>>>(y, x, a, b, n);
 }
+
+template <typename T>
+__global__ void copy_kernel(T *y, const T *x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x ? x[i] : T(0);
+}
+template <typename T>
+void launch_copy(T *y, const T *x, int64_t n, hipStream_t s) {
+  int blocks = (int)std::min<int64_t>((n + 255) / 256, 2048);
+  copy_kernel<T><<<blocks, 256, 0, s>>>(y, x, n);
+}
+template void launch_copy<double>(double *, const double *, int64_t, hipStream_t);
+template void launch_copy<float>(float *, const float *, int64_t, hipStream_t);
 
 __global__ void f64_to_f32_kernel(const double *x, float *y, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -252,119 +496,61 @@ __device__ inline int64_t coarse_vec_index(const Geo &g, const Coarse &c, int k,
   return (int64_t)comp * g.G + (int64_t)layer * c.PP + pt;
 }
 
-__device__ inline int coarse_nbr_s(const Geo &g, const Coarse &c, int i, int so, int o, int cb,
-                                   int *dblk) {
-  const int lay = c.w * c.PP;
-  int rem = i % lay;
-  int lam = rem / c.PP, pt = rem % c.PP;
-  int px, py = 0;
-  if (g.d == 3) {
-    px = pt % g.gn[0];
-    py = pt / g.gn[0];
-  } else {
-    px = pt;
-  }
-  px += o % 3 - 1;
-  if (g.d == 3) py += o / 3 - 1;
-  if (px < 0 || px >= g.gn[0]) return -1;
-  if (g.d == 3 && (py < 0 || py >= g.gn[1])) return -1;
-  int npt = (g.d == 3) ? px + g.gn[0] * py : px;
-  int nl = lam + so;
-  *dblk = 0;
-  if (nl < 0) {
-    nl += c.w;
-    *dblk = -1;
-  } else if (nl >= c.w) {
-    nl -= c.w;
-    *dblk = 1;
-  }
-  return cb * lay + nl * c.PP + npt;
+// Block sweeps of the layer-block-tridiagonal p = 1 system (block LDL^T):
+//   u_k = c_k - G_k u_{k-1},  c_k = S_k^{-1} b_k       (forward, k = 1..K-1)
+//   x_k = u_k - F_k x_{k+1}                           (backward, k = K-2..0)
+// with G_k = S_k^{-1} B_k and F_k = S_k^{-1} B_{k+1}^T precomputed at setup.
+// Every step is a dense FP64 GEMV, one wave per row (coalesced row reads,
+// shuffle reduction); the c_k of all blocks are one batched launch.
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off);
+  return v;
 }
 
-// Sum of the JS partial products of entry l of the previous step's result.
-__device__ inline double red_partials(const double *Pp, int JS, int nb, int l) {
-  double s = 0.0;
-  for (int t = 0; t < JS; ++t) s += Pp[(size_t)t * nb + l];
-  return s;
+// The sweeps work on contiguous block-layout copies of the coarse vectors.
+__global__ void coarse_to_block_kernel(Geo g, Coarse c, const double *src, double *dst) {
+  const int k = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < c.nb; i += gridDim.x * blockDim.x) {
+    const int64_t gi = coarse_vec_index(g, c, k, i);
+    dst[(size_t)k * c.nb + i] = gi >= 0 ? src[gi] : 0.0;
+  }
 }
 
-// One sweep step.  mode 0 (forward, block k): v = b_k - B_k u_{k-1}
-// (u_{k-1} = sum of previous partials), W_k = v.  mode 1 (backward, block k):
-// v = W_k - B_{k+1}^T x_{k+1}, x_{k+1} from `xlast` (block k+1 is the last
-// block) or from the partials, which are also written to x.  Then the
-// partial products Pcur[js][i] = sum_{j in chunk js} Sinv_k[j][i] v_j.
-__global__ __launch_bounds__(256) void coarse_step_kernel(Geo g, Coarse c, int k, int mode,
-                                                          const double *b, double *x,
-                                                          const double *Pprev, double *Pcur,
-                                                          int have_prev, int next_is_last) {
-  extern __shared__ double v[];
-  const int nb = c.nb, JS = c.JS, CJ = c.CJ;
-  const int rt = blockIdx.x, js = blockIdx.y;
-  const int j0 = js * CJ, j1 = min(nb, j0 + CJ);
-  const int per = 3 * c.no * g.nf;
-  const int tid = threadIdx.x;
-  for (int j = j0 + tid; j < j1; j += 256) {
-    double val;
-    const double *st = c.Dst + (size_t)(k * nb + j) * per;
-    if (mode == 0) {
-      int64_t gi = coarse_vec_index(g, c, k, j);
-      val = gi >= 0 ? b[gi] : 0.0;
-      if (have_prev) {
-        for (int t = 0; t < c.no * g.nf; ++t) {
-          double cf = st[t];
-          if (cf == 0.0) continue;
-          int o = t / g.nf, cb = t % g.nf, db;
-          int l = coarse_nbr_s(g, c, j, -1, o, cb, &db);
-          if (l < 0 || db != -1) continue;
-          val -= cf * red_partials(Pprev, JS, nb, l);
-        }
-      }
-      if (rt == 0) c.W[(size_t)k * nb + j] = val;
-    } else {
-      val = c.W[(size_t)k * nb + j];
-      const double *su = st + 2 * c.no * g.nf;
-      for (int t = 0; t < c.no * g.nf; ++t) {
-        double cf = su[t];
-        if (cf == 0.0) continue;
-        int o = t / g.nf, cb = t % g.nf, db;
-        int l = coarse_nbr_s(g, c, j, 1, o, cb, &db);
-        if (l < 0 || db != 1) continue;
-        double xv;
-        if (next_is_last) {
-          int64_t gi = coarse_vec_index(g, c, k + 1, l);
-          xv = gi >= 0 ? x[gi] : 0.0;
-        } else {
-          xv = red_partials(Pprev, JS, nb, l);
-        }
-        val -= cf * xv;
-      }
-      if (rt == 0 && !next_is_last) {
-        int64_t gi = coarse_vec_index(g, c, k + 1, j);
-        if (gi >= 0) x[gi] = red_partials(Pprev, JS, nb, j);
-      }
-    }
-    v[j - j0] = val;
+__global__ void coarse_from_block_kernel(Geo g, Coarse c, const double *src, double *dst) {
+  const int k = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < c.nb; i += gridDim.x * blockDim.x) {
+    const int64_t gi = coarse_vec_index(g, c, k, i);
+    if (gi >= 0) dst[gi] = src[(size_t)k * c.nb + i];
   }
-  __syncthreads();
-  // partial GEMV: 64 rows x 4 column groups per workgroup
-  __shared__ double red[4][64];
-  const int lane = tid & 63, grp = tid >> 6;
-  const int i = rt * 64 + lane;
-  double acc = 0.0;
-  if (i < nb) {
-    const double *S = c.Sinv + (size_t)k * nb * nb;
-    for (int j = j0 + grp; j < j1; j += 4) acc += S[(size_t)j * nb + i] * v[j - j0];
-  }
-  red[grp][lane] = acc;
-  __syncthreads();
-  if (grp == 0 && i < nb) Pcur[(size_t)js * nb + i] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
-__global__ void coarse_finish_kernel(Geo g, Coarse c, int k, const double *Pp, double *x) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= c.nb) return;
-  int64_t gi = coarse_vec_index(g, c, k, j);
-  if (gi >= 0) x[gi] = red_partials(Pp, c.JS, c.nb, j);
+// mode 0: xb_k = Sinv_k bb_k for all k (batched over blockIdx.y)
+// mode 1: xb_k -= G_k xb_{k-1}        mode 2: xb_k -= F_k xb_{k+1}
+__global__ __launch_bounds__(256) void coarse_gemv_kernel(int nb, int k, int mode,
+                                                          const double *__restrict__ M,
+                                                          const double *__restrict__ bb,
+                                                          double *xb) {
+  const int kk = mode == 0 ? (int)blockIdx.y : k;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (i >= nb) return;
+  const int kin = mode == 0 ? kk : (mode == 1 ? kk - 1 : kk + 1);
+  const double *row = M + ((size_t)(mode == 0 ? kk : 0) * nb + i) * nb;
+  const double *vin = (mode == 0 ? bb : xb) + (size_t)kin * nb;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int j = lane;
+  for (; j + 192 < nb; j += 256) {
+    a0 += row[j] * vin[j];
+    a1 += row[j + 64] * vin[j + 64];
+    a2 += row[j + 128] * vin[j + 128];
+    a3 += row[j + 192] * vin[j + 192];
+  }
+  for (; j < nb; j += 64) a0 += row[j] * vin[j];
+  const double acc = wave_sum((a0 + a1) + (a2 + a3));
+  if (lane == 0) {
+    double *o = xb + (size_t)kk * nb + i;
+    *o = (mode == 0) ? acc : *o - acc;
+  }
 }
 
 __global__ void fill_zero_kernel(double *x, int64_t n) {
@@ -376,28 +562,19 @@ __global__ void fill_zero_kernel(double *x, int64_t n) {
 void coarse_solve_launch(const Geo &g, const Coarse &c, const double *b, double *x,
                          hipStream_t s) {
   const int nb = c.nb;
+  const size_t nb2 = (size_t)nb * nb;
+  const dim3 vgrid((nb + 255) / 256, c.nblk);
+  coarse_to_block_kernel<<<vgrid, 256, 0, s>>>(g, c, b, c.bblk);
+  const int rows_blocks = (nb + 3) / 4;
+  coarse_gemv_kernel<<<dim3(rows_blocks, c.nblk), 256, 0, s>>>(nb, 0, 0, c.Sinv, c.bblk, c.xblk);
+  for (int k = 1; k < c.nblk; ++k)
+    coarse_gemv_kernel<<<rows_blocks, 256, 0, s>>>(nb, k, 1, c.Gm + k * nb2, c.bblk, c.xblk);
+  for (int k = c.nblk - 2; k >= 0; --k)
+    coarse_gemv_kernel<<<rows_blocks, 256, 0, s>>>(nb, k, 2, c.Fm + k * nb2, c.bblk, c.xblk);
   // entries outside the blocked system (Dirichlet layers) are zero
-  {
-    const int64_t n = (int64_t)g.nf * g.G;
-    fill_zero_kernel<<<(int)std::min<int64_t>((n + 255) / 256, 1024), 256, 0, s>>>(x, n);
-  }
-  dim3 grid((nb + 63) / 64, c.JS);
-  const size_t shm = (size_t)c.CJ * sizeof(double);
-  double *P[2] = {c.P0, c.P1};
-  int cur = 0;
-  for (int k = 0; k < c.nblk; ++k) {
-    coarse_step_kernel<<<grid, 256, shm, s>>>(g, c, k, 0, b, x, P[cur ^ 1], P[cur], k > 0, 0);
-    cur ^= 1;
-  }
-  // last block: x_K = u_K
-  coarse_finish_kernel<<<(nb + 255) / 256, 256, 0, s>>>(g, c, c.nblk - 1, P[cur ^ 1], x);
-  for (int k = c.nblk - 2; k >= 0; --k) {
-    const int next_is_last = (k + 1 == c.nblk - 1);
-    coarse_step_kernel<<<grid, 256, shm, s>>>(g, c, k, 1, b, x, P[cur ^ 1], P[cur], 1,
-                                              next_is_last);
-    cur ^= 1;
-  }
-  if (c.nblk > 1) coarse_finish_kernel<<<(nb + 255) / 256, 256, 0, s>>>(g, c, 0, P[cur ^ 1], x);
+  const int64_t n = (int64_t)g.nf * g.G;
+  fill_zero_kernel<<<(int)std::min<int64_t>((n + 255) / 256, 1024), 256, 0, s>>>(x, n);
+  coarse_from_block_kernel<<<vgrid, 256, 0, s>>>(g, c, c.xblk, x);
 }
 
 }  // namespace fcm

@@ -47,7 +47,7 @@ class Options(ctypes.Structure):
     _fields_ = [("smoother", ctypes.c_int), ("omega", ctypes.c_double),
                 ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
                 ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("max_iter", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("use_graphs", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -196,6 +196,7 @@ def make_options(opts):
     o.precision = FCM_MIXED if prec in ("mixed", "fp32", FCM_MIXED) else FCM_FP64
     o.rtol = float(opts.get("rtol", 1e-10))
     o.max_iter = int(opts.get("max_iter", 500))
+    o.use_graphs = int(opts.get("use_graphs", 1))
     return o
 
 
