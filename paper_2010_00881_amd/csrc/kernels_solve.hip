@@ -152,24 +152,21 @@ __global__ __launch_bounds__(256) void shared_elem_kernel(Geo g, const int *__re
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 
-// FP64 matrix-core variant with the shared matrix staged in LDS.  The class
-// loop is uniform over the workgroup: for each distinct shared matrix present
-// among the workgroup's 64 elements, the matrix is copied to LDS (column stride
-// m+1 against bank conflicts) and every wave multiplies its own elements of
-// that class.
-constexpr int kLdsM = 64 * 65;
-
+// FP64 matrix-core variant.  A workgroup takes 16 elements of the class-sorted
+// list; wave w computes rows [16w, 16w+16) of Y = M X for them with
+// v_mfma_f64_16x16x4f64 (one wave per row tile keeps enough waves in flight
+// to hide the gather latency).  A operands are read straight from the
+// (L1/L2-resident) shared matrix, one pass per distinct class in the wave.
 template <typename T>
-__device__ void shared_mfma64_wg(Geo g, const int *__restrict__ xoff,
-                                 const double *__restrict__ matS, OpArgs<T> a,
-                                 double *__restrict__ Ys, int wg, double *Ms) {
+__global__ __launch_bounds__(256) void shared_mfma64_kernel(Geo g, const int *__restrict__ xoff,
+                                                            const double *__restrict__ matS,
+                                                            OpArgs<T> a, double *__restrict__ Ys) {
   constexpr int KS = 16;   // k-steps of 4 (m_in <= 64)
-  __shared__ int s_next;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int rt = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int n = lane & 15, kq = lane >> 4;
-  // elements come from a list sorted by shared matrix, so a workgroup
-  // usually meets a single class
-  const int li = (wg * 4 + wave) * 16 + n;
+  const int ld = a.ld, mi = a.m_in, mo = a.m_out;
+  if (16 * rt >= mo) return;   // whole wave
+  const int li = blockIdx.x * 16 + n;
   const bool in = li < a.nsh;
   const int e = in ? a.shlist[li] : 0;
   const int id = in ? a.mid[e] : -1;
@@ -178,7 +175,6 @@ __device__ void shared_mfma64_wg(Geo g, const int *__restrict__ xoff,
   const int ee = shared ? e : 0;
   const int ex = ee % g.n[0], r = ee / g.n[0];
   const int base = ex + g.gn[0] * ((r % g.n[1]) + g.gn[1] * (r / g.n[1]));
-  const int ld = a.ld, mi = a.m_in, mo = a.m_out, lds = mo + 1;   // column k holds mo rows
   double bv[KS];
 #pragma unroll
   for (int ks = 0; ks < KS; ++ks) {
@@ -187,54 +183,35 @@ __device__ void shared_mfma64_wg(Geo g, const int *__restrict__ xoff,
     bv[ks] = (shared && 4 * ks + kq < mi) ? v : 0.0;
   }
   const int nks = (mi + 3) / 4;
+  const int row = min(16 * rt + n, mo - 1);
+  const bool rowv = 16 * rt + n < mo;
   for (;;) {
-    // smallest pending class id in the workgroup
-    if (threadIdx.x == 0) s_next = 0x7fffffff;
-    __syncthreads();
-    if (todo) atomicMin(&s_next, id);
-    __syncthreads();
-    const int id0 = s_next;
-    if (id0 == 0x7fffffff) break;
-    const double *M0 = matS + (size_t)id0 * ld * ld;
-    for (int t = threadIdx.x; t < mi * mo; t += 256) {
-      const int k = t / mo, rr = t % mo;
-      Ms[k * lds + rr] = M0[(size_t)k * ld + rr];   // column k of the symmetric matrix
-    }
-    __syncthreads();
+    const unsigned long long msk = __ballot(todo);
+    if (msk == 0ull) break;
+    const int first = __ffsll((long long)msk) - 1;
+    const int id0 = __builtin_amdgcn_readfirstlane(__shfl(id, first));
     const bool mine = todo && id == id0;
     todo = todo && !mine;
-    if (__ballot(mine) != 0ull) {
-      for (int rt = 0; rt < 4; ++rt) {
-        if (16 * rt >= mo) break;
-        const int row = min(16 * rt + n, mo - 1);
-        doublex4 c = {0.0, 0.0, 0.0, 0.0};
+    const double *M0 = matS + (size_t)id0 * ld * ld;
+    double av[KS];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          if (ks < nks) {
-            const int k = min(4 * ks + kq, mi - 1);
-            const double av = (4 * ks + kq < mi && 16 * rt + n < mo) ? Ms[k * lds + row] : 0.0;
-            c = __builtin_amdgcn_mfma_f64_16x16x4f64(av, mine ? bv[ks] : 0.0, c, 0, 0, 0);
-          }
-        }
-        if (mine) {
+    for (int ks = 0; ks < KS; ++ks) {
+      const int k = min(4 * ks + kq, mi - 1);
+      const double v = M0[(size_t)k * ld + row];   // M[row][k] = M[k][row]
+      av[ks] = (4 * ks + kq < mi && rowv) ? v : 0.0;
+    }
+    doublex4 c = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int rr = 16 * rt + 4 * j + kq;
-            if (rr < mo) Ys[(size_t)rr * g.E + e] = c[j];
-          }
-        }
+    for (int ks = 0; ks < KS; ++ks)
+      if (ks < nks) c = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], mine ? bv[ks] : 0.0, c, 0, 0, 0);
+    if (mine) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int rr = 16 * rt + 4 * j + kq;
+        if (rr < mo) Ys[(size_t)rr * g.E + e] = c[j];
       }
     }
-    __syncthreads();
   }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void shared_mfma64_kernel(Geo g, const int *__restrict__ xoff,
-                                                            const double *__restrict__ matS,
-                                                            OpArgs<T> a, double *__restrict__ Ys) {
-  __shared__ double Ms[kLdsM];
-  shared_mfma64_wg<T>(g, xoff, matS, a, Ys, blockIdx.x, Ms);
 }
 
 // Phase C: owner gather.  One thread per output entry (grid point g, plane P)
@@ -321,7 +298,7 @@ void launch_elem_op(const Geo &g, const Tables &t, const OpArgs<T> &a, hipStream
     if (a.nstored > 0)
       stored_gemv_kernel<T><<<(a.nstored + 3) / 4, 256, 0, s>>>(g, t.xoff, a);
     if (a.nsh > 0)
-      shared_mfma64_kernel<T><<<(a.nsh + 63) / 64, 256, 0, s>>>(g, t.xoff, mS64, a, Ys);
+      shared_mfma64_kernel<T><<<(a.nsh + 15) / 16, 256, 0, s>>>(g, t.xoff, mS64, a, Ys);
     dim3 grid((g.G + 255) / 256, a.nP_out);
     gather_kernel<T, double><<<grid, 256, 0, s>>>(g, t.rows, t.pinfo, a, Ys);
     return;
