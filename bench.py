@@ -48,6 +48,64 @@ def cpu_baseline(n_sample=8):
                        f"x{scale:.1f} to the 32^3 workload")}
 
 
+def serve_bench(args):
+    """Serving stream: seeded requests of mixed grids and orders arriving as a
+    Poisson process, admitted by device-memory footprint and advanced together
+    (one CG iteration per tick); compared with one-at-a-time plain FP64 solves."""
+    import numpy as np
+    import torch
+    import fcm_inputs as fi
+    from paper_2010_00881_amd import Server, Solver
+
+    R = args.requests
+    reqs = [fi.serving_request(i) for i in range(R)]
+    arrivals = fi.arrival_times(args.rate, R)
+    print(f"[bench] serving {R} requests at {args.rate}/s", file=sys.stderr, flush=True)
+    srv = Server(memory_budget_bytes=int(args.budget_gb * (1 << 30)), max_active=args.slots,
+                 n_streams=4)
+    ids = []
+    t0 = time.perf_counter()
+    for i, (d, o) in enumerate(reqs):
+        now = time.perf_counter() - t0
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        ids.append((srv.submit(d, dict(o, precision="mixed")), time.perf_counter() - t0))
+    done = {}
+    while len(done) < R:
+        for k, (rid, ts) in enumerate(ids):
+            if k not in done:
+                r = srv.poll(rid, 0)
+                if r is not None:
+                    done[k] = (r, ts)
+        time.sleep(0.002)
+    srv.close()
+    lat = [done[k][0]["latency_ms"] for k in range(R)]
+    t_end = max(done[k][1] + done[k][0]["latency_ms"] / 1e3 for k in range(R))
+    failed = [k for k in range(R) if done[k][0]["status"] != 0]
+    served = R / t_end
+    print("[bench] one-at-a-time plain FP64", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    its = []
+    for d, o in reqs:
+        s = Solver(d, dict(o, precision="fp64", use_graphs=0))
+        _, info = s.pcg()
+        torch.cuda.synchronize()
+        its.append(info["iterations"])
+        s.close()
+    alone = R / (time.perf_counter() - t1)
+    out = {
+        "metric": "served MG-PCG solves/s (p50/p99 latency) vs one-at-a-time plain FP64",
+        "value": served, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "config": {"workload": f"serving_stream_{R}_requests", "rate_per_s": args.rate,
+                   "slots": args.slots, "budget_gb": args.budget_gb},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "one_at_a_time_fp64_solves_s": alone, "speedup": served / alone,
+        "failed_requests": failed, "iterations_fp64": its,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -58,11 +116,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="also time the plain FP64 form one problem at a time")
+    ap.add_argument("--workload", default="cube", choices=["cube", "serving"],
+                    help="cube: the 32^3 solve benchmark; serving: the request stream")
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=16)
+    ap.add_argument("--budget-gb", type=float, default=96.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
               "described in DESIGN.md and not built", file=sys.stderr)
         return 2
+
+    if args.workload == "serving":
+        return serve_bench(args)
 
     import torch
     import fcm_inputs as fi

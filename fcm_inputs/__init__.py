@@ -9,7 +9,7 @@ sharing any numerical code.
 Problem shapes follow the paper's examples: voided unit squares/cubes embedded
 in a uniform Cartesian grid (finite cell method, Section 2.1), Poisson and
 linear elasticity, integrated-Legendre tensor basis of order p, cut cells
-integrated by quadtree/octree subdivision (Section 4.4).
+integrated by quadtree/octree subdivision (Section 4.3.1).
 
 Draw order for every generator is fixed and documented below; changing it
 changes every downstream test case.

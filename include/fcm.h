@@ -10,7 +10,7 @@
  * where alpha = 1 in the physical domain and alpha = eps << 1 in the
  * fictitious part.  Poisson (one field, C = kappa I) or isotropic linear
  * elasticity (dim fields).  Cut cells are integrated by recursive bisection
- * (quadtree/octree, Section 4.4) with a (p+1)^d Gauss rule per leaf.
+ * (quadtree/octree, Section 4.3.1) with a (p+1)^d Gauss rule per leaf.
  * Homogeneous Dirichlet conditions are imposed strongly on grid-aligned box
  * faces; elements entirely outside the physical domain are dropped.
  *

@@ -6,7 +6,7 @@ Implements, in the plainest form:
   * the tensor-product integrated Legendre basis (Section 2.1);
   * cut-cell integration by recursive bisection of cut cells to a fixed depth,
     with a (p+1)^d Gauss rule on every leaf sub-cell and alpha evaluated per
-    point (quadtree/octree integration, Section 4.4);
+    point (quadtree/octree integration, Section 4.3.1);
   * strong homogeneous Dirichlet conditions on grid-aligned box faces
     (DOFs on those faces are removed), Neumann tractions on box faces;
   * elements entirely outside the physical domain are dropped, and so are the

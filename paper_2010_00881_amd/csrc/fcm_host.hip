@@ -109,8 +109,10 @@ template <typename T>
 static fcm_status upload(fcm_handle *h, T **p, const std::vector<T> &v) {
   fcm_status st = dalloc(h, p, v.size());
   if (st != FCM_OK) return st;
+  // ordered on the handle's stream (which may be non-blocking) and drained
+  // before v can go out of scope
+  FCM_HIP(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
   FCM_HIP(hipStreamSynchronize(h->stream));
-  FCM_HIP(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   return FCM_OK;
 }
 
@@ -498,7 +500,9 @@ static fcm_status setup_levels(fcm_handle *h) {
     }
     // unique blocks whose Jacobi-scaled condition number exceeds kKappa64 are
     // applied from their FP64 inverse inside the FP32 V-cycle
-    FCM_HIP(hipMemcpy(hk.data(), kappa, nblocks * sizeof(double), hipMemcpyDeviceToHost));
+    FCM_HIP(hipMemcpyAsync(hk.data(), kappa, nblocks * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
+    FCM_HIP(hipStreamSynchronize(h->stream));
     std::vector<uint8_t> fl(std::max(1, h->n_unique), 0);
     L.n_hi64 = 0;
     for (int u = 0; u < h->n_unique; ++u)
@@ -867,41 +871,45 @@ static void cg_issue_body(fcm_handle *h, CGState &cg, hipStream_t s) {
   hipMemcpyAsync(h->hscal, h->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s);
 }
 
-// One CG iteration.  With use_graphs, every iteration after the first is a
-// replay of a HIP graph captured once per (b, x) pair; the launches inside it
-// are the same as the eager ones and the graph holds no memset nodes.
+// Capture the steady-state CG iteration for (cg.b, cg.x) as a HIP graph on
+// stream s (not the legacy default stream).  Nothing is executed.  Callers
+// capture from the thread that owns the handle, before iterating.
+fcm_status cg_capture(fcm_handle *h, const CGState &cg, hipStream_t s) {
+  if (!h->opt.use_graphs || s == nullptr) return FCM_OK;
+  if (h->cg_exec && h->graph_x == cg.x && h->graph_b == cg.b) return FCM_OK;
+  if (h->cg_exec) {
+    hipGraphExecDestroy(h->cg_exec);
+    hipGraphDestroy(h->cg_graph);
+    h->cg_exec = nullptr;
+    h->cg_graph = nullptr;
+  }
+  CGState steady = cg;
+  steady.first = false;
+  FCM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  cg_issue_body(h, steady, s);
+  hipGraph_t gph = nullptr;
+  FCM_HIP(hipStreamEndCapture(s, &gph));
+  if (hipGraphInstantiate(&h->cg_exec, gph, nullptr, nullptr, 0) != hipSuccess) {
+    hipGraphDestroy(gph);
+    h->cg_exec = nullptr;
+    set_error("graph instantiation failed");
+    return FCM_ERR_HIP;
+  }
+  h->cg_graph = gph;
+  h->graph_x = cg.x;
+  h->graph_b = cg.b;
+  return FCM_OK;
+}
+
+// One CG iteration: the captured graph after the first iteration when one
+// exists for (b, x) (same launches as the eager body, no memset nodes).
 void cg_issue(fcm_handle *h, CGState &cg, hipStream_t s) {
-  if (!h->opt.use_graphs || cg.first || s == nullptr) {
-    cg_issue_body(h, cg, s);
+  if (h->opt.use_graphs && !cg.first && h->cg_exec && h->graph_x == cg.x &&
+      h->graph_b == cg.b && s != nullptr) {
+    hipGraphLaunch(h->cg_exec, s);
     return;
   }
-  if (!h->cg_exec || h->graph_x != cg.x || h->graph_b != cg.b) {
-    if (h->cg_exec) {
-      hipGraphExecDestroy(h->cg_exec);
-      hipGraphDestroy(h->cg_graph);
-      h->cg_exec = nullptr;
-    }
-    if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-      cg_issue_body(h, cg, s);
-      return;
-    }
-    cg_issue_body(h, cg, s);
-    hipGraph_t gph = nullptr;
-    if (hipStreamEndCapture(s, &gph) != hipSuccess || !gph) {
-      set_error("graph capture failed");
-      return;
-    }
-    if (hipGraphInstantiate(&h->cg_exec, gph, nullptr, nullptr, 0) != hipSuccess) {
-      hipGraphDestroy(gph);
-      h->cg_exec = nullptr;
-      cg_issue_body(h, cg, s);
-      return;
-    }
-    h->cg_graph = gph;
-    h->graph_x = cg.x;
-    h->graph_b = cg.b;
-  }
-  hipGraphLaunch(h->cg_exec, s);
+  cg_issue_body(h, cg, s);
 }
 
 void cg_finish(fcm_handle *h, CGState &cg) {
@@ -1176,10 +1184,13 @@ fcm_status fcm_element(const fcm_handle *h, int64_t e, int *state, double *K, do
   int kid = h->h_kmat[e];
   if (K && kid >= 0) {
     const double *src = kid == 0 ? h->Kref64 : h->Kcut64 + (size_t)(kid - 1) * m * m;
-    FCM_HIP(hipMemcpy(K, src, (size_t)m * m * sizeof(double), hipMemcpyDeviceToHost));
+    FCM_HIP(hipMemcpyAsync(K, src, (size_t)m * m * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
   }
   if (be && kid >= 0)
-    FCM_HIP(hipMemcpy(be, h->be + (size_t)e * m, (size_t)m * sizeof(double), hipMemcpyDeviceToHost));
+    FCM_HIP(hipMemcpyAsync(be, h->be + (size_t)e * m, (size_t)m * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream));
+  FCM_HIP(hipStreamSynchronize(h->stream));
   return FCM_OK;
 }
 
@@ -1273,6 +1284,10 @@ fcm_status fcm_pcg_solve(fcm_handle *h, const double *b_dev, double *x_dev, fcm_
   CGState cg;
   fcm_status st = cg_begin(h, cg, b_dev, x_dev, s);
   if (st < 0) return st;
+  if (h->opt.use_graphs && !cg.done) {
+    st = cg_capture(h, cg, s);
+    if (st < 0) return st;
+  }
   while (!cg.done) {
     cg_issue(h, cg, s);
     FCM_HIP(hipStreamSynchronize(s));

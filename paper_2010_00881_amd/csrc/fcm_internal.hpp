@@ -258,6 +258,7 @@ struct CGState {
 };
 fcm_status cg_begin(fcm_handle *h, CGState &cg, const double *b_dev, double *x, hipStream_t s);
 void cg_issue(fcm_handle *h, CGState &cg, hipStream_t s);
+fcm_status cg_capture(fcm_handle *h, const CGState &cg, hipStream_t s);
 void cg_finish(fcm_handle *h, CGState &cg);
 fcm_status cg_report(fcm_handle *h, CGState &cg, fcm_solve_info *info, hipStream_t s);
 int64_t footprint_estimate(const fcm_problem &p);

@@ -2,7 +2,7 @@
 //
 //  classify        element state from ball/box tests (Section 2.1)
 //  integrate       cut-cell stiffness and load by recursive bisection of cut
-//                  cells (Section 4.4); uncut sub-cells use separable closed
+//                  cells (Section 4.3.1); uncut sub-cells use separable closed
 //                  forms, cut leaf sub-cells a (p+1)^d Gauss rule with alpha
 //                  per point (eq. weakform)
 //  phys/traction   loads of uncut elements and of box-face tractions

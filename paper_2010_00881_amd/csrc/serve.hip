@@ -1,14 +1,15 @@
 // Serving loop of libfcm: continuous batching of MG-PCG solves on one GPU.
 //
-// Two host threads share the device:
-//  * admission: takes pending requests in arrival order and, while a batch
-//    slot is free and the estimated device footprint of the request fits the
-//    memory budget next to the hierarchies already resident, builds its
-//    hierarchy (fcm_setup) on the admission stream;
-//  * ticks: every tick enqueues one CG iteration (V-cycle, apply, fused
-//    updates) for every active solve, spread over several streams, then waits
-//    and retires the solves that converged.  Requests join and leave between
-//    ticks, so solves of different grids and orders overlap on the device.
+// Host threads share the device:
+//  * admission (two threads): take pending requests in arrival order and,
+//    while a batch slot is free and the estimated device footprint of the
+//    request fits the memory budget next to the hierarchies already resident,
+//    build its hierarchy (fcm_setup) on their own admission stream;
+//  * ticks: each active solve has one CG iteration (V-cycle, apply, fused
+//    updates; a captured graph after the first) in flight on one of several
+//    streams; when its completion event fires, the iteration is finished on
+//    the host and the next one issued.  Requests join and leave at any time,
+//    so solves of different grids and orders overlap on the device.
 // Results are copied to host memory when a solve retires and its hierarchy is
 // freed at once, returning its footprint to the budget.
 #include <atomic>
@@ -19,6 +20,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <shared_mutex>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -97,6 +100,9 @@ struct Request {
   std::vector<double> hist;
   int64_t footprint = 0;
   double t_solve_start_ms = 0.0;
+  hipEvent_t ev = nullptr;     // completion of the iteration in flight
+  bool inflight = false;
+  std::string err;             // error text of a failed request
 };
 
 }  // namespace
@@ -113,8 +119,12 @@ struct fcm_server {
   int64_t resident = 0;          // bytes of admitted hierarchies (estimates until set up)
   int n_admitting = 0;
   std::vector<hipStream_t> streams;
-  hipStream_t setup_stream = nullptr;
-  std::thread admit_thr, tick_thr;
+  hipStream_t setup_stream[2] = {nullptr, nullptr};
+  std::thread admit_thr[2], tick_thr;
+  // Graph captures run alone: setup work and ticks hold this lock shared,
+  // a capture holds it exclusively (capture must not overlap synchronous
+  // allocation or copy calls of other threads).
+  std::shared_mutex hip_mu;
   int device = 0;
 };
 
@@ -141,8 +151,9 @@ static void finish_request(fcm_server *s, std::shared_ptr<Request> &r, hipStream
   r->h = nullptr;
 }
 
-static void admission_loop(fcm_server *s) {
+static void admission_loop(fcm_server *s, int which) {
   hipSetDevice(s->device);
+  hipStream_t setup_stream = s->setup_stream[which];
   for (;;) {
     std::shared_ptr<Request> r;
     {
@@ -162,7 +173,9 @@ static void admission_loop(fcm_server *s) {
       s->n_admitting++;
     }
     fcm_handle *h = nullptr;
-    fcm_status st = fcm_setup(&r->pr, &r->opt, s->setup_stream, &h);
+    std::shared_lock<std::shared_mutex> hl(s->hip_mu);
+    fcm_status st = fcm_setup(&r->pr, &r->opt, setup_stream, &h);
+    if (st < 0) r->err = fcm_last_error();
     double *x = nullptr;
     if (st == FCM_OK) {
       const int64_t n = h->lev[h->L].npad;
@@ -174,14 +187,25 @@ static void admission_loop(fcm_server *s) {
       r->h = h;
       r->x = x;
       r->stream = (int)(r->id % s->streams.size());
-      hipStream_t hs = s->streams[r->stream];
-      st = cg_begin(h, r->cg, nullptr, x, hs);
+      // the first CG steps run on the admission stream (never on a tick stream,
+      // which the tick thread may be capturing a graph on)
+      st = cg_begin(h, r->cg, nullptr, x, setup_stream);
+      hl.unlock();
+      if (st >= 0 && !r->cg.done) {
+        std::unique_lock<std::shared_mutex> xl(s->hip_mu);
+        st = cg_capture(h, r->cg, setup_stream);
+      }
+      hl.lock();
+      if (st < 0) r->err = fcm_last_error();
+      if (st >= 0 && hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess)
+        st = FCM_ERR_HIP;
       r->t_solve_start_ms = std::chrono::duration<double, std::milli>(
                                 std::chrono::steady_clock::now() - r->t_submit)
                                 .count();
     } else if (h) {
       fcm_destroy(h);
     }
+    hl.unlock();
     std::lock_guard<std::mutex> lk(s->mu);
     s->n_admitting--;
     if (st < 0) {
@@ -203,6 +227,10 @@ static void admission_loop(fcm_server *s) {
   }
 }
 
+// Ticks: each active solve has at most one CG iteration in flight, followed
+// by an event.  As soon as a solve's event has completed its iteration is
+// finished on the host and the next one issued, so small and large solves
+// progress at their own pace while sharing the device.
 static void tick_loop(fcm_server *s) {
   hipSetDevice(s->device);
   for (;;) {
@@ -213,19 +241,40 @@ static void tick_loop(fcm_server *s) {
       if (s->stop) return;
       batch = s->active;
     }
-    // issue one CG iteration for every active solve, then wait for all
-    for (auto &r : batch)
-      if (!r->cg.done) cg_issue(r->h, r->cg, s->streams[r->stream]);
-    for (auto st : s->streams) hipStreamSynchronize(st);
+    bool progressed = false;
     std::vector<std::shared_ptr<Request>> retired;
+    std::shared_lock<std::shared_mutex> hl(s->hip_mu);
     for (auto &r : batch) {
-      if (!r->cg.done) cg_finish(r->h, r->cg);
-      if (r->cg.done) retired.push_back(r);
+      hipStream_t st = s->streams[r->stream];
+      if (r->inflight) {
+        const hipError_t q = hipEventQuery(r->ev);
+        if (q == hipErrorNotReady) continue;
+        r->inflight = false;
+        progressed = true;
+        if (q != hipSuccess) {
+          r->cg.done = true;
+          r->cg.status = FCM_ERR_HIP;
+          set_error("device error in a CG iteration: %s", hipGetErrorString(q));
+        } else {
+          cg_finish(r->h, r->cg);
+        }
+      }
+      if (r->cg.done) {
+        retired.push_back(r);
+        continue;
+      }
+      cg_issue(r->h, r->cg, st);
+      hipEventRecord(r->ev, st);
+      r->inflight = true;
+      progressed = true;
     }
     for (auto &r : retired) {
       r->status = (fcm_status)r->cg.status;
+      if (r->status < 0) r->err = fcm_last_error();
       int64_t fp = r->footprint;
       finish_request(s, r, s->streams[r->stream]);
+      if (r->ev) hipEventDestroy(r->ev);
+      r->ev = nullptr;
       std::lock_guard<std::mutex> lk(s->mu);
       r->done = true;
       s->resident -= fp;
@@ -236,6 +285,8 @@ static void tick_loop(fcm_server *s) {
         }
       s->cv.notify_all();
     }
+    hl.unlock();
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(50));
   }
 }
 
@@ -255,11 +306,12 @@ fcm_status fcm_server_create(const fcm_server_opts *o, fcm_server **out) {
       set_error("stream creation failed");
       return FCM_ERR_HIP;
     }
-  if (hipStreamCreateWithFlags(&s->setup_stream, hipStreamNonBlocking) != hipSuccess) {
-    set_error("stream creation failed");
-    return FCM_ERR_HIP;
-  }
-  s->admit_thr = std::thread(admission_loop, s);
+  for (int k = 0; k < 2; ++k)
+    if (hipStreamCreateWithFlags(&s->setup_stream[k], hipStreamNonBlocking) != hipSuccess) {
+      set_error("stream creation failed");
+      return FCM_ERR_HIP;
+    }
+  for (int k = 0; k < 2; ++k) s->admit_thr[k] = std::thread(admission_loop, s, k);
   s->tick_thr = std::thread(tick_loop, s);
   *out = s;
   return FCM_OK;
@@ -324,6 +376,7 @@ fcm_status fcm_serve_poll(fcm_server *s, uint64_t req_id, int *done, double *x_h
   }
   if (latency_ms)
     *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+  if (r->status < 0) set_error("request %llu: %s", (unsigned long long)req_id, r->err.c_str());
   return r->status;
 }
 
@@ -334,14 +387,18 @@ fcm_status fcm_server_destroy(fcm_server *s) {
     s->stop = true;
     s->cv.notify_all();
   }
-  if (s->admit_thr.joinable()) s->admit_thr.join();
+  for (int k = 0; k < 2; ++k)
+    if (s->admit_thr[k].joinable()) s->admit_thr[k].join();
   if (s->tick_thr.joinable()) s->tick_thr.join();
   for (auto &r : s->active) {
+    if (r->inflight && r->ev) hipEventSynchronize(r->ev);
+    if (r->ev) hipEventDestroy(r->ev);
     if (r->x) hipFree(r->x);
     if (r->h) fcm_destroy(r->h);
   }
   for (auto st : s->streams) hipStreamDestroy(st);
-  if (s->setup_stream) hipStreamDestroy(s->setup_stream);
+  for (int k = 0; k < 2; ++k)
+    if (s->setup_stream[k]) hipStreamDestroy(s->setup_stream[k]);
   delete s;
   return FCM_OK;
 }

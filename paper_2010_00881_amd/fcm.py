@@ -375,6 +375,8 @@ class Server:
         d["status"] = st
         d["latency_ms"] = lat.value
         d["x"] = x
+        if st < 0:
+            d["error"] = lib().fcm_last_error().decode()
         return d
 
     def close(self):
