@@ -6,8 +6,9 @@ Follows Section 3 of the paper:
     of A (eq. hierarchicalMatrices); restriction keeps the prefix and
     prolongation zero-extends it (eq. restrictionoperation);
   * additive Schwarz smoother M_l^{-1} = sum_i P_i (P_i^T A_l P_i)^{-1} P_i^T
-    (eq. AdditiveSchwarz) with elementwise blocks: block i = all level-l DOFs
-    supported on kept element i (Section 3.3.1);
+    (eq. AdditiveSchwarz) with elementwise blocks (block i = all level-l DOFs
+    supported on kept element i) or patchwise blocks (block v = all level-l
+    DOFs supported on the kept elements around grid node v), Section 3.3.1;
   * damped update x <- x + omega M^{-1} r (Section 3.1); the residual is
     recomputed after every smoothing step;
   * V-cycle of Alg. 1 with n_s pre- and post-smoothing steps, exact solve on
@@ -18,9 +19,38 @@ Follows Section 3 of the paper:
 """
 from __future__ import annotations
 
+import itertools
+
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse.linalg as spla
+
+
+def block_sets(disc, n_l, smoother="elementwise"):
+    """Index sets of the Schwarz blocks of a level with n_l DOFs (Section 3.3.1).
+
+    elementwise: one block per kept element, the level DOFs nonzero on it;
+    patchwise: one block per grid node v, the level DOFs nonzero on any kept
+    element among the 2^d elements that share v (a node whose elements are
+    all void has no block).
+    """
+    ed = disc.elem_dofs
+    if smoother != "patchwise":
+        for k in range(ed.shape[0]):
+            dofs = ed[k]
+            yield np.sort(dofs[(dofs >= 0) & (dofs < n_l)])
+        return
+    row = {tuple(int(c) for c in disc.kept_idx[k]): k for k in range(disc.kept.size)}
+    d = disc.dim
+    for v in itertools.product(*[range(int(nc) + 1) for nc in disc.n[::-1]]):
+        v = v[::-1]                                   # axis 0 fastest
+        around = [tuple(v[a] - s[a] for a in range(d))
+                  for s in itertools.product((0, 1), repeat=d)]
+        ks = [row[c] for c in around if c in row]
+        if not ks:
+            continue
+        dofs = np.concatenate([ed[k] for k in ks])
+        yield np.unique(dofs[(dofs >= 0) & (dofs < n_l)])
 
 
 class Hierarchy:
@@ -40,14 +70,14 @@ class Hierarchy:
         self._build_coarse()
 
     # ------------------------------------------------------------- smoother
+    def block_sets(self, l):
+        return block_sets(self.disc, self.sizes[l], self.opts.get("smoother", "elementwise"))
+
     def _build_blocks(self, l):
-        """Dense inverse of P_i^T A_l P_i for every kept element (grouped by size)."""
-        n_l = self.sizes[l]
+        """Dense inverse of P_i^T A_l P_i for every block (grouped by size)."""
         Al = self.As[l]
         groups = {}
-        for k in range(self.disc.elem_dofs.shape[0]):
-            dofs = self.disc.elem_dofs[k]
-            I = np.sort(dofs[(dofs >= 0) & (dofs < n_l)])
+        for I in self.block_sets(l):
             if I.size == 0:
                 continue
             Ai = Al[I][:, I].toarray()

@@ -378,3 +378,122 @@ def test_p12_block_sizes_match_paper_formula():
             desc = _uncut(3, 2, p, nf=3)
             disc = fcm.Discretization(desc, assemble=False)
             assert disc.m == m
+
+
+# ------------------------------------------------- P13 patchwise Schwarz blocks
+def _patch_opts(dim):
+    return fi.default_options(dim, smoother="patchwise")
+
+
+def test_p13_patch_block_sizes_match_paper_formula():
+    """Table tab::upperbound with n = 2 (patchwise): m_max = n_f (2p + 1)^3."""
+    path = __file__.replace("test_oracle_pins.py", "golden/upperbound_tensor_patch.txt")
+    rows = [r.split() for r in open(path).read().split("\n") if r and not r.startswith("#")]
+    for nf_s, p_s, m_s in rows:
+        nf, p, m = int(nf_s), int(p_s), int(m_s)
+        assert m == nf * (2 * p + 1) ** 3
+        if (nf == 1 and p <= 3) or (nf == 3 and p <= 2):
+            disc = fcm.Discretization(_uncut(3, 4, p, nf=nf, faces=0), assemble=False)
+            sizes = [I.size for I in mg.block_sets(disc, disc.n_dofs, "patchwise")]
+            assert max(sizes) == m
+            # 2^d elements around an interior node; corner nodes see one element
+            assert min(sizes) == nf * (p + 1) ** 3
+
+
+def test_p13_patch_blocks_hold_the_functions_nonzero_near_the_node():
+    """Brute force: block v = the DOFs whose basis function is nonzero at some
+    point of a kept element touching grid node v (sampled geometrically)."""
+    desc, _ = fi.plate_with_hole(0, n=4, p=2)
+    disc = fcm.Discretization(desc, assemble=False)
+    N = disc.n_dofs
+    rng = np.random.default_rng(5)
+    blocks = list(mg.block_sets(disc, N, "patchwise"))
+    nodes = [(i, j) for j in range(5) for i in range(5)]
+    kept = {tuple(int(c) for c in k) for k in disc.kept_idx}
+    it = iter(blocks)
+    for (i, j) in nodes:
+        cells = [(i - a, j - b) for a in (0, 1) for b in (0, 1) if (i - a, j - b) in kept]
+        if not cells:
+            continue
+        I = next(it)
+        pts = []
+        for (cx, cy) in cells:
+            u = rng.uniform(0.05, 0.95, (12, 2))
+            pts.append(disc.lo + (np.array([cx, cy]) + u) * disc.h)
+        pts = np.vstack(pts)
+        nz = []
+        for k in range(N):
+            e = np.zeros(N)
+            e[k] = 1.0
+            if np.abs(disc.evaluate(e, pts)).max() > 1e-12:
+                nz.append(k)
+        assert np.array_equal(I, np.array(nz)), (i, j)
+    assert next(it, None) is None
+
+
+def test_p13_single_element_patches():
+    """One element: each of its 2^d nodes has the whole element as its patch, so
+    M^-1 = 2^d A^-1 exactly."""
+    desc = _uncut(2, 1, 3, faces=0b0001)
+    disc = fcm.Discretization(desc)
+    h = mg.Hierarchy(disc, _patch_opts(2))
+    A = h.As[h.L].toarray()
+    Minv = np.column_stack([h.smooth(h.L, e) for e in np.eye(A.shape[0])])
+    assert np.allclose(Minv @ A, 4.0 * np.eye(A.shape[0]), atol=1e-10)
+
+
+def test_p13_patch_overlap_and_eigenvalue_bound():
+    """A vertex function lies in 3^d node patches.  The A-projection onto block v
+    is bounded by the energy on the union of its functions' supports (the 4^d
+    elements v-2..v+1 per axis), and every element lies in 4^d such unions, so
+    lambda_max(M^-1 A) <= 4^d.  The paper's patchwise relaxation (Section 3.3.2)
+    keeps omega*lambda_max < 2 here."""
+    for desc, opts in [(fi.plate_with_hole(0, n=8, p=2)[0], _patch_opts(2)),
+                       (fi.voided_cube_poisson(0, n=4, p=2)[0], _patch_opts(3))]:
+        disc = fcm.Discretization(desc)
+        h = mg.Hierarchy(disc, opts)
+        L = h.L
+        count = np.zeros(h.sizes[L], dtype=int)
+        for I in mg.block_sets(disc, h.sizes[L], "patchwise"):
+            count[I] += 1
+        assert count.max() == 3 ** disc.dim
+        A = h.As[L]
+        x = np.random.default_rng(1).standard_normal(A.shape[0])
+        lam = 0.0
+        for _ in range(300):
+            y = h.smooth(L, A @ x)
+            lam = np.linalg.norm(y) / np.linalg.norm(x)
+            x = y / np.linalg.norm(y)
+        assert 1.0 < lam <= 4 ** disc.dim * (1 + 1e-8)
+        assert opts["omega"] * lam < 2.0
+
+
+def test_p13_patchwise_vcycle_symmetric():
+    """Symmetric up to rounding; the explicit inverses of strongly cut patch
+    blocks (alpha = 1e-8) carry relative asymmetries of order kappa * eps."""
+    desc, _ = fi.plate_with_hole(0, n=8, p=3)
+    disc = fcm.Discretization(desc)
+    h = mg.Hierarchy(disc, _patch_opts(2))
+    rng = np.random.default_rng(4)
+    x, y = rng.standard_normal((2, disc.n_dofs))
+    Vx, Vy = h.precondition(x), h.precondition(y)
+    assert abs(x @ Vy - y @ Vx) <= 1e-8 * abs(x @ Vy)
+    assert x @ Vx > 0
+
+
+def test_p13_patchwise_robust_on_cut_cells():
+    """Section 4.1: patchwise blocks treat the small cut-cell modes, giving
+    h-independent counts; the voided cube needs far fewer iterations than with
+    elementwise blocks."""
+    its = []
+    for n in [8, 16, 32]:
+        desc, _ = fi.plate_with_hole(0, n=n, p=2)
+        disc = fcm.Discretization(desc)
+        _, it, _ = mg.Hierarchy(disc, _patch_opts(2)).pcg(disc.b, rtol=1e-9)
+        its.append(it)
+    assert max(its) - min(its) <= 1 and max(its) <= 8, its
+    desc, eopts = fi.voided_cube_poisson(0, n=5, p=2)
+    disc = fcm.Discretization(desc)
+    _, it_p, _ = mg.Hierarchy(disc, _patch_opts(3)).pcg(disc.b)
+    _, it_e, _ = mg.Hierarchy(disc, eopts).pcg(disc.b)
+    assert it_p <= 10 and it_p < it_e, (it_p, it_e)
