@@ -71,7 +71,7 @@ typedef enum {
 
 enum { FCM_GEOM_BOX_MINUS_BALLS = 0, FCM_GEOM_BALL_INTERIOR = 1 };
 enum { FCM_FP64 = 0, FCM_MIXED = 1 };           /* V-cycle precision           */
-enum { FCM_SMOOTH_ELEMENTWISE = 0 };             /* additive Schwarz blocks     */
+enum { FCM_SMOOTH_ELEMENTWISE = 0, FCM_SMOOTH_PATCHWISE = 1 };  /* Schwarz blocks */
 
 typedef struct fcm_handle fcm_handle;
 typedef struct fcm_server fcm_server;
@@ -105,8 +105,13 @@ typedef struct {
 
 /* Solver options (Sections 3.3.2 and 4). */
 typedef struct {
-  int smoother;               /* FCM_SMOOTH_ELEMENTWISE                          */
-  double omega;               /* relaxation; 1/3 (2D) or 2/15 (3D) for elementwise */
+  int smoother;               /* FCM_SMOOTH_ELEMENTWISE: one block per kept element,
+                                 all functions nonzero on it; FCM_SMOOTH_PATCHWISE:
+                                 one block per grid node, all functions nonzero on
+                                 the kept elements sharing it (Section 3.3.1); the
+                                 patch size n_f (2p+1)^d must not exceed 512      */
+  double omega;               /* relaxation (Section 3.3.2): elementwise 1/3 (2D),
+                                 2/15 (3D); patchwise 1/6 (2D), 1/18 (3D)         */
   int n_pre, n_post;          /* smoothing steps per level (5 and 5 in the paper) */
   int precision;              /* FCM_FP64 or FCM_MIXED (FP32 V-cycle)            */
   double rtol;                /* ||r||/||b|| stopping tolerance                  */
@@ -126,8 +131,9 @@ typedef struct {
 } fcm_solve_info;
 
 /* Build the discretisation and the whole multigrid hierarchy on the device:
- * cell classification, cut-cell integration, RHS, elementwise Schwarz block
- * inverses for every level >= 1 and the exact factorisation of level 0.
+ * cell classification, cut-cell integration, RHS, Schwarz block inverses
+ * (elementwise or patchwise) for every level >= 1 and the exact factorisation
+ * of level 0.
  * On success *out owns all device memory.  Errors: FCM_ERR_ARG (invalid
  * problem/options), FCM_ERR_OOM, FCM_ERR_HIP, FCM_ERR_NOT_SPD (a Schwarz block
  * or the coarse matrix lost positive definiteness in FP64).                 */

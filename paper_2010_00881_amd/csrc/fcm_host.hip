@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fcm_internal.hpp"
@@ -182,14 +183,55 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
   }
   if (!(o->omega > 0.0) || o->n_pre < 0 || o->n_post < 0 || o->max_iter < 0 ||
       !(o->rtol >= 0.0) || (o->precision != FCM_FP64 && o->precision != FCM_MIXED) ||
-      o->smoother != FCM_SMOOTH_ELEMENTWISE) {
+      (o->smoother != FCM_SMOOTH_ELEMENTWISE && o->smoother != FCM_SMOOTH_PATCHWISE)) {
     set_error("invalid options");
     return FCM_ERR_ARG;
+  }
+  if (o->smoother == FCM_SMOOTH_PATCHWISE) {
+    int mpatch = p->n_fields;
+    for (int ax = 0; ax < p->dim; ++ax) mpatch *= 2 * p->p + 1;
+    if (mpatch > kMaxPatchM) {
+      set_error("patchwise blocks of size %d exceed the supported %d (n_f (2p+1)^d)", mpatch,
+                kMaxPatchM);
+      return FCM_ERR_ARG;
+    }
   }
   return FCM_OK;
 }
 
 // --------------------------------------------------------------- tables
+static void plane_types(const fcm_handle *h, std::vector<int> &pt) {
+  const Geo &g = h->geo;
+  const int p = g.p, d = g.d, nf = g.nf;
+  pt.clear();
+  for (int s = 1; s <= p; ++s)
+    for (int t2 = 0; t2 < (d == 3 ? p : 1); ++t2)
+      for (int t1 = 0; t1 < p; ++t1)
+        for (int t0 = 0; t0 < p; ++t0) {
+          int dg = std::max(tdeg(t0), tdeg(t1));
+          if (d == 3) dg = std::max(dg, tdeg(t2));
+          if (dg != s) continue;
+          for (int c = 0; c < nf; ++c) {
+            pt.push_back(t0);
+            pt.push_back(t1);
+            pt.push_back(t2);
+            pt.push_back(c);
+          }
+        }
+}
+
+
+// Per-axis slot of a patch-local mode (see kernels_patch.hip): slot 0 / p / 2p
+// are the hats at nodes v-1 / v / v+1, slots 1..p-1 and p+1..2p-1 the bubbles
+// of elements v-1 and v.
+static void patch_slot_host(int sl, int p, int &t, int &dl) {
+  if (sl == 0) { t = 0; dl = -1; }
+  else if (sl < p) { t = sl; dl = -1; }
+  else if (sl == p) { t = 0; dl = 0; }
+  else if (sl < 2 * p) { t = sl - p; dl = 0; }
+  else { t = 0; dl = 1; }
+}
+
 static fcm_status build_tables(fcm_handle *h) {
   const Geo &g = h->geo;
   const int d = g.d, nf = g.nf, p = g.p, np = p + 1;
@@ -516,6 +558,250 @@ static fcm_status setup_levels(fcm_handle *h) {
   return check_flag(h, "Schwarz block inversion");
 }
 
+// ------------------------------------------------------- patchwise blocks
+// Patch-local modes at order p, degree-sorted (level q = prefix), with their
+// vector offsets, element masks and the owner-gather row table.
+static fcm_status build_patch_tables(fcm_handle *h) {
+  const Geo &g = h->geo;
+  const int d = g.d, nf = g.nf, p = g.p, S = 2 * p + 1;
+  std::vector<int> pt;
+  plane_types(h, pt);
+  const int nP = (int)pt.size() / 4;
+  std::map<int, int> pidx;
+  for (int P = 0; P < nP; ++P)
+    pidx[((pt[4 * P] + p * (pt[4 * P + 1] + p * pt[4 * P + 2])) * nf) + pt[4 * P + 3]] = P;
+  auto sdeg = [&](int sl) {
+    int t, dl;
+    patch_slot_host(sl, p, t, dl);
+    return t == 0 ? 1 : t + 1;
+  };
+  std::vector<int> pm;
+  std::map<int, int> kmap;
+  for (int q = 1; q <= p; ++q)
+    for (int s2 = (d == 3 ? 0 : p); s2 <= (d == 3 ? 2 * p : p); ++s2)
+      for (int s1 = 0; s1 < S; ++s1)
+        for (int s0 = 0; s0 < S; ++s0) {
+          int dg = std::max(sdeg(s0), sdeg(s1));
+          if (d == 3) dg = std::max(dg, sdeg(s2));
+          if (dg != q) continue;
+          for (int c = 0; c < nf; ++c) {
+            kmap[((s0 + S * (s1 + S * s2)) * nf) + c] = (int)pm.size() / 4;
+            pm.push_back(s0);
+            pm.push_back(s1);
+            pm.push_back(s2);
+            pm.push_back(c);
+          }
+        }
+  const int m = (int)pm.size() / 4;
+  h->ptab.m = m;
+  std::vector<int> pxoff(m), pinfo(m);
+  for (int k = 0; k < m; ++k) {
+    int t[3] = {0, 0, 0}, dl[3] = {0, 0, 0};
+    for (int ax = 0; ax < d; ++ax) patch_slot_host(pm[4 * k + ax], p, t[ax], dl[ax]);
+    const int P = pidx.at(((t[0] + p * (t[1] + p * t[2])) * nf) + pm[4 * k + 3]);
+    pxoff[k] = P * g.G + dl[0] + g.gn[0] * (dl[1] + g.gn[1] * dl[2]);
+    int info = 0;
+    for (int sm = 0; sm < (1 << d); ++sm) {
+      bool ok = true;
+      for (int ax = 0; ax < d; ++ax) {
+        const int rel = -((sm >> ax) & 1);
+        const int lo = t[ax] == 0 ? dl[ax] - 1 : dl[ax], hi = dl[ax];
+        ok = ok && rel >= lo && rel <= hi;
+      }
+      if (ok) info |= 1 << sm;
+    }
+    for (int ax = 0; ax < d; ++ax) {
+      if (t[ax] == 0) info |= 1 << (8 + ax);
+      info |= (dl[ax] + 1) << (12 + 2 * ax);
+    }
+    pinfo[k] = info;
+  }
+  std::vector<int> prow((size_t)nP * 27, -1);
+  const int ncb = d == 3 ? 27 : 9;
+  for (int P = 0; P < nP; ++P)
+    for (int cb = 0; cb < ncb; ++cb) {
+      const int dl[3] = {cb % 3 - 1, (cb / 3) % 3 - 1, d == 3 ? cb / 9 - 1 : 0};
+      int sl[3] = {p, p, p};
+      bool ok = true;
+      for (int ax = 0; ax < d; ++ax) {
+        const int t = pt[4 * P + ax];
+        if (t == 0) sl[ax] = dl[ax] == -1 ? 0 : (dl[ax] == 0 ? p : 2 * p);
+        else if (dl[ax] == 1) ok = false;
+        else sl[ax] = dl[ax] == -1 ? t : p + t;
+      }
+      if (!ok) continue;
+      prow[(size_t)P * 27 + cb] = kmap.at(((sl[0] + S * (sl[1] + S * sl[2])) * nf) + pt[4 * P + 3]);
+    }
+  TRY(upload(h, &h->ptab.pm, pm));
+  TRY(upload(h, &h->ptab.pxoff, pxoff));
+  TRY(upload(h, &h->ptab.pinfo, pinfo));
+  TRY(upload(h, &h->ptab.prow, prow));
+  return FCM_OK;
+}
+
+// Patches: grid nodes with at least one kept element around them.  A patch
+// whose functions touch only uncut elements (the 4^d elements v-2..v+1 per
+// axis) has a block that depends only on its position relative to the box
+// faces and shares one inverse per class; all others are unique.
+static fcm_status build_patches(fcm_handle *h, std::vector<int> &bnode, std::vector<int> &bkm) {
+  const Geo &g = h->geo;
+  const int d = g.d;
+  std::vector<int> km(g.G, 0), key(g.G, -1);
+  for (int z = 0; z < g.gn[2]; ++z)
+    for (int y = 0; y < g.gn[1]; ++y)
+      for (int x = 0; x < g.gn[0]; ++x) {
+        const int v[3] = {x, y, z};
+        const int node = x + g.gn[0] * (y + g.gn[1] * z);
+        int mask = 0;
+        for (int sm = 0; sm < (1 << d); ++sm) {
+          int ec[3] = {0, 0, 0};
+          bool in = true;
+          for (int ax = 0; ax < d; ++ax) {
+            ec[ax] = v[ax] - ((sm >> ax) & 1);
+            in = in && ec[ax] >= 0 && ec[ax] < g.n[ax];
+          }
+          if (in && h->h_state[elin(g, ec[0], ec[1], ec[2])] != kVoid) mask |= 1 << sm;
+        }
+        km[node] = mask;
+        if (!mask) continue;
+        int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+        for (int ax = 0; ax < d; ++ax) {
+          lo[ax] = std::max(0, v[ax] - 2);
+          hi[ax] = std::min(g.n[ax] - 1, v[ax] + 1);
+        }
+        bool shared = true;
+        for (int ez = lo[2]; ez <= hi[2] && shared; ++ez)
+          for (int ey = lo[1]; ey <= hi[1] && shared; ++ey)
+            for (int ex = lo[0]; ex <= hi[0] && shared; ++ex)
+              if (h->h_state[elin(g, ex, ey, ez)] != kPhys) shared = false;
+        if (!shared) continue;
+        int k = 0;
+        for (int ax = d - 1; ax >= 0; --ax)
+          k = 9 * k + 3 * std::min(v[ax], 2) + std::min(g.n[ax] - v[ax], 2);
+        key[node] = k;
+      }
+  std::map<int, int> cls;
+  std::vector<std::vector<int>> members;
+  std::vector<int> uniq;
+  for (int node = 0; node < g.G; ++node) {
+    if (!km[node]) continue;
+    if (key[node] < 0) {
+      uniq.push_back(node);
+      continue;
+    }
+    auto it = cls.find(key[node]);
+    if (it == cls.end()) {
+      cls[key[node]] = (int)members.size();
+      members.emplace_back();
+      members.back().push_back(node);
+    } else {
+      members[it->second].push_back(node);
+    }
+  }
+  std::vector<int> pnode, pkm, pcls, pid(g.G, -1);
+  for (size_t c = 0; c < members.size(); ++c)
+    for (int node : members[c]) {
+      pid[node] = (int)pnode.size();
+      pnode.push_back(node);
+      pkm.push_back(km[node]);
+      pcls.push_back((int)c);
+    }
+  h->np_shared = (int)pnode.size();
+  h->np_classes = (int)members.size();
+  for (int node : uniq) {
+    pid[node] = (int)pnode.size();
+    pnode.push_back(node);
+    pkm.push_back(km[node]);
+  }
+  h->np_unique = (int)uniq.size();
+  bnode.clear();
+  bkm.clear();
+  for (auto &mem : members) {
+    bnode.push_back(mem[0]);
+    bkm.push_back(km[mem[0]]);
+  }
+  for (int node : uniq) {
+    bnode.push_back(node);
+    bkm.push_back(km[node]);
+  }
+  h->h_pnode = pnode;
+  h->h_pkm = pkm;
+  if (pnode.empty()) {
+    pnode.push_back(0);
+    pkm.push_back(0);
+  }
+  if (pcls.empty()) pcls.push_back(0);
+  TRY(upload(h, &h->pnode, pnode));
+  TRY(upload(h, &h->pkm, pkm));
+  TRY(upload(h, &h->pcls, pcls));
+  TRY(upload(h, &h->pid, pid));
+  return FCM_OK;
+}
+
+// Form and invert the patch blocks of every level >= 1 (FP64, Jacobi-scaled
+// Gauss-Jordan sweep) in chunks, stored as m x ld (ld = m rounded up to 4).
+static fcm_status setup_patch_levels(fcm_handle *h, const std::vector<int> &bnode,
+                                     const std::vector<int> &bkm) {
+  const Geo &g = h->geo;
+  const bool mixed = h->opt.precision == FCM_MIXED;
+  const int nblocks = (int)bnode.size();
+  const int ncls = h->np_classes;
+  int *dbn = nullptr, *dbk = nullptr;
+  TRY(upload(h, &dbn, bnode.empty() ? std::vector<int>{0} : bnode));
+  TRY(upload(h, &dbk, bkm.empty() ? std::vector<int>{0} : bkm));
+  double *kappa = nullptr;
+  FCM_HIP(hipMalloc((void **)&kappa, std::max(1, nblocks) * sizeof(double)));
+  std::vector<double> hk(std::max(1, nblocks));
+  for (int l = 1; l <= h->L; ++l) {
+    Level &L = h->lev[l];
+    int m = g.nf;
+    for (int ax = 0; ax < g.d; ++ax) m *= 2 * L.q + 1;
+    const int ld = (m + 3) & ~3;
+    L.mpatch = m;
+    L.ldp = ld;
+    const size_t mm = (size_t)m * ld;
+    TRY(dalloc(h, &L.invS64, mm * std::max(1, nblocks)));
+    if (mixed) TRY(dalloc(h, &L.invS32, mm * std::max(1, nblocks)));
+    L.invU64 = L.invS64 + mm * ncls;
+    L.invU32 = mixed ? L.invS32 + mm * ncls : nullptr;
+    if (nblocks > 0) {
+      const size_t per = (size_t)m * m * sizeof(double);
+      const int chunk = (int)std::max<size_t>(1, std::min<size_t>(1024, ((size_t)256 << 20) / per));
+      const int cb = std::min(chunk, nblocks);
+      double *blk = nullptr, *scr = nullptr;
+      FCM_HIP(hipMalloc((void **)&blk, (size_t)cb * m * m * sizeof(double)));
+      FCM_HIP(hipMalloc((void **)&scr, spd_inverse_scratch_doubles(m, cb) * sizeof(double)));
+      for (int b0 = 0; b0 < nblocks; b0 += cb) {
+        const int nb = std::min(cb, nblocks - b0);
+        launch_form_patch_blocks(g, h->tab, h->ptab, m, dbn + b0, dbk + b0, nb, h->kmat,
+                                 h->Kref64, h->Kcut64, blk, h->stream);
+        spd_inverse_batched(blk, m, nb, scr, h->dflag, kappa + b0, h->stream);
+        launch_pack_blocks(blk, m, ld, nb, L.invS64 + mm * b0,
+                           mixed ? L.invS32 + mm * b0 : nullptr, h->stream);
+      }
+      FCM_HIP(hipStreamSynchronize(h->stream));
+      FCM_HIP(hipFree(blk));
+      FCM_HIP(hipFree(scr));
+      FCM_HIP(hipMemcpyAsync(hk.data(), kappa, nblocks * sizeof(double), hipMemcpyDeviceToHost,
+                             h->stream));
+      FCM_HIP(hipStreamSynchronize(h->stream));
+    }
+    std::vector<uint8_t> fl(std::max(1, h->np_unique), 0);
+    L.n_hi64 = 0;
+    for (int u = 0; u < h->np_unique; ++u)
+      if (!(hk[ncls + u] <= kKappa64)) {
+        fl[u] = 1;
+        L.n_hi64++;
+      }
+    TRY(upload(h, &L.hi64, fl));
+  }
+  FCM_HIP(hipFree(kappa));
+  const int mtop = h->lev[h->L].mpatch;
+  TRY(dalloc(h, &h->pYs, (size_t)std::max(1, h->np_shared) * mtop));
+  TRY(dalloc(h, &h->pYu, (size_t)std::max(1, h->np_unique) * mtop));
+  return check_flag(h, "patch Schwarz block inversion");
+}
+
 static fcm_status do_setup(fcm_handle *h) {
   Geo &g = h->geo;
   const fcm_problem &pr = h->prob.pr;
@@ -588,7 +874,14 @@ static fcm_status do_setup(fcm_handle *h) {
     TRY(upload(h, &h->uncut_list, ul));
     TRY(upload(h, &h->class_list, cl));
   }
-  TRY(setup_levels(h));
+  if (h->opt.smoother == FCM_SMOOTH_PATCHWISE) {
+    std::vector<int> bnode, bkm;
+    TRY(build_patch_tables(h));
+    TRY(build_patches(h, bnode, bkm));
+    TRY(setup_patch_levels(h, bnode, bkm));
+  } else {
+    TRY(setup_levels(h));
+  }
   TRY(setup_coarse(h));
   // work vectors
   for (int l = 0; l <= L; ++l) {
@@ -713,6 +1006,54 @@ static OpArgs<T> smoother_args(fcm_handle *h, int l) {
   return a;
 }
 
+template <typename T>
+static PatchArgs<T> patch_args(fcm_handle *h, int l) {
+  Level &L = h->lev[l];
+  PatchArgs<T> a;
+  a.m = L.mpatch;
+  a.ld = L.ldp;
+  a.nP_out = L.nP;
+  a.pnode = h->pnode;
+  a.pkm = h->pkm;
+  a.pcls = h->pcls;
+  a.pid = h->pid;
+  a.nsh = h->np_shared;
+  a.npu = h->np_unique;
+  a.matS64 = L.invS64;
+  a.matU = Prec<T>::invU(L);
+  if (std::is_same<T, float>::value) {
+    // FP32 storage where the block is well conditioned, FP64 otherwise
+    a.matU64 = L.invU64;
+    a.u64flag = L.hi64;
+  }
+  a.Ys = h->pYs;
+  a.Yu = h->pYu;
+  return a;
+}
+
+// out = M_l^{-1} x; if xs: xs = (first ? 0 : xs) + omega * out.
+template <typename T>
+static void smooth_launch(fcm_handle *h, int l, const T *x, T *out, T *xs, T omega, int first,
+                          hipStream_t s) {
+  if (h->opt.smoother == FCM_SMOOTH_PATCHWISE) {
+    PatchArgs<T> a = patch_args<T>(h, l);
+    a.x = x;
+    a.out = out;
+    a.xs = xs;
+    a.omega = omega;
+    a.first = first;
+    launch_patch_op<T>(h->geo, h->tab, h->ptab, a, s);
+    return;
+  }
+  OpArgs<T> a = smoother_args<T>(h, l);
+  a.x = x;
+  a.out = out;
+  a.xs = xs;
+  a.omega = omega;
+  a.first = first;
+  launch_elem_op<T>(h->geo, h->tab, a, s);
+}
+
 // Alg. 1 on level l with zero initial guess: x = V(l, b).  The residual is
 // updated after every smoothing step (r -= omega A delta == b - A x).
 template <typename T>
@@ -725,11 +1066,7 @@ static void vcycle_level(fcm_handle *h, int l, const T *b, T *x, hipStream_t s) 
   Level &L = h->lev[l];
   T *r = Prec<T>::r(L), *dl = Prec<T>::d(L);
   const T w = (T)h->opt.omega;
-  OpArgs<T> sm = smoother_args<T>(h, l);
   OpArgs<T> ap = stiffness_args<T>(h, l);
-  sm.out = dl;
-  sm.xs = x;
-  sm.omega = w;
   ap.x = dl;
   ap.out = r;
   ap.scale = -w;
@@ -739,9 +1076,7 @@ static void vcycle_level(fcm_handle *h, int l, const T *b, T *x, hipStream_t s) 
     launch_copy<T>(x, nullptr, L.npad, s);
   }
   for (int it = 0; it < npre; ++it) {
-    sm.x = it == 0 ? b : r;
-    sm.first = it == 0;
-    launch_elem_op<T>(g, h->tab, sm, s);
+    smooth_launch<T>(h, l, it == 0 ? b : r, dl, x, w, it == 0, s);
     ap.cvec = it == 0 ? b : r;
     launch_elem_op<T>(g, h->tab, ap, s);
   }
@@ -760,9 +1095,7 @@ static void vcycle_level(fcm_handle *h, int l, const T *b, T *x, hipStream_t s) 
   pr.nP_e = Lc.nP;
   launch_elem_op<T>(g, h->tab, pr, s);
   for (int it = 0; it < npost; ++it) {
-    sm.x = r;
-    sm.first = 0;
-    launch_elem_op<T>(g, h->tab, sm, s);
+    smooth_launch<T>(h, l, (const T *)r, dl, x, w, 0, s);
     if (it + 1 < npost) {
       ap.cvec = r;
       launch_elem_op<T>(g, h->tab, ap, s);
@@ -1088,26 +1421,6 @@ static bool dof_exists(const fcm_handle *h, const int *gc, const int *tt) {
   return false;
 }
 
-static void plane_types(const fcm_handle *h, std::vector<int> &pt) {
-  const Geo &g = h->geo;
-  const int p = g.p, d = g.d, nf = g.nf;
-  pt.clear();
-  for (int s = 1; s <= p; ++s)
-    for (int t2 = 0; t2 < (d == 3 ? p : 1); ++t2)
-      for (int t1 = 0; t1 < p; ++t1)
-        for (int t0 = 0; t0 < p; ++t0) {
-          int dg = std::max(tdeg(t0), tdeg(t1));
-          if (d == 3) dg = std::max(dg, tdeg(t2));
-          if (dg != s) continue;
-          for (int c = 0; c < nf; ++c) {
-            pt.push_back(t0);
-            pt.push_back(t1);
-            pt.push_back(t2);
-            pt.push_back(c);
-          }
-        }
-}
-
 fcm_status fcm_sizes(const fcm_handle *h, int *n_levels, int64_t *n_dofs, int64_t *n_padded) {
   if (!h || !n_levels) {
     set_error("null argument");
@@ -1204,8 +1517,9 @@ fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s) {
   for (auto v : h->h_state) kept += v != kVoid;
   s->n_kept = kept;
   s->n_cut = (int64_t)h->h_cut.size();
-  s->n_unique_blocks = h->n_unique;
-  s->n_shared_classes = h->n_shared;
+  const bool patch = h->opt.smoother == FCM_SMOOTH_PATCHWISE;
+  s->n_unique_blocks = patch ? h->np_unique : h->n_unique;
+  s->n_shared_classes = patch ? h->np_classes : h->n_shared;
   s->device_bytes = h->bytes;
   s->coarse_blocks = h->co.nblk;
   s->coarse_block_size = h->co.nb;
@@ -1239,10 +1553,7 @@ fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z, void
     set_error("invalid argument");
     return FCM_ERR_ARG;
   }
-  OpArgs<double> a = smoother_args<double>(h, level);
-  a.x = r;
-  a.out = z;
-  launch_elem_op<double>(h->geo, h->tab, a, (hipStream_t)stream);
+  smooth_launch<double>(h, level, r, z, nullptr, 1.0, 0, (hipStream_t)stream);
   FCM_HIP(hipGetLastError());
   return FCM_OK;
 }
@@ -1364,6 +1675,15 @@ static double op_bytes(const fcm_handle *h, int op, int l) {
   const fcm::Level &L = h->lev[l];
   const double mm = (double)L.m * L.m;
   const double E = h->geo.E;
+  if (op == FCM_OP_SMOOTH && h->opt.smoother == FCM_SMOOTH_PATCHWISE) {
+    // unique inverses streamed once, class inverses once, x read, delta and
+    // the iterate written, the iterate read
+    const double pm2 = (double)L.mpatch * L.mpatch;
+    const double nhi = mixed ? L.n_hi64 : 0;
+    const double mats = (h->np_unique - nhi) * pm2 * sv + nhi * pm2 * 8.0 +
+                        (double)h->np_classes * pm2 * 8.0;
+    return 4.0 * L.npad * sv + mats;
+  }
   if (op == FCM_OP_SMOOTH) {
     double nhi = mixed ? L.n_hi64 : 0;
     double mats = (h->n_shared + h->n_unique - nhi) * mm * sv + nhi * mm * 8.0;
@@ -1395,7 +1715,12 @@ fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
   auto launch = [&]() {
     if (op == FCM_OP_SMOOTH || op == FCM_OP_RESIDUAL) {
       fcm::Level &L = h->lev[level];
-      if (mixed) {
+      if (op == FCM_OP_SMOOTH) {
+        if (mixed)
+          smooth_launch<float>(h, level, L.r32, L.d32, L.x32, (float)h->opt.omega, 0, s);
+        else
+          smooth_launch<double>(h, level, L.r64, L.d64, L.x64, h->opt.omega, 0, s);
+      } else if (mixed) {
         OpArgs<float> a = op == FCM_OP_SMOOTH ? smoother_args<float>(h, level)
                                               : stiffness_args<float>(h, level);
         a.x = op == FCM_OP_SMOOTH ? L.r32 : L.d32;

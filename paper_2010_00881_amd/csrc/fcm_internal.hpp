@@ -32,6 +32,7 @@ constexpr double kKappa64 = 1e5; // scaled kappa_1 above which a Schwarz block s
 constexpr int kSmallInv = 88;
 // Schwarz blocks up to kSmallInv are formed and inverted in LDS (<= 64 KB).
 constexpr int kMaxStoredIn = 1029; // largest element matrix (p = 6 elasticity: 3*7^3)
+constexpr int kMaxPatchM = 512;    // largest patchwise Schwarz block (n_f (2p+1)^d)
 
 enum : uint8_t { kVoid = 0, kPhys = 1, kCut = 2 };
 
@@ -52,11 +53,13 @@ struct Geo {
 // Per-level Schwarz data and work vectors.
 struct Level {
   int q = 0, m = 0, nP = 0;
+  int mpatch = 0;              // patchwise block size n_f (2q+1)^d
   int64_t npad = 0, ndofs = 0;
   double *invS64 = nullptr, *invU64 = nullptr;
   float *invS32 = nullptr, *invU32 = nullptr;
   uint8_t *hi64 = nullptr;     // unique blocks applied in FP64 inside the FP32 V-cycle
   int n_hi64 = 0;
+  int ldp = 0;                 // patchwise: leading dimension of the stored inverses
   int *units = nullptr;        // owner-kernel work units of this level
   int nunits = 0;
   double *x64 = nullptr, *r64 = nullptr, *d64 = nullptr;
@@ -101,6 +104,15 @@ struct Tables {
   double *gsrc = nullptr;   // [ngauss][5]
 };
 
+// Patchwise Schwarz tables (order p, see kernels_patch.hip).
+struct PatchTables {
+  int m = 0;                // patch modes at order p: n_f (2p+1)^d
+  int *pm = nullptr;        // [m][4] per-axis slot 0..2p and component (degree-sorted)
+  int *pxoff = nullptr;     // [m] plane * G + grid offset relative to the node
+  int *pinfo = nullptr;     // [m] element mask, hat axes and offsets (kernels_patch.hip)
+  int *prow = nullptr;      // [nP][27] local mode of plane P in the patch of node g - delta
+};
+
 }  // namespace fcm
 
 struct fcm_handle {
@@ -126,6 +138,13 @@ struct fcm_handle {
   int *uncut_list = nullptr;                  // kept uncut elements (K_ref)
   int *class_list = nullptr;                  // elements with a shared Schwarz class, by class
   int n_uncut = 0, n_classed = 0;
+  // patchwise smoother: patches (grid nodes with a kept element) ordered
+  // class-sorted shared patches first, then unique patches
+  fcm::PatchTables ptab;
+  int np_shared = 0, np_unique = 0, np_classes = 0;
+  int *pnode = nullptr, *pkm = nullptr, *pcls = nullptr, *pid = nullptr;
+  std::vector<int> h_pnode, h_pkm;            // host copies (patch order)
+  double *pYs = nullptr, *pYu = nullptr;      // patch products (scratch)
   double *Yscr = nullptr;                     // stored-matrix products (scratch)
   double *Yshr = nullptr;                     // shared-matrix element products (scratch)
   double *Kref64 = nullptr, *Kcut64 = nullptr, *be = nullptr, *b = nullptr;
@@ -230,6 +249,35 @@ struct OpArgs {
 };
 template <typename T>
 void launch_elem_op(const Geo &g, const Tables &t, const OpArgs<T> &a, hipStream_t s);
+
+// Patchwise smoother apply: out = M^-1 x (delta); xs = (first ? 0 : xs) + omega * delta.
+template <typename T>
+struct PatchArgs {
+  const T *x = nullptr;
+  int m = 0, ld = 0;              // level block size, matrix leading dimension (ld % 4 == 0)
+  int nP_out = 0;
+  const int *pnode = nullptr, *pkm = nullptr, *pcls = nullptr, *pid = nullptr;
+  int nsh = 0, npu = 0;           // class patches, unique patches
+  const double *matS64 = nullptr; // [classes][m][ld]
+  const T *matU = nullptr;        // [npu][m][ld]
+  const double *matU64 = nullptr; // FP32 V-cycle: FP64 unique inverses where u64flag != 0
+  const uint8_t *u64flag = nullptr;
+  double *Ys = nullptr;           // [m][nsh]
+  double *Yu = nullptr;           // [npu][m]
+  T *out = nullptr;
+  T *xs = nullptr;
+  T omega = 0;
+  int first = 0;
+};
+template <typename T>
+void launch_patch_op(const Geo &g, const Tables &t, const PatchTables &pt, const PatchArgs<T> &a,
+                     hipStream_t s);
+void launch_form_patch_blocks(const Geo &g, const Tables &t, const PatchTables &pt, int m,
+                              const int *bnode, const int *bkm, int nblocks, const int *kmat,
+                              const double *Kref, const double *Kcut, double *out,
+                              hipStream_t s);
+void launch_pack_blocks(const double *src, int m, int ld, int nb, double *d64, float *d32,
+                        hipStream_t s);
 
 void launch_dot_partial(const double *x, const double *y, int64_t n, double *partial, int nblk,
                         hipStream_t s);

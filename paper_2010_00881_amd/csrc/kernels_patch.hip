@@ -1,0 +1,371 @@
+// Patchwise additive Schwarz smoother of libfcm (gfx950).
+//
+// One block per grid node v (Section 3.3.1, patchwise groups on a uniform
+// grid): every level-q function that is nonzero on a kept element among the
+// 2^d elements sharing v.  Per axis the patch sees 2q+1 one-dimensional
+// functions -- the hats at nodes v-1, v, v+1 and the bubbles of elements v-1
+// and v -- so m_q = n_f (2q+1)^d (Table tab::upperbound with n = 2).
+//
+// Patch-local modes are sorted by degree, so the level-q block is the leading
+// m_q x m_q block of the order-p patch (eq. hierarchicalMatrices).  A local
+// mode is one per-axis slot (0..2p) per axis plus a component:
+//   slot 0        hat at node v-1           (delta -1)
+//   slot 1..p-1   bubble of element v-1     (type t = slot, degree t+1)
+//   slot p        hat at node v             (delta  0)
+//   slot p+1..2p-1 bubble of element v      (type t = slot-p)
+//   slot 2p       hat at node v+1           (delta +1)
+// A mode is absent from patch v when it is Dirichlet-constrained or nonzero
+// on no kept element of the patch; absent modes get identity rows in the
+// block and a zero input, so their outputs are exactly zero.
+//
+// Application M^-1 r = sum_v P_v A_v^{-1} P_v^T r (eq. AdditiveSchwarz):
+//  * unique patches (a cut or void element within the 4^d elements that their
+//    functions touch): stored inverses streamed from HBM, one workgroup per
+//    patch, 4 rows per lane (128-bit loads of the symmetric matrix);
+//  * class patches (translation-invariant blocks): A_v^{-1} shared per class,
+//    Y = A^{-1} X on the FP64 matrix cores for 16 patches per workgroup;
+//  * owner gather: each DOF sums its rows of the <= 3^d patches containing
+//    it in a fixed order (deterministic) and applies the smoother epilogue.
+#include <algorithm>
+#include <type_traits>
+
+#include "fcm_internal.hpp"
+
+namespace fcm {
+
+__device__ __host__ inline void patch_slot(int sl, int p, int &t, int &dl) {
+  if (sl == 0) { t = 0; dl = -1; }
+  else if (sl < p) { t = sl; dl = -1; }
+  else if (sl == p) { t = 0; dl = 0; }
+  else if (sl < 2 * p) { t = sl - p; dl = 0; }
+  else { t = 0; dl = 1; }
+}
+
+__device__ inline void node_coords(const Geo &g, int node, int *vc) {
+  vc[0] = node % g.gn[0];
+  const int r = node / g.gn[0];
+  vc[1] = r % g.gn[1];
+  vc[2] = r / g.gn[1];
+}
+
+// pinfo bits: 0..7 element mask (bit s: element v - s, s_a = 1 meaning
+// element index v_a - 1), 8..10 hat axes, 12+2a..13+2a delta_a + 1.
+__device__ inline bool patch_present(const Geo &g, int info, int kmask, const int *vc) {
+  if (!(info & kmask & 0xff)) return false;
+  for (int ax = 0; ax < g.d; ++ax) {
+    if (!((info >> (8 + ax)) & 1)) continue;
+    const int node = vc[ax] + ((info >> (12 + 2 * ax)) & 3) - 1;
+    if (node == 0 && ((g.dir >> (2 * ax)) & 1)) return false;
+    if (node == g.n[ax] && ((g.dir >> (2 * ax + 1)) & 1)) return false;
+  }
+  return true;
+}
+
+// Entry (i, j) of the patch block at node vc: sum over the kept elements in
+// the common support of the two functions of the element-matrix entries.
+__device__ double patch_entry(const Geo &g, const PatchTables &pt, const int *smap, int mp,
+                              const int *kmat, const double *Kref, const double *Kcut,
+                              const int *vc, int kmask, int i, int j) {
+  const int ii = pt.pinfo[i], ij = pt.pinfo[j];
+  const bool pi = patch_present(g, ii, kmask, vc), pj = patch_present(g, ij, kmask, vc);
+  if (!pi || !pj) return i == j ? 1.0 : 0.0;
+  const int *mi = pt.pm + 4 * i, *mj = pt.pm + 4 * j;
+  const int p = g.p, np = p + 1;
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  int ti[3] = {0, 0, 0}, di[3] = {0, 0, 0}, tj[3] = {0, 0, 0}, dj[3] = {0, 0, 0};
+  for (int ax = 0; ax < g.d; ++ax) {
+    patch_slot(mi[ax], p, ti[ax], di[ax]);
+    patch_slot(mj[ax], p, tj[ax], dj[ax]);
+    // element index ranges of the two supports (hat at node c: elements
+    // c-1, c; bubble of element c: element c), relative to v
+    const int li = ti[ax] == 0 ? di[ax] - 1 : di[ax], hi_ = di[ax];
+    const int lj = tj[ax] == 0 ? dj[ax] - 1 : dj[ax], hj = dj[ax];
+    lo[ax] = max(li, lj);
+    hi[ax] = min(hi_, hj);
+    if (lo[ax] > hi[ax]) return 0.0;
+  }
+  double sum = 0.0;
+  for (int e2 = lo[2]; e2 <= hi[2]; ++e2)
+    for (int e1 = lo[1]; e1 <= hi[1]; ++e1)
+      for (int e0 = lo[0]; e0 <= hi[0]; ++e0) {
+        const int rel[3] = {e0, e1, e2};
+        int ec[3] = {0, 0, 0};
+        bool in = true;
+        for (int ax = 0; ax < g.d; ++ax) {
+          ec[ax] = vc[ax] + rel[ax];
+          in = in && ec[ax] >= 0 && ec[ax] < g.n[ax];
+        }
+        if (!in) continue;
+        const int kid = kmat[ec[0] + g.n[0] * (ec[1] + g.n[1] * ec[2])];
+        if (kid < 0) continue;
+        int ai[3] = {0, 0, 0}, aj[3] = {0, 0, 0};
+        for (int ax = 0; ax < g.d; ++ax) {
+          // element-local 1D mode: 0 / 1 = hat at the element's left / right
+          // node, t + 1 = bubble of type t
+          ai[ax] = ti[ax] == 0 ? di[ax] - rel[ax] : ti[ax] + 1;
+          aj[ax] = tj[ax] == 0 ? dj[ax] - rel[ax] : tj[ax] + 1;
+        }
+        const int la = smap[(ai[0] + np * (ai[1] + np * ai[2])) * g.nf + mi[3]];
+        const int lb = smap[(aj[0] + np * (aj[1] + np * aj[2])) * g.nf + mj[3]];
+        const double *K = kid == 0 ? Kref : Kcut + (size_t)(kid - 1) * mp * mp;
+        sum += K[(size_t)la * mp + lb];
+      }
+  return sum;
+}
+
+__global__ __launch_bounds__(256) void form_patch_blocks_kernel(Geo g, PatchTables pt,
+                                                                const int *smap, int mp, int m,
+                                                                const int *bnode,
+                                                                const int *bkm, const int *kmat,
+                                                                const double *Kref,
+                                                                const double *Kcut,
+                                                                double *out) {
+  const int blk = blockIdx.y;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m * m) return;
+  int vc[3];
+  node_coords(g, bnode[blk], vc);
+  out[(size_t)blk * m * m + i] =
+      patch_entry(g, pt, smap, mp, kmat, Kref, Kcut, vc, bkm[blk], i / m, i % m);
+}
+
+void launch_form_patch_blocks(const Geo &g, const Tables &t, const PatchTables &pt, int m,
+                              const int *bnode, const int *bkm, int nblocks, const int *kmat,
+                              const double *Kref, const double *Kcut, double *out,
+                              hipStream_t s) {
+  if (nblocks <= 0) return;
+  dim3 grid((m * m + 255) / 256, nblocks);
+  form_patch_blocks_kernel<<<grid, 256, 0, s>>>(g, pt, t.smap, t.m, m, bnode, bkm, kmat, Kref,
+                                                Kcut, out);
+}
+
+// dst[b] (m x ld, zero-padded columns) <- src[b] (m x m), FP64 and/or FP32
+__global__ void pack_blocks_kernel(const double *src, int m, int ld, int nb, double *d64,
+                                   float *d32) {
+  const size_t tot = (size_t)nb * m * ld;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = i / ((size_t)m * ld);
+    const int r = (int)((i / ld) % m), c = (int)(i % ld);
+    const double v = c < m ? src[b * m * m + (size_t)r * m + c] : 0.0;
+    if (d64) d64[i] = v;
+    if (d32) d32[i] = (float)v;
+  }
+}
+
+void launch_pack_blocks(const double *src, int m, int ld, int nb, double *d64, float *d32,
+                        hipStream_t s) {
+  if (nb <= 0) return;
+  const size_t tot = (size_t)nb * m * ld;
+  const int blocks = (int)std::min<size_t>((tot + 255) / 256, 8192);
+  pack_blocks_kernel<<<blocks, 256, 0, s>>>(src, m, ld, nb, d64, d32);
+}
+
+// ---------------------------------------------------------------- apply
+// Unique patches: workgroup u computes Yu[u][r] = sum_b A^{-1}[b][r] x_v[b]
+// (symmetric inverse, so row b holds column b).  Thread (c, bg) owns rows
+// 4c..4c+3 over the bg-th slice of b; slices are summed in a fixed order.
+template <typename T>
+__global__ __launch_bounds__(256) void patch_gemv_kernel(Geo g, const int *__restrict__ pxoff,
+                                                         const int *__restrict__ pinfo,
+                                                         PatchArgs<T> a) {
+  __shared__ double xs[kMaxPatchM];
+  __shared__ double red[2 * kMaxPatchM + 256];
+  const int u = blockIdx.x;
+  const int pi = a.nsh + u;
+  const int node = a.pnode[pi], kmask = a.pkm[pi];
+  int vc[3];
+  node_coords(g, node, vc);
+  const int m = a.m, ld = a.ld;
+  for (int k = threadIdx.x; k < m; k += 256)
+    xs[k] = patch_present(g, pinfo[k], kmask, vc) ? (double)a.x[node + pxoff[k]] : 0.0;
+  __syncthreads();
+  const int nch = (m + 3) >> 2;
+  const int nbg = max(1, min(256 / nch, 8));
+  const int c = threadIdx.x % nch, bg = threadIdx.x / nch;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (bg < nbg) {
+    const int b0 = (bg * m) / nbg, b1 = ((bg + 1) * m) / nbg;
+    const bool hi = a.matU64 && (!a.u64flag || a.u64flag[u]);
+    if (hi) {
+      const double *M = a.matU64 + (size_t)u * m * ld + 4 * c;
+#pragma unroll 4
+      for (int b = b0; b < b1; ++b) {
+        const double2 v0 = *reinterpret_cast<const double2 *>(M + (size_t)b * ld);
+        const double2 v1 = *reinterpret_cast<const double2 *>(M + (size_t)b * ld + 2);
+        const double xb = xs[b];
+        acc[0] += v0.x * xb;
+        acc[1] += v0.y * xb;
+        acc[2] += v1.x * xb;
+        acc[3] += v1.y * xb;
+      }
+    } else {
+      const T *M = a.matU + (size_t)u * m * ld + 4 * c;
+      if constexpr (std::is_same<T, float>::value) {
+#pragma unroll 4
+        for (int b = b0; b < b1; ++b) {
+          const float4 v = *reinterpret_cast<const float4 *>(M + (size_t)b * ld);
+          const double xb = xs[b];
+          acc[0] += (double)v.x * xb;
+          acc[1] += (double)v.y * xb;
+          acc[2] += (double)v.z * xb;
+          acc[3] += (double)v.w * xb;
+        }
+      } else {
+#pragma unroll 4
+        for (int b = b0; b < b1; ++b) {
+          const double2 v0 = *reinterpret_cast<const double2 *>(M + (size_t)b * ld);
+          const double2 v1 = *reinterpret_cast<const double2 *>(M + (size_t)b * ld + 2);
+          const double xb = xs[b];
+          acc[0] += v0.x * xb;
+          acc[1] += v0.y * xb;
+          acc[2] += v1.x * xb;
+          acc[3] += v1.y * xb;
+        }
+      }
+    }
+  }
+  // partial sums per slice: red[bg][4c + r]
+  const int ldr = 4 * nch;
+  if (bg < nbg)
+    for (int r = 0; r < 4; ++r) red[bg * ldr + 4 * c + r] = acc[r];
+  __syncthreads();
+  for (int r = threadIdx.x; r < m; r += 256) {
+    double s = 0.0;
+    for (int q = 0; q < nbg; ++q) s += red[q * ldr + r];
+    a.Yu[(size_t)u * m + r] = s;
+  }
+}
+
+// Class patches on the FP64 matrix cores: a workgroup takes 16 consecutive
+// patches of the class-sorted list and gathers X (m x 16) into LDS; wave w
+// computes row tiles w, w+4, ... of Y = A^{-1} X with v_mfma_f64_16x16x4f64
+// (lane l supplies A[l%16][l/16] and B[l/16][l%16], holds D[4j+l/16][l%16]),
+// one pass per distinct class present in the workgroup.
+typedef double doublex4p __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__global__ __launch_bounds__(256) void patch_shared_mfma64_kernel(Geo g,
+                                                                  const int *__restrict__ pxoff,
+                                                                  const int *__restrict__ pinfo,
+                                                                  PatchArgs<T> a) {
+  extern __shared__ double X[];   // [m][16]
+  __shared__ int cls_s[16];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m = a.m, ld = a.ld;
+  const int p0 = blockIdx.x * 16;
+  // gather: column n = patch p0 + n, row k
+  for (int i = threadIdx.x; i < 16 * m; i += 256) {
+    const int n = i & 15, k = i >> 4;
+    const int pi = p0 + n;
+    double v = 0.0;
+    if (pi < a.nsh) {
+      const int node = a.pnode[pi];
+      int vc[3];
+      node_coords(g, node, vc);
+      if (patch_present(g, pinfo[k], a.pkm[pi], vc)) v = (double)a.x[node + pxoff[k]];
+    }
+    X[k * 16 + n] = v;
+  }
+  if (threadIdx.x < 16) cls_s[threadIdx.x] = p0 + threadIdx.x < a.nsh ? a.pcls[p0 + threadIdx.x] : -1;
+  __syncthreads();
+  const int n = lane & 15, kq = lane >> 4;
+  const int mycls = cls_s[n];
+  const int nks = (m + 3) >> 2, nrt = (m + 15) >> 4;
+  int done_mask = 0;   // classes handled (by position of first occurrence)
+  for (int first = 0; first < 16; ++first) {
+    const int c0 = cls_s[first];
+    if (c0 < 0 || ((done_mask >> first) & 1)) continue;
+    for (int q = first; q < 16; ++q)
+      if (cls_s[q] == c0) done_mask |= 1 << q;
+    const bool mine = mycls == c0;
+    const double *A0 = a.matS64 + (size_t)c0 * m * ld;
+    for (int rt = wave; rt < nrt; rt += 4) {
+      const int row = min(16 * rt + n, m - 1);
+      const bool rowv = 16 * rt + n < m;
+      doublex4p acc = {0.0, 0.0, 0.0, 0.0};
+      for (int ks = 0; ks < nks; ++ks) {
+        const int k = 4 * ks + kq;
+        const bool kv = k < m;
+        const double av = (kv && rowv) ? A0[(size_t)k * ld + row] : 0.0;   // A[row][k]
+        const double bv = (kv && mine) ? X[k * 16 + n] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+      }
+      const int pi = p0 + n;
+      if (mine && pi < a.nsh) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rr = 16 * rt + 4 * j + kq;
+          if (rr < m) a.Ys[(size_t)rr * a.nsh + pi] = acc[j];
+        }
+      }
+    }
+  }
+}
+
+// Owner gather with the smoother epilogue: out = delta, xs = (first ? 0 :
+// xs) + omega * delta.  One thread per (grid point, plane).
+template <typename T>
+__global__ __launch_bounds__(256) void patch_gather_kernel(Geo g, const int *__restrict__ prow,
+                                                           const int *__restrict__ pinfoP,
+                                                           PatchArgs<T> a) {
+  const int P = blockIdx.y;
+  const int gi = blockIdx.x * 256 + threadIdx.x;
+  if (gi >= g.G) return;
+  int gc[3];
+  node_coords(g, gi, gc);
+  const int info = pinfoP[P], vmask = info & 7, bmask = (info >> 8) & 7;
+  bool valid = true;
+  for (int ax = 0; ax < g.d; ++ax) {
+    if (((bmask >> ax) & 1) && gc[ax] == g.n[ax]) valid = false;
+    if ((vmask >> ax) & 1) {
+      if (gc[ax] == 0 && ((g.dir >> (2 * ax)) & 1)) valid = false;
+      if (gc[ax] == g.n[ax] && ((g.dir >> (2 * ax + 1)) & 1)) valid = false;
+    }
+  }
+  double acc = 0.0;
+  if (valid) {
+    const int nc = g.d == 3 ? 27 : 9;
+    for (int cb = 0; cb < nc; ++cb) {
+      const int dl[3] = {cb % 3 - 1, (cb / 3) % 3 - 1, g.d == 3 ? cb / 9 - 1 : 0};
+      int vcn[3] = {0, 0, 0};
+      bool ok = true;
+      for (int ax = 0; ax < g.d; ++ax) {
+        // a bubble of element c sits in the patches of nodes c and c+1
+        if (((bmask >> ax) & 1) && dl[ax] == 1) ok = false;
+        vcn[ax] = gc[ax] - dl[ax];
+        ok = ok && vcn[ax] >= 0 && vcn[ax] <= g.n[ax];
+      }
+      if (!ok) continue;
+      const int node = vcn[0] + g.gn[0] * (vcn[1] + g.gn[1] * vcn[2]);
+      const int pi = a.pid[node];
+      if (pi < 0) continue;
+      const int row = prow[P * 27 + cb];
+      acc += pi < a.nsh ? a.Ys[(size_t)row * a.nsh + pi] : a.Yu[(size_t)(pi - a.nsh) * a.m + row];
+    }
+  }
+  const T val = valid ? (T)acc : T(0);
+  const size_t oi = (size_t)P * g.G + gi;
+  a.out[oi] = val;
+  if (a.xs) {
+    const T xo = a.first ? T(0) : a.xs[oi];
+    a.xs[oi] = xo + a.omega * val;
+  }
+}
+
+template <typename T>
+void launch_patch_op(const Geo &g, const Tables &t, const PatchTables &pt, const PatchArgs<T> &a,
+                     hipStream_t s) {
+  if (a.npu > 0) patch_gemv_kernel<T><<<a.npu, 256, 0, s>>>(g, pt.pxoff, pt.pinfo, a);
+  if (a.nsh > 0)
+    patch_shared_mfma64_kernel<T><<<(a.nsh + 15) / 16, 256, (size_t)a.m * 16 * sizeof(double), s>>>(
+        g, pt.pxoff, pt.pinfo, a);
+  dim3 grid((g.G + 255) / 256, a.nP_out);
+  patch_gather_kernel<T><<<grid, 256, 0, s>>>(g, pt.prow, t.pinfo, a);
+}
+template void launch_patch_op<double>(const Geo &, const Tables &, const PatchTables &,
+                                      const PatchArgs<double> &, hipStream_t);
+template void launch_patch_op<float>(const Geo &, const Tables &, const PatchTables &,
+                                     const PatchArgs<float> &, hipStream_t);
+
+}  // namespace fcm

@@ -868,12 +868,16 @@ __global__ void apply_scale_kernel(double *A, int n, const double *scale, double
   }
 }
 
-// Invert the pivot tile (in LDS) and form the panel W_KJ = P A_KJ for tile J.
+// Sweep the pivot rows of tile K over column tile J in LDS: the pivot tile
+// becomes -A_KK^{-1} and, for J != K, the panel becomes W_KJ = A_KK^{-1} A_KJ.
+// The panel is updated pivot by pivot together with the pivot tile (product
+// form), which keeps the accuracy of the unblocked sweep; forming A_KK^{-1}
+// first and multiplying loses digits on ill-conditioned cut-cell blocks.
 __global__ __launch_bounds__(256) void sweep_panel_kernel(double *A, int n, int K, double *W,
                                                           int *flag) {
   __shared__ double P[kTB][kTB + 1];
   __shared__ double T[kTB][kTB + 1];
-  __shared__ double ck[kTB], rk[kTB];
+  __shared__ double ck[kTB], rk[kTB], tk[kTB];
   const int b = blockIdx.y, J = blockIdx.x;
   double *M = A + (size_t)b * n * n;
   const int k0 = K * kTB, j0 = J * kTB;
@@ -891,6 +895,7 @@ __global__ __launch_bounds__(256) void sweep_panel_kernel(double *A, int n, int 
     if (tid < kTB) {
       ck[tid] = P[tid][k];
       rk[tid] = P[k][tid];
+      tk[tid] = T[k][tid];
     }
     __syncthreads();
     const double piv = ck[k];
@@ -904,23 +909,17 @@ __global__ __launch_bounds__(256) void sweep_panel_kernel(double *A, int n, int 
       else if (c != k) v = rk[c] * ip;
       else v = -ip;
       P[r][c] = v;
+      if (J != K) T[r][c] = r != k ? T[r][c] - ck[r] * tk[c] * ip : tk[c] * ip;
     }
     __syncthreads();
   }
-  // P now holds -A_KK^{-1}
+  // P now holds -A_KK^{-1}; T holds A_KK^{-1} A_KJ
   double *Wb = W + (size_t)b * kTB * n;
   for (int i = tid; i < kTB * kTB; i += 256) {
     int r = i / kTB, c = i % kTB;
     int gj = j0 + c;
     if (gj >= n) continue;
-    double v;
-    if (J == K) {
-      v = -P[r][c];
-    } else {
-      v = 0.0;
-      for (int k = 0; k < kTB; ++k) v -= P[r][k] * T[k][c];
-    }
-    Wb[(size_t)r * n + gj] = v;
+    Wb[(size_t)r * n + gj] = J == K ? -P[r][c] : T[r][c];
   }
 }
 

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcm.so")
 
 FCM_FP64, FCM_MIXED = 0, 1
+FCM_SMOOTH_ELEMENTWISE, FCM_SMOOTH_PATCHWISE = 0, 1
 STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "out of device memory",
           -3: "HIP error", -4: "not SPD", -5: "CG breakdown", -6: "non-finite value", -7: "busy"}
 
@@ -188,7 +189,10 @@ class _ProblemData:
 
 def make_options(opts):
     o = Options()
-    o.smoother = 0
+    sm = opts.get("smoother", "elementwise")
+    if sm not in ("elementwise", "patchwise"):
+        raise ValueError(f"unknown smoother {sm!r}")
+    o.smoother = FCM_SMOOTH_PATCHWISE if sm == "patchwise" else FCM_SMOOTH_ELEMENTWISE
     o.omega = float(opts["omega"])
     o.n_pre = int(opts.get("n_pre", 5))
     o.n_post = int(opts.get("n_post", 5))

@@ -26,7 +26,19 @@ CASES = {
     "cube13_p2": lambda: fi.voided_cube_poisson(2, n=13, p=2),
     "elast4_p3": lambda: fi.voided_cube_elasticity(0, n=4, p=3),
     "elast3_p4": lambda: fi.voided_cube_elasticity(1, n=3, p=4),
+    # patchwise Schwarz blocks (one per grid node): m = 25, 49 (2D); 343, 125
+    # (3D Poisson p = 3, 2); 375 (elasticity p = 2)
+    "plate16_p2_patch": lambda: _patch(fi.plate_with_hole(0)),
+    "plate40_p3_patch": lambda: _patch(fi.plate_with_hole(1, n=40, p=3)),
+    "cube7_p3_patch": lambda: _patch(fi.voided_cube_poisson(0, n=7, p=3)),
+    "cube13_p2_patch": lambda: _patch(fi.voided_cube_poisson(2, n=13, p=2)),
+    "elast3_p2_patch": lambda: _patch(fi.voided_cube_elasticity(1, n=3, p=2)),
 }
+
+
+def _patch(case_):
+    desc, opts = case_
+    return desc, dict(opts, smoother="patchwise", omega=1 / 6 if desc["dim"] == 2 else 1 / 18)
 
 _cache = {}
 
