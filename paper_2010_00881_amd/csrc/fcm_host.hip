@@ -616,6 +616,7 @@ static fcm_status build_patch_tables(fcm_handle *h) {
     }
     pinfo[k] = info;
   }
+  h->h_ppinfo = pinfo;
   std::vector<int> prow((size_t)nP * 27, -1);
   const int ncb = d == 3 ? 27 : 9;
   for (int P = 0; P < nP; ++P)
@@ -698,14 +699,38 @@ static fcm_status build_patches(fcm_handle *h, std::vector<int> &bnode, std::vec
       members[it->second].push_back(node);
     }
   }
-  std::vector<int> pnode, pkm, pcls, pid(g.G, -1);
-  for (size_t c = 0; c < members.size(); ++c)
+  std::vector<int> pnode, pkm, pid(g.G, -1), chk;
+  const int mp = h->ptab.m, W = (mp + 31) / 32;
+  std::vector<unsigned> cpres(std::max<size_t>(1, members.size()) * W, 0u);
+  for (size_t c = 0; c < members.size(); ++c) {
+    const int first = (int)pnode.size(), cnt = (int)members[c].size();
+    for (int q = 0; q < cnt; q += 256) {
+      chk.push_back((int)c);
+      chk.push_back(first + q);
+      chk.push_back(std::min(256, cnt - q));
+    }
     for (int node : members[c]) {
       pid[node] = (int)pnode.size();
       pnode.push_back(node);
       pkm.push_back(km[node]);
-      pcls.push_back((int)c);
     }
+    // modes present in every patch of the class (same box-face position)
+    const int v0 = members[c][0];
+    const int vc[3] = {v0 % g.gn[0], (v0 / g.gn[0]) % g.gn[1], v0 / (g.gn[0] * g.gn[1])};
+    for (int k = 0; k < mp; ++k) {
+      const int info = h->h_ppinfo[k];
+      bool pres = (info & km[v0] & 0xff) != 0;
+      for (int ax = 0; ax < d && pres; ++ax) {
+        if (!((info >> (8 + ax)) & 1)) continue;
+        const int nd = vc[ax] + ((info >> (12 + 2 * ax)) & 3) - 1;
+        if (nd == 0 && ((g.dir >> (2 * ax)) & 1)) pres = false;
+        if (nd == g.n[ax] && ((g.dir >> (2 * ax + 1)) & 1)) pres = false;
+      }
+      if (pres) cpres[c * W + k / 32] |= 1u << (k % 32);
+    }
+  }
+  h->np_chunks = (int)chk.size() / 3;
+  h->p_words = W;
   h->np_shared = (int)pnode.size();
   h->np_classes = (int)members.size();
   for (int node : uniq) {
@@ -730,10 +755,11 @@ static fcm_status build_patches(fcm_handle *h, std::vector<int> &bnode, std::vec
     pnode.push_back(0);
     pkm.push_back(0);
   }
-  if (pcls.empty()) pcls.push_back(0);
+  if (chk.empty()) chk.assign(3, 0);
   TRY(upload(h, &h->pnode, pnode));
   TRY(upload(h, &h->pkm, pkm));
-  TRY(upload(h, &h->pcls, pcls));
+  TRY(upload(h, &h->pchk, chk));
+  TRY(upload(h, &h->pcpres, cpres));
   TRY(upload(h, &h->pid, pid));
   return FCM_OK;
 }
@@ -1015,7 +1041,10 @@ static PatchArgs<T> patch_args(fcm_handle *h, int l) {
   a.nP_out = L.nP;
   a.pnode = h->pnode;
   a.pkm = h->pkm;
-  a.pcls = h->pcls;
+  a.chk = h->pchk;
+  a.nchunks = h->np_chunks;
+  a.cpres = h->pcpres;
+  a.pwords = h->p_words;
   a.pid = h->pid;
   a.nsh = h->np_shared;
   a.npu = h->np_unique;

@@ -32,7 +32,7 @@ constexpr double kKappa64 = 1e5; // scaled kappa_1 above which a Schwarz block s
 constexpr int kSmallInv = 88;
 // Schwarz blocks up to kSmallInv are formed and inverted in LDS (<= 64 KB).
 constexpr int kMaxStoredIn = 1029; // largest element matrix (p = 6 elasticity: 3*7^3)
-constexpr int kMaxPatchM = 512;    // largest patchwise Schwarz block (n_f (2p+1)^d)
+constexpr int kMaxPatchM = 384;    // largest patchwise Schwarz block (n_f (2p+1)^d)
 
 enum : uint8_t { kVoid = 0, kPhys = 1, kCut = 2 };
 
@@ -142,8 +142,12 @@ struct fcm_handle {
   // class-sorted shared patches first, then unique patches
   fcm::PatchTables ptab;
   int np_shared = 0, np_unique = 0, np_classes = 0;
-  int *pnode = nullptr, *pkm = nullptr, *pcls = nullptr, *pid = nullptr;
+  int *pnode = nullptr, *pkm = nullptr, *pid = nullptr;
+  int *pchk = nullptr, np_chunks = 0;         // class chunks of <= 256 patches
+  unsigned *pcpres = nullptr;                 // class mode-presence bits
+  int p_words = 0;
   std::vector<int> h_pnode, h_pkm;            // host copies (patch order)
+  std::vector<int> h_ppinfo;                  // host copy of the patch mode info
   double *pYs = nullptr, *pYu = nullptr;      // patch products (scratch)
   double *Yscr = nullptr;                     // stored-matrix products (scratch)
   double *Yshr = nullptr;                     // shared-matrix element products (scratch)
@@ -256,8 +260,12 @@ struct PatchArgs {
   const T *x = nullptr;
   int m = 0, ld = 0;              // level block size, matrix leading dimension (ld % 4 == 0)
   int nP_out = 0;
-  const int *pnode = nullptr, *pkm = nullptr, *pcls = nullptr, *pid = nullptr;
+  const int *pnode = nullptr, *pkm = nullptr, *pid = nullptr;
   int nsh = 0, npu = 0;           // class patches, unique patches
+  const int *chk = nullptr;       // [nchunks][3]: class, first patch, count (<= 256)
+  int nchunks = 0;
+  const unsigned *cpres = nullptr; // [classes][pwords] mode presence bits per class
+  int pwords = 0;
   const double *matS64 = nullptr; // [classes][m][ld]
   const T *matU = nullptr;        // [npu][m][ld]
   const double *matU64 = nullptr; // FP32 V-cycle: FP64 unique inverses where u64flag != 0

@@ -23,7 +23,7 @@
 //    functions touch): stored inverses streamed from HBM, one workgroup per
 //    patch, 4 rows per lane (128-bit loads of the symmetric matrix);
 //  * class patches (translation-invariant blocks): A_v^{-1} shared per class,
-//    Y = A^{-1} X on the FP64 matrix cores for 16 patches per workgroup;
+//    Y = A^{-1} X on the FP64 matrix cores with the inverse held in registers;
 //  * owner gather: each DOF sums its rows of the <= 3^d patches containing
 //    it in a fixed order (deterministic) and applies the smoother epilogue.
 #include <algorithm>
@@ -237,70 +237,117 @@ __global__ __launch_bounds__(256) void patch_gemv_kernel(Geo g, const int *__res
   }
 }
 
-// Class patches on the FP64 matrix cores: a workgroup takes 16 consecutive
-// patches of the class-sorted list and gathers X (m x 16) into LDS; wave w
-// computes row tiles w, w+4, ... of Y = A^{-1} X with v_mfma_f64_16x16x4f64
-// (lane l supplies A[l%16][l/16] and B[l/16][l%16], holds D[4j+l/16][l%16]),
-// one pass per distinct class present in the workgroup.
+// Class patches on the FP64 matrix cores.  Work item = (8 row tiles of 16,
+// chunk of <= 256 patches of one class).  Wave w keeps rows [16 rt, 16 rt + 16)
+// of the class inverse in registers (A operands, loaded once per chunk) and
+// streams the chunk in groups of 16 patches: the workgroup gathers X (m x 16)
+// into LDS, then each wave runs NKS back-to-back v_mfma_f64_16x16x4f64 with
+// B from LDS.  Lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
+// D[4j+l/16][l%16].  Mode presence of a class patch depends only on its
+// class (bit k of cpres[class]).
 typedef double doublex4p __attribute__((ext_vector_type(4)));
 
-template <typename T>
-__global__ __launch_bounds__(256) void patch_shared_mfma64_kernel(Geo g,
-                                                                  const int *__restrict__ pxoff,
-                                                                  const int *__restrict__ pinfo,
-                                                                  PatchArgs<T> a) {
-  extern __shared__ double X[];   // [m][16]
-  __shared__ int cls_s[16];
+template <typename T, int NKS>
+__global__ __launch_bounds__(512) void patch_class_mfma_kernel(Geo g,
+                                                               const int *__restrict__ pxoff,
+                                                               PatchArgs<T> a) {
+  extern __shared__ double X[];   // [NKS * 4][16]
+  constexpr int KP = NKS * 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int m = a.m, ld = a.ld;
-  const int p0 = blockIdx.x * 16;
-  // gather: column n = patch p0 + n, row k
-  for (int i = threadIdx.x; i < 16 * m; i += 256) {
-    const int n = i & 15, k = i >> 4;
-    const int pi = p0 + n;
-    double v = 0.0;
-    if (pi < a.nsh) {
-      const int node = a.pnode[pi];
-      int vc[3];
-      node_coords(g, node, vc);
-      if (patch_present(g, pinfo[k], a.pkm[pi], vc)) v = (double)a.x[node + pxoff[k]];
-    }
-    X[k * 16 + n] = v;
-  }
-  if (threadIdx.x < 16) cls_s[threadIdx.x] = p0 + threadIdx.x < a.nsh ? a.pcls[p0 + threadIdx.x] : -1;
-  __syncthreads();
   const int n = lane & 15, kq = lane >> 4;
-  const int mycls = cls_s[n];
-  const int nks = (m + 3) >> 2, nrt = (m + 15) >> 4;
-  int done_mask = 0;   // classes handled (by position of first occurrence)
-  for (int first = 0; first < 16; ++first) {
-    const int c0 = cls_s[first];
-    if (c0 < 0 || ((done_mask >> first) & 1)) continue;
-    for (int q = first; q < 16; ++q)
-      if (cls_s[q] == c0) done_mask |= 1 << q;
-    const bool mine = mycls == c0;
-    const double *A0 = a.matS64 + (size_t)c0 * m * ld;
-    for (int rt = wave; rt < nrt; rt += 4) {
-      const int row = min(16 * rt + n, m - 1);
-      const bool rowv = 16 * rt + n < m;
-      doublex4p acc = {0.0, 0.0, 0.0, 0.0};
-      for (int ks = 0; ks < nks; ++ks) {
-        const int k = 4 * ks + kq;
-        const bool kv = k < m;
-        const double av = (kv && rowv) ? A0[(size_t)k * ld + row] : 0.0;   // A[row][k]
-        const double bv = (kv && mine) ? X[k * 16 + n] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  const int *ch = a.chk + 3 * blockIdx.y;
+  const int c = ch[0], p0 = ch[1], cnt = ch[2];
+  const int m = a.m, ld = a.ld;
+  const int rt = blockIdx.x * 8 + wave;
+  const bool rtv = 16 * rt < m;
+  const unsigned *pres = a.cpres + (size_t)c * a.pwords;
+  double av[NKS];
+  {
+    const double *A0 = a.matS64 + (size_t)c * m * ld;
+    const int r = 16 * rt + n;
+    const bool rv = rtv && r < m;
+    const int rc = min(r, m - 1);
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int k = 4 * ks + kq;
+      const double v = A0[(size_t)min(k, m - 1) * ld + rc];   // A[r][k] = A[k][r]
+      av[ks] = (rv && k < m) ? v : 0.0;
+    }
+  }
+  const int ngroups = (cnt + 15) >> 4;
+  // gathered inputs of the next group are prefetched into registers while the
+  // current group runs on the matrix cores (element i = tid + 512 j of X);
+  // the widest tiles have no registers to spare and gather in place
+  constexpr int PER = NKS / 8;
+  constexpr bool kPrefetch = NKS <= 64;
+  T pf[PER];
+  auto fetch = [&](int gi) {
+    const int q0 = p0 + 16 * gi, qn = min(16, cnt - 16 * gi);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = threadIdx.x + 512 * j;
+      const int nn = i & 15, k = i >> 4;
+      T v = T(0);
+      if (nn < qn && k < m && ((pres[k >> 5] >> (k & 31)) & 1u))
+        v = a.x[a.pnode[q0 + nn] + pxoff[k]];
+      pf[j] = v;
+    }
+  };
+  if (kPrefetch) fetch(0);
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const int q0 = p0 + 16 * gi, qn = min(16, cnt - 16 * gi);
+    if (kPrefetch) {
+#pragma unroll
+      for (int j = 0; j < PER; ++j) X[threadIdx.x + 512 * j] = (double)pf[j];
+    } else {
+      for (int i = threadIdx.x; i < 16 * KP; i += 512) {
+        const int nn = i & 15, k = i >> 4;
+        double v = 0.0;
+        if (nn < qn && k < m && ((pres[k >> 5] >> (k & 31)) & 1u))
+          v = (double)a.x[a.pnode[q0 + nn] + pxoff[k]];
+        X[i] = v;
       }
-      const int pi = p0 + n;
-      if (mine && pi < a.nsh) {
+    }
+    __syncthreads();
+    if (kPrefetch && gi + 1 < ngroups) fetch(gi + 1);
+    if (rtv) {
+      doublex4p acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], X[(4 * ks + kq) * 16 + n], acc, 0, 0, 0);
+      if (n < qn) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int rr = 16 * rt + 4 * j + kq;
-          if (rr < m) a.Ys[(size_t)rr * a.nsh + pi] = acc[j];
+          if (rr < m) a.Ys[(size_t)rr * a.nsh + q0 + n] = acc[j];
         }
       }
     }
+    __syncthreads();
   }
+}
+
+template <typename T, int NKS>
+static void launch_class_nks(const Geo &g, const PatchTables &pt, const PatchArgs<T> &a,
+                             hipStream_t s) {
+  const int nrt = (a.m + 15) / 16;
+  dim3 grid((nrt + 7) / 8, a.nchunks);
+  patch_class_mfma_kernel<T, NKS><<<grid, 512, (size_t)NKS * 4 * 16 * sizeof(double), s>>>(
+      g, pt.pxoff, a);
+}
+
+template <typename T>
+static void launch_class(const Geo &g, const PatchTables &pt, const PatchArgs<T> &a,
+                         hipStream_t s) {
+  const int nks = (a.m + 3) / 4;
+  if (nks <= 8) launch_class_nks<T, 8>(g, pt, a, s);
+  else if (nks <= 16) launch_class_nks<T, 16>(g, pt, a, s);
+  else if (nks <= 24) launch_class_nks<T, 24>(g, pt, a, s);
+  else if (nks <= 32) launch_class_nks<T, 32>(g, pt, a, s);
+  else if (nks <= 48) launch_class_nks<T, 48>(g, pt, a, s);
+  else if (nks <= 64) launch_class_nks<T, 64>(g, pt, a, s);
+  else if (nks <= 88) launch_class_nks<T, 88>(g, pt, a, s);
+  else launch_class_nks<T, 96>(g, pt, a, s);
 }
 
 // Owner gather with the smoother epilogue: out = delta, xs = (first ? 0 :
@@ -357,9 +404,7 @@ template <typename T>
 void launch_patch_op(const Geo &g, const Tables &t, const PatchTables &pt, const PatchArgs<T> &a,
                      hipStream_t s) {
   if (a.npu > 0) patch_gemv_kernel<T><<<a.npu, 256, 0, s>>>(g, pt.pxoff, pt.pinfo, a);
-  if (a.nsh > 0)
-    patch_shared_mfma64_kernel<T><<<(a.nsh + 15) / 16, 256, (size_t)a.m * 16 * sizeof(double), s>>>(
-        g, pt.pxoff, pt.pinfo, a);
+  if (a.nsh > 0 && a.nchunks > 0) launch_class<T>(g, pt, a, s);
   dim3 grid((g.G + 255) / 256, a.nP_out);
   patch_gather_kernel<T><<<grid, 256, 0, s>>>(g, pt.prow, t.pinfo, a);
 }
