@@ -4,15 +4,17 @@
 Workload: 3D Poisson on the unit cube minus 8 seeded spherical voids, 32^3
 cells, integrated-Legendre tensor basis p = 3 (848k unknowns for seed 0),
 alpha = 1e-10, octree depth 3, u = 0 on the box faces, f = 1; FP32 V-cycle
-inside FP64 CG (rtol 1e-10).  One step = one complete solve of a fresh
-seeded problem: classification, cut-cell integration, loads, Schwarz
+inside FP64 CG (rtol 1e-10), patchwise additive Schwarz smoothing (one block
+per grid node, omega = 1/18, Section 3.3).  One step = one complete solve of
+a fresh seeded problem: classification, cut-cell integration, loads, Schwarz
 inverses, coarse factorisation (setup) and the MG-preconditioned CG.  Step k
 uses generator seed k; warm-up steps use seeds 1000+.
 
 Prints one JSON line.  `value` is solves/s over the timed steps; p50/p99 are
 per-solve latencies; the V-cycle throughput and the roofline of the dominant
-kernel (the finest-level Schwarz smoother) are timed with HIP events on the
-stream the library launches on, after the timed region.
+V-cycle kernel (the finest-level GEMV over the unique patch inverses, HBM
+bound) are timed with HIP events on the stream the library launches on,
+after the timed region.
 """
 import argparse
 import json
@@ -28,12 +30,13 @@ METRIC = "MG-PCG solves/s + V-cycle DOF/s (%HBM roofline) at rel. err 1e-8; p50/
 HBM_PEAK_GBS = 8000.0
 
 
-def cpu_baseline(n_sample=8):
+def cpu_baseline(n_sample=6):
     """Oracle (FP64 NumPy/SciPy) MG-PCG, setup + solve, on the workload's geometry
     at a reduced grid; scaled to the full workload by the ratio of fine DOFs."""
     import fcm_inputs as fi
     from oracle import fcm, mg
     desc, opts = fi.voided_cube_poisson(0, n=n_sample, p=3)
+    opts = dict(opts, smoother="patchwise", omega=1.0 / 18.0)
     t0 = time.perf_counter()
     disc = fcm.Discretization(desc)
     hier = mg.Hierarchy(disc, opts)
@@ -43,7 +46,7 @@ def cpu_baseline(n_sample=8):
     scale = full / disc.n_dofs
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": (f"oracle setup+MG-PCG of the same seeded voided cube at {n_sample}^3 cells, "
+            "sample": (f"oracle setup+MG-PCG (patchwise) of the same seeded voided cube at {n_sample}^3 cells, "
                        f"p=3 ({disc.n_dofs} DOFs, {it} iterations, {t:.1f} s), scaled by fine DOFs "
                        f"x{scale:.1f} to the 32^3 workload")}
 
@@ -113,6 +116,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--smoother", default="patchwise", choices=["patchwise", "elementwise"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="also time the plain FP64 form one problem at a time")
@@ -137,7 +141,8 @@ def main():
 
     def problem(seed, precision):
         d, o = fi.voided_cube_poisson(seed, n=args.n, p=3)
-        return d, dict(o, precision=precision)
+        return d, dict(o, precision=precision, smoother=args.smoother,
+                       omega=1.0 / 18.0 if args.smoother == "patchwise" else 2.0 / 15.0)
 
     def run_steps(seeds, precision, keep_last=False):
         lat, its, setup, solve, errs = [], [], [], [], []
@@ -176,9 +181,15 @@ def main():
     L = s.n_levels - 1
     n_fine = s.n_dofs[-1]
     ms_v, bytes_v = s.time_op("vcycle", reps=10)
-    ms_k, bytes_k = s.time_op("smooth", level=L, reps=50)
+    ms_s, bytes_s = s.time_op("smooth", level=L, reps=50)
     ms_r, bytes_r = s.time_op("residual", level=L, reps=50)
     ms_c, bytes_c = s.time_op("coarse", reps=10)
+    if args.smoother == "patchwise":
+        ms_k, bytes_k = s.time_op("smooth_stored", level=L, reps=50)
+        dom = "patch_gemv_kernel (finest level, unique patch inverses)"
+    else:
+        ms_k, bytes_k = ms_s, bytes_s
+        dom = "finest-level elementwise smoother"
     achieved = bytes_k / (ms_k * 1e-3) / 1e9
     st = s.stats()
     out = {
@@ -195,7 +206,8 @@ def main():
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic (seeded voided cube, seeds 0..steps-1)",
         "config": {"workload": f"cube_voids_poisson_{args.n}^3_p3", "n": args.n, "p": 3,
-                   "dofs": n_fine, "precision": args.precision, "alpha": 1e-10,
+                   "dofs": n_fine, "precision": args.precision, "smoother": args.smoother,
+                   "alpha": 1e-10,
                    "quad_depth": 3, "rtol": 1e-10, "parallelism": "none (1 GPU)"},
         "p50_ms": statistics.median(lat),
         "p99_ms": sorted(lat)[max(0, int(round(0.99 * len(lat))) - 1)],
@@ -207,7 +219,9 @@ def main():
         "vcycle_gdof_s": n_fine / (ms_v * 1e-3) / 1e9,
         "vcycle_hbm_frac": bytes_v / (ms_v * 1e-3) / 1e9 / HBM_PEAK_GBS,
         "kernels": {
-            "smooth_fine": {"ms": ms_k, "bytes": bytes_k},
+            "smooth_fine": {"ms": ms_s, "bytes": bytes_s,
+                            "gbs": bytes_s / (ms_s * 1e-3) / 1e9},
+            "stored_gemv_fine": {"ms": ms_k, "bytes": bytes_k},
             "residual_fine": {"ms": ms_r, "bytes": bytes_r,
                               "gbs": bytes_r / (ms_r * 1e-3) / 1e9},
             "coarse_solve": {"ms": ms_c, "bytes": bytes_c,
@@ -215,8 +229,8 @@ def main():
         },
         "problem": {k: st[k] for k in ("n_cut", "n_unique_blocks", "n_fp64_blocks",
                                         "coarse_blocks", "coarse_block_size", "device_bytes")},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }
     s.close()
     if args.compare_fp64:

@@ -215,9 +215,11 @@ fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s);
  * op: FCM_OP_SMOOTH (Schwarz smoother of `level`, handle precision),
  *     FCM_OP_RESIDUAL (residual update r -= omega A delta of `level`),
  *     FCM_OP_COARSE (one exact coarse solve), FCM_OP_VCYCLE (one V-cycle,
- *     bytes = sum over its launches).  Work vectors of the handle are used;
+ *     bytes = sum over its launches), FCM_OP_SMOOTH_STORED (patchwise only:
+ *     the kernel that streams the unique patch inverses of `level`, alone).  Work vectors of the handle are used;
  * their contents are overwritten.                                          */
-enum { FCM_OP_SMOOTH = 0, FCM_OP_RESIDUAL = 1, FCM_OP_COARSE = 2, FCM_OP_VCYCLE = 3 };
+enum { FCM_OP_SMOOTH = 0, FCM_OP_RESIDUAL = 1, FCM_OP_COARSE = 2, FCM_OP_VCYCLE = 3,
+       FCM_OP_SMOOTH_STORED = 4 };
 fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
                        double *ms_per_launch, double *bytes_per_launch);
 

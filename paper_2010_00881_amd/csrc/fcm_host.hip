@@ -1051,9 +1051,11 @@ static PatchArgs<T> patch_args(fcm_handle *h, int l) {
   a.matS64 = L.invS64;
   a.matU = Prec<T>::invU(L);
   if (std::is_same<T, float>::value) {
-    // FP32 storage where the block is well conditioned, FP64 otherwise
+    // FP32 storage where the block is well conditioned, FP64 otherwise; class
+    // (uncut) inverses in FP32 on the FP32 matrix cores
     a.matU64 = L.invU64;
     a.u64flag = L.hi64;
+    a.matS32 = L.invS32;
   }
   a.Ys = h->pYs;
   a.Yu = h->pYu;
@@ -1063,9 +1065,10 @@ static PatchArgs<T> patch_args(fcm_handle *h, int l) {
 // out = M_l^{-1} x; if xs: xs = (first ? 0 : xs) + omega * out.
 template <typename T>
 static void smooth_launch(fcm_handle *h, int l, const T *x, T *out, T *xs, T omega, int first,
-                          hipStream_t s) {
+                          hipStream_t s, bool stored_only = false) {
   if (h->opt.smoother == FCM_SMOOTH_PATCHWISE) {
     PatchArgs<T> a = patch_args<T>(h, l);
+    a.stored_only = stored_only;
     a.x = x;
     a.out = out;
     a.xs = xs;
@@ -1723,6 +1726,17 @@ static double op_bytes(const fcm_handle *h, int op, int l) {
   return 3.0 * L.npad * sv + mats + 4.0 * E;
 }
 
+// Unique-patch GEMV: every stored inverse streamed once (FP64 where flagged),
+// the gathered inputs read once, the FP64 products written once.
+static double stored_bytes(const fcm_handle *h, int l) {
+  const bool mixed = h->opt.precision == FCM_MIXED;
+  const fcm::Level &L = h->lev[l];
+  const double pm2 = (double)L.mpatch * L.mpatch;
+  const double nhi = mixed ? L.n_hi64 : h->np_unique;
+  const double mats = (h->np_unique - nhi) * pm2 * 4.0 + nhi * pm2 * 8.0;
+  return mats + (double)h->np_unique * L.mpatch * ((mixed ? 4.0 : 8.0) + 8.0);
+}
+
 static double coarse_bytes(const fcm_handle *h) {
   const fcm::Coarse &c = h->co;
   // S_k^{-1} (all blocks), G_k (k >= 1) and F_k (k < K-1) are each read once
@@ -1731,8 +1745,13 @@ static double coarse_bytes(const fcm_handle *h) {
 
 fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
                        double *ms_per_launch, double *bytes_per_launch) {
-  if (!h || reps < 1 || (op != FCM_OP_COARSE && op != FCM_OP_VCYCLE && (level < 1 || level > h->L))) {
+  if (!h || reps < 1 || op < FCM_OP_SMOOTH || op > FCM_OP_SMOOTH_STORED ||
+      (op != FCM_OP_COARSE && op != FCM_OP_VCYCLE && (level < 1 || level > h->L))) {
     set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  if (op == FCM_OP_SMOOTH_STORED && h->opt.smoother != FCM_SMOOTH_PATCHWISE) {
+    set_error("FCM_OP_SMOOTH_STORED needs the patchwise smoother");
     return FCM_ERR_ARG;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -1742,13 +1761,18 @@ fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
   FCM_HIP(hipEventCreate(&e1));
   double bytes = 0.0;
   auto launch = [&]() {
-    if (op == FCM_OP_SMOOTH || op == FCM_OP_RESIDUAL) {
+    if (op == FCM_OP_SMOOTH || op == FCM_OP_RESIDUAL || op == FCM_OP_SMOOTH_STORED) {
       fcm::Level &L = h->lev[level];
       if (op == FCM_OP_SMOOTH) {
         if (mixed)
           smooth_launch<float>(h, level, L.r32, L.d32, L.x32, (float)h->opt.omega, 0, s);
         else
           smooth_launch<double>(h, level, L.r64, L.d64, L.x64, h->opt.omega, 0, s);
+      } else if (op == FCM_OP_SMOOTH_STORED) {
+        if (mixed)
+          smooth_launch<float>(h, level, L.r32, L.d32, L.x32, (float)h->opt.omega, 0, s, true);
+        else
+          smooth_launch<double>(h, level, L.r64, L.d64, L.x64, h->opt.omega, 0, s, true);
       } else if (mixed) {
         OpArgs<float> a = op == FCM_OP_SMOOTH ? smoother_args<float>(h, level)
                                               : stiffness_args<float>(h, level);
@@ -1783,6 +1807,7 @@ fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
     }
   };
   if (op == FCM_OP_SMOOTH || op == FCM_OP_RESIDUAL) bytes = op_bytes(h, op, level);
+  else if (op == FCM_OP_SMOOTH_STORED) bytes = stored_bytes(h, level);
   else if (op == FCM_OP_COARSE) bytes = coarse_bytes(h);
   else {
     for (int l = 1; l <= h->L; ++l)

@@ -267,6 +267,7 @@ struct PatchArgs {
   const unsigned *cpres = nullptr; // [classes][pwords] mode presence bits per class
   int pwords = 0;
   const double *matS64 = nullptr; // [classes][m][ld]
+  const float *matS32 = nullptr;  // FP32 V-cycle: FP32 class inverses (matrix-core FP32 path)
   const T *matU = nullptr;        // [npu][m][ld]
   const double *matU64 = nullptr; // FP32 V-cycle: FP64 unique inverses where u64flag != 0
   const uint8_t *u64flag = nullptr;
@@ -276,6 +277,7 @@ struct PatchArgs {
   T *xs = nullptr;
   T omega = 0;
   int first = 0;
+  int stored_only = 0;            // timing hook: launch only the unique-patch GEMV
 };
 template <typename T>
 void launch_patch_op(const Geo &g, const Tables &t, const PatchTables &pt, const PatchArgs<T> &a,

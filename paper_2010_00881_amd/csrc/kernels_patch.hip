@@ -327,6 +327,106 @@ __global__ __launch_bounds__(512) void patch_class_mfma_kernel(Geo g,
   }
 }
 
+// FP32 variant for the FP32 V-cycle: class inverses are well conditioned
+// (uncut patches), so their products use v_mfma_f32_16x16x4f32 (FP32 inputs,
+// FP32 accumulation; lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
+// D[4(l/16)+j][l%16]).  Half-width registers leave room for the next group's
+// prefetch and two accumulation chains.
+typedef float floatx4p __attribute__((ext_vector_type(4)));
+
+template <int NKS>
+__global__ __launch_bounds__(512) void patch_class_mfma32_kernel(Geo g,
+                                                                 const int *__restrict__ pxoff,
+                                                                 PatchArgs<float> a) {
+  extern __shared__ float Xf[];   // [NKS * 4][16]
+  constexpr int KP = NKS * 4;
+  constexpr int PER = NKS / 8;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = lane & 15, kq = lane >> 4;
+  const int *ch = a.chk + 3 * blockIdx.y;
+  const int c = ch[0], p0 = ch[1], cnt = ch[2];
+  const int m = a.m, ld = a.ld;
+  const int rt = blockIdx.x * 8 + wave;
+  const bool rtv = 16 * rt < m;
+  const unsigned *pres = a.cpres + (size_t)c * a.pwords;
+  float av[NKS];
+  {
+    const float *A0 = a.matS32 + (size_t)c * m * ld;
+    const int r = 16 * rt + n;
+    const bool rv = rtv && r < m;
+    const int rc = min(r, m - 1);
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int k = 4 * ks + kq;
+      const float v = A0[(size_t)min(k, m - 1) * ld + rc];   // A[r][k] = A[k][r]
+      av[ks] = (rv && k < m) ? v : 0.f;
+    }
+  }
+  const int ngroups = (cnt + 15) >> 4;
+  float pf[PER];
+  auto fetch = [&](int gi) {
+    const int q0 = p0 + 16 * gi, qn = min(16, cnt - 16 * gi);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int i = threadIdx.x + 512 * j;
+      const int nn = i & 15, k = i >> 4;
+      float v = 0.f;
+      if (nn < qn && k < m && ((pres[k >> 5] >> (k & 31)) & 1u))
+        v = a.x[a.pnode[q0 + nn] + pxoff[k]];
+      pf[j] = v;
+    }
+  };
+  fetch(0);
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const int q0 = p0 + 16 * gi, qn = min(16, cnt - 16 * gi);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) Xf[threadIdx.x + 512 * j] = pf[j];
+    __syncthreads();
+    if (gi + 1 < ngroups) fetch(gi + 1);
+    if (rtv) {
+      floatx4p acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ks += 2) {
+        acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks], Xf[(4 * ks + kq) * 16 + n], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(av[ks + 1], Xf[(4 * ks + 4 + kq) * 16 + n], acc1,
+                                                    0, 0, 0);
+      }
+      if (n < qn) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rr = 16 * rt + 4 * kq + j;
+          if (rr < m) a.Ys[(size_t)rr * a.nsh + q0 + n] = (double)(acc0[j] + acc1[j]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <int NKS>
+static void launch_class32_nks(const Geo &g, const PatchTables &pt, const PatchArgs<float> &a,
+                               hipStream_t s) {
+  const int nrt = (a.m + 15) / 16;
+  dim3 grid((nrt + 7) / 8, a.nchunks);
+  patch_class_mfma32_kernel<NKS><<<grid, 512, (size_t)NKS * 4 * 16 * sizeof(float), s>>>(
+      g, pt.pxoff, a);
+}
+
+static bool launch_class32(const Geo &g, const PatchTables &pt, const PatchArgs<float> &a,
+                           hipStream_t s) {
+  if (!a.matS32) return false;
+  const int nks = (a.m + 3) / 4;
+  if (nks <= 8) launch_class32_nks<8>(g, pt, a, s);
+  else if (nks <= 16) launch_class32_nks<16>(g, pt, a, s);
+  else if (nks <= 24) launch_class32_nks<24>(g, pt, a, s);
+  else if (nks <= 32) launch_class32_nks<32>(g, pt, a, s);
+  else if (nks <= 48) launch_class32_nks<48>(g, pt, a, s);
+  else if (nks <= 64) launch_class32_nks<64>(g, pt, a, s);
+  else if (nks <= 88) launch_class32_nks<88>(g, pt, a, s);
+  else launch_class32_nks<96>(g, pt, a, s);
+  return true;
+}
+
 template <typename T, int NKS>
 static void launch_class_nks(const Geo &g, const PatchTables &pt, const PatchArgs<T> &a,
                              hipStream_t s) {
@@ -404,7 +504,12 @@ template <typename T>
 void launch_patch_op(const Geo &g, const Tables &t, const PatchTables &pt, const PatchArgs<T> &a,
                      hipStream_t s) {
   if (a.npu > 0) patch_gemv_kernel<T><<<a.npu, 256, 0, s>>>(g, pt.pxoff, pt.pinfo, a);
-  if (a.nsh > 0 && a.nchunks > 0) launch_class<T>(g, pt, a, s);
+  if (a.stored_only) return;
+  if (a.nsh > 0 && a.nchunks > 0) {
+    bool done = false;
+    if constexpr (std::is_same<T, float>::value) done = launch_class32(g, pt, a, s);
+    if (!done) launch_class<T>(g, pt, a, s);
+  }
   dim3 grid((g.G + 255) / 256, a.nP_out);
   patch_gather_kernel<T><<<grid, 256, 0, s>>>(g, pt.prow, t.pinfo, a);
 }

@@ -135,46 +135,57 @@ void launch_classify(const Geo &g, const double *ball, uint8_t *state, hipStream
 }
 
 // ----------------------------------------------------------------- integrate
-// One workgroup per cut element.  Leaves of the sub-cell tree are enumerated
-// breadth first in a fixed order (deterministic accumulation).  The stiffness
-// is accumulated as gradient moments G_kl(a,b) = int alpha d_k N_a d_l N_b
-// over scalar modes a,b (one moment, the trace, for Poisson), each thread
-// owning a 4x4 tile of mode pairs.
+// One workgroup per cut element (or the reference element).  Leaves of the
+// sub-cell tree (bisection of cut sub-cells to the given depth) are
+// enumerated breadth first in a fixed order; every leaf gets the tensor Gauss
+// rule with NP = p+1 points per axis and alpha evaluated per point (constant
+// on uncut leaves), as in Section 4.3.1.  The stiffness moments
+//   G^{kl}_{ab} = sum_q w_q alpha_q (dN_a/dx_k)(dN_b/dx_l)
+// over scalar tensor modes a = (a0,a1,a2), b = (b0,b1,b2) are evaluated by sum
+// factorisation over the leaf's tensor points (F = value V or derivative D of
+// the 1D modes per axis, chosen by the moment):
+//   T1[q0 q1][a2 b2] = sum_q2 F2_a2(q2) F2_b2(q2) W[q0 q1 q2]     (LDS)
+//   t2[q0]           = sum_q1 F1_a1(q1) F1_b1(q1) T1[q0 q1][a2 b2] (thread)
+//   G[a0 b0; r]     += sum_q0 F0_a0(q0) F0_b0(q0) t2[q0]           (registers)
+// Each thread owns one rest index r = (a1,b1,a2,b2) and all NP^2 pairs
+// (a0,b0), so the element matrix accumulates in registers in a fixed order.
+// Poisson: K = kappa sum_k G^{kk}; elasticity: K_{(a,i),(b,j)} = lambda G^{ij}
+// + mu G^{ji} + mu delta_ij sum_k G^{kk} (eq. weakform with isotropic C).
 constexpr int kIntThreads = 256;
 
 struct IntegArgs {
   Geo g;
-  const double *ball, *gsrc, *tab1d, *gxw;
+  const double *ball, *gsrc, *gxw;
   const int *smap;
-  int ngauss, ms, m, np, elastic;
+  int ngauss, ms, m, elastic;
   double fconst, kappa, lam, mu;
   double bf[3];
   const int *elist;
   int ref_mode;
   double *Kout, *be_all;
-  // shared-memory carve (in doubles / ints)
-  int max_leaves, max_cur, max_child, pb;
+  int max_leaves, max_cur, max_child;
 };
 
 __device__ inline int leaf_pack(int lvl, int kind, int ix, int iy, int iz) {
   return lvl | (kind << 3) | (ix << 5) | (iy << 10) | (iz << 15);
 }
 
-template <int NM>
+template <int NP>
 __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
+  constexpr int NP2 = NP * NP, NP3 = NP2 * NP;
   extern __shared__ double smem[];
   const Geo &g = A.g;
-  const int d = g.d, np = A.np, np2 = np * np, ms = A.ms;
-  const int nint = (2 << g.depth) - 1;
-  double *tab = smem;                              // nint*3*np2
-  double *V1 = tab + nint * 3 * np2;               // [3][np][np]
-  double *D1v = V1 + 3 * np2;                      // [3][np][np]
-  double *wa = D1v + 3 * np2;                      // [np^d]
-  double *grads = wa + 343;                        // [pb][ms][d]
-  int *leaves = (int *)(grads + A.pb * ms * d);    // [max_leaves]
-  int *curA = leaves + A.max_leaves;               // [max_cur]
+  const int d = g.d, nf = g.nf, ms = A.ms, m = A.m;
+  double *Fv = smem;                     // [3][NP q][NP a] mode values
+  double *Fd = Fv + 3 * NP2;             // [3][NP][NP] physical derivatives
+  double *W = Fd + 3 * NP2;              // [NP^3] w * alpha
+  double *Wf = W + NP3;                  // [NP^3] w * alpha * f
+  double *P = Wf + NP3;                  // [2 axes][4 types][NP q][NP a][NP b]
+  double *T1 = P + 8 * NP3;              // [2][NP^2 (q0,q1)][NP^2 (a2,b2)]
+  int *leaves = (int *)(T1 + 2 * NP2 * NP2);
+  int *curA = leaves + A.max_leaves;
   int *curB = curA + A.max_cur;
-  uint8_t *chst = (uint8_t *)(curB + A.max_cur);   // [max_child]
+  uint8_t *chst = (uint8_t *)(curB + A.max_cur);
   __shared__ int s_nleaf, s_ncur;
 
   const int tid = threadIdx.x;
@@ -184,8 +195,6 @@ __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
   double elo[3];
   for (int ax = 0; ax < 3; ++ax) elo[ax] = g.lo[ax] + ec[ax] * g.h[ax];
   if (A.ref_mode) elo[0] = elo[1] = elo[2] = 0.0;
-
-  for (int i = tid; i < nint * 3 * np2; i += kIntThreads) tab[i] = A.tab1d[i];
 
   // ---- enumerate leaves
   if (tid == 0) {
@@ -204,7 +213,7 @@ __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
     }
   }
   __syncthreads();
-  for (int lvl = 0; lvl < g.depth; ++lvl) {
+  for (int lvl = 0; lvl < g.depth && !A.ref_mode; ++lvl) {
     int *cur = (lvl & 1) ? curB : curA;
     int *nxt = (lvl & 1) ? curA : curB;
     const int ncur = s_ncur;
@@ -232,13 +241,9 @@ __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
         int ci[3];
         for (int ax = 0; ax < 3; ++ax) ci[ax] = ax < d ? 2 * idx[ax] + ((bits >> ax) & 1) : 0;
         int st = chst[c];
-        if (st != kCut) {
-          leaves[nl++] = leaf_pack(lvl + 1, st, ci[0], ci[1], ci[2]);
-        } else if (lvl + 1 < g.depth) {
-          nxt[nn++] = leaf_pack(lvl + 1, kCut, ci[0], ci[1], ci[2]);
-        } else {
-          leaves[nl++] = leaf_pack(lvl + 1, kCut, ci[0], ci[1], ci[2]);
-        }
+        if (st != kCut) leaves[nl++] = leaf_pack(lvl + 1, st, ci[0], ci[1], ci[2]);
+        else if (lvl + 1 < g.depth) nxt[nn++] = leaf_pack(lvl + 1, kCut, ci[0], ci[1], ci[2]);
+        else leaves[nl++] = leaf_pack(lvl + 1, kCut, ci[0], ci[1], ci[2]);
       }
       s_nleaf = nl;
       s_ncur = nn;
@@ -246,224 +251,175 @@ __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
     __syncthreads();
   }
   const int nleaf = s_nleaf;
+  const int nq2 = d == 3 ? NP : 1;
+  const int Q = NP2 * nq2;
+  const double *gx = A.gxw, *gw = A.gxw + NP;
+  const int R = d == 3 ? NP2 * NP2 : NP2;           // rest indices (a1,b1[,a2,b2])
+  const int ngroups = A.elastic ? d * d : 1;        // moment groups
+  double bacc[2] = {0.0, 0.0};
+  const bool want_load = !A.ref_mode;
+  double *Kel = A.ref_mode ? A.Kout : A.Kout + (size_t)blockIdx.x * m * m;
 
-  // Jacobian factors: d/dx_k = (2/h_k) d/dxi_k ; dx = prod (h/2) dxi
-  double vol = 1.0;
-  for (int ax = 0; ax < d; ++ax) vol *= 0.5 * g.h[ax];
-  double inv_h2[3];
-  for (int ax = 0; ax < 3; ++ax) inv_h2[ax] = 2.0 / g.h[ax];
-  const int Q = (d == 2) ? np2 : np2 * np;
-  const double *gx = A.gxw, *gw = A.gxw + np;
-
-  // ---- stiffness moments, 4x4 mode-pair tiles per thread
-  const int nta = (ms + 3) / 4;
-  const int ntile = nta * nta;
-  for (int base = 0; base < ntile; base += kIntThreads) {
-    const int tile = base + tid;
-    const bool active = tile < ntile;
-    const int ta = active ? tile / nta : 0, tb = active ? tile % nta : 0;
-    int sa[4], sb[4], aa[4][3], bb[4][3];
-    for (int i = 0; i < 4; ++i) {
-      sa[i] = min(4 * ta + i, ms - 1);
-      sb[i] = min(4 * tb + i, ms - 1);
-      int r = sa[i];
-      aa[i][0] = r % np; r /= np; aa[i][1] = r % np; aa[i][2] = r / np;
-      r = sb[i];
-      bb[i][0] = r % np; r /= np; bb[i][1] = r % np; bb[i][2] = r / np;
-      if (d == 2) { aa[i][2] = 0; bb[i][2] = 0; }
+  for (int r0 = 0; r0 < R; r0 += kIntThreads) {
+    const int r = r0 + tid;
+    const bool ractive = r < R;
+    const int rr = ractive ? r : 0;
+    const int a1 = (rr % NP2) / NP, b1 = rr % NP;
+    const int a2 = d == 3 ? (rr / NP2) / NP : 0, b2 = d == 3 ? (rr / NP2) % NP : 0;
+    if (A.elastic && ractive) {
+      // this thread owns the K entries of its (a, b) pairs for all components
+      for (int a0 = 0; a0 < NP; ++a0)
+        for (int b0 = 0; b0 < NP; ++b0) {
+          const int sa = a0 + NP * (a1 + NP * a2), sb = b0 + NP * (b1 + NP * b2);
+          for (int ci = 0; ci < nf; ++ci)
+            for (int cj = 0; cj < nf; ++cj)
+              Kel[(size_t)A.smap[sa * nf + ci] * m + A.smap[sb * nf + cj]] = 0.0;
+        }
     }
-    double acc[4][4][NM];
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 4; ++j)
-        for (int k = 0; k < NM; ++k) acc[i][j][k] = 0.0;
-
-    for (int lf = 0; lf < nleaf; ++lf) {
-      const int pk = leaves[lf];
-      const int lvl = pk & 7, kind = (pk >> 3) & 3;
-      const int li[3] = {(pk >> 5) & 31, (pk >> 10) & 31, (pk >> 15) & 31};
-      const int nsub = 1 << lvl;
-      if (kind != kCut) {
-        // closed form over the sub-box: product of 1D sub-interval integrals
-        const double al = (kind == kPhys) ? 1.0 : g.alpha;
-        const double *T[3];
-        for (int ax = 0; ax < 3; ++ax) T[ax] = tab + ((nsub - 1) + (ax < d ? li[ax] : 0)) * 3 * np2;
-        if (active) {
-          for (int i = 0; i < 4; ++i)
-            for (int j = 0; j < 4; ++j) {
-              if (NM == 1) {
-                double s = 0.0;
-                for (int k = 0; k < d; ++k) {
-                  double pr = inv_h2[k] * inv_h2[k];
-                  for (int ax = 0; ax < d; ++ax) {
-                    const double *M = T[ax] + (ax == k ? np2 : 0);
-                    pr *= M[aa[i][ax] * np + bb[j][ax]];
-                  }
-                  s += pr;
-                }
-                acc[i][j][0] += al * vol * s;
-              } else {
-                for (int k = 0; k < d; ++k)
-                  for (int l = 0; l < d; ++l) {
-                    double pr = inv_h2[k] * inv_h2[l] * vol * al;
-                    for (int ax = 0; ax < d; ++ax) {
-                      double v;
-                      if (ax == k && ax == l) v = T[ax][np2 + aa[i][ax] * np + bb[j][ax]];
-                      else if (ax == k) v = T[ax][2 * np2 + aa[i][ax] * np + bb[j][ax]];
-                      else if (ax == l) v = T[ax][2 * np2 + bb[j][ax] * np + aa[i][ax]];
-                      else v = T[ax][aa[i][ax] * np + bb[j][ax]];
-                      pr *= v;
-                    }
-                    acc[i][j][k * d + l] += pr;
-                  }
-              }
-            }
+    for (int grp = 0; grp < ngroups; ++grp) {
+      const int mk = grp / d, ml = grp % d;   // elasticity moment (k, l)
+      double acc[NP2];
+#pragma unroll
+      for (int i = 0; i < NP2; ++i) acc[i] = 0.0;
+      const bool do_load = want_load && r0 == 0 && grp == 0;
+      for (int lf = 0; lf < nleaf; ++lf) {
+        const int pk = leaves[lf];
+        const int lvl = pk & 7, kind = (pk >> 3) & 3;
+        const int li[3] = {(pk >> 5) & 31, (pk >> 10) & 31, (pk >> 15) & 31};
+        const double half = 1.0 / (1 << lvl);
+        __syncthreads();
+        // phase A: 1D tables at the leaf's Gauss points, point weights
+        if (tid < d * NP) {
+          const int ax = tid / NP, q = tid % NP;
+          const double xi = -1.0 + (2.0 * li[ax] + 1.0) * half + half * gx[q];
+          double v[kMaxP + 1], dv[kMaxP + 1];
+          modes1d_dev(NP - 1, xi, v, dv);
+          const double sc = 2.0 / g.h[ax];
+          for (int a = 0; a < NP; ++a) {
+            Fv[(ax * NP + q) * NP + a] = v[a];
+            Fd[(ax * NP + q) * NP + a] = sc * dv[a];
+          }
         }
-        continue;
-      }
-      // pointwise quadrature on a cut leaf
-      __syncthreads();
-      const double half = 1.0 / nsub;                       // half-width in xi
-      if (tid < d * np) {
-        int ax = tid / np, qa = tid % np;
-        double xi = -1.0 + (2.0 * li[ax] + 1.0) * half + half * gx[qa];
-        modes1d_dev(A.np - 1, xi, V1 + ax * np2 + qa * np, D1v + ax * np2 + qa * np);
-      }
-      for (int q = tid; q < Q; q += kIntThreads) {
-        int qc[3] = {q % np, (q / np) % np, q / np2};
-        double x[3] = {0, 0, 0};
-        double w = 1.0;
-        for (int ax = 0; ax < d; ++ax) {
-          double xi = -1.0 + (2.0 * li[ax] + 1.0) * half + half * gx[qc[ax]];
-          x[ax] = elo[ax] + 0.5 * (xi + 1.0) * g.h[ax];
-          w *= gw[qc[ax]] * half * 0.5 * g.h[ax];
-        }
-        wa[q] = w * (inside_phys_dev(g, A.ball, x) ? 1.0 : g.alpha);
-      }
-      __syncthreads();
-      for (int q0 = 0; q0 < Q; q0 += A.pb) {
-        const int nq = min(A.pb, Q - q0);
-        for (int i = tid; i < nq * ms * d; i += kIntThreads) {
-          int k = i % d, s = (i / d) % ms, qq = i / (d * ms);
-          int q = q0 + qq;
-          int qc[3] = {q % np, (q / np) % np, q / np2};
-          int sc[3] = {s % np, (s / np) % np, s / np2};
-          double v = inv_h2[k];
+        for (int q = tid; q < Q; q += kIntThreads) {
+          const int qc[3] = {q % NP, (q / NP) % NP, q / NP2};
+          double x[3] = {0.0, 0.0, 0.0};
+          double w = 1.0;
           for (int ax = 0; ax < d; ++ax) {
-            const double *tb1 = (ax == k ? D1v : V1) + ax * np2 + qc[ax] * np;
-            v *= tb1[sc[ax]];
+            const double xi = -1.0 + (2.0 * li[ax] + 1.0) * half + half * gx[qc[ax]];
+            x[ax] = elo[ax] + 0.5 * (xi + 1.0) * g.h[ax];
+            w *= gw[qc[ax]] * half * 0.5 * g.h[ax];
           }
-          grads[i] = v;
+          double al;
+          if (kind == kPhys) al = 1.0;
+          else if (kind == kVoid) al = g.alpha;
+          else al = inside_phys_dev(g, A.ball, x) ? 1.0 : g.alpha;
+          W[q] = w * al;
+          if (do_load)
+            Wf[q] = w * al * (A.elastic ? 1.0 : source_dev(A.gsrc, A.ngauss, A.fconst, x, d));
         }
         __syncthreads();
-        if (active) {
-          for (int qq = 0; qq < nq; ++qq) {
-            const double w = wa[q0 + qq];
-            const double *gq = grads + qq * ms * d;
-            double ga[4][3], gb[4][3];
-            for (int i = 0; i < 4; ++i)
-              for (int k = 0; k < d; ++k) {
-                ga[i][k] = gq[sa[i] * d + k] * w;
-                gb[i][k] = gq[sb[i] * d + k];
-              }
-            for (int i = 0; i < 4; ++i)
-              for (int j = 0; j < 4; ++j) {
-                if (NM == 1) {
-                  double s = 0.0;
-                  for (int k = 0; k < d; ++k) s += ga[i][k] * gb[j][k];
-                  acc[i][j][0] += s;
-                } else {
-                  for (int k = 0; k < d; ++k)
-                    for (int l = 0; l < d; ++l) acc[i][j][k * d + l] += ga[i][k] * gb[j][l];
-                }
-              }
+        // phase B: pair tables of axes 0, 1 and the q2-contraction T1
+        for (int i = tid; i < 8 * NP3; i += kIntThreads) {
+          const int ax = i / (4 * NP3), t = (i / NP3) & 3, q = (i / NP2) % NP;
+          const int a = (i / NP) % NP, b = i % NP;
+          const double fa = ((t >> 1) ? Fd : Fv)[(ax * NP + q) * NP + a];
+          const double fb = ((t & 1) ? Fd : Fv)[(ax * NP + q) * NP + b];
+          P[i] = fa * fb;
+        }
+        if (d == 3) {
+          // T1[0]: axis-2 pair type of the group (Poisson: VV), T1[1]: DD (Poisson k = 2)
+          const int t0 = A.elastic ? 2 * (mk == 2) + (ml == 2) : 0;
+          const int nt = A.elastic ? 1 : 2;
+          for (int i = tid; i < nt * NP2 * NP2; i += kIntThreads) {
+            const int which = i / (NP2 * NP2), j = i % (NP2 * NP2);
+            const int t = which ? 3 : t0;
+            const int q01 = j / NP2, a2i = (j % NP2) / NP, b2i = j % NP;
+            const double *Fa = (t >> 1) ? Fd : Fv, *Fb = (t & 1) ? Fd : Fv;
+            double sum = 0.0;
+            for (int q2 = 0; q2 < NP; ++q2)
+              sum += Fa[(2 * NP + q2) * NP + a2i] * Fb[(2 * NP + q2) * NP + b2i] * W[q01 + NP2 * q2];
+            T1[i] = sum;
+          }
+        } else {
+          for (int i = tid; i < NP2; i += kIntThreads) T1[i] = W[i];
+        }
+        if (do_load) {
+          for (int k = 0; k < 2; ++k) {
+            const int sidx = tid + k * kIntThreads;
+            if (sidx >= ms) continue;
+            const int sc[3] = {sidx % NP, (sidx / NP) % NP, sidx / NP2};
+            double sum = 0.0;
+            for (int q = 0; q < Q; ++q) {
+              const int qc[3] = {q % NP, (q / NP) % NP, q / NP2};
+              double v = Wf[q] * Fv[qc[0] * NP + sc[0]] * Fv[(NP + qc[1]) * NP + sc[1]];
+              if (d == 3) v *= Fv[(2 * NP + qc[2]) * NP + sc[2]];
+              sum += v;
+            }
+            bacc[k] += sum;
           }
         }
         __syncthreads();
+        // phase C: per-thread contraction over q1 and q0
+        if (ractive) {
+          const int ncombo = A.elastic ? 1 : d;
+#pragma unroll 1
+          for (int cb = 0; cb < ncombo; ++cb) {
+            int t0, t1, tT;
+            if (A.elastic) {
+              t0 = 2 * (mk == 0) + (ml == 0);
+              t1 = 2 * (mk == 1) + (ml == 1);
+              tT = 0;
+            } else {
+              // Poisson moment k = cb: DD on axis k, VV elsewhere
+              t0 = cb == 0 ? 3 : 0;
+              t1 = cb == 1 ? 3 : 0;
+              tT = (d == 3 && cb == 2) ? 1 : 0;
+            }
+            const double *P0 = P + t0 * NP3;
+            const double *P1 = P + (4 + t1) * NP3 + a1 * NP + b1;
+            const double *Tb = T1 + tT * NP2 * NP2 + a2 * NP + b2;
+            const int tstride = d == 3 ? NP2 : 1;
+#pragma unroll 1
+            for (int q0 = 0; q0 < NP; ++q0) {
+              double s2 = 0.0;
+#pragma unroll
+              for (int q1 = 0; q1 < NP; ++q1) s2 += P1[q1 * NP2] * Tb[(q0 + NP * q1) * tstride];
+              const double *p0 = P0 + q0 * NP2;
+#pragma unroll
+              for (int ab = 0; ab < NP2; ++ab) acc[ab] += p0[ab] * s2;
+            }
+          }
+        }
       }
-    }
-    // ---- write element matrix entries of this tile
-    if (active) {
-      const int m = A.m, nf = A.g.nf;
-      double *K = A.ref_mode ? A.Kout : A.Kout + (size_t)blockIdx.x * m * m;
-      for (int i = 0; i < 4; ++i) {
-        if (4 * ta + i >= ms) continue;
-        for (int j = 0; j < 4; ++j) {
-          if (4 * tb + j >= ms) continue;
-          if (NM == 1) {
-            int la = A.smap[sa[i]], lb = A.smap[sb[j]];
-            K[(size_t)la * m + lb] = A.kappa * acc[i][j][0];
-          } else {
-            double tr = 0.0;
-            for (int k = 0; k < d; ++k) tr += acc[i][j][k * d + k];
-            for (int ci = 0; ci < nf; ++ci)
-              for (int cj = 0; cj < nf; ++cj) {
-                int la = A.smap[sa[i] * nf + ci], lb = A.smap[sb[j] * nf + cj];
-                double v = A.lam * acc[i][j][ci * d + cj] + A.mu * acc[i][j][cj * d + ci];
-                if (ci == cj) v += A.mu * tr;
-                K[(size_t)la * m + lb] = v;
-              }
+      // ---- write this group's contribution
+      if (ractive) {
+#pragma unroll
+        for (int a0 = 0; a0 < NP; ++a0)
+#pragma unroll
+          for (int b0 = 0; b0 < NP; ++b0) {
+            const double G = acc[a0 * NP + b0];
+            const int sa = a0 + NP * (a1 + NP * a2), sb = b0 + NP * (b1 + NP * b2);
+            if (!A.elastic) {
+              Kel[(size_t)A.smap[sa] * m + A.smap[sb]] = A.kappa * G;
+            } else {
+              Kel[(size_t)A.smap[sa * nf + mk] * m + A.smap[sb * nf + ml]] += A.lam * G;
+              Kel[(size_t)A.smap[sa * nf + ml] * m + A.smap[sb * nf + mk]] += A.mu * G;
+              if (mk == ml)
+                for (int c = 0; c < nf; ++c)
+                  Kel[(size_t)A.smap[sa * nf + c] * m + A.smap[sb * nf + c]] += A.mu * G;
+            }
           }
-        }
       }
     }
   }
-  if (A.ref_mode) return;
-
-  // ---- element load: all leaves, pointwise source, alpha per point
-  double accb[2] = {0.0, 0.0};
-  const int s0 = tid, s1 = tid + kIntThreads;
-  for (int lf = 0; lf < nleaf; ++lf) {
-    const int pk = leaves[lf];
-    const int lvl = pk & 7, kind = (pk >> 3) & 3;
-    const int li[3] = {(pk >> 5) & 31, (pk >> 10) & 31, (pk >> 15) & 31};
-    const double half = 1.0 / (1 << lvl);
-    __syncthreads();
-    if (tid < d * np) {
-      int ax = tid / np, qa = tid % np;
-      double xi = -1.0 + (2.0 * li[ax] + 1.0) * half + half * gx[qa];
-      modes1d_dev(A.np - 1, xi, V1 + ax * np2 + qa * np, D1v + ax * np2 + qa * np);
-    }
-    for (int q = tid; q < Q; q += kIntThreads) {
-      int qc[3] = {q % np, (q / np) % np, q / np2};
-      double x[3] = {0, 0, 0};
-      double w = 1.0;
-      for (int ax = 0; ax < d; ++ax) {
-        double xi = -1.0 + (2.0 * li[ax] + 1.0) * half + half * gx[qc[ax]];
-        x[ax] = elo[ax] + 0.5 * (xi + 1.0) * g.h[ax];
-        w *= gw[qc[ax]] * half * 0.5 * g.h[ax];
-      }
-      double al;
-      if (kind == kPhys) al = 1.0;
-      else if (kind == kVoid) al = g.alpha;
-      else al = inside_phys_dev(g, A.ball, x) ? 1.0 : g.alpha;
-      double f = A.elastic ? 1.0 : source_dev(A.gsrc, A.ngauss, A.fconst, x, d);
-      wa[q] = w * al * f;
-    }
-    __syncthreads();
-    for (int r = 0; r < 2; ++r) {
-      int s = r == 0 ? s0 : s1;
-      if (s >= ms) continue;
-      int sc[3] = {s % np, (s / np) % np, s / np2};
-      double sum = 0.0;
-      for (int q = 0; q < Q; ++q) {
-        int qc[3] = {q % np, (q / np) % np, q / np2};
-        double v = wa[q];
-        for (int ax = 0; ax < d; ++ax) v *= V1[ax * np2 + qc[ax] * np + sc[ax]];
-        sum += v;
-      }
-      accb[r] += sum;
-    }
-  }
-  for (int r = 0; r < 2; ++r) {
-    int s = r == 0 ? s0 : s1;
-    if (s >= ms) continue;
-    const int m = A.m, nf = A.g.nf;
+  if (!want_load) return;
+  for (int k = 0; k < 2; ++k) {
+    const int sidx = tid + k * kIntThreads;
+    if (sidx >= ms) continue;
     double *be = A.be_all + (size_t)e * m;
-    if (!A.elastic) {
-      be[A.smap[s]] = accb[r];
-    } else {
-      for (int c = 0; c < nf; ++c) be[A.smap[s * nf + c]] = A.bf[c] * accb[r];
-    }
+    if (!A.elastic) be[A.smap[sidx]] = bacc[k];
+    else
+      for (int c = 0; c < nf; ++c) be[A.smap[sidx * nf + c]] = A.bf[c] * bacc[k];
   }
 }
 
@@ -476,13 +432,11 @@ void launch_integrate(const Geo &g, const Tables &t, const fcm_problem &pr, cons
   A.g = g;
   A.ball = t.ball;
   A.gsrc = t.gsrc;
-  A.tab1d = t.tab1d;
   A.gxw = t.gxw;
   A.smap = t.smap;
   A.ngauss = pr.n_gauss;
   A.ms = t.ms;
   A.m = t.m;
-  A.np = g.p + 1;
   A.elastic = g.nf > 1;
   A.fconst = pr.f_const;
   A.kappa = pr.kappa;
@@ -503,25 +457,20 @@ void launch_integrate(const Geo &g, const Tables &t, const fcm_problem &pr, cons
   A.max_leaves = maxl;
   A.max_cur = cur;
   A.max_child = maxc;
-  const int np = g.p + 1, np2 = np * np;
-  const int nint = (2 << g.depth) - 1;
-  size_t fixed = (size_t)(nint * 3 * np2 + 6 * np2 + 343) * 8 + (size_t)(maxl + 2 * cur) * 4 + maxc + 64;
-  const size_t budget = 60 * 1024;
-  int pb = (int)((budget - std::min(budget - 8192, fixed)) / ((size_t)t.ms * g.d * 8));
-  pb = std::max(1, std::min(pb, 64));
-  A.pb = pb;
-  size_t shm = fixed + (size_t)pb * t.ms * g.d * 8;
+  const int np = g.p + 1, np2 = np * np, np3 = np2 * np;
+  const size_t shm = (size_t)(6 * np2 + 2 * np3 + 8 * np3 + 2 * np2 * np2) * sizeof(double) +
+                     (size_t)(maxl + 2 * cur) * sizeof(int) + maxc + 16;
   dim3 grid(ref_mode ? 1 : nlist);
-  if (g.nf == 1)
-    integrate_kernel<1><<<grid, kIntThreads, shm, s>>>(A);
-  else if (g.d == 3)
-    integrate_kernel<9><<<grid, kIntThreads, shm, s>>>(A);
-  else
-    integrate_kernel<4><<<grid, kIntThreads, shm, s>>>(A);
+  switch (np) {
+    case 2: integrate_kernel<2><<<grid, kIntThreads, shm, s>>>(A); break;
+    case 3: integrate_kernel<3><<<grid, kIntThreads, shm, s>>>(A); break;
+    case 4: integrate_kernel<4><<<grid, kIntThreads, shm, s>>>(A); break;
+    case 5: integrate_kernel<5><<<grid, kIntThreads, shm, s>>>(A); break;
+    case 6: integrate_kernel<6><<<grid, kIntThreads, shm, s>>>(A); break;
+    default: integrate_kernel<7><<<grid, kIntThreads, shm, s>>>(A); break;
+  }
 }
 
-// ------------------------------------------------------------ uncut loads
-// One 64-thread workgroup per uncut element: (p+1)^d Gauss rule on the element.
 __global__ __launch_bounds__(64) void phys_rhs_kernel(Geo g, const double *gxw,
                                                       const double *vgauss, const int *smap,
                                                       const double *gsrc, int ngauss,

@@ -327,7 +327,7 @@ class Solver:
         _check(lib().fcm_element(self.h, int(e), ctypes.byref(st), _dptr(K), _dptr(be)))
         return st.value, K, be
 
-    OPS = {"smooth": 0, "residual": 1, "coarse": 2, "vcycle": 3}
+    OPS = {"smooth": 0, "residual": 1, "coarse": 2, "vcycle": 3, "smooth_stored": 4}
 
     def time_op(self, op, level=None, reps=20):
         """(ms per launch, algorithmic bytes per launch) timed with HIP events."""
