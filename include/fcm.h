@@ -158,6 +158,15 @@ fcm_status fcm_apply(fcm_handle *h, int level, const double *x, double *y,
 fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z,
                       void *stream);
 
+/* Test hook for the batched SPD inversion used by the Schwarz blocks and the
+ * coarse factorisation: A_dev (device, `batch` row-major n x n FP64 SPD
+ * matrices, contiguous) is overwritten by the inverses, computed on `stream`
+ * by the Jacobi-scaled Gauss-Jordan sweep.  kappa_dev (device, may be NULL)
+ * receives ||A_s||_1 ||A_s^{-1}||_1 of each Jacobi-scaled matrix.  Returns
+ * FCM_ERR_NOT_SPD if a pivot was not positive.  Synchronises the stream.    */
+fcm_status fcm_spd_inverse(double *A_dev, int n, int batch, double *kappa_dev,
+                           void *stream);
+
 /* x = A_0^{-1} b on the coarsest level (exact FP64 solve).                  */
 fcm_status fcm_coarse_solve(fcm_handle *h, const double *b, double *x,
                             void *stream);

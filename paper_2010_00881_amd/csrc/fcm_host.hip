@@ -419,7 +419,11 @@ static fcm_status check_flag(fcm_handle *h, const char *what) {
   return FCM_OK;
 }
 
-static fcm_status setup_coarse(fcm_handle *h) {
+// Coarse level: layer-block-tridiagonal factorisation (exact solve on level
+// 0).  Allocation happens on the handle's stream; the factorisation chain is
+// issued on a second stream `cs` (it depends only on the element matrices)
+// so that it overlaps the Schwarz block setup; coarse_join waits for it.
+static fcm_status setup_coarse_alloc(fcm_handle *h) {
   const Geo &g = h->geo;
   Coarse &c = h->co;
   const int sl = g.d - 1;
@@ -446,20 +450,41 @@ static fcm_status setup_coarse(fcm_handle *h) {
   TRY(dalloc(h, &c.xblk, (size_t)c.nblk * c.nb));
   TRY(dalloc(h, &c.bblk, (size_t)c.nblk * c.nb));
   TRY(dalloc(h, &c.bb, (size_t)g.nf * g.G));
-  double *scr = nullptr;
-  FCM_HIP(hipMalloc((void **)&scr, spd_inverse_scratch_doubles(c.nb, 1) * sizeof(double)));
-  launch_coarse_stencils(g, h->tab, c, h->kmat, h->Kref64, h->Kcut64, h->stream);
+  FCM_HIP(hipMalloc((void **)&h->co_scr, spd_inverse_scratch_doubles(c.nb, 1) * sizeof(double)));
+  return FCM_OK;
+}
+
+static fcm_status setup_coarse_launch(fcm_handle *h, hipStream_t cs) {
+  const Geo &g = h->geo;
+  Coarse &c = h->co;
+  const size_t nb2 = (size_t)c.nb * c.nb;
+  FCM_HIP(hipEventRecord(h->co_ready, h->stream));
+  FCM_HIP(hipStreamWaitEvent(cs, h->co_ready, 0));
+  launch_coarse_stencils(g, h->tab, c, h->kmat, h->Kref64, h->Kcut64, cs);
   for (int k = 0; k < c.nblk; ++k) {
     double *S = c.Sinv + (size_t)k * nb2;
-    launch_coarse_first(g, c, k, S, h->stream);
+    launch_coarse_first(g, c, k, S, cs);
     // S_k = D_k - B_k F_{k-1},  F_{k-1} = S_{k-1}^{-1} B_k^T is kept for the back sweep
-    if (k > 0) launch_coarse_schur(g, c, k, S, c.Fm + (size_t)(k - 1) * nb2, h->stream);
-    spd_inverse_batched(S, c.nb, 1, scr, h->dflag, nullptr, h->stream);
-    if (k > 0) launch_coarse_G(g, c, k, h->stream);
+    if (k > 0) launch_coarse_schur(g, c, k, S, c.Fm + (size_t)(k - 1) * nb2, cs);
+    spd_inverse_batched(S, c.nb, 1, h->co_scr, h->dflag_co, nullptr, cs);
+    if (k > 0) launch_coarse_G(g, c, k, cs);
   }
+  FCM_HIP(hipGetLastError());
+  return FCM_OK;
+}
+
+static fcm_status coarse_join(fcm_handle *h, hipStream_t cs) {
+  FCM_HIP(hipStreamSynchronize(cs));
+  FCM_HIP(hipFree(h->co_scr));
+  h->co_scr = nullptr;
+  int f = 0;
+  FCM_HIP(hipMemcpyAsync(&f, h->dflag_co, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   FCM_HIP(hipStreamSynchronize(h->stream));
-  FCM_HIP(hipFree(scr));
-  return check_flag(h, "coarse factorisation");
+  if (f) {
+    set_error("coarse factorisation: a pivot was not positive (matrix not SPD in FP64)");
+    return FCM_ERR_NOT_SPD;
+  }
+  return FCM_OK;
 }
 
 // Owner-kernel work units of level l: planes grouped by (vertex mask, comp),
@@ -764,10 +789,47 @@ static fcm_status build_patches(fcm_handle *h, std::vector<int> &bnode, std::vec
   return FCM_OK;
 }
 
+// Scratch of the patch-block setup, sized for the largest level and
+// allocated before the coarse factorisation is launched (freeing memory
+// synchronises the device, which would serialise the two).
+struct PatchScratch {
+  double *blk = nullptr, *scr = nullptr, *kappa = nullptr;
+  int chunk = 0;
+};
+
+static int patch_chunk(int m, int nblocks) {
+  const size_t per = (size_t)m * m * sizeof(double);
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(1024, ((size_t)256 << 20) / per));
+  return std::max(1, std::min(chunk, nblocks));
+}
+
+static fcm_status patch_scratch_alloc(fcm_handle *h, int nblocks, PatchScratch &ps) {
+  const Geo &g = h->geo;
+  size_t nblk = 1, nscr = 1;
+  for (int l = 1; l <= h->L; ++l) {
+    int m = g.nf;
+    for (int ax = 0; ax < g.d; ++ax) m *= 2 * h->lev[l].q + 1;
+    const int cb = patch_chunk(m, std::max(1, nblocks));
+    nblk = std::max(nblk, (size_t)cb * m * m);
+    nscr = std::max(nscr, spd_inverse_scratch_doubles(m, cb));
+  }
+  FCM_HIP(hipMalloc((void **)&ps.blk, nblk * sizeof(double)));
+  FCM_HIP(hipMalloc((void **)&ps.scr, nscr * sizeof(double)));
+  FCM_HIP(hipMalloc((void **)&ps.kappa, std::max(1, nblocks) * sizeof(double)));
+  return FCM_OK;
+}
+
+static void patch_scratch_free(PatchScratch &ps) {
+  if (ps.blk) hipFree(ps.blk);
+  if (ps.scr) hipFree(ps.scr);
+  if (ps.kappa) hipFree(ps.kappa);
+  ps = PatchScratch();
+}
+
 // Form and invert the patch blocks of every level >= 1 (FP64, Jacobi-scaled
 // Gauss-Jordan sweep) in chunks, stored as m x ld (ld = m rounded up to 4).
 static fcm_status setup_patch_levels(fcm_handle *h, const std::vector<int> &bnode,
-                                     const std::vector<int> &bkm) {
+                                     const std::vector<int> &bkm, const PatchScratch &ps) {
   const Geo &g = h->geo;
   const bool mixed = h->opt.precision == FCM_MIXED;
   const int nblocks = (int)bnode.size();
@@ -775,8 +837,6 @@ static fcm_status setup_patch_levels(fcm_handle *h, const std::vector<int> &bnod
   int *dbn = nullptr, *dbk = nullptr;
   TRY(upload(h, &dbn, bnode.empty() ? std::vector<int>{0} : bnode));
   TRY(upload(h, &dbk, bkm.empty() ? std::vector<int>{0} : bkm));
-  double *kappa = nullptr;
-  FCM_HIP(hipMalloc((void **)&kappa, std::max(1, nblocks) * sizeof(double)));
   std::vector<double> hk(std::max(1, nblocks));
   for (int l = 1; l <= h->L; ++l) {
     Level &L = h->lev[l];
@@ -791,25 +851,17 @@ static fcm_status setup_patch_levels(fcm_handle *h, const std::vector<int> &bnod
     L.invU64 = L.invS64 + mm * ncls;
     L.invU32 = mixed ? L.invS32 + mm * ncls : nullptr;
     if (nblocks > 0) {
-      const size_t per = (size_t)m * m * sizeof(double);
-      const int chunk = (int)std::max<size_t>(1, std::min<size_t>(1024, ((size_t)256 << 20) / per));
-      const int cb = std::min(chunk, nblocks);
-      double *blk = nullptr, *scr = nullptr;
-      FCM_HIP(hipMalloc((void **)&blk, (size_t)cb * m * m * sizeof(double)));
-      FCM_HIP(hipMalloc((void **)&scr, spd_inverse_scratch_doubles(m, cb) * sizeof(double)));
+      const int cb = patch_chunk(m, nblocks);
       for (int b0 = 0; b0 < nblocks; b0 += cb) {
         const int nb = std::min(cb, nblocks - b0);
         launch_form_patch_blocks(g, h->tab, h->ptab, m, dbn + b0, dbk + b0, nb, h->kmat,
-                                 h->Kref64, h->Kcut64, blk, h->stream);
-        spd_inverse_batched(blk, m, nb, scr, h->dflag, kappa + b0, h->stream);
-        launch_pack_blocks(blk, m, ld, nb, L.invS64 + mm * b0,
+                                 h->Kref64, h->Kcut64, ps.blk, h->stream);
+        spd_inverse_batched(ps.blk, m, nb, ps.scr, h->dflag, ps.kappa + b0, h->stream);
+        launch_pack_blocks(ps.blk, m, ld, nb, L.invS64 + mm * b0,
                            mixed ? L.invS32 + mm * b0 : nullptr, h->stream);
       }
-      FCM_HIP(hipStreamSynchronize(h->stream));
-      FCM_HIP(hipFree(blk));
-      FCM_HIP(hipFree(scr));
-      FCM_HIP(hipMemcpyAsync(hk.data(), kappa, nblocks * sizeof(double), hipMemcpyDeviceToHost,
-                             h->stream));
+      FCM_HIP(hipMemcpyAsync(hk.data(), ps.kappa, nblocks * sizeof(double),
+                             hipMemcpyDeviceToHost, h->stream));
       FCM_HIP(hipStreamSynchronize(h->stream));
     }
     std::vector<uint8_t> fl(std::max(1, h->np_unique), 0);
@@ -821,7 +873,6 @@ static fcm_status setup_patch_levels(fcm_handle *h, const std::vector<int> &bnod
       }
     TRY(upload(h, &L.hi64, fl));
   }
-  FCM_HIP(hipFree(kappa));
   const int mtop = h->lev[h->L].mpatch;
   TRY(dalloc(h, &h->pYs, (size_t)std::max(1, h->np_shared) * mtop));
   TRY(dalloc(h, &h->pYu, (size_t)std::max(1, h->np_unique) * mtop));
@@ -834,7 +885,7 @@ static fcm_status do_setup(fcm_handle *h) {
   TRY(build_tables(h));
   const int m = h->tab.m;
   TRY(dalloc(h, &h->dflag, 1));
-  FCM_HIP(hipMemsetAsync(h->dflag, 0, sizeof(int), h->stream));
+  TRY(dalloc(h, &h->dflag_co, 1));
   // classification
   TRY(dalloc(h, &h->state, (size_t)g.E));
   launch_classify(g, h->tab.ball, h->state, h->stream);
@@ -900,15 +951,28 @@ static fcm_status do_setup(fcm_handle *h) {
     TRY(upload(h, &h->uncut_list, ul));
     TRY(upload(h, &h->class_list, cl));
   }
+  TRY(setup_coarse_alloc(h));
+  FCM_HIP(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
+  FCM_HIP(hipEventCreateWithFlags(&h->co_ready, hipEventDisableTiming));
   if (h->opt.smoother == FCM_SMOOTH_PATCHWISE) {
+    // patch tables and scratch first; the block setup then overlaps the
+    // coarse factorisation running on the second stream
     std::vector<int> bnode, bkm;
+    PatchScratch ps;
     TRY(build_patch_tables(h));
     TRY(build_patches(h, bnode, bkm));
-    TRY(setup_patch_levels(h, bnode, bkm));
+    fcm_status sst = patch_scratch_alloc(h, (int)bnode.size(), ps);
+    if (sst == FCM_OK) sst = setup_coarse_launch(h, h->own);
+    if (sst == FCM_OK) sst = setup_patch_levels(h, bnode, bkm, ps);
+    fcm_status cst = coarse_join(h, h->own);
+    patch_scratch_free(ps);
+    if (sst != FCM_OK) return sst;
+    TRY(cst);
   } else {
     TRY(setup_levels(h));
+    TRY(setup_coarse_launch(h, h->own));
+    TRY(coarse_join(h, h->own));
   }
-  TRY(setup_coarse(h));
   // work vectors
   for (int l = 0; l <= L; ++l) {
     Level &lv = h->lev[l];
@@ -931,7 +995,6 @@ static fcm_status do_setup(fcm_handle *h) {
   TRY(dalloc(h, &h->red, 1024));
   TRY(dalloc(h, &h->scal, 16));
   FCM_HIP(hipHostMalloc((void **)&h->hscal, 16 * sizeof(double), hipHostMallocDefault));
-  FCM_HIP(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
   FCM_HIP(hipStreamSynchronize(h->stream));
   return FCM_OK;
 }
@@ -1341,6 +1404,9 @@ const char *fcm_status_string(fcm_status s) {
 
 void fcm_destroy(fcm_handle *h) {
   if (!h) return;
+  if (h->own) hipStreamSynchronize(h->own);   // a failed setup may leave coarse work in flight
+  if (h->co_scr) hipFree(h->co_scr);
+  if (h->co_ready) hipEventDestroy(h->co_ready);
   if (h->cg_exec) hipGraphExecDestroy(h->cg_exec);
   if (h->cg_graph) hipGraphDestroy(h->cg_graph);
   if (h->own) hipStreamDestroy(h->own);
@@ -1587,6 +1653,31 @@ fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z, void
   }
   smooth_launch<double>(h, level, r, z, nullptr, 1.0, 0, (hipStream_t)stream);
   FCM_HIP(hipGetLastError());
+  return FCM_OK;
+}
+
+fcm_status fcm_spd_inverse(double *A, int n, int batch, double *kappa, void *stream) {
+  if (!A || n < 1 || batch < 1) {
+    set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  double *scr = nullptr;
+  int *flag = nullptr;
+  FCM_HIP(hipMalloc((void **)&scr, spd_inverse_scratch_doubles(n, batch) * sizeof(double)));
+  FCM_HIP(hipMalloc((void **)&flag, sizeof(int)));
+  FCM_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+  spd_inverse_batched(A, n, batch, scr, flag, kappa, s);
+  int f = 0;
+  FCM_HIP(hipMemcpyAsync(&f, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  FCM_HIP(hipStreamSynchronize(s));
+  FCM_HIP(hipFree(scr));
+  FCM_HIP(hipFree(flag));
+  FCM_HIP(hipGetLastError());
+  if (f) {
+    set_error("a pivot was not positive (matrix not SPD in FP64)");
+    return FCM_ERR_NOT_SPD;
+  }
   return FCM_OK;
 }
 

@@ -161,8 +161,12 @@ struct fcm_handle {
   double *scal = nullptr;                     // device scalars
   double *hscal = nullptr;                    // pinned host mirror
   int *dflag = nullptr;                       // device error flag
+  int *dflag_co = nullptr;                    // device error flag of the coarse factorisation
   std::vector<double> history;
-  hipStream_t own = nullptr;                  // stream of captured CG iterations
+  hipStream_t own = nullptr;                  // stream of captured CG iterations (and of
+                                              // the coarse factorisation during setup)
+  hipEvent_t co_ready = nullptr;              // element matrices ready for the coarse setup
+  double *co_scr = nullptr;                   // coarse factorisation scratch (setup only)
   hipGraphExec_t cg_exec = nullptr;           // captured steady-state CG iteration
   hipGraph_t cg_graph = nullptr;
   const double *graph_b = nullptr;

@@ -789,10 +789,11 @@ void launch_form_blocks(const Geo &g, const Tables &t, int q, int m, const int *
 }
 
 // --------------------------------------------- batched blocked SPD inverse
-// In-place symmetric Gauss-Jordan sweep by 32x32 tiles: sweeping pivot block K
-// maps [[A_KK, A_KJ],[A_IK, A_IJ]] to [[-P, P A_KJ],[A_IK P, A_IJ - A_IK P A_KJ]]
-// with P = A_KK^{-1}; after all K the matrix holds -A^{-1}.  Three launches
-// per pivot block (panel, trailing update, pivot column); the matrix is
+// In-place symmetric Gauss-Jordan sweep by blocks of 32 pivots: sweeping
+// pivot block K maps [[A_KK, A_KJ],[A_IK, A_IJ]] to
+// [[-P, P A_KJ],[A_IK P, A_IJ - A_IK P A_KJ]] with P = A_KK^{-1}; after all
+// K the matrix holds -A^{-1}.  Two launches per pivot block (pivot rows,
+// symmetric trailing update on the FP64 matrix cores); the matrix is
 // Jacobi-scaled first.
 constexpr int kTB = 32;
 
@@ -817,110 +818,141 @@ __global__ void apply_scale_kernel(double *A, int n, const double *scale, double
   }
 }
 
-// Sweep the pivot rows of tile K over column tile J in LDS: the pivot tile
-// becomes -A_KK^{-1} and, for J != K, the panel becomes W_KJ = A_KK^{-1} A_KJ.
-// The panel is updated pivot by pivot together with the pivot tile (product
-// form), which keeps the accuracy of the unblocked sweep; forming A_KK^{-1}
-// first and multiplying loses digits on ill-conditioned cut-cell blocks.
-__global__ __launch_bounds__(256) void sweep_panel_kernel(double *A, int n, int K, double *W,
-                                                          int *flag) {
+// Pivot rows of block K: workgroup (J, b) sweeps rows K over its 64 columns
+// [64 J, 64 J + 64) in LDS, pivot by pivot (product form, the unblocked
+// sweep restricted to these rows), tracking a private copy of the 32 x 32
+// pivot tile for the pivot columns; rows past n of a partial last block are
+// identity rows.  It writes the swept rows W and the rows before the sweep R
+// for its columns.  Because the swept matrix stays symmetric, the block
+// column is A_IK = R^T, so the update kernel needs nothing that another
+// workgroup of the same launch writes.
+constexpr int kTJ = 64;
+
+__global__ __launch_bounds__(256) void sweep_rows_kernel(double *A, int n, int K, double *W,
+                                                         double *Rg, int *flag) {
   __shared__ double P[kTB][kTB + 1];
-  __shared__ double T[kTB][kTB + 1];
-  __shared__ double ck[kTB], rk[kTB], tk[kTB];
-  const int b = blockIdx.y, J = blockIdx.x;
-  double *M = A + (size_t)b * n * n;
-  const int k0 = K * kTB, j0 = J * kTB;
+  __shared__ double T[kTB][kTJ + 1];
+  __shared__ double ck[kTB], rk[kTB], tk[kTJ];
+  const int J = blockIdx.x, b = blockIdx.y;
+  const double *M = A + (size_t)b * n * n;
+  double *Wb = W + (size_t)b * kTB * n;
+  double *Rb = Rg + (size_t)b * kTB * n;
+  const int k0 = K * kTB, j0 = J * kTJ;
   const int tid = threadIdx.x;
   for (int i = tid; i < kTB * kTB; i += 256) {
-    int r = i / kTB, c = i % kTB;
-    int gr = k0 + r, gc = k0 + c;
-    double v = (gr < n && gc < n) ? M[(size_t)gr * n + gc] : (r == c ? 1.0 : 0.0);
-    P[r][c] = v;
-    int gj = j0 + c;
-    T[r][c] = (gr < n && gj < n) ? M[(size_t)gr * n + gj] : 0.0;
+    const int r = i / kTB, c = i % kTB;
+    const int gr = k0 + r, gc = k0 + c;
+    P[r][c] = (gr < n && gc < n) ? M[(size_t)gr * n + gc] : (r == c ? 1.0 : 0.0);
+  }
+  for (int i = tid; i < kTB * kTJ; i += 256) {
+    const int r = i / kTJ, c = i % kTJ;
+    const int gr = k0 + r, gc = j0 + c;
+    double v = 0.0;
+    if (gc < n) v = gr < n ? M[(size_t)gr * n + gc] : (gc == gr ? 1.0 : 0.0);
+    T[r][c] = v;
+    if (gc < n) Rb[(size_t)r * n + gc] = v;
   }
   __syncthreads();
-  for (int k = 0; k < kTB; ++k) {
+  for (int kk = 0; kk < kTB; ++kk) {
+    const int kc = k0 + kk;   // pivot column
     if (tid < kTB) {
-      ck[tid] = P[tid][k];
-      rk[tid] = P[k][tid];
-      tk[tid] = T[k][tid];
+      ck[tid] = P[tid][kk];
+      rk[tid] = P[kk][tid];
     }
+    if (tid < kTJ) tk[tid] = T[kk][tid];
     __syncthreads();
-    const double piv = ck[k];
-    if (tid == 0 && J == 0 && !(piv > 0.0)) atomicOr(flag, 1);
+    const double piv = ck[kk];
+    if (tid == 0 && J == 0 && kc < n && !(piv > 0.0)) atomicOr(flag, 1);
     const double ip = 1.0 / piv;
     for (int i = tid; i < kTB * kTB; i += 256) {
-      int r = i / kTB, c = i % kTB;
+      const int r = i / kTB, c = i % kTB;
       double v;
-      if (r != k && c != k) v = P[r][c] - ck[r] * rk[c] * ip;
-      else if (r != k) v = ck[r] * ip;
-      else if (c != k) v = rk[c] * ip;
-      else v = -ip;
+      if (c == kk) v = r == kk ? -ip : ck[r] * ip;
+      else v = r == kk ? rk[c] * ip : P[r][c] - ck[r] * rk[c] * ip;
       P[r][c] = v;
-      if (J != K) T[r][c] = r != k ? T[r][c] - ck[r] * tk[c] * ip : tk[c] * ip;
+    }
+    for (int i = tid; i < kTB * kTJ; i += 256) {
+      const int r = i / kTJ, c = i % kTJ;
+      double v;
+      if (j0 + c == kc) v = r == kk ? -ip : ck[r] * ip;
+      else v = r == kk ? tk[c] * ip : T[r][c] - ck[r] * tk[c] * ip;
+      T[r][c] = v;
     }
     __syncthreads();
   }
-  // P now holds -A_KK^{-1}; T holds A_KK^{-1} A_KJ
-  double *Wb = W + (size_t)b * kTB * n;
-  for (int i = tid; i < kTB * kTB; i += 256) {
-    int r = i / kTB, c = i % kTB;
-    int gj = j0 + c;
-    if (gj >= n) continue;
-    Wb[(size_t)r * n + gj] = J == K ? -P[r][c] : T[r][c];
+  for (int i = tid; i < kTB * kTJ; i += 256) {
+    const int r = i / kTJ, c = i % kTJ;
+    if (j0 + c < n) Wb[(size_t)r * n + j0 + c] = T[r][c];
   }
 }
 
-__global__ __launch_bounds__(256) void sweep_update_kernel(double *A, int n, int K,
-                                                           const double *W) {
-  __shared__ double Ai[kTB][kTB + 1];
-  __shared__ double Wk[kTB][kTB + 1];
-  const int b = blockIdx.z, I = blockIdx.y, J = blockIdx.x;
-  if (J == K) return;
+// M_IJ -= R_KI^T W_KJ for I, J outside block K; rows of K <- W; columns of K
+// <- W^T.  Only the upper triangle is computed and every value is stored at
+// (i, j) and (j, i): the swept matrix is symmetric in exact arithmetic, and
+// keeping it exactly symmetric matters for cut-cell blocks whose scaled
+// condition reaches 1e12 or more, where R^T (A_KK^{-1} R) and its mirror
+// image differ by the pivot-block solve error.  64 x 64 output tile (ti <= tj)
+// per workgroup, wave w owns the 32 x 32 quarter (w / 2, w % 2) as 2 x 2
+// v_mfma_f64_16x16x4f64 tiles (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16], holds D[4j + l/16][l%16]).
+typedef double doublex4s __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n, int K,
+                                                                const double *W,
+                                                                const double *Rg, int ntile) {
+  const int b = blockIdx.y;
+  int ti = 0, rem = blockIdx.x;
+  while (rem >= ntile - ti) {
+    rem -= ntile - ti;
+    ++ti;
+  }
+  const int tj = ti + rem;
   double *M = A + (size_t)b * n * n;
   const double *Wb = W + (size_t)b * kTB * n;
-  const int i0 = I * kTB, j0 = J * kTB, k0 = K * kTB;
-  const int tid = threadIdx.x;
-  if (I == K) {
-    for (int i = tid; i < kTB * kTB; i += 256) {
-      int r = i / kTB, c = i % kTB;
-      int gr = k0 + r, gc = j0 + c;
-      if (gr < n && gc < n) M[(size_t)gr * n + gc] = Wb[(size_t)r * n + gc];
+  const double *Rb = Rg + (size_t)b * kTB * n;
+  const int k0 = K * kTB, k1 = min(n, k0 + kTB);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ln = lane & 15, lq = lane >> 4;
+  const int i0 = ti * 64 + (wave >> 1) * 32, j0 = tj * 64 + (wave & 1) * 32;
+  if (i0 >= n || j0 >= n || i0 > j0 + 31) return;   // whole wave: nothing on or above the diagonal
+  doublex4s acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = doublex4s{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int ks = 0; ks < kTB / 4; ++ks) {
+    const int kk = 4 * ks + lq;
+    double av[2], bv[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = i0 + 16 * u + ln;
+      av[u] = i < n ? Rb[(size_t)kk * n + i] : 0.0;        // A[i][kk] = R[kk][i]
+      const int j = j0 + 16 * u + ln;
+      bv[u] = j < n ? Wb[(size_t)kk * n + j] : 0.0;        // B[kk][j] = W[kk][j]
     }
-    return;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+        acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
   }
-  for (int i = tid; i < kTB * kTB; i += 256) {
-    int r = i / kTB, c = i % kTB;
-    int gr = i0 + r, gk = k0 + c;
-    Ai[r][c] = (gr < n && gk < n) ? M[(size_t)gr * n + gk] : 0.0;
-    int gj = j0 + c;
-    Wk[r][c] = (gj < n && k0 + r < n) ? Wb[(size_t)r * n + gj] : 0.0;
-  }
-  __syncthreads();
-  for (int i = tid; i < kTB * kTB; i += 256) {
-    int r = i / kTB, c = i % kTB;
-    int gr = i0 + r, gc = j0 + c;
-    if (gr >= n || gc >= n) continue;
-    double s = 0.0;
-    for (int k = 0; k < kTB; ++k) s += Ai[r][k] * Wk[k][c];
-    M[(size_t)gr * n + gc] -= s;
-  }
-}
-
-__global__ void sweep_column_kernel(double *A, int n, int K, const double *W) {
-  const int b = blockIdx.y, I = blockIdx.x;
-  double *M = A + (size_t)b * n * n;
-  const double *Wb = W + (size_t)b * kTB * n;
-  const int i0 = I * kTB, k0 = K * kTB;
-  for (int i = threadIdx.x; i < kTB * kTB; i += blockDim.x) {
-    int r = i / kTB, c = i % kTB;
-    int gr = i0 + r, gk = k0 + c;
-    if (gr >= n || gk >= n) continue;
-    double v = Wb[(size_t)c * n + gr];   // (P A_KI)^T = A_IK P ; for I == K: W_KK = P
-    if (I == K) v = -v;
-    M[(size_t)gr * n + gk] = v;
-  }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int i = i0 + 16 * u + 4 * jj + lq, j = j0 + 16 * v + ln;
+        if (i >= n || j >= n || i > j) continue;
+        const bool ik = i >= k0 && i < k1, jk = j >= k0 && j < k1;
+        double val;
+        if (ik) val = Wb[(size_t)(i - k0) * n + j];
+        else if (jk) val = Wb[(size_t)(j - k0) * n + i];
+        else val = M[(size_t)i * n + j] - acc[u][v][jj];
+        M[(size_t)i * n + j] = val;
+        M[(size_t)j * n + i] = val;
+      }
 }
 
 // kappa[b] = (or *=) max absolute column sum of matrix b (one workgroup per matrix)
@@ -944,23 +976,25 @@ __global__ void norm1_kernel(const double *A, int n, double *kappa, int multiply
 }
 
 size_t spd_inverse_scratch_doubles(int n, int batch) {
-  return (size_t)batch * kTB * n + (size_t)batch * n;
+  // W (and R for the panel-wide variant) of kTB rows, scale
+  return (size_t)batch * kTB * n * 2 + (size_t)batch * n;
 }
 
 int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag, double *kappa,
                         hipStream_t s) {
   if (batch <= 0 || n <= 0) return 0;
   double *W = scratch;
-  double *scale = scratch + (size_t)batch * kTB * n;
+  double *scale = scratch + (size_t)batch * kTB * n * 2;
   const int NB = (n + kTB - 1) / kTB;
   jacobi_scale_kernel<<<dim3((n + 255) / 256, batch), 256, 0, s>>>(A, n, scale, flag);
   int sblk = (int)std::min<size_t>(((size_t)n * n + 255) / 256, 1024);
   apply_scale_kernel<<<dim3(sblk, batch), 256, 0, s>>>(A, n, scale, 1.0);
   if (kappa) norm1_kernel<<<batch, 256, 0, s>>>(A, n, kappa, 0);
+  double *R = W + (size_t)batch * kTB * n;
+  const int nt = (n + 63) / 64;
   for (int K = 0; K < NB; ++K) {
-    sweep_panel_kernel<<<dim3(NB, batch), 256, 0, s>>>(A, n, K, W, flag);
-    sweep_update_kernel<<<dim3(NB, NB, batch), 256, 0, s>>>(A, n, K, W);
-    sweep_column_kernel<<<dim3(NB, batch), 256, 0, s>>>(A, n, K, W);
+    sweep_rows_kernel<<<dim3((n + kTJ - 1) / kTJ, batch), 256, 0, s>>>(A, n, K, W, R, flag);
+    sweep_update_mfma_kernel<<<dim3(nt * (nt + 1) / 2, batch), 256, 0, s>>>(A, n, K, W, R, nt);
   }
   if (kappa) norm1_kernel<<<batch, 256, 0, s>>>(A, n, kappa, 1);
   apply_scale_kernel<<<dim3(sblk, batch), 256, 0, s>>>(A, n, scale, -1.0);

@@ -87,6 +87,7 @@ SIGNATURES = {
     "fcm_apply": ([_P, ctypes.c_int, _P, _P, _P], ctypes.c_int),
     "fcm_smooth": ([_P, ctypes.c_int, _P, _P, _P], ctypes.c_int),
     "fcm_coarse_solve": ([_P, _P, _P, _P], ctypes.c_int),
+    "fcm_spd_inverse": ([_P, ctypes.c_int, ctypes.c_int, _P, _P], ctypes.c_int),
     "fcm_vcycle": ([_P, _P, _P, _P], ctypes.c_int),
     "fcm_pcg_solve": ([_P, _P, _P, ctypes.POINTER(SolveInfo), _P], ctypes.c_int),
     "fcm_mg_solve": ([_P, _P, _P, ctypes.POINTER(SolveInfo), ctypes.POINTER(ctypes.c_double), _P],
@@ -387,3 +388,17 @@ class Server:
         if getattr(self, "s", None):
             lib().fcm_server_destroy(self.s)
             self.s = None
+
+
+def spd_inverse(A, kappa=None):
+    """In-place batched inverse of SPD matrices on the device (test hook).
+
+    A: CUDA float64 tensor of shape (batch, n, n), contiguous; kappa: optional
+    CUDA float64 tensor of shape (batch,) receiving the scaled 1-norm condition
+    numbers."""
+    assert A.is_cuda and A.dtype.is_floating_point and A.element_size() == 8 and A.is_contiguous()
+    b, n, n2 = A.shape
+    assert n == n2
+    _check(lib().fcm_spd_inverse(_ptr(A), n, b, _ptr(kappa) if kappa is not None else None,
+                                 _stream()))
+    return A
