@@ -28,6 +28,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MG-PCG solves/s + V-cycle DOF/s (%HBM roofline) at rel. err 1e-8; p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
+# HBM traffic of one launch of the finest-level unique-patch GEMV on the seed-0
+# 32^3 p = 3 problem, FP32 V-cycle: rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch) of `bench.py --steps 1 --warmup 0 --no-cpu-baseline --pmc-calibration`,
+# each scaled by the reading of a 1 GiB elementwise copy (see
+# profiles/patch_gemv_cube32_p3_traffic.md).  Valid for the kernel as profiled.
+GEMV_TRAFFIC = {"bytes": 4.255e9}
 
 
 def cpu_baseline(n_sample=6):
@@ -126,6 +132,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=96.0)
+    ap.add_argument("--pmc-calibration", action="store_true",
+                    help="finish with a 1 GiB elementwise copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
@@ -144,9 +152,9 @@ def main():
         return d, dict(o, precision=precision, smoother=args.smoother,
                        omega=1.0 / 18.0 if args.smoother == "patchwise" else 2.0 / 15.0)
 
-    def run_steps(seeds, precision, keep_last=False):
+    def run_steps(seeds, precision, keep_first=False):
         lat, its, setup, solve, errs = [], [], [], [], []
-        last = None
+        first = None
         for sd in seeds:
             t = time.perf_counter()
             s = Solver(*problem(sd, precision))
@@ -159,12 +167,12 @@ def main():
             errs.append(info["true_rel_res"])
             if info["status"] != 0:
                 raise RuntimeError(f"solve of seed {sd} did not converge: {info}")
-            if keep_last and sd == seeds[-1]:
-                last = s
+            if keep_first and sd == seeds[0]:
+                first = s
             else:
                 s.close()
             del x
-        return lat, its, setup, solve, errs, last
+        return lat, its, setup, solve, errs, first
 
     print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
     run_steps([1000 + w for w in range(args.warmup)], args.precision)
@@ -172,12 +180,13 @@ def main():
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     lat, its, setup, solve, errs, s = run_steps(list(range(args.steps)), args.precision,
-                                                keep_last=True)
+                                                keep_first=True)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
     value = args.steps / T
 
-    # V-cycle throughput and dominant kernel (finest-level smoother), HIP events
+    # V-cycle throughput and dominant kernel on the seed-0 problem (the one the
+    # committed counter profile covers), HIP events on the library's stream
     L = s.n_levels - 1
     n_fine = s.n_dofs[-1]
     ms_v, bytes_v = s.time_op("vcycle", reps=10)
@@ -230,7 +239,13 @@ def main():
         "problem": {k: st[k] for k in ("n_cut", "n_unique_blocks", "n_fp64_blocks",
                                         "coarse_blocks", "coarse_block_size", "device_bytes")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (GEMV_TRAFFIC["bytes"] / 1e9
+                                 if GEMV_TRAFFIC["bytes"] is not None and args.n == 32
+                                 and args.smoother == "patchwise" and args.precision == "mixed"
+                                 else None),
+                     "traffic_unit": "GB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
+                     "algorithmic_gb": bytes_k / 1e9},
     }
     s.close()
     if args.compare_fp64:
@@ -242,6 +257,13 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
+    if args.pmc_calibration:
+        a = torch.ones(256 * 2**20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.neg(a, out=b)          # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        print("[bench] calibration copy: 1 GiB read, 1 GiB written", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
     return 0
 
