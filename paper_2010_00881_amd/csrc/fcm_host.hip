@@ -946,10 +946,31 @@ static fcm_status do_setup(fcm_handle *h) {
         if (h->h_blk[e] == c) cl.push_back(e);
     h->n_uncut = (int)ul.size();
     h->n_classed = (int)cl.size();
+    // chunks of <= 256 consecutive list entries with the same shared matrix
+    auto chunks = [](const std::vector<int> &list, const std::vector<int> &id) {
+      std::vector<int> ch;
+      size_t i = 0;
+      while (i < list.size()) {
+        const int c = id[list[i]];
+        size_t j = i;
+        while (j < list.size() && id[list[j]] == c && j - i < 256) ++j;
+        ch.push_back(c);
+        ch.push_back((int)i);
+        ch.push_back((int)(j - i));
+        i = j;
+      }
+      if (ch.empty()) ch.assign(3, 0);
+      return ch;
+    };
+    std::vector<int> uck = chunks(ul, h->h_kmat), cck = chunks(cl, h->h_blk);
+    h->n_uncut_chk = ul.empty() ? 0 : (int)uck.size() / 3;
+    h->n_class_chk = cl.empty() ? 0 : (int)cck.size() / 3;
     if (ul.empty()) ul.push_back(0);
     if (cl.empty()) cl.push_back(0);
     TRY(upload(h, &h->uncut_list, ul));
     TRY(upload(h, &h->class_list, cl));
+    TRY(upload(h, &h->uncut_chk, uck));
+    TRY(upload(h, &h->class_chk, cck));
   }
   TRY(setup_coarse_alloc(h));
   FCM_HIP(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
@@ -1049,6 +1070,8 @@ static OpArgs<T> stiffness_args(fcm_handle *h, int l) {
   a.Yshared = h->Yshr;
   a.shlist = h->uncut_list;
   a.nsh = h->n_uncut;
+  a.chk = h->uncut_chk;
+  a.nchunks = h->n_uncut_chk;
   set_fp64_parts<T>(h, l, a, false);
   return a;
 }
@@ -1091,6 +1114,8 @@ static OpArgs<T> smoother_args(fcm_handle *h, int l) {
   a.Yshared = h->Yshr;
   a.shlist = h->class_list;
   a.nsh = h->n_classed;
+  a.chk = h->class_chk;
+  a.nchunks = h->n_class_chk;
   set_fp64_parts<T>(h, l, a, true);
   return a;
 }

@@ -138,6 +138,8 @@ struct fcm_handle {
   int *uncut_list = nullptr;                  // kept uncut elements (K_ref)
   int *class_list = nullptr;                  // elements with a shared Schwarz class, by class
   int n_uncut = 0, n_classed = 0;
+  int *uncut_chk = nullptr, *class_chk = nullptr;   // same-matrix chunks of the two lists
+  int n_uncut_chk = 0, n_class_chk = 0;
   // patchwise smoother: patches (grid nodes with a kept element) ordered
   // class-sorted shared patches first, then unique patches
   fcm::PatchTables ptab;
@@ -245,6 +247,8 @@ struct OpArgs {
   void *Yshared = nullptr;    // [m_out][E] shared-matrix products (scratch, TM)
   const int *shlist = nullptr; // elements with a shared matrix, sorted by matrix id
   int nsh = 0;
+  const int *chk = nullptr;   // [nchunks][3]: matrix id, first list entry, count (<= 256)
+  int nchunks = 0;
   T *out = nullptr;           // out = cvec + scale*acc  (cvec may be null)
   const T *cvec = nullptr;
   T scale = 1;

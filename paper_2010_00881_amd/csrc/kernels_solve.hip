@@ -214,6 +214,97 @@ __global__ __launch_bounds__(256) void shared_mfma64_kernel(Geo g, const int *__
   }
 }
 
+// Phase B for wide element matrices (64 < m <= 384, e.g. elasticity at p = 4):
+// work item = (8 row tiles of 16, chunk of <= 256 elements with the same
+// shared matrix).  Wave w keeps rows [16 rt, 16 rt + 16) of the shared matrix
+// in registers as v_mfma_f64_16x16x4f64 A operands (the matrix is symmetric,
+// so row r is read as column r, coalesced), 16-element groups of gathered
+// inputs stream through LDS as B operands (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16], holds D[4j+l/16][l%16]).
+typedef double doublex4e __attribute__((ext_vector_type(4)));
+
+template <typename T, int NKS>
+__global__ __launch_bounds__(512) void elem_class_mfma_kernel(Geo g, const int *__restrict__ xoff,
+                                                              const double *__restrict__ matS,
+                                                              OpArgs<T> a,
+                                                              double *__restrict__ Ys) {
+  extern __shared__ double X[];   // [NKS * 4][16]
+  constexpr int KP = NKS * 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int n = lane & 15, kq = lane >> 4;
+  const int *ch = a.chk + 3 * blockIdx.y;
+  const int c = ch[0], p0 = ch[1], cnt = ch[2];
+  const int mi = a.m_in, mo = a.m_out, ld = a.ld;
+  const int rt = blockIdx.x * 8 + wave;
+  const bool rtv = 16 * rt < mo;
+  double av[NKS];
+  {
+    const double *A0 = matS + (size_t)c * ld * ld;
+    const int r = 16 * rt + n;
+    const bool rv = rtv && r < mo;
+    const int rc = min(r, mo - 1);
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int k = 4 * ks + kq;
+      const double v = A0[(size_t)min(k, mi - 1) * ld + rc];   // M[r][k] = M[k][r]
+      av[ks] = (rv && k < mi) ? v : 0.0;
+    }
+  }
+  const int ngroups = (cnt + 15) >> 4;
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const int q0 = p0 + 16 * gi, qn = min(16, cnt - 16 * gi);
+    for (int i = threadIdx.x; i < 16 * KP; i += 512) {
+      const int nn = i & 15, k = i >> 4;
+      double v = 0.0;
+      if (nn < qn && k < mi) {
+        const int e = a.shlist[q0 + nn];
+        const int ex = e % g.n[0], r = e / g.n[0];
+        const int base = ex + g.gn[0] * ((r % g.n[1]) + g.gn[1] * (r / g.n[1]));
+        v = (double)a.x[base + xoff[k]];
+      }
+      X[i] = v;
+    }
+    __syncthreads();
+    if (rtv) {
+      doublex4e acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks], X[(4 * ks + kq) * 16 + n], acc, 0, 0, 0);
+      if (n < qn) {
+        const int e = a.shlist[q0 + n];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rr = 16 * rt + 4 * j + kq;
+          if (rr < mo) Ys[(size_t)rr * g.E + e] = acc[j];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int NKS>
+static void launch_elem_class_nks(const Geo &g, const Tables &t, const OpArgs<T> &a,
+                                  const double *matS, double *Ys, hipStream_t s) {
+  const int nrt = (a.m_out + 15) / 16;
+  dim3 grid((nrt + 7) / 8, a.nchunks);
+  elem_class_mfma_kernel<T, NKS><<<grid, 512, (size_t)NKS * 4 * 16 * sizeof(double), s>>>(
+      g, t.xoff, matS, a, Ys);
+}
+
+template <typename T>
+static bool launch_elem_class(const Geo &g, const Tables &t, const OpArgs<T> &a,
+                              const double *matS, double *Ys, hipStream_t s) {
+  const int nks = (a.m_in + 3) / 4;
+  if (!a.chk || a.nchunks <= 0 || nks > 96) return false;
+  if (nks <= 24) launch_elem_class_nks<T, 24>(g, t, a, matS, Ys, s);
+  else if (nks <= 48) launch_elem_class_nks<T, 48>(g, t, a, matS, Ys, s);
+  else if (nks <= 64) launch_elem_class_nks<T, 64>(g, t, a, matS, Ys, s);
+  else if (nks <= 88) launch_elem_class_nks<T, 88>(g, t, a, matS, Ys, s);
+  else launch_elem_class_nks<T, 96>(g, t, a, matS, Ys, s);
+  return true;
+}
+
 // Phase C: owner gather.  One thread per output entry (grid point g, plane P)
 // sums the 2^k element results that belong to this DOF and applies the fused
 // epilogue (damped update, residual update, prolongation).
@@ -305,6 +396,14 @@ void launch_elem_op(const Geo &g, const Tables &t, const OpArgs<T> &a, hipStream
   }
   if (a.nstored > 0)
     stored_gemv_kernel<T><<<(a.nstored + 3) / 4, 256, 0, s>>>(g, t.xoff, a);
+  if (mS64 && a.nsh > 0) {
+    double *Ys = reinterpret_cast<double *>(a.Yshared);
+    if (launch_elem_class<T>(g, t, a, mS64, Ys, s)) {
+      dim3 grid((g.G + 255) / 256, a.nP_out);
+      gather_kernel<T, double><<<grid, 256, 0, s>>>(g, t.rows, t.pinfo, a, Ys);
+      return;
+    }
+  }
   if (a.matS64)
     launch_op3<T, double>(g, t, a, a.matS64, s);
   else
