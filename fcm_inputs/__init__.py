@@ -154,7 +154,7 @@ def sphere_multilevel(seed: int = 0, n: int = 8, k: int = 3, p: int = 3):
 
 
 def serving_request(i: int):
-    """Request i of the serving stream (generator seed 10000+i).
+    """Request i of the serving stream (generator seed 10000+i), patchwise smoothing.
 
     Draw order: u (<0.6 -> 2D); grid n; order p; number of holes; centres;
     radii; then (2D only) four Gaussians as in the plate problem.
@@ -176,7 +176,7 @@ def serving_request(i: int):
     else:
         d["f_const"] = 1.0
     d["name"] = f"serve_req{i}_{dim}d_n{n}_p{p}"
-    o = default_options(dim)
+    o = default_options(dim, smoother="patchwise")
     o["rtol"] = 1e-8
     return d, o
 

@@ -19,9 +19,11 @@
  * vector is a prefix of the fine vector, restriction keeps the prefix and
  * prolongation zero-extends it (eq. restrictionoperation), and the level
  * matrix is the leading principal block of the fine one (eq.
- * hierarchicalMatrices).  Levels >= 1 are smoothed by elementwise additive
- * Schwarz (eq. AdditiveSchwarz) with relaxation omega; level 0 (p = 1) is
- * solved exactly.  One V-cycle (Alg. 1) preconditions an FP64 CG (Section 4).
+ * hierarchicalMatrices).  Levels >= 1 are smoothed by additive Schwarz (eq.
+ * AdditiveSchwarz) with relaxation omega, over element blocks or over patch
+ * blocks (the basis functions nonzero on the kept elements around one grid
+ * node, Section 3.3.1); level 0 (p = 1) is solved exactly.  One V-cycle
+ * (Alg. 1) preconditions an FP64 CG (Section 4).
  *
  * Vectors.  All device vectors use the library's padded "plane" layout: the
  * vector of level l is nplanes(l) contiguous planes of G grid points each
@@ -34,7 +36,8 @@
  * numbering.
  *
  * Memory ownership.  The handle owns every device allocation it makes (level
- * operators, Schwarz inverses, coarse factors, work vectors).  Pointers passed
+ * operators, Schwarz inverses, coarse factors, work vectors); they come from
+ * the device's stream-ordered pool (see fcm_trim_pool).  Pointers passed
  * in (device vectors, host arrays) remain owned by the caller; the library
  * never frees or retains them beyond the call.  Device vectors must be
  * hipMalloc'ed (or torch-allocated) memory on the handle's device.
@@ -109,7 +112,7 @@ typedef struct {
                                  all functions nonzero on it; FCM_SMOOTH_PATCHWISE:
                                  one block per grid node, all functions nonzero on
                                  the kept elements sharing it (Section 3.3.1); the
-                                 patch size n_f (2p+1)^d must not exceed 512      */
+                                 patch size n_f (2p+1)^d must not exceed 384      */
   double omega;               /* relaxation (Section 3.3.2): elementwise 1/3 (2D),
                                  2/15 (3D); patchwise 1/6 (2D), 1/18 (3D)         */
   int n_pre, n_post;          /* smoothing steps per level (5 and 5 in the paper) */
@@ -232,7 +235,19 @@ enum { FCM_OP_SMOOTH = 0, FCM_OP_RESIDUAL = 1, FCM_OP_COARSE = 2, FCM_OP_VCYCLE 
 fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
                        double *ms_per_launch, double *bytes_per_launch);
 
+/* Releases every device allocation of the handle.  The memory is returned
+ * to the device's stream-ordered pool in stream order after the work queued
+ * on the stream given to fcm_setup(); work the caller queued with this
+ * handle on any other stream must have completed (synchronise it first).
+ * NULL is ignored.                                                          */
 void fcm_destroy(fcm_handle *h);
+
+/* The library allocates device memory from the current device's default
+ * stream-ordered memory pool (hipMallocAsync), which keeps released memory
+ * cached for the next setup instead of returning it, so that setups and
+ * teardowns never synchronise the whole device.  This call returns the
+ * cached, unused memory of the current device's pool to the system.        */
+fcm_status fcm_trim_pool(void);
 
 /* ---------------------------------------------------------------------------
  * Serving: a request loop that admits solves of different grids and orders

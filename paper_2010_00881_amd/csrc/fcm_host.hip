@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -87,18 +88,85 @@ static void modes1d_host(int p, double xi, double *v, double *dv) {
 static int deg1(int a) { return a < 2 ? 1 : a; }      // local 1D mode -> degree
 static int tdeg(int t) { return t == 0 ? 1 : t + 1; }  // slot type -> degree
 
+#define TRY(x)                         \
+  do {                                 \
+    fcm_status s_ = (x);               \
+    if (s_ != FCM_OK) return s_;       \
+  } while (0)
+
+// ------------------------------------------------------- device memory
+// Device memory comes from the device's default stream-ordered pool.  An
+// allocation or release is an operation on a stream and, unlike hipMalloc /
+// hipFree, never synchronises the whole device, so setups and teardowns of
+// independent solves (the request server) do not serialise each other.  The
+// pool keeps released memory for reuse (release threshold raised once per
+// device) until fcm_trim_pool().
+static std::mutex g_pool_mu;
+static std::vector<char> g_pool_ready;
+
+static fcm_status pool_prepare() {
+  int dev = 0;
+  FCM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if ((int)g_pool_ready.size() <= dev) g_pool_ready.resize(dev + 1, 0);
+  if (g_pool_ready[dev]) return FCM_OK;
+  hipMemPool_t pool;
+  FCM_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t thr = UINT64_MAX;
+  FCM_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+  g_pool_ready[dev] = 1;
+  return FCM_OK;
+}
+
+fcm_status pool_alloc(void **p, size_t bytes, hipStream_t s) {
+  *p = nullptr;
+  TRY(pool_prepare());
+  hipError_t e = hipMallocAsync(p, std::max<size_t>(bytes, 1), s);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    set_error("hipMallocAsync of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? FCM_ERR_OOM : FCM_ERR_HIP;
+  }
+  return FCM_OK;
+}
+
+void pool_free(void *p, hipStream_t s) {
+  if (p) hipFreeAsync(p, s);
+}
+
+// Pinned host blocks of 16 doubles for scalar read-back, recycled across
+// handles (freeing pinned memory synchronises the device as hipFree does).
+static std::vector<double *> g_pinned_free;
+
+double *pinned_get() {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  if (g_pinned_free.empty()) {
+    const int per = 64;
+    double *slab = nullptr;
+    if (hipHostMalloc((void **)&slab, per * 16 * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess)
+      return nullptr;
+    for (int k = per - 1; k >= 0; --k) g_pinned_free.push_back(slab + 16 * k);
+  }
+  double *b = g_pinned_free.back();
+  g_pinned_free.pop_back();
+  return b;
+}
+
+void pinned_put(double *b) {
+  if (!b) return;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  g_pinned_free.push_back(b);
+}
+
 template <typename T>
 static fcm_status dalloc(fcm_handle *h, T **p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
-  hipError_t e = hipMalloc((void **)p, n * sizeof(T));
-  if (e != hipSuccess) {
-    set_error("hipMalloc of %zu bytes failed: %s", n * sizeof(T), hipGetErrorString(e));
-    return e == hipErrorOutOfMemory ? FCM_ERR_OOM : FCM_ERR_HIP;
-  }
+  TRY(pool_alloc((void **)p, n * sizeof(T), h->stream));
   h->allocs.push_back(*p);
   h->bytes += (int64_t)(n * sizeof(T));
-  e = hipMemsetAsync(*p, 0, n * sizeof(T), h->stream);
+  hipError_t e = hipMemsetAsync(*p, 0, n * sizeof(T), h->stream);
   if (e != hipSuccess) {
     set_error("hipMemsetAsync failed: %s", hipGetErrorString(e));
     return FCM_ERR_HIP;
@@ -116,12 +184,6 @@ static fcm_status upload(fcm_handle *h, T **p, const std::vector<T> &v) {
   FCM_HIP(hipStreamSynchronize(h->stream));
   return FCM_OK;
 }
-
-#define TRY(x)                         \
-  do {                                 \
-    fcm_status s_ = (x);               \
-    if (s_ != FCM_OK) return s_;       \
-  } while (0)
 
 // ------------------------------------------------------------ validation
 static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
@@ -450,7 +512,8 @@ static fcm_status setup_coarse_alloc(fcm_handle *h) {
   TRY(dalloc(h, &c.xblk, (size_t)c.nblk * c.nb));
   TRY(dalloc(h, &c.bblk, (size_t)c.nblk * c.nb));
   TRY(dalloc(h, &c.bb, (size_t)g.nf * g.G));
-  FCM_HIP(hipMalloc((void **)&h->co_scr, spd_inverse_scratch_doubles(c.nb, 1) * sizeof(double)));
+  TRY(pool_alloc((void **)&h->co_scr, spd_inverse_scratch_doubles(c.nb, 1) * sizeof(double),
+                 h->stream));
   return FCM_OK;
 }
 
@@ -474,9 +537,9 @@ static fcm_status setup_coarse_launch(fcm_handle *h, hipStream_t cs) {
 }
 
 static fcm_status coarse_join(fcm_handle *h, hipStream_t cs) {
-  FCM_HIP(hipStreamSynchronize(cs));
-  FCM_HIP(hipFree(h->co_scr));
+  pool_free(h->co_scr, cs);
   h->co_scr = nullptr;
+  FCM_HIP(hipStreamSynchronize(cs));
   int f = 0;
   FCM_HIP(hipMemcpyAsync(&f, h->dflag_co, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   FCM_HIP(hipStreamSynchronize(h->stream));
@@ -537,7 +600,7 @@ static fcm_status setup_levels(fcm_handle *h) {
   TRY(upload(h, &belems, h->h_block_elems));
   const int nblocks = (int)h->h_block_elems.size();
   double *kappa = nullptr;
-  FCM_HIP(hipMalloc((void **)&kappa, std::max(1, nblocks) * sizeof(double)));
+  TRY(pool_alloc((void **)&kappa, std::max(1, nblocks) * sizeof(double), h->stream));
   std::vector<double> hk(nblocks);
   for (int l = 1; l <= h->L; ++l) {
     Level &L = h->lev[l];
@@ -554,7 +617,7 @@ static fcm_status setup_levels(fcm_handle *h) {
       const int chunk = 512;
       double *scr = nullptr;
       const int cb = std::min(chunk, nblocks);
-      FCM_HIP(hipMalloc((void **)&scr, spd_inverse_scratch_doubles(m, cb) * sizeof(double)));
+      TRY(pool_alloc((void **)&scr, spd_inverse_scratch_doubles(m, cb) * sizeof(double), h->stream));
       launch_form_blocks(g, h->tab, L.q, m, belems, nblocks, h->kmat, h->Kref64, h->Kcut64,
                          L.invS64, h->stream);
       for (int b0 = 0; b0 < nblocks; b0 += chunk) {
@@ -562,8 +625,7 @@ static fcm_status setup_levels(fcm_handle *h) {
         spd_inverse_batched(L.invS64 + mm * b0, m, nbat, scr, h->dflag, kappa + b0, h->stream);
       }
       launch_to_f32(L.invS64, L.invS32, (int64_t)(mm * nblocks), h->stream);
-      FCM_HIP(hipStreamSynchronize(h->stream));
-      FCM_HIP(hipFree(scr));
+      pool_free(scr, h->stream);
     }
     // unique blocks whose Jacobi-scaled condition number exceeds kKappa64 are
     // applied from their FP64 inverse inside the FP32 V-cycle
@@ -579,7 +641,7 @@ static fcm_status setup_levels(fcm_handle *h) {
       }
     TRY(upload(h, &L.hi64, fl));
   }
-  FCM_HIP(hipFree(kappa));
+  pool_free(kappa, h->stream);
   return check_flag(h, "Schwarz block inversion");
 }
 
@@ -813,16 +875,16 @@ static fcm_status patch_scratch_alloc(fcm_handle *h, int nblocks, PatchScratch &
     nblk = std::max(nblk, (size_t)cb * m * m);
     nscr = std::max(nscr, spd_inverse_scratch_doubles(m, cb));
   }
-  FCM_HIP(hipMalloc((void **)&ps.blk, nblk * sizeof(double)));
-  FCM_HIP(hipMalloc((void **)&ps.scr, nscr * sizeof(double)));
-  FCM_HIP(hipMalloc((void **)&ps.kappa, std::max(1, nblocks) * sizeof(double)));
+  TRY(pool_alloc((void **)&ps.blk, nblk * sizeof(double), h->stream));
+  TRY(pool_alloc((void **)&ps.scr, nscr * sizeof(double), h->stream));
+  TRY(pool_alloc((void **)&ps.kappa, std::max(1, nblocks) * sizeof(double), h->stream));
   return FCM_OK;
 }
 
-static void patch_scratch_free(PatchScratch &ps) {
-  if (ps.blk) hipFree(ps.blk);
-  if (ps.scr) hipFree(ps.scr);
-  if (ps.kappa) hipFree(ps.kappa);
+static void patch_scratch_free(fcm_handle *h, PatchScratch &ps) {
+  pool_free(ps.blk, h->stream);
+  pool_free(ps.scr, h->stream);
+  pool_free(ps.kappa, h->stream);
   ps = PatchScratch();
 }
 
@@ -986,7 +1048,7 @@ static fcm_status do_setup(fcm_handle *h) {
     if (sst == FCM_OK) sst = setup_coarse_launch(h, h->own);
     if (sst == FCM_OK) sst = setup_patch_levels(h, bnode, bkm, ps);
     fcm_status cst = coarse_join(h, h->own);
-    patch_scratch_free(ps);
+    patch_scratch_free(h, ps);
     if (sst != FCM_OK) return sst;
     TRY(cst);
   } else {
@@ -1015,7 +1077,11 @@ static fcm_status do_setup(fcm_handle *h) {
   TRY(dalloc(h, &h->vout32, nf));
   TRY(dalloc(h, &h->red, 1024));
   TRY(dalloc(h, &h->scal, 16));
-  FCM_HIP(hipHostMalloc((void **)&h->hscal, 16 * sizeof(double), hipHostMallocDefault));
+  h->hscal = pinned_get();
+  if (!h->hscal) {
+    set_error("pinned host allocation failed");
+    return FCM_ERR_OOM;
+  }
   FCM_HIP(hipStreamSynchronize(h->stream));
   return FCM_OK;
 }
@@ -1430,14 +1496,31 @@ const char *fcm_status_string(fcm_status s) {
 void fcm_destroy(fcm_handle *h) {
   if (!h) return;
   if (h->own) hipStreamSynchronize(h->own);   // a failed setup may leave coarse work in flight
-  if (h->co_scr) hipFree(h->co_scr);
-  if (h->co_ready) hipEventDestroy(h->co_ready);
   if (h->cg_exec) hipGraphExecDestroy(h->cg_exec);
   if (h->cg_graph) hipGraphDestroy(h->cg_graph);
+  // release the memory in stream order after the work queued on the handle's
+  // stream (on the library's own stream when it exists, so that a caller's
+  // legacy default stream never hosts the release)
+  hipStream_t fs = h->stream;
+  if (h->own && h->co_ready && hipEventRecord(h->co_ready, h->stream) == hipSuccess &&
+      hipStreamWaitEvent(h->own, h->co_ready, 0) == hipSuccess)
+    fs = h->own;
+  pool_free(h->co_scr, fs);
+  for (void *p : h->allocs) pool_free(p, fs);
+  if (h->own) hipStreamSynchronize(h->own);
+  if (h->co_ready) hipEventDestroy(h->co_ready);
   if (h->own) hipStreamDestroy(h->own);
-  for (void *p : h->allocs) hipFree(p);
-  if (h->hscal) hipHostFree(h->hscal);
+  pinned_put(h->hscal);
   delete h;
+}
+
+fcm_status fcm_trim_pool(void) {
+  int dev = 0;
+  FCM_HIP(hipGetDevice(&dev));
+  hipMemPool_t pool;
+  FCM_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+  FCM_HIP(hipMemPoolTrimTo(pool, 0));
+  return FCM_OK;
 }
 
 fcm_status fcm_setup(const fcm_problem *pr, const fcm_options *op, void *stream,

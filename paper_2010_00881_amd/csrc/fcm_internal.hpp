@@ -192,6 +192,13 @@ void set_error(const char *fmt, ...);
     }                                                                         \
   } while (0)
 
+// Stream-ordered device memory from the device's default pool, and recycled
+// pinned host blocks of 16 doubles (fcm_host.hip).
+fcm_status pool_alloc(void **p, size_t bytes, hipStream_t s);
+void pool_free(void *p, hipStream_t s);
+double *pinned_get();
+void pinned_put(double *b);
+
 // ------------------------------------------------------- kernel launchers
 // Setup (kernels_setup.hip).
 void launch_classify(const Geo &g, const double *ball, uint8_t *state, hipStream_t s);
@@ -327,7 +334,7 @@ void cg_issue(fcm_handle *h, CGState &cg, hipStream_t s);
 fcm_status cg_capture(fcm_handle *h, const CGState &cg, hipStream_t s);
 void cg_finish(fcm_handle *h, CGState &cg);
 fcm_status cg_report(fcm_handle *h, CGState &cg, fcm_solve_info *info, hipStream_t s);
-int64_t footprint_estimate(const fcm_problem &p);
+int64_t footprint_estimate(const fcm_problem &p, const fcm_options &o);
 
 // Coarse solve.  b, x: level-0 vectors (FP64, padded planes).
 void coarse_solve_launch(const Geo &g, const Coarse &c, const double *b, double *x,

@@ -31,9 +31,12 @@ namespace fcm {
 
 // Device footprint estimate of a problem before setup (bytes): padded vectors,
 // element matrices of the cells within one cell of a hole surface, Schwarz
-// inverses of those blocks and the dense coarse Schur inverses.
-int64_t footprint_estimate(const fcm_problem &p) {
+// inverses (elementwise: of the cut-affected elements; patchwise: of the
+// cut-affected grid nodes, about 4-5 per cut cell, plus the class inverses and
+// the transient block scratch), and the dense coarse S^-1, G, F blocks.
+int64_t footprint_estimate(const fcm_problem &p, const fcm_options &o) {
   const int d = p.dim, nf = p.n_fields;
+  const bool mixed = o.precision == FCM_MIXED;
   int64_t G = 1, E = 1;
   double h = 1.0;
   for (int ax = 0; ax < d; ++ax) {
@@ -53,26 +56,41 @@ int64_t footprint_estimate(const fcm_problem &p) {
     surf += (d == 3) ? 4.0 * M_PI * r * r / (h * h) : 2.0 * M_PI * r / h;
   }
   int64_t ncut = std::min<int64_t>(E, (int64_t)(3.0 * surf) + 1);
-  int64_t nuniq = std::min<int64_t>(E, ncut * (d == 3 ? 4 : 3));
   int64_t bytes = 0;
   bytes += ncut * mp * mp * 12;               // cut matrices FP64 + FP32
   bytes += E * mp * 8;                        // element loads
+  const int64_t per = mixed ? 12 : 8;         // FP64 (+ FP32) copy per inverse entry
   int64_t inv = 0;
-  for (int q = 2; q <= p.p; ++q) {
-    int64_t m = nf;
-    for (int ax = 0; ax < d; ++ax) m *= q + 1;
-    inv += (nuniq + 64) * m * m * 12;
+  if (o.smoother == FCM_SMOOTH_PATCHWISE) {
+    const int64_t nuniq = std::min<int64_t>(G, ncut * (d == 3 ? 5 : 4));
+    int64_t mtop = 0;
+    for (int q = 2; q <= p.p; ++q) {
+      int64_t m = nf;
+      for (int ax = 0; ax < d; ++ax) m *= 2 * q + 1;
+      const int64_t ld = (m + 3) & ~3;
+      inv += (nuniq + 128) * m * ld * per;
+      mtop = m;
+    }
+    inv += G * mtop * 8 + (int64_t)320 << 20;  // patch products, block scratch
+  } else {
+    const int64_t nuniq = std::min<int64_t>(E, ncut * (d == 3 ? 4 : 3));
+    for (int q = 2; q <= p.p; ++q) {
+      int64_t m = nf;
+      for (int ax = 0; ax < d; ++ax) m *= q + 1;
+      inv += (nuniq + 64) * m * m * per;
+    }
+    inv += E * mp * 8;                         // element products
   }
   bytes += inv;
   // vectors: ~10 FP64 + 6 FP32 fine-level vectors
   bytes += nP * G * (10 * 8 + 6 * 4);
-  // coarse: layers of ~1024 unknowns
+  // coarse: layers of ~1024 unknowns, S^-1, G and F blocks
   int64_t per_layer = nf;
   for (int ax = 0; ax < d - 1; ++ax) per_layer *= p.n[ax] + 1;
   int64_t w = std::max<int64_t>(1, (int64_t)(1024.0 / per_layer + 0.5));
   int64_t nb = per_layer * w;
   int64_t nblk = (p.n[d - 1] + w) / w;
-  bytes += nblk * nb * nb * 8 + nblk * nb * 27 * nf * 8;
+  bytes += 3 * nblk * nb * nb * 8 + nblk * nb * 27 * nf * 8;
   return bytes + (16 << 20);
 }
 
@@ -145,7 +163,7 @@ static void finish_request(fcm_server *s, std::shared_ptr<Request> &r, hipStream
   r->info.t_solve_ms =
       std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count() -
       r->t_solve_start_ms;
-  if (r->x) hipFree(r->x);
+  fcm::pool_free(r->x, st);
   r->x = nullptr;
   if (r->h) fcm_destroy(r->h);
   r->h = nullptr;
@@ -179,7 +197,7 @@ static void admission_loop(fcm_server *s, int which) {
     double *x = nullptr;
     if (st == FCM_OK) {
       const int64_t n = h->lev[h->L].npad;
-      if (hipMalloc((void **)&x, n * sizeof(double)) != hipSuccess) st = FCM_ERR_OOM;
+      st = fcm::pool_alloc((void **)&x, n * sizeof(double), setup_stream);
     }
     if (st == FCM_OK) {
       h->stream = nullptr;
@@ -212,7 +230,7 @@ static void admission_loop(fcm_server *s, int which) {
       r->status = st;
       r->done = true;
       r->t_done = std::chrono::steady_clock::now();
-      if (r->x) hipFree(r->x);
+      fcm::pool_free(r->x, setup_stream);
       if (r->h) fcm_destroy(r->h);
       r->h = nullptr;
       r->x = nullptr;
@@ -337,7 +355,7 @@ fcm_status fcm_serve_submit(fcm_server *s, const fcm_problem *prob, const fcm_op
   r->pr.gauss = r->gauss.data();
   r->pr.traction_face = r->tface.data();
   r->pr.traction_vec = r->tvec.data();
-  r->footprint = footprint_estimate(r->pr);
+  r->footprint = footprint_estimate(r->pr, r->opt);
   r->t_submit = std::chrono::steady_clock::now();
   *req_id = r->id;
   std::lock_guard<std::mutex> lk(s->mu);
@@ -390,15 +408,19 @@ fcm_status fcm_server_destroy(fcm_server *s) {
   for (int k = 0; k < 2; ++k)
     if (s->admit_thr[k].joinable()) s->admit_thr[k].join();
   if (s->tick_thr.joinable()) s->tick_thr.join();
+  hipSetDevice(s->device);
+  for (auto st : s->streams) hipStreamSynchronize(st);
+  for (int k = 0; k < 2; ++k)
+    if (s->setup_stream[k]) hipStreamSynchronize(s->setup_stream[k]);
   for (auto &r : s->active) {
-    if (r->inflight && r->ev) hipEventSynchronize(r->ev);
     if (r->ev) hipEventDestroy(r->ev);
-    if (r->x) hipFree(r->x);
+    fcm::pool_free(r->x, s->setup_stream[0]);
     if (r->h) fcm_destroy(r->h);
   }
   for (auto st : s->streams) hipStreamDestroy(st);
   for (int k = 0; k < 2; ++k)
     if (s->setup_stream[k]) hipStreamDestroy(s->setup_stream[k]);
+  fcm_trim_pool();
   delete s;
   return FCM_OK;
 }

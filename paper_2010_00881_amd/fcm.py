@@ -100,6 +100,7 @@ SIGNATURES = {
     "fcm_time_op": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double),
                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "fcm_destroy": ([_P], None),
+    "fcm_trim_pool": ([], ctypes.c_int),
     "fcm_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)], ctypes.c_int),
     "fcm_serve_submit": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Options),
                           ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -246,6 +247,10 @@ class Solver:
 
     def close(self):
         if getattr(self, "h", None):
+            # the handle's memory is released in order on its setup stream;
+            # work queued with it on other streams must finish first
+            import torch
+            torch.cuda.synchronize()
             lib().fcm_destroy(self.h)
             self.h = None
 
@@ -388,6 +393,11 @@ class Server:
         if getattr(self, "s", None):
             lib().fcm_server_destroy(self.s)
             self.s = None
+
+
+def trim_pool():
+    """Return the cached, unused device memory of the library's pool."""
+    _check(lib().fcm_trim_pool())
 
 
 def spd_inverse(A, kappa=None):
