@@ -818,71 +818,62 @@ __global__ void apply_scale_kernel(double *A, int n, const double *scale, double
   }
 }
 
-// Pivot rows of block K: workgroup (J, b) sweeps rows K over its 64 columns
-// [64 J, 64 J + 64) in LDS, pivot by pivot (product form, the unblocked
-// sweep restricted to these rows), tracking a private copy of the 32 x 32
-// pivot tile for the pivot columns; rows past n of a partial last block are
-// identity rows.  It writes the swept rows W and the rows before the sweep R
-// for its columns.  Because the swept matrix stays symmetric, the block
-// column is A_IK = R^T, so the update kernel needs nothing that another
-// workgroup of the same launch writes.
-constexpr int kTJ = 64;
+// Pivot rows of block K: one wave per workgroup (J, b).  Lanes 0..31 hold
+// the columns of the 32 x 32 pivot tile (a private copy, needed for the
+// pivot columns), lanes 32..63 the panel columns [32 J, 32 J + 32), each a
+// column of 32 rows in registers; the wave sweeps them pivot by pivot
+// (product form: the unblocked sweep restricted to the rows of block K),
+// the pivot column being broadcast from its lane through LDS.  Rows past n
+// of a partial last block are identity rows.  It writes the swept rows W and
+// the rows before the sweep R of its panel columns.  Because the swept
+// matrix stays symmetric, the block column is A_IK = R^T, so the update
+// kernel needs nothing that another workgroup of the same launch writes.
+constexpr int kTJ = 32;
 
-__global__ __launch_bounds__(256) void sweep_rows_kernel(double *A, int n, int K, double *W,
-                                                         double *Rg, int *flag) {
-  __shared__ double P[kTB][kTB + 1];
-  __shared__ double T[kTB][kTJ + 1];
-  __shared__ double ck[kTB], rk[kTB], tk[kTJ];
-  const int J = blockIdx.x, b = blockIdx.y;
+__global__ __launch_bounds__(64) void sweep_rows_kernel(double *A, int n, int K, double *W,
+                                                        double *Rg, int *flag) {
+  __shared__ double bc[2][kTB];
+  const int J = blockIdx.x, b = blockIdx.y, l = threadIdx.x;
   const double *M = A + (size_t)b * n * n;
   double *Wb = W + (size_t)b * kTB * n;
   double *Rb = Rg + (size_t)b * kTB * n;
-  const int k0 = K * kTB, j0 = J * kTJ;
-  const int tid = threadIdx.x;
-  for (int i = tid; i < kTB * kTB; i += 256) {
-    const int r = i / kTB, c = i % kTB;
-    const int gr = k0 + r, gc = k0 + c;
-    P[r][c] = (gr < n && gc < n) ? M[(size_t)gr * n + gc] : (r == c ? 1.0 : 0.0);
+  const int k0 = K * kTB;
+  const bool panel = l >= kTB;
+  const int col = panel ? J * kTJ + (l - kTB) : k0 + l;
+  double x[kTB];
+#pragma unroll
+  for (int r = 0; r < kTB; ++r) {
+    const int gr = k0 + r;
+    const double v = (gr < n && col < n) ? M[(size_t)gr * n + col] : (gr == col ? 1.0 : 0.0);
+    x[r] = v;
+    if (panel && col < n) Rb[(size_t)r * n + col] = v;
   }
-  for (int i = tid; i < kTB * kTJ; i += 256) {
-    const int r = i / kTJ, c = i % kTJ;
-    const int gr = k0 + r, gc = j0 + c;
-    double v = 0.0;
-    if (gc < n) v = gr < n ? M[(size_t)gr * n + gc] : (gc == gr ? 1.0 : 0.0);
-    T[r][c] = v;
-    if (gc < n) Rb[(size_t)r * n + gc] = v;
-  }
-  __syncthreads();
+#pragma unroll
   for (int kk = 0; kk < kTB; ++kk) {
-    const int kc = k0 + kk;   // pivot column
-    if (tid < kTB) {
-      ck[tid] = P[tid][kk];
-      rk[tid] = P[kk][tid];
+    const int kc = k0 + kk;   // pivot column; lane kk holds it
+    if (l == kk) {
+#pragma unroll
+      for (int r = 0; r < kTB; ++r) bc[kk & 1][r] = x[r];
     }
-    if (tid < kTJ) tk[tid] = T[kk][tid];
     __syncthreads();
+    double ck[kTB];
+#pragma unroll
+    for (int r = 0; r < kTB; ++r) ck[r] = bc[kk & 1][r];
     const double piv = ck[kk];
-    if (tid == 0 && J == 0 && kc < n && !(piv > 0.0)) atomicOr(flag, 1);
+    if (l == 0 && J == 0 && kc < n && !(piv > 0.0)) atomicOr(flag, 1);
     const double ip = 1.0 / piv;
-    for (int i = tid; i < kTB * kTB; i += 256) {
-      const int r = i / kTB, c = i % kTB;
-      double v;
-      if (c == kk) v = r == kk ? -ip : ck[r] * ip;
-      else v = r == kk ? rk[c] * ip : P[r][c] - ck[r] * rk[c] * ip;
-      P[r][c] = v;
+    if (col == kc) {
+#pragma unroll
+      for (int r = 0; r < kTB; ++r) x[r] = r == kk ? -ip : ck[r] * ip;
+    } else {
+      const double xk = x[kk] * ip;
+#pragma unroll
+      for (int r = 0; r < kTB; ++r) x[r] = r == kk ? xk : x[r] - ck[r] * xk;
     }
-    for (int i = tid; i < kTB * kTJ; i += 256) {
-      const int r = i / kTJ, c = i % kTJ;
-      double v;
-      if (j0 + c == kc) v = r == kk ? -ip : ck[r] * ip;
-      else v = r == kk ? tk[c] * ip : T[r][c] - ck[r] * tk[c] * ip;
-      T[r][c] = v;
-    }
-    __syncthreads();
   }
-  for (int i = tid; i < kTB * kTJ; i += 256) {
-    const int r = i / kTJ, c = i % kTJ;
-    if (j0 + c < n) Wb[(size_t)r * n + j0 + c] = T[r][c];
+  if (panel && col < n) {
+#pragma unroll
+    for (int r = 0; r < kTB; ++r) Wb[(size_t)r * n + col] = x[r];
   }
 }
 
@@ -937,6 +928,23 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
       for (int v = 0; v < 2; ++v)
         acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
   }
+  // all loads of the write phase are issued before any store (the output
+  // entries are distinct and W is not written here)
+  double old[2][2][4];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int i = i0 + 16 * u + 4 * jj + lq, j = j0 + 16 * v + ln;
+        const bool ok = i < n && j < n && i <= j;
+        const bool ik = i >= k0 && i < k1, jk = j >= k0 && j < k1;
+        const double *src = !ok ? M : ik ? Wb + (size_t)(i - k0) * n + j
+                                      : jk ? Wb + (size_t)(j - k0) * n + i
+                                           : M + (size_t)i * n + j;
+        old[u][v][jj] = *src;
+      }
 #pragma unroll
   for (int u = 0; u < 2; ++u)
 #pragma unroll
@@ -945,11 +953,8 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
       for (int jj = 0; jj < 4; ++jj) {
         const int i = i0 + 16 * u + 4 * jj + lq, j = j0 + 16 * v + ln;
         if (i >= n || j >= n || i > j) continue;
-        const bool ik = i >= k0 && i < k1, jk = j >= k0 && j < k1;
-        double val;
-        if (ik) val = Wb[(size_t)(i - k0) * n + j];
-        else if (jk) val = Wb[(size_t)(j - k0) * n + i];
-        else val = M[(size_t)i * n + j] - acc[u][v][jj];
+        const bool inK = (i >= k0 && i < k1) || (j >= k0 && j < k1);
+        const double val = inK ? old[u][v][jj] : old[u][v][jj] - acc[u][v][jj];
         M[(size_t)i * n + j] = val;
         M[(size_t)j * n + i] = val;
       }
@@ -993,7 +998,7 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
   double *R = W + (size_t)batch * kTB * n;
   const int nt = (n + 63) / 64;
   for (int K = 0; K < NB; ++K) {
-    sweep_rows_kernel<<<dim3((n + kTJ - 1) / kTJ, batch), 256, 0, s>>>(A, n, K, W, R, flag);
+    sweep_rows_kernel<<<dim3((n + kTJ - 1) / kTJ, batch), 64, 0, s>>>(A, n, K, W, R, flag);
     sweep_update_mfma_kernel<<<dim3(nt * (nt + 1) / 2, batch), 256, 0, s>>>(A, n, K, W, R, nt);
   }
   if (kappa) norm1_kernel<<<batch, 256, 0, s>>>(A, n, kappa, 1);

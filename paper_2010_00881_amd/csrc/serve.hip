@@ -71,7 +71,7 @@ int64_t footprint_estimate(const fcm_problem &p, const fcm_options &o) {
       inv += (nuniq + 128) * m * ld * per;
       mtop = m;
     }
-    inv += G * mtop * 8 + (int64_t)320 << 20;  // patch products, block scratch
+    inv += G * mtop * 8 + ((int64_t)320 << 20);  // patch products, block scratch
   } else {
     const int64_t nuniq = std::min<int64_t>(E, ncut * (d == 3 ? 4 : 3));
     for (int q = 2; q <= p.p; ++q) {
@@ -123,6 +123,11 @@ struct Request {
   std::string err;             // error text of a failed request
 };
 
+// Setups of admitted requests run on this many threads, each with its own
+// stream: the coarse factorisation of a small request is a chain of launches
+// that fills a few compute units, so several setups share the device.
+constexpr int kAdmitThreads = 4;
+
 }  // namespace
 
 struct fcm_server {
@@ -137,8 +142,8 @@ struct fcm_server {
   int64_t resident = 0;          // bytes of admitted hierarchies (estimates until set up)
   int n_admitting = 0;
   std::vector<hipStream_t> streams;
-  hipStream_t setup_stream[2] = {nullptr, nullptr};
-  std::thread admit_thr[2], tick_thr;
+  hipStream_t setup_stream[kAdmitThreads] = {};
+  std::thread admit_thr[kAdmitThreads], tick_thr;
   // Graph captures run alone: setup work and ticks hold this lock shared,
   // a capture holds it exclusively (capture must not overlap synchronous
   // allocation or copy calls of other threads).
@@ -324,12 +329,12 @@ fcm_status fcm_server_create(const fcm_server_opts *o, fcm_server **out) {
       set_error("stream creation failed");
       return FCM_ERR_HIP;
     }
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < kAdmitThreads; ++k)
     if (hipStreamCreateWithFlags(&s->setup_stream[k], hipStreamNonBlocking) != hipSuccess) {
       set_error("stream creation failed");
       return FCM_ERR_HIP;
     }
-  for (int k = 0; k < 2; ++k) s->admit_thr[k] = std::thread(admission_loop, s, k);
+  for (int k = 0; k < kAdmitThreads; ++k) s->admit_thr[k] = std::thread(admission_loop, s, k);
   s->tick_thr = std::thread(tick_loop, s);
   *out = s;
   return FCM_OK;
@@ -405,12 +410,12 @@ fcm_status fcm_server_destroy(fcm_server *s) {
     s->stop = true;
     s->cv.notify_all();
   }
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < kAdmitThreads; ++k)
     if (s->admit_thr[k].joinable()) s->admit_thr[k].join();
   if (s->tick_thr.joinable()) s->tick_thr.join();
   hipSetDevice(s->device);
   for (auto st : s->streams) hipStreamSynchronize(st);
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < kAdmitThreads; ++k)
     if (s->setup_stream[k]) hipStreamSynchronize(s->setup_stream[k]);
   for (auto &r : s->active) {
     if (r->ev) hipEventDestroy(r->ev);
@@ -418,7 +423,7 @@ fcm_status fcm_server_destroy(fcm_server *s) {
     if (r->h) fcm_destroy(r->h);
   }
   for (auto st : s->streams) hipStreamDestroy(st);
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < kAdmitThreads; ++k)
     if (s->setup_stream[k]) hipStreamDestroy(s->setup_stream[k]);
   fcm_trim_pool();
   delete s;
