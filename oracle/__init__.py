@@ -11,6 +11,8 @@ The oracle is deliberately plain and slow:
   * ``fcm``        -- DOFs, cut-cell integration by recursive bisection, assembly
   * ``mg``         -- additive Schwarz smoother (eq. AdditiveSchwarz), V-cycle (Alg. 1),
                       hierarchical transfers (eq. restrictionoperation), PCG and MG solver.
+  * ``mlhp``       -- multi-level hp overlay discretisation (Section 2.2) and its
+                      hp-multigrid levels and node-patch Schwarz blocks (Section 3.2).
 
 Every floating-point computation is IEEE double precision.
 
@@ -18,4 +20,4 @@ Parity pins: see tests/test_oracle_*.py.  Parity unpinned: none of the
 functions below is unpinned; the paper's exact iteration counts are not
 reproduced because its geometries exist only in figures.
 """
-from . import basis, geometry, fcm, mg  # noqa: F401
+from . import basis, geometry, fcm, mg, mlhp  # noqa: F401

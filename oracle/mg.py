@@ -71,6 +71,8 @@ class Hierarchy:
 
     # ------------------------------------------------------------- smoother
     def block_sets(self, l):
+        if hasattr(self.disc, "schwarz_blocks"):      # multi-level hp: level-wise node patches
+            return self.disc.schwarz_blocks(l)
         return block_sets(self.disc, self.sizes[l], self.opts.get("smoother", "elementwise"))
 
     def _build_blocks(self, l):
