@@ -87,7 +87,11 @@ typedef struct {
   double lo[3], hi[3];        /* embedding box                                   */
   int p;                      /* polynomial order, 1..6                          */
   int n_fields;               /* 1 (Poisson) or dim (linear elasticity)          */
-  int refine_levels;          /* multi-level hp depth k; only 0 is supported     */
+  int refine_levels;          /* multi-level hp depth K (Section 2.2): elements cut
+                                 by the sphere are bisected recursively K times;
+                                 K > 0 needs Poisson, one ball, FP64 V-cycle and
+                                 patchwise blocks (all functions on the base
+                                 elements around a base node, Section 3.3.1)   */
   int geom;                   /* FCM_GEOM_*                                      */
   int n_balls;                /* holes (BOX_MINUS_BALLS) or 1 (BALL_INTERIOR)    */
   const double *ball_c;       /* [n_balls][dim] centres                          */
@@ -104,6 +108,11 @@ typedef struct {
   const double *gauss;        /* [n_gauss][5]: A, w, c_x, c_y, c_z               */
   double f_const;             /* constant scalar source                          */
   double body_force[3];       /* constant body force (elasticity)                */
+  double beta;                /* penalty for u = 0 on the sphere (multi-level hp,
+                                 BALL_INTERIOR; eq. weakform), 0 = none          */
+  int surf_n[2];              /* surface rule of the penalty: Gauss-Legendre
+                                 points in cos(theta) and trapezoid points in phi
+                                 (2D: phi only); 0 = 256 x 512                   */
 } fcm_problem;
 
 /* Solver options (Sections 3.3.2 and 4). */

@@ -107,7 +107,7 @@ class MultiLevelDiscretization:
         self.depth = int(desc.get("quad_depth", 3))
         self.beta = float(desc.get("beta", 0.0))
         self.modes = [tuple(reversed(t)) for t in itertools.product(range(self.p + 1), repeat=d)]
-        self.surface = surface
+        self.surface = tuple(desc.get("surface_rule", surface))
         if int(desc.get("n_fields", 1)) != 1:
             raise ValueError("multi-level hp: Poisson only")
         self._build_tree()

@@ -32,7 +32,7 @@ void set_error(const char *fmt, ...) {
 
 // ------------------------------------------------------------ host basis
 // Gauss-Legendre nodes by Newton iteration on L_n.
-static void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w) {
   x.assign(n, 0.0);
   w.assign(n, 0.0);
   for (int i = 0; i < n; ++i) {
@@ -194,10 +194,30 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
     set_error("n_fields must be 1 or dim");
     return FCM_ERR_ARG;
   }
-  if (p->refine_levels != 0) {
-    set_error("multi-level hp refinement (refine_levels > 0) is not supported by this build");
+  if (p->refine_levels < 0 || p->refine_levels > 4) {
+    set_error("refine_levels must be in 0..4");
     return FCM_ERR_ARG;
   }
+  if (p->refine_levels > 0) {
+    if (p->n_fields != 1) { set_error("multi-level hp: Poisson only"); return FCM_ERR_ARG; }
+    if (o->precision != FCM_FP64) {
+      set_error("multi-level hp: the V-cycle runs in FP64 only");
+      return FCM_ERR_ARG;
+    }
+    if (o->smoother != FCM_SMOOTH_PATCHWISE) {
+      set_error("multi-level hp: patchwise Schwarz blocks only");
+      return FCM_ERR_ARG;
+    }
+    if (p->quad_depth > (p->dim == 3 ? 3 : 4)) {
+      set_error("multi-level hp: quad_depth must be <= %d", p->dim == 3 ? 3 : 4);
+      return FCM_ERR_ARG;
+    }
+    if (p->p > 3) { set_error("multi-level hp: p must be <= 3"); return FCM_ERR_ARG; }
+  } else if (p->beta != 0.0) {
+    set_error("beta (sphere penalty) needs refine_levels > 0");
+    return FCM_ERR_ARG;
+  }
+  if (!std::isfinite(p->beta) || p->beta < 0.0) { set_error("invalid beta"); return FCM_ERR_ARG; }
   for (int ax = 0; ax < p->dim; ++ax) {
     if (p->n[ax] < 1 || p->n[ax] > 4096) { set_error("n[%d] out of range", ax); return FCM_ERR_ARG; }
     if (!(p->hi[ax] > p->lo[ax])) { set_error("empty box on axis %d", ax); return FCM_ERR_ARG; }
@@ -1495,6 +1515,7 @@ const char *fcm_status_string(fcm_status s) {
 
 void fcm_destroy(fcm_handle *h) {
   if (!h) return;
+  if (h->ml) mlhp_free(h);
   if (h->own) hipStreamSynchronize(h->own);   // a failed setup may leave coarse work in flight
   if (h->cg_exec) hipGraphExecDestroy(h->cg_exec);
   if (h->cg_graph) hipGraphDestroy(h->cg_graph);
@@ -1588,7 +1609,7 @@ fcm_status fcm_setup(const fcm_problem *pr, const fcm_options *op, void *stream,
     set_error("problem too large for 32-bit plane offsets");
     return FCM_ERR_ARG;
   }
-  st = do_setup(h);
+  st = pr->refine_levels > 0 ? mlhp_setup(h) : do_setup(h);
   if (st != FCM_OK) {
     fcm_destroy(h);
     return st;
@@ -1632,6 +1653,7 @@ fcm_status fcm_sizes(const fcm_handle *h, int *n_levels, int64_t *n_dofs, int64_
     set_error("null argument");
     return FCM_ERR_ARG;
   }
+  if (h->ml) return mlhp_sizes(h, n_levels, n_dofs, n_padded);
   *n_levels = h->L + 1;
   if (n_padded)
     for (int l = 0; l <= h->L; ++l) n_padded[l] = h->lev[l].npad;
@@ -1659,6 +1681,7 @@ fcm_status fcm_dof_keys(const fcm_handle *h, int64_t *keys) {
     set_error("null argument");
     return FCM_ERR_ARG;
   }
+  if (h->ml) return mlhp_dof_keys(h, keys);
   const Geo &g = h->geo;
   std::vector<int> pt;
   plane_types(h, pt);
@@ -1688,12 +1711,20 @@ fcm_status fcm_local_modes(const fcm_handle *h, int *m, int *modes) {
     set_error("null argument");
     return FCM_ERR_ARG;
   }
+  if (h->ml) {
+    set_error("multi-level hp handles have no uniform element layout");
+    return FCM_ERR_ARG;
+  }
   *m = h->tab.m;
   if (modes) std::memcpy(modes, h->h_lm.data(), h->h_lm.size() * sizeof(int));
   return FCM_OK;
 }
 
 fcm_status fcm_element(const fcm_handle *h, int64_t e, int *state, double *K, double *be) {
+  if (h && h->ml) {
+    set_error("multi-level hp handles have no uniform element layout");
+    return FCM_ERR_ARG;
+  }
   if (!h || e < 0 || e >= h->geo.E) {
     set_error("element index out of range");
     return FCM_ERR_ARG;
@@ -1718,6 +1749,7 @@ fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s) {
     set_error("null argument");
     return FCM_ERR_ARG;
   }
+  if (h->ml) return mlhp_stats(h, s);
   s->n_elements = h->geo.E;
   int64_t kept = 0;
   for (auto v : h->h_state) kept += v != kVoid;
@@ -1739,12 +1771,14 @@ fcm_status fcm_rhs(fcm_handle *h, double *b_dev, void *stream) {
     set_error("null argument");
     return FCM_ERR_ARG;
   }
+  if (h->ml) return mlhp_rhs(h, b_dev, (hipStream_t)stream);
   FCM_HIP(hipMemcpyAsync(b_dev, h->b, h->lev[h->L].npad * sizeof(double),
                          hipMemcpyDeviceToDevice, (hipStream_t)stream));
   return FCM_OK;
 }
 
 fcm_status fcm_apply(fcm_handle *h, int level, const double *x, double *y, void *stream) {
+  if (h && h->ml && x && y) return mlhp_apply(h, level, x, y, (hipStream_t)stream);
   if (!h || !x || !y || level < 0 || level > h->L) {
     set_error("invalid argument");
     return FCM_ERR_ARG;
@@ -1755,6 +1789,7 @@ fcm_status fcm_apply(fcm_handle *h, int level, const double *x, double *y, void 
 }
 
 fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z, void *stream) {
+  if (h && h->ml && r && z) return mlhp_smooth(h, level, r, z, (hipStream_t)stream);
   if (!h || !r || !z || level < 1 || level > h->L) {
     set_error("invalid argument");
     return FCM_ERR_ARG;
@@ -1794,6 +1829,7 @@ fcm_status fcm_coarse_solve(fcm_handle *h, const double *b, double *x, void *str
     set_error("invalid argument");
     return FCM_ERR_ARG;
   }
+  if (h->ml) return mlhp_coarse_solve(h, b, x, (hipStream_t)stream);
   coarse_solve_launch(h->geo, h->co, b, x, (hipStream_t)stream);
   FCM_HIP(hipGetLastError());
   return FCM_OK;
@@ -1804,6 +1840,7 @@ fcm_status fcm_vcycle(fcm_handle *h, const double *r, double *z, void *stream) {
     set_error("invalid argument");
     return FCM_ERR_ARG;
   }
+  if (h->ml) return mlhp_vcycle(h, r, z, (hipStream_t)stream);
   vcycle_top(h, r, z, (hipStream_t)stream);
   FCM_HIP(hipGetLastError());
   return FCM_OK;
@@ -1816,6 +1853,7 @@ fcm_status fcm_pcg_solve(fcm_handle *h, const double *b_dev, double *x_dev, fcm_
     return FCM_ERR_ARG;
   }
   hipStream_t s = (hipStream_t)stream;
+  if (h->ml) return mlhp_pcg(h, b_dev, x_dev, info, s);
   auto t0 = std::chrono::steady_clock::now();
   if (h->opt.use_graphs) {
     // captured iterations run on the library's own stream (capture is not
@@ -1849,6 +1887,10 @@ fcm_status fcm_mg_solve(fcm_handle *h, const double *b_dev, double *x_dev, fcm_s
                         double *rho_max, void *stream) {
   if (!h || !x_dev) {
     set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  if (h->ml) {
+    set_error("multi-level hp: use fcm_pcg_solve");
     return FCM_ERR_ARG;
   }
   hipStream_t s = (hipStream_t)stream;
@@ -1944,6 +1986,10 @@ static double coarse_bytes(const fcm_handle *h) {
 
 fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
                        double *ms_per_launch, double *bytes_per_launch) {
+  if (h && h->ml) {
+    set_error("multi-level hp: no timing hook");
+    return FCM_ERR_ARG;
+  }
   if (!h || reps < 1 || op < FCM_OP_SMOOTH || op > FCM_OP_SMOOTH_STORED ||
       (op != FCM_OP_COARSE && op != FCM_OP_VCYCLE && (level < 1 || level > h->L))) {
     set_error("invalid argument");

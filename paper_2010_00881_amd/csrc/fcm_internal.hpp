@@ -113,6 +113,8 @@ struct PatchTables {
   int *prow = nullptr;      // [nP][27] local mode of plane P in the patch of node g - delta
 };
 
+struct MlhpState;   // multi-level hp path (mlhp.hip)
+
 }  // namespace fcm
 
 struct fcm_handle {
@@ -176,6 +178,7 @@ struct fcm_handle {
   double t_setup_ms = 0.0;
   int64_t bytes = 0;
   std::vector<void *> allocs;
+  fcm::MlhpState *ml = nullptr;               // set when refine_levels > 0
 };
 
 namespace fcm {
@@ -195,6 +198,22 @@ void set_error(const char *fmt, ...);
 // Stream-ordered device memory from the device's default pool, and recycled
 // pinned host blocks of 16 doubles (fcm_host.hip).
 fcm_status pool_alloc(void **p, size_t bytes, hipStream_t s);
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
+
+// Multi-level hp path (mlhp.hip): setup, operators and solvers of a handle
+// whose problem has refine_levels > 0.
+fcm_status mlhp_setup(fcm_handle *h);
+void mlhp_free(fcm_handle *h);
+fcm_status mlhp_sizes(const fcm_handle *h, int *n_levels, int64_t *n_dofs, int64_t *n_padded);
+fcm_status mlhp_dof_keys(const fcm_handle *h, int64_t *keys);
+fcm_status mlhp_rhs(fcm_handle *h, double *b, hipStream_t s);
+fcm_status mlhp_apply(fcm_handle *h, int level, const double *x, double *y, hipStream_t s);
+fcm_status mlhp_smooth(fcm_handle *h, int level, const double *r, double *z, hipStream_t s);
+fcm_status mlhp_coarse_solve(fcm_handle *h, const double *b, double *x, hipStream_t s);
+fcm_status mlhp_vcycle(fcm_handle *h, const double *r, double *z, hipStream_t s);
+fcm_status mlhp_pcg(fcm_handle *h, const double *b, double *x, fcm_solve_info *info,
+                    hipStream_t s);
+fcm_status mlhp_stats(const fcm_handle *h, fcm_stats *st);
 void pool_free(void *p, hipStream_t s);
 double *pinned_get();
 void pinned_put(double *b);

@@ -41,6 +41,7 @@ class Problem(ctypes.Structure):
         ("traction_vec", ctypes.POINTER(ctypes.c_double)),
         ("n_gauss", ctypes.c_int), ("gauss", ctypes.POINTER(ctypes.c_double)),
         ("f_const", ctypes.c_double), ("body_force", ctypes.c_double * 3),
+        ("beta", ctypes.c_double), ("surf_n", ctypes.c_int * 2),
     ]
 
 
@@ -186,6 +187,9 @@ class _ProblemData:
         bf = list(desc.get("body_force", [0.0] * d)) + [0.0] * 3
         for i in range(3):
             P.body_force[i] = float(bf[i])
+        P.beta = float(desc.get("beta", 0.0))
+        sn = desc.get("surface_rule", (0, 0))
+        P.surf_n[0], P.surf_n[1] = int(sn[0]), int(sn[1])
         self.struct = P
 
 

@@ -1,0 +1,137 @@
+"""GPU parity of the multi-level hp path (Section 2.2, Section 3.2).
+
+The oracle builds the same overlay discretisation on the CPU; the GPU DOF
+numbering uses the same key and the same (group, key) order, so vectors are
+compared entry by entry: DOF keys and level sizes (exact), the assembled load
+and A_l x on every multigrid level (rounding of the leaf quadrature), the
+patchwise smoother and the V-cycle (in the energy norm: patch blocks with
+fictitious leaves have scaled condition numbers up to ~1e14, so individual
+entries of their inverses carry errors ~ cond * eps), and the preconditioned
+CG (iterations, residual, energy-norm distance of the solutions).
+
+Tolerances.  With alpha = 1 and beta = 1 the blocks are well conditioned and
+smoother, V-cycle and solution agree to 1e-6 in the energy norm.  With the
+FCM values alpha = 1e-10, beta = 1e4 the Jacobi-scaled patch blocks reach
+condition numbers of 2e13..5e13 (measured with the oracle), so both sides'
+inverses carry relative errors up to cond * eps ~ 5e-3; the test allows 1e-3
+(measured 3e-5..1e-4).  The solutions of the two CGs, each stopped at a
+relative residual of 1e-10 with cond(A) ~ 1e14, may differ by
+1e-10 sqrt(cond) ~ 1e-3 in the energy norm (measured 4e-5).
+"""
+import numpy as np
+import pytest
+
+import fcm_inputs as fi
+
+pytestmark = pytest.mark.gpu
+
+
+def _desc(dim, n, K, p, depth=2, c=None, alpha=1e-10, beta=1e4):
+    d, o = fi.sphere_multilevel(0, n=n, k=K, p=p)
+    d.update(dim=dim, n=[n] * dim, lo=[0.0] * dim, hi=[1.0] * dim,
+             ball_c=[list(c if c is not None else [0.5] * dim)], ball_r=[0.35],
+             quad_depth=depth, surface_rule=(48, 96), alpha=alpha, beta=beta)
+    if dim == 2:
+        d["gauss"] = [(g[0], g[1], list(g[2][:2])) for g in d["gauss"][:4]]
+    o = fi.default_options(dim, "patchwise")
+    return d, o
+
+
+CASES = {
+    "2d_n4_K2_p2_a1": lambda: _desc(2, 4, 2, 2, alpha=1.0, beta=1.0),
+    "3d_n2_K1_p2_a1": lambda: _desc(3, 2, 1, 2, alpha=1.0, beta=1.0),
+    "2d_n4_K2_p2": lambda: _desc(2, 4, 2, 2),
+    "2d_n3_K3_p3": lambda: _desc(2, 3, 3, 3, c=[0.47, 0.53]),
+    "3d_n2_K1_p2": lambda: _desc(3, 2, 1, 2),
+    "3d_n4_K2_p2": lambda: _desc(3, 4, 2, 2),
+}
+
+_cache = {}
+
+
+def _tol(name):
+    return 1e-6 if name.endswith("_a1") else 1e-3
+
+
+def _case(name):
+    if name in _cache:
+        return _cache[name]
+    for k in list(_cache):
+        _cache.pop(k)[0].close()
+    from oracle import mg, mlhp
+    from paper_2010_00881_amd import Solver
+    d, o = CASES[name]()
+    print(f"[mlhp] {name}: oracle", flush=True)
+    D = mlhp.MultiLevelDiscretization(d)
+    H = mg.Hierarchy(D, o, scaled_blocks=True)
+    print(f"[mlhp] {name}: setup on cuda:0 ({D.n_dofs} dofs, {len(D.leaves)} leaves)", flush=True)
+    s = Solver(d, dict(o, precision="fp64"))
+    _cache[name] = (s, D, H)
+    return _cache[name]
+
+
+def _t(x):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64).cuda()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mlhp_dofs_load_and_operator(name):
+    s, D, H = _case(name)
+    assert s.n_dofs == D.level_sizes
+    keys = s.dof_keys()
+    assert np.array_equal(keys, D.dof_keys)
+    b = s.rhs()
+    bo = D.b
+    assert np.abs(b.cpu().numpy() - bo).max() <= 1e-12 * np.abs(bo).max()
+    rng = np.random.default_rng(5)
+    for l in range(len(D.level_sizes)):
+        n = D.level_sizes[l]
+        x = rng.standard_normal(n)
+        y = s.apply(l, _t(x)).cpu().numpy()
+        yo = H.As[l] @ x
+        err = np.abs(y - yo).max() / np.abs(yo).max()
+        print(f"[mlhp] {name} level {l}: A x rel err {err:.1e}", flush=True)
+        assert err <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mlhp_smoother_and_vcycle(name):
+    s, D, H = _case(name)
+    rng = np.random.default_rng(6)
+    L = len(D.level_sizes) - 1
+    for l in range(1, L + 1):
+        A = H.As[l]
+        r = A @ rng.standard_normal(D.level_sizes[l])
+        z = s.smooth(l, _t(r)).cpu().numpy()
+        zo = H.smooth(l, r)
+        e = z - zo
+        err = np.sqrt(e @ (A @ e) / (zo @ (A @ zo)))
+        print(f"[mlhp] {name} smoother level {l}: energy rel err {err:.1e}", flush=True)
+        assert err <= _tol(name)
+    A = H.As[L]
+    r = A @ rng.standard_normal(D.n_dofs)
+    v = s.vcycle(_t(r)).cpu().numpy()
+    vo = H.precondition(r)
+    e = v - vo
+    err = np.sqrt(e @ (A @ e) / (vo @ (A @ vo)))
+    print(f"[mlhp] {name} vcycle: energy rel err {err:.1e}", flush=True)
+    assert err <= _tol(name)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_mlhp_pcg(name):
+    s, D, H = _case(name)
+    x, info = s.pcg()
+    xo, it, hist = H.pcg(D.b)
+    print(f"[mlhp] {name}: gpu it {info['iterations']} rel {info['rel_res']:.1e} true "
+          f"{info['true_rel_res']:.1e}; oracle it {it}", flush=True)
+    assert info["status"] == 0
+    assert abs(info["iterations"] - it) <= 1
+    assert info["true_rel_res"] <= 1e-9
+    x = x.cpu().numpy()
+    A = D.A
+    e = x - xo
+    err = np.sqrt(e @ (A @ e)) / np.sqrt(xo @ (A @ xo))
+    print(f"[mlhp] {name}: solution energy rel diff {err:.1e}", flush=True)
+    assert err <= _tol(name)
