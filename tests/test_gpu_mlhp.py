@@ -135,3 +135,67 @@ def test_mlhp_pcg(name):
     err = np.sqrt(e @ (A @ e)) / np.sqrt(xo @ (A @ xo))
     print(f"[mlhp] {name}: solution energy rel diff {err:.1e}", flush=True)
     assert err <= _tol(name)
+
+
+def test_mlhp_c4_base_grid_depth1():
+    """The c4 problem (8^3 base grid, p = 3, sphere r = 0.35, alpha = 1e-10,
+    beta = 1e4, six Gaussian sources) at refinement depth 1: 31,069 unknowns,
+    patches of up to 1,858 functions.  (Depth 3 needs 696 GB of patch
+    inverses.)  The oracle supplies the DOF keys and, from its leaf systems,
+    sampled rows of A x and b; the GPU solve must converge to rtol 1e-10 with
+    a symmetric positive V-cycle."""
+    import torch
+    from oracle import mlhp
+    from paper_2010_00881_amd import Solver
+    for k in list(_cache):
+        _cache.pop(k)[0].close()
+    d, o = fi.sphere_multilevel(0, n=8, k=1, p=3)
+    d.update(quad_depth=2, surface_rule=(64, 128))
+    print("[mlhp] c4 depth 1: oracle tables", flush=True)
+    D = mlhp.MultiLevelDiscretization(d, assemble=False)
+    s = Solver(d, dict(o, precision="fp64"))
+    try:
+        assert np.array_equal(s.dof_keys(), D.dof_keys)
+        assert s.n_dofs == D.level_sizes
+        rng = np.random.default_rng(21)
+        x = rng.standard_normal(D.n_dofs)
+        y = s.apply(len(D.level_sizes) - 1, _t(x)).cpu().numpy()
+        b = s.rhs().cpu().numpy()
+        dofs = rng.choice(D.n_dofs, 40, replace=False)
+        owners = {}
+        for L, (f, _, _) in enumerate(D.leaf_funcs):
+            for li, i in enumerate(f):
+                owners.setdefault(int(i), []).append((L, li))
+        surf = D._surface_points()
+        cache = {}
+        worst_a = worst_b = 0.0
+        for i in dofs:
+            ax = bx = 0.0
+            for L, li in owners[int(i)]:
+                if L not in cache:
+                    cache[L] = D.leaf_system(L, surf)
+                K, be = cache[L]
+                ax += K[li] @ x[D.leaf_funcs[L][0]]
+                bx += be[li]
+            worst_a = max(worst_a, abs(y[i] - ax) / np.abs(y).max())
+            worst_b = max(worst_b, abs(b[i] - bx) / np.abs(b).max())
+        print(f"[mlhp] c4 depth 1: sampled A x {worst_a:.1e}, b {worst_b:.1e}", flush=True)
+        assert worst_a <= 1e-12 and worst_b <= 1e-12
+        n = D.n_dofs
+        r1 = s.apply(len(D.level_sizes) - 1, _t(rng.standard_normal(n)))
+        r2 = s.apply(len(D.level_sizes) - 1, _t(rng.standard_normal(n)))
+        v1, v2 = s.vcycle(r1), s.vcycle(r2)
+        a12, a21 = float(r2 @ v1), float(r1 @ v2)
+        # exactly symmetric block inverses; the V-cycle's rounding is amplified by
+        # block condition numbers ~1e13 (bound ~ cond * eps ~ 1e-3)
+        print(f"[mlhp] c4 depth 1: vcycle asym {abs(a12 - a21) / abs(float(r1 @ v1)):.1e}",
+              flush=True)
+        assert abs(a12 - a21) <= 1e-4 * abs(float(r1 @ v1)) and float(r1 @ v1) > 0.0
+        xs, info = s.pcg()
+        torch.cuda.synchronize()
+        print(f"[mlhp] c4 depth 1: it {info['iterations']} true {info['true_rel_res']:.1e} "
+              f"setup {info['t_setup_ms']:.0f} ms solve {info['t_solve_ms']:.0f} ms", flush=True)
+        assert info["status"] == 0 and info["iterations"] <= 40
+        assert info["true_rel_res"] <= 1e-9
+    finally:
+        s.close()
