@@ -115,6 +115,60 @@ def serve_bench(args):
     return 0
 
 
+def mlhp_bench(args):
+    """Multi-level hp sphere problem (8^3 base grid, p = 3, sphere r = 0.35,
+    alpha = 1e-10, beta = 1e4, six seeded Gaussian sources) at refinement depth
+    --mlhp-k (the paper's configuration uses 3, whose base-node patch inverses
+    need ~700 GB; 1 and 2 fit one GPU): setup + FP64 MG-PCG per seed."""
+    import torch
+    import fcm_inputs as fi
+    from paper_2010_00881_amd import Solver
+    K = args.mlhp_k
+    p = args.mlhp_p
+
+    def one(seed):
+        d, o = fi.sphere_multilevel(seed, n=8, k=K, p=p)
+        d["quad_depth"] = 2
+        t = time.perf_counter()
+        s = Solver(d, dict(o, precision="fp64"))
+        x, info = s.pcg()
+        torch.cuda.synchronize()
+        lat = (time.perf_counter() - t) * 1e3
+        st = s.stats()
+        n = s.n_dofs[-1]
+        s.close()
+        if info["status"] != 0:
+            raise RuntimeError(f"seed {seed} did not converge: {info}")
+        return lat, info, st, n
+
+    print(f"[bench] multi-level hp K={K} p={p}: warmup", file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        one(1000 + w)
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    res = [one(sd) for sd in range(args.steps)]
+    T = time.perf_counter() - t0
+    lat = [r[0] for r in res]
+    out = {
+        "metric": "multi-level hp MG-PCG solves/s (setup + solve)", "value": args.steps / T,
+        "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": T * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded Gaussian sources, seeds 0..steps-1)",
+        "config": {"workload": f"sphere_mlhp_8^3_k{K}_p{p}", "dofs": res[0][3],
+                   "leaves": res[0][2]["n_kept"], "patches": res[0][2]["n_unique_blocks"],
+                   "alpha": 1e-10, "beta": 1e4, "quad_depth": 2, "rtol": 1e-10},
+        "p50_ms": statistics.median(lat),
+        "setup_ms_median": statistics.median(r[1]["t_setup_ms"] for r in res),
+        "solve_ms_median": statistics.median(r[1]["t_solve_ms"] for r in res),
+        "iterations": [r[1]["iterations"] for r in res],
+        "max_true_rel_res": max(r[1]["true_rel_res"] for r in res),
+        "device_bytes": res[0][2]["device_bytes"],
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -126,8 +180,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="also time the plain FP64 form one problem at a time")
-    ap.add_argument("--workload", default="cube", choices=["cube", "serving"],
-                    help="cube: the 32^3 solve benchmark; serving: the request stream")
+    ap.add_argument("--workload", default="cube", choices=["cube", "serving", "mlhp"],
+                    help="cube: the 32^3 solve benchmark; serving: the request stream; "
+                         "mlhp: the multi-level hp sphere problem")
+    ap.add_argument("--mlhp-k", type=int, default=1)
+    ap.add_argument("--mlhp-p", type=int, default=3)
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=16)
@@ -142,6 +199,8 @@ def main():
 
     if args.workload == "serving":
         return serve_bench(args)
+    if args.workload == "mlhp":
+        return mlhp_bench(args)
 
     import torch
     import fcm_inputs as fi
