@@ -76,8 +76,8 @@ struct MlhpState {
   int nsurf = 0;
   double *gx = nullptr;                  // Gauss nodes and weights, p + 1 each
   std::vector<MlPatches> pl;             // multigrid levels 1 .. nlev-1
-  double *A0 = nullptr;                  // inverse of the level-0 matrix
-  int n0 = 0;
+  double *A0 = nullptr;                  // inverse of the level-0 matrix (n0p x n0p)
+  int n0 = 0, n0p = 0;
   std::vector<double *> vx, vr, vy, vz;  // per level work vectors
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
   double *red = nullptr;
@@ -445,22 +445,23 @@ __global__ __launch_bounds__(256) void ml_apply_kernel(const int *leaf, const in
 
 // dense level-0 matrix from the leaf matrices (functions with DOF < n0)
 __global__ void ml_coarse_assemble_kernel(const int *leaf, const int64_t *koff, const int *fdof,
-                                          const double *Kl, int n0, double *A0) {
+                                          const double *Kl, int n0, int ld, double *A0) {
   const int L = blockIdx.x;
   const int foff = leaf[7 * L + 4], m = leaf[7 * L + 5];
   const double *K = Kl + koff[L];
   for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
     const int i = fdof[foff + e / m], j = fdof[foff + e % m];
-    if (i < n0 && j < n0) atomicAdd(A0 + (size_t)i * n0 + j, K[e]);
+    if (i < n0 && j < n0) atomicAdd(A0 + (size_t)i * ld + j, K[e]);
   }
 }
 
-// x = M b for a dense n x n matrix (one wave per row)
-__global__ void ml_gemv_kernel(const double *M, int n, const double *b, double *x) {
+// x = M b for the leading n x n block of a matrix with leading dimension ld
+// (one wave per row)
+__global__ void ml_gemv_kernel(const double *M, int n, int ld, const double *b, double *x) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (row >= n) return;
   double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += M[(size_t)row * n + j] * b[j];
+  for (int j = lane; j < n; j += 64) s += M[(size_t)row * ld + j] * b[j];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) x[row] = s;
 }
@@ -493,20 +494,24 @@ __global__ __launch_bounds__(256) void ml_form_blocks_kernel(
   }
 }
 
-// z += sum_patches P_i A_i^{-1} P_i^T r
+// z += sum_patches P_i A_i^{-1} P_i^T r; workgroup (P, c) takes rows
+// [64 c, 64 c + 64) of patch P (grid.y = max rows / 64)
 __global__ __launch_bounds__(256) void ml_smooth_kernel(const int *pm, const int64_t *pinv,
                                                         const int64_t *poff, const int *pidx,
                                                         const double *inv, const double *r,
                                                         double *z) {
   const int P = blockIdx.x, tid = threadIdx.x;
   const int mb = pm[2 * P], mreal = pm[2 * P + 1];
+  const int row0 = 64 * blockIdx.y;
+  if (row0 >= mreal) return;
   const int *idx = pidx + poff[P];
   __shared__ double rs[kMlMaxPatch];
   for (int i = tid; i < mb; i += 256) rs[i] = i < mreal ? r[idx[i]] : 0.0;
   __syncthreads();
   const double *M = inv + pinv[P];
   const int wave = tid >> 6, lane = tid & 63;
-  for (int i = wave; i < mreal; i += 4) {
+  const int row1 = min(mreal, row0 + 64);
+  for (int i = row0 + wave; i < row1; i += 4) {
     double s = 0.0;
     for (int j = lane; j < mreal; j += 64) s += M[(size_t)i * mb + j] * rs[j];
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
@@ -514,19 +519,25 @@ __global__ __launch_bounds__(256) void ml_smooth_kernel(const int *pm, const int
   }
 }
 
-// In-place inverse of SPD blocks as a Gram matrix: B_s = S B S (Jacobi
-// scaling), B_s = L L^T (Cholesky, right-looking), W = L^{-1} (forward
-// substitution, one column per thread), B^{-1} = S W^T W S.  Unlike an
-// explicit elimination inverse, W^T W stays positive definite when the
-// scaled condition number reaches 1e13 and more (fictitious leaves), which
-// keeps the additive Schwarz smoother positive.  One workgroup per block;
-// Wg is n x n scratch per block.
-__global__ __launch_bounds__(256) void ml_chol_inverse_kernel(double *Ball, int n, double *Wall,
-                                                              int *flag) {
-  double *B = Ball + (size_t)blockIdx.x * n * n;
-  double *W = Wall + (size_t)blockIdx.x * n * n;
+// Gram-form inverse of SPD blocks, first stage (one workgroup per block):
+// Jacobi scaling S, left-looking Cholesky S B S = L L^T in place (the current
+// row of L in LDS), then the scaled inverse factor: WT[c][i] = s_c (L^{-1})[i][c]
+// and W = WT^T, so that B^{-1} = S L^{-T} L^{-1} S = WT W (formed by
+// ml_gemm_kernel with a symmetric store).  Unlike an elimination inverse, this
+// stays positive definite when the scaled condition reaches 1e13 and more
+// (patch blocks with fictitious leaves).
+__global__ __launch_bounds__(256) void ml_chol_factor_kernel(double *Ball, const int *pm,
+                                                             const int64_t *pinv, double *WTall,
+                                                             double *Wall, int *flag) {
+  const int n = pm[2 * blockIdx.x];
+  const int64_t off = pinv[blockIdx.x];
+  double *B = Ball + off;
+  double *WT = WTall + off;
+  double *W = Wall + off;
   const int tid = threadIdx.x;
   __shared__ double sc[kMlMaxPatch];
+  __shared__ double lj[kMlMaxPatch];
+  __shared__ double red[256];
   for (int i = tid; i < n; i += 256) {
     const double dg = B[(size_t)i * n + i];
     if (!(dg > 0.0)) atomicOr(flag, 1);
@@ -538,42 +549,98 @@ __global__ __launch_bounds__(256) void ml_chol_inverse_kernel(double *Ball, int 
     B[e] *= sc[i] * sc[j];
   }
   __syncthreads();
-  // Cholesky, lower triangle of B
   for (int j = 0; j < n; ++j) {
-    const double dj = B[(size_t)j * n + j];
+    double part = 0.0;
+    for (int k = tid; k < j; k += 256) {
+      const double v = B[(size_t)j * n + k];
+      lj[k] = v;
+      part += v * v;
+    }
+    red[tid] = part;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double dj = B[(size_t)j * n + j] - red[0];
     if (tid == 0 && !(dj > 0.0)) atomicOr(flag, 1);
     const double piv = dj > 0.0 ? sqrt(dj) : 1.0;
+    for (int i = j + 1 + tid; i < n; i += 256) {
+      const double *row = B + (size_t)i * n;
+      double acc = row[j];
+      for (int k = 0; k < j; ++k) acc -= row[k] * lj[k];
+      B[(size_t)i * n + j] = acc / piv;
+    }
     __syncthreads();
-    for (int i = j + 1 + tid; i < n; i += 256) B[(size_t)i * n + j] /= piv;
     if (tid == 0) B[(size_t)j * n + j] = piv;
     __syncthreads();
-    const int r = n - j - 1;
-    for (int64_t e = tid; e < (int64_t)r * r; e += 256) {
-      const int i = j + 1 + (int)(e / r), k = j + 1 + (int)(e % r);
-      if (k <= i) B[(size_t)i * n + k] -= B[(size_t)i * n + j] * B[(size_t)k * n + j];
-    }
-    __syncthreads();
   }
-  // W = L^{-1}, column c by thread c (W is lower triangular)
+  // scaled inverse factor, one column c of L^{-1} per thread (row c of WT)
   for (int c = tid; c < n; c += 256) {
-    for (int i = 0; i < c; ++i) W[(size_t)i * n + c] = 0.0;
+    double *wt = WT + (size_t)c * n;
+    for (int i = 0; i < c; ++i) wt[i] = 0.0;
     for (int i = c; i < n; ++i) {
+      const double *row = B + (size_t)i * n;
       double acc = i == c ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) acc -= B[(size_t)i * n + k] * W[(size_t)k * n + c];
-      W[(size_t)i * n + c] = acc / B[(size_t)i * n + i];
+      for (int k = c; k < i; ++k) acc -= row[k] * wt[k];
+      wt[i] = acc / row[i];
+    }
+    for (int i = 0; i < n; ++i) {
+      wt[i] *= sc[c];
+      W[(size_t)i * n + c] = wt[i];
     }
   }
-  __syncthreads();
-  // B^{-1} = S W^T W S, upper triangle computed, mirrored
-  for (int64_t e = tid; e < (int64_t)n * n; e += 256) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    if (j < i) continue;
-    double acc = 0.0;
-    for (int k = j; k < n; ++k) acc += W[(size_t)k * n + i] * W[(size_t)k * n + j];
-    acc *= sc[i] * sc[j];
-    B[(size_t)i * n + j] = acc;
-    B[(size_t)j * n + i] = acc;
+}
+
+// C_b = A_b B_b for a batch of n x n row-major matrices (n a multiple of 32)
+// on the FP64 matrix cores: 64 x 64 output tile per workgroup, wave w owns
+// the 32 x 32 quarter (w / 2, w % 2) as 2 x 2 v_mfma_f64_16x16x4f64 tiles
+// (lane l supplies A[l%16][l/16] and B[l/16][l%16], holds D[4j + l/16][l%16]).
+// sym = 1: C is symmetric in exact arithmetic; only tiles on or above the
+// diagonal are computed and every entry (i <= j) is stored at (i, j) and
+// (j, i), so the result is exactly symmetric.
+typedef double ml_d4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void ml_gemm_kernel(const double *Aall, const double *Ball,
+                                                      double *Call, int n, int sym) {
+  const int nt = n / 64 + (n % 64 ? 1 : 0);
+  int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
+  if (sym && ti > tj) return;
+  const size_t off = (size_t)blockIdx.y * n * n;
+  const double *A = Aall + off, *B = Ball + off;
+  double *C = Call + off;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ln = lane & 15, lq = lane >> 4;
+  const int i0 = ti * 64 + (wave >> 1) * 32, j0 = tj * 64 + (wave & 1) * 32;
+  if (i0 >= n || j0 >= n) return;
+  if (sym && i0 > j0 + 31) return;
+  ml_d4 acc[2][2];
+  for (int u = 0; u < 2; ++u)
+    for (int v = 0; v < 2; ++v) acc[u][v] = ml_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < n; k += 4) {
+    double av[2], bv[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      av[u] = A[(size_t)(i0 + 16 * u + ln) * n + k + lq];
+      bv[u] = B[(size_t)(k + lq) * n + j0 + 16 * u + ln];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+        acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
   }
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int i = i0 + 16 * u + 4 * jj + lq, j = j0 + 16 * v + ln;
+        if (sym && i > j) continue;
+        C[(size_t)i * n + j] = acc[u][v][jj];
+        if (sym) C[(size_t)j * n + i] = acc[u][v][jj];
+      }
 }
 
 // ------------------------------------------------------------ vectors
@@ -605,6 +672,24 @@ __global__ void ml_dot_kernel(int64_t n, const double *x, const double *y, doubl
 }
 
 static int ml_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
+
+// Inverses of the npatch SPD blocks of a level in place as Gram matrices
+// WT W: one factor launch over all blocks (pm: padded size per block, pinv:
+// offset of each block in inv and in the scratch arrays wt, w), then the
+// symmetric MFMA products per bucket of equal-size blocks.
+static fcm_status ml_spd_inverse(double *inv, int npatch, const int *pm, const int64_t *pinv,
+                                 const std::vector<std::pair<int64_t, std::pair<int, int>>> &bk,
+                                 double *wt, double *w, int *flag, hipStream_t s) {
+  if (npatch <= 0) return FCM_OK;
+  ml_chol_factor_kernel<<<npatch, 256, 0, s>>>(inv, pm, pinv, wt, w, flag);
+  for (const auto &b : bk) {
+    const int n = b.second.second, nt = (n + 63) / 64;
+    ml_gemm_kernel<<<dim3(nt * nt, b.second.first), 256, 0, s>>>(wt + b.first, w + b.first,
+                                                                 inv + b.first, n, 1);
+  }
+  FCM_HIP(hipGetLastError());
+  return FCM_OK;
+}
 
 // ------------------------------------------------------------ host: tree and basis
 namespace {
@@ -1089,19 +1174,33 @@ fcm_status mlhp_setup(fcm_handle *h) {
   }
   // coarse level: dense inverse of A_0
   S->n0 = (int)S->level_size[0];
+  S->n0p = (S->n0 + 31) / 32 * 32;
   {
-    ML_TRY(ml_alloc(h, &S->A0, (size_t)S->n0 * S->n0));
+    const size_t nn = (size_t)S->n0p * S->n0p;
+    ML_TRY(ml_alloc(h, &S->A0, nn));
+    std::vector<double> eye(nn, 0.0);
+    for (int i = S->n0; i < S->n0p; ++i) eye[(size_t)i * S->n0p + i] = 1.0;
+    FCM_HIP(hipMemcpyAsync(S->A0, eye.data(), nn * sizeof(double), hipMemcpyHostToDevice,
+                           h->stream));
     if (S->nleaf > 0)
       ml_coarse_assemble_kernel<<<S->nleaf, 256, 0, h->stream>>>(S->leaf, S->koff, S->fdof,
-                                                                S->Kl, S->n0, S->A0);
-    if (S->n0 > kMlMaxPatch) {
+                                                                S->Kl, S->n0, S->n0p, S->A0);
+    if (S->n0p > kMlMaxPatch) {
       set_error("multi-level hp: %d coarse unknowns (limit %d)", S->n0, kMlMaxPatch);
       return FCM_ERR_ARG;
     }
-    double *scr = nullptr;
-    ML_TRY(pool_alloc((void **)&scr, (size_t)S->n0 * S->n0 * sizeof(double), h->stream));
-    if (S->n0 > 0) ml_chol_inverse_kernel<<<1, 256, 0, h->stream>>>(S->A0, S->n0, scr, S->flag);
-    pool_free(scr, h->stream);
+    double *s1 = nullptr, *s2 = nullptr;
+    int *cpm = nullptr;
+    int64_t *cpinv = nullptr;
+    ML_TRY(pool_alloc((void **)&s1, nn * sizeof(double), h->stream));
+    ML_TRY(pool_alloc((void **)&s2, nn * sizeof(double), h->stream));
+    ML_TRY(ml_upload(h, &cpm, std::vector<int>{S->n0p, S->n0}));
+    ML_TRY(ml_upload(h, &cpinv, std::vector<int64_t>{0}));
+    ML_TRY(ml_spd_inverse(S->A0, 1, cpm, cpinv, {{0, {1, S->n0p}}}, s1, s2, S->flag,
+                          h->stream));
+    FCM_HIP(hipStreamSynchronize(h->stream));
+    pool_free(s1, h->stream);
+    pool_free(s2, h->stream);
   }
   // Schwarz patches of every level >= 1
   std::vector<std::vector<int>> leaves_of_base((size_t)B.lv[0].N[0] * B.lv[0].N[1] * B.lv[0].N[2]);
@@ -1116,22 +1215,22 @@ fcm_status mlhp_setup(fcm_handle *h) {
   size_t scr_need = 1;
   for (int l = 1; l < S->nlev; ++l) {
     ML_TRY(ml_patches(B, l, fdof, leaves_of_base, leaves_of_dof, S->pl[l]));
-    for (auto &bk : S->pl[l].buckets)
-      scr_need = std::max(scr_need, (size_t)bk.second.first * bk.second.second * bk.second.second);
+    scr_need = std::max(scr_need, (size_t)S->pl[l].inv_doubles);
   }
-  double *scr = nullptr;
-  ML_TRY(pool_alloc((void **)&scr, scr_need * sizeof(double), h->stream));
+  double *s1 = nullptr, *s2 = nullptr;
+  ML_TRY(pool_alloc((void **)&s1, scr_need * sizeof(double), h->stream));
+  ML_TRY(pool_alloc((void **)&s2, scr_need * sizeof(double), h->stream));
   for (int l = 1; l < S->nlev; ++l) {
     MlPatches &P = S->pl[l];
     if (P.npatch == 0) continue;
     ml_form_blocks_kernel<<<P.npatch, 256, 0, h->stream>>>(P.pm, P.pinv, P.plf, P.pair_leaf,
                                                            P.pair_map, P.map, S->leaf, S->koff,
                                                            S->Kl, P.inv);
-    for (auto &bk : P.buckets)
-      ml_chol_inverse_kernel<<<bk.second.first, 256, 0, h->stream>>>(P.inv + bk.first,
-                                                                    bk.second.second, scr, S->flag);
+    ML_TRY(ml_spd_inverse(P.inv, P.npatch, P.pm, P.pinv, P.buckets, s1, s2, S->flag, h->stream));
   }
-  pool_free(scr, h->stream);
+  FCM_HIP(hipStreamSynchronize(h->stream));
+  pool_free(s1, h->stream);
+  pool_free(s2, h->stream);
   FCM_HIP(hipGetLastError());
   // work vectors
   S->vx.assign(S->nlev, nullptr);
@@ -1178,11 +1277,12 @@ static void ml_smooth(MlhpState *S, int l, const double *r, double *z, hipStream
   (void)hipMemsetAsync(z, 0, n * sizeof(double), s);
   const MlPatches &P = S->pl[l];
   if (P.npatch > 0)
-    ml_smooth_kernel<<<P.npatch, 256, 0, s>>>(P.pm, P.pinv, P.poff, P.pidx, P.inv, r, z);
+    ml_smooth_kernel<<<dim3(P.npatch, (P.max_mb + 63) / 64), 256, 0, s>>>(P.pm, P.pinv, P.poff,
+                                                                          P.pidx, P.inv, r, z);
 }
 
 static void ml_coarse(MlhpState *S, const double *b, double *x, hipStream_t s) {
-  if (S->n0 > 0) ml_gemv_kernel<<<(S->n0 + 3) / 4, 256, 0, s>>>(S->A0, S->n0, b, x);
+  if (S->n0 > 0) ml_gemv_kernel<<<(S->n0 + 3) / 4, 256, 0, s>>>(S->A0, S->n0, S->n0p, b, x);
 }
 
 // Alg. 1 with the residual recomputed after every smoothing step
