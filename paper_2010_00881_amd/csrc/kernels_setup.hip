@@ -807,15 +807,37 @@ __global__ void jacobi_scale_kernel(double *A, int n, double *scale, int *flag) 
   }
 }
 
-__global__ void apply_scale_kernel(double *A, int n, const double *scale, double sign) {
+// M <- sign * S M S, one wave per row; with nrm, also the largest absolute
+// row sum (= 1-norm, the matrices are symmetric) of the result (sign > 0:
+// the scaled matrix) or of the input (sign < 0: the swept matrix -B_s^{-1}),
+// combined over rows by atomicMax on the bit pattern (order-preserving for
+// non-negative doubles).
+__global__ void apply_scale_kernel(double *A, int n, const double *scale, double sign,
+                                   double *nrm) {
   const int b = blockIdx.y;
-  double *M = A + (size_t)b * n * n;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= n) return;
+  double *M = A + (size_t)b * n * n + (size_t)r * n;
   const double *s = scale + (size_t)b * n;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)n * n;
-       i += (size_t)gridDim.x * blockDim.x) {
-    int r = (int)(i / n), c = (int)(i % n);
-    M[i] = sign * M[i] * s[r] * s[c];
+  const double sr = s[r];
+  double sum_in = 0.0, sum_out = 0.0;
+  for (int c = lane; c < n; c += 64) {
+    const double v = M[c];
+    const double w = sign * v * sr * s[c];
+    M[c] = w;
+    sum_in += fabs(v);
+    sum_out += fabs(w);
   }
+  if (!nrm) return;
+  double rs = sign > 0.0 ? sum_out : sum_in;
+  for (int off = 32; off > 0; off >>= 1) rs += __shfl_down(rs, off, 64);
+  if (lane == 0)
+    atomicMax((unsigned long long *)(nrm + b), (unsigned long long)__double_as_longlong(rs));
+}
+
+__global__ void kappa_product_kernel(const double *nrm, int batch, double *kappa) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < batch) kappa[b] = nrm[b] * nrm[batch + b];
 }
 
 // Pivot rows of block K: one wave per workgroup (J, b).  Lanes 0..31 hold
@@ -960,29 +982,9 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
       }
 }
 
-// kappa[b] = (or *=) max absolute column sum of matrix b (one workgroup per matrix)
-__global__ void norm1_kernel(const double *A, int n, double *kappa, int multiply) {
-  __shared__ double red[256];
-  const int b = blockIdx.x;
-  const double *M = A + (size_t)b * n * n;
-  double best = 0.0;
-  for (int c = threadIdx.x; c < n; c += 256) {
-    double cs = 0.0;
-    for (int r = 0; r < n; ++r) cs += fabs(M[(size_t)r * n + c]);
-    best = fmax(best, cs);
-  }
-  red[threadIdx.x] = best;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) kappa[b] = multiply ? kappa[b] * red[0] : red[0];
-}
-
 size_t spd_inverse_scratch_doubles(int n, int batch) {
-  // W (and R for the panel-wide variant) of kTB rows, scale
-  return (size_t)batch * kTB * n * 2 + (size_t)batch * n;
+  // W and R of kTB rows, scale, two norms per matrix
+  return (size_t)batch * kTB * n * 2 + (size_t)batch * n + 2 * (size_t)batch;
 }
 
 int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag, double *kappa,
@@ -991,18 +993,19 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
   double *W = scratch;
   double *scale = scratch + (size_t)batch * kTB * n * 2;
   const int NB = (n + kTB - 1) / kTB;
+  double *nrm = scale + (size_t)batch * n;
+  if (kappa) (void)hipMemsetAsync(nrm, 0, 2 * (size_t)batch * sizeof(double), s);
   jacobi_scale_kernel<<<dim3((n + 255) / 256, batch), 256, 0, s>>>(A, n, scale, flag);
-  int sblk = (int)std::min<size_t>(((size_t)n * n + 255) / 256, 1024);
-  apply_scale_kernel<<<dim3(sblk, batch), 256, 0, s>>>(A, n, scale, 1.0);
-  if (kappa) norm1_kernel<<<batch, 256, 0, s>>>(A, n, kappa, 0);
+  const dim3 sgrid((n + 3) / 4, batch);
+  apply_scale_kernel<<<sgrid, 256, 0, s>>>(A, n, scale, 1.0, kappa ? nrm : nullptr);
   double *R = W + (size_t)batch * kTB * n;
   const int nt = (n + 63) / 64;
   for (int K = 0; K < NB; ++K) {
     sweep_rows_kernel<<<dim3((n + kTJ - 1) / kTJ, batch), 64, 0, s>>>(A, n, K, W, R, flag);
     sweep_update_mfma_kernel<<<dim3(nt * (nt + 1) / 2, batch), 256, 0, s>>>(A, n, K, W, R, nt);
   }
-  if (kappa) norm1_kernel<<<batch, 256, 0, s>>>(A, n, kappa, 1);
-  apply_scale_kernel<<<dim3(sblk, batch), 256, 0, s>>>(A, n, scale, -1.0);
+  apply_scale_kernel<<<sgrid, 256, 0, s>>>(A, n, scale, -1.0, kappa ? nrm + batch : nullptr);
+  if (kappa) kappa_product_kernel<<<(batch + 255) / 256, 256, 0, s>>>(nrm, batch, kappa);
   return 0;
 }
 
