@@ -909,7 +909,9 @@ static void patch_scratch_free(fcm_handle *h, PatchScratch &ps) {
 }
 
 // Form and invert the patch blocks of every level >= 1 (FP64, Jacobi-scaled
-// Gauss-Jordan sweep) in chunks, stored as m x ld (ld = m rounded up to 4).
+// Gauss-Jordan sweep) in chunks.  Class inverses are stored as m x ld (ld = m
+// rounded up to 4, the layout of the class-product kernels), unique inverses
+// as their 16 x 16 tiles on and above the diagonal (symmetric GEMV).
 static fcm_status setup_patch_levels(fcm_handle *h, const std::vector<int> &bnode,
                                      const std::vector<int> &bkm, const PatchScratch &ps) {
   const Geo &g = h->geo;
@@ -928,10 +930,11 @@ static fcm_status setup_patch_levels(fcm_handle *h, const std::vector<int> &bnod
     L.mpatch = m;
     L.ldp = ld;
     const size_t mm = (size_t)m * ld;
-    TRY(dalloc(h, &L.invS64, mm * std::max(1, nblocks)));
-    if (mixed) TRY(dalloc(h, &L.invS32, mm * std::max(1, nblocks)));
-    L.invU64 = L.invS64 + mm * ncls;
-    L.invU32 = mixed ? L.invS32 + mm * ncls : nullptr;
+    const size_t tp = (size_t)patch_tiles(m) * 256;
+    TRY(dalloc(h, &L.invS64, mm * std::max(1, ncls)));
+    if (mixed) TRY(dalloc(h, &L.invS32, mm * std::max(1, ncls)));
+    TRY(dalloc(h, &L.invU64, tp * std::max(1, h->np_unique)));
+    if (mixed) TRY(dalloc(h, &L.invU32, tp * std::max(1, h->np_unique)));
     if (nblocks > 0) {
       const int cb = patch_chunk(m, nblocks);
       for (int b0 = 0; b0 < nblocks; b0 += cb) {
@@ -939,8 +942,15 @@ static fcm_status setup_patch_levels(fcm_handle *h, const std::vector<int> &bnod
         launch_form_patch_blocks(g, h->tab, h->ptab, m, dbn + b0, dbk + b0, nb, h->kmat,
                                  h->Kref64, h->Kcut64, ps.blk, h->stream);
         spd_inverse_batched(ps.blk, m, nb, ps.scr, h->dflag, ps.kappa + b0, h->stream);
-        launch_pack_blocks(ps.blk, m, ld, nb, L.invS64 + mm * b0,
-                           mixed ? L.invS32 + mm * b0 : nullptr, h->stream);
+        const int ce = std::min(b0 + nb, ncls);
+        if (b0 < ce)
+          launch_pack_blocks(ps.blk, m, ld, ce - b0, L.invS64 + mm * b0,
+                             mixed ? L.invS32 + mm * b0 : nullptr, h->stream);
+        const int ub = std::max(b0, ncls);
+        if (ub < b0 + nb)
+          launch_pack_tiles(ps.blk + (size_t)(ub - b0) * m * m, m, b0 + nb - ub,
+                            L.invU64 + tp * (ub - ncls),
+                            mixed ? L.invU32 + tp * (ub - ncls) : nullptr, h->stream);
       }
       FCM_HIP(hipMemcpyAsync(hk.data(), ps.kappa, nblocks * sizeof(double),
                              hipMemcpyDeviceToHost, h->stream));
@@ -1212,6 +1222,7 @@ static PatchArgs<T> patch_args(fcm_handle *h, int l) {
   PatchArgs<T> a;
   a.m = L.mpatch;
   a.ld = L.ldp;
+  a.ntile = (L.mpatch + 15) / 16;
   a.nP_out = L.nP;
   a.pnode = h->pnode;
   a.pkm = h->pkm;
@@ -1951,9 +1962,11 @@ static double op_bytes(const fcm_handle *h, int op, int l) {
   if (op == FCM_OP_SMOOTH && h->opt.smoother == FCM_SMOOTH_PATCHWISE) {
     // unique inverses streamed once, class inverses once, x read, delta and
     // the iterate written, the iterate read
+    // (a symmetric unique inverse carries m (m + 1) / 2 numbers)
     const double pm2 = (double)L.mpatch * L.mpatch;
+    const double ps2 = 0.5 * L.mpatch * (L.mpatch + 1.0);
     const double nhi = mixed ? L.n_hi64 : 0;
-    const double mats = (h->np_unique - nhi) * pm2 * sv + nhi * pm2 * 8.0 +
+    const double mats = (h->np_unique - nhi) * ps2 * sv + nhi * ps2 * 8.0 +
                         (double)h->np_classes * pm2 * 8.0;
     return 4.0 * L.npad * sv + mats;
   }
@@ -1967,14 +1980,15 @@ static double op_bytes(const fcm_handle *h, int op, int l) {
   return 3.0 * L.npad * sv + mats + 4.0 * E;
 }
 
-// Unique-patch GEMV: every stored inverse streamed once (FP64 where flagged),
-// the gathered inputs read once, the FP64 products written once.
+// Unique-patch GEMV: every symmetric inverse (m (m + 1) / 2 numbers) streamed
+// once (FP64 where flagged), the gathered inputs read once, the FP64 products
+// written once.
 static double stored_bytes(const fcm_handle *h, int l) {
   const bool mixed = h->opt.precision == FCM_MIXED;
   const fcm::Level &L = h->lev[l];
-  const double pm2 = (double)L.mpatch * L.mpatch;
+  const double ps2 = 0.5 * L.mpatch * (L.mpatch + 1.0);
   const double nhi = mixed ? L.n_hi64 : h->np_unique;
-  const double mats = (h->np_unique - nhi) * pm2 * 4.0 + nhi * pm2 * 8.0;
+  const double mats = (h->np_unique - nhi) * ps2 * 4.0 + nhi * ps2 * 8.0;
   return mats + (double)h->np_unique * L.mpatch * ((mixed ? 4.0 : 8.0) + 8.0);
 }
 

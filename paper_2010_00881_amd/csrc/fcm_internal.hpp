@@ -302,8 +302,10 @@ struct PatchArgs {
   int pwords = 0;
   const double *matS64 = nullptr; // [classes][m][ld]
   const float *matS32 = nullptr;  // FP32 V-cycle: FP32 class inverses (matrix-core FP32 path)
-  const T *matU = nullptr;        // [npu][m][ld]
+  const T *matU = nullptr;        // [npu][tiles][16][16]: symmetric unique inverses, the 16 x 16
+                                  // tiles on and above the diagonal, I-major
   const double *matU64 = nullptr; // FP32 V-cycle: FP64 unique inverses where u64flag != 0
+  int ntile = 0;                  // tiles per row of a unique inverse: ceil(m / 16)
   const uint8_t *u64flag = nullptr;
   double *Ys = nullptr;           // [m][nsh]
   double *Yu = nullptr;           // [npu][m]
@@ -320,6 +322,12 @@ void launch_form_patch_blocks(const Geo &g, const Tables &t, const PatchTables &
                               const int *bnode, const int *bkm, int nblocks, const int *kmat,
                               const double *Kref, const double *Kcut, double *out,
                               hipStream_t s);
+// Symmetric m x m blocks -> tiles on and above the diagonal (see PatchArgs::matU)
+void launch_pack_tiles(const double *src, int m, int nb, double *d64, float *d32, hipStream_t s);
+inline int patch_tiles(int m) {
+  const int nt = (m + 15) / 16;
+  return nt * (nt + 1) / 2;
+}
 void launch_pack_blocks(const double *src, int m, int ld, int nb, double *d64, float *d32,
                         hipStream_t s);
 

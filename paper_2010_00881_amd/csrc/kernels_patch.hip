@@ -161,79 +161,148 @@ void launch_pack_blocks(const double *src, int m, int ld, int nb, double *d64, f
   pack_blocks_kernel<<<blocks, 256, 0, s>>>(src, m, ld, nb, d64, d32);
 }
 
+// Tile (I, J), I <= J, at index t of the I-major enumeration
+__device__ __host__ inline void tile_ij(int t, int nt, int &I, int &J) {
+  I = 0;
+  while (t >= nt - I) {
+    t -= nt - I;
+    ++I;
+  }
+  J = I + t;
+}
+
+__global__ void pack_tiles_kernel(const double *src, int m, int nb, double *d64, float *d32) {
+  const int nt = (m + 15) / 16, tiles = nt * (nt + 1) / 2;
+  const size_t tot = (size_t)nb * tiles * 256;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t b = i / ((size_t)tiles * 256);
+    const int t = (int)((i / 256) % tiles), e = (int)(i % 256);
+    int I, J;
+    tile_ij(t, nt, I, J);
+    const int r = 16 * I + e / 16, c = 16 * J + e % 16;
+    const double v = (r < m && c < m) ? src[b * m * m + (size_t)r * m + c] : 0.0;
+    if (d64) d64[i] = v;
+    if (d32) d32[i] = (float)v;
+  }
+}
+
+void launch_pack_tiles(const double *src, int m, int nb, double *d64, float *d32, hipStream_t s) {
+  if (nb <= 0) return;
+  const size_t tot = (size_t)nb * patch_tiles(m) * 256;
+  const int blocks = (int)std::min<size_t>((tot + 255) / 256, 8192);
+  pack_tiles_kernel<<<blocks, 256, 0, s>>>(src, m, nb, d64, d32);
+}
+
 // ---------------------------------------------------------------- apply
-// Unique patches: workgroup u computes Yu[u][r] = sum_b A^{-1}[b][r] x_v[b]
-// (symmetric inverse, so row b holds column b).  Thread (c, bg) owns rows
-// 4c..4c+3 over the bg-th slice of b; slices are summed in a fixed order.
+// Unique patches: workgroup u computes Yu[u] = A_u^{-1} x_v from the stored
+// tiles on and above the diagonal of the symmetric inverse: tile (I, J) adds
+// M_IJ x_J to the rows of I and, for I < J, M_IJ^T x_I to the rows of J, so
+// every stored entry is read once and used twice.  Wave w takes the tiles
+// t = w, w + 4, ...; a tile is read contiguously (lane l: row l / 4, columns
+// 4 (l % 4) .. + 3, one 128-bit FP32 or two FP64 loads) and staged in LDS.
+// Every half-wave adds into its own LDS copy of y in a fixed order, and the
+// eight copies are added in a fixed order, so the result is the same on
+// every run.
+template <typename T>
+__device__ inline void tile_load(const T *p, double v[4]) {
+  if constexpr (std::is_same<T, float>::value) {
+    const float4 q = *reinterpret_cast<const float4 *>(p);
+    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+  } else {
+    const double2 q0 = *reinterpret_cast<const double2 *>(p);
+    const double2 q1 = *reinterpret_cast<const double2 *>(p + 2);
+    v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+  }
+}
+
+// One wave's share of the tiles, two at a time (t and t + 4 of the wave's
+// sequence t = w, w + 8, ...): each lane loads 4 entries of both tiles and
+// stages them in the wave's LDS buffer (rows padded to 17 doubles); then in
+// each half-wave 16 lanes form the row sums M_IJ x_J and 16 lanes the column
+// sums M_IJ^T x_I of one tile, adding them to that half-wave's copy of y.
+template <typename M>
+__device__ inline void tile_sweep(const M *base, int ntiles, const unsigned char *tI,
+                                  const unsigned char *tJ, const double *xs, double (*tb)[16][17],
+                                  double *yh0, double *yh1, int wave, int lane) {
+  const int r = lane >> 2, c0 = (lane & 3) * 4;
+  const int half = lane >> 5, i = lane & 15;
+  const bool rowpart = (lane & 16) == 0;
+  double *yh = half ? yh1 : yh0;
+  for (int t0 = wave; t0 < ntiles; t0 += 8) {
+    double va[4], vb[4];
+    tile_load<M>(base + (size_t)t0 * 256 + r * 16 + c0, va);
+    const bool hasb = t0 + 4 < ntiles;
+    if (hasb) tile_load<M>(base + (size_t)(t0 + 4) * 256 + r * 16 + c0, vb);
+    else vb[0] = vb[1] = vb[2] = vb[3] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      tb[0][r][c0 + q] = va[q];
+      tb[1][r][c0 + q] = vb[q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int t = t0 + 4 * half;
+    if (t < ntiles) {
+      const int I = tI[t], J = tJ[t];
+      double acc = 0.0;
+      if (rowpart) {
+        const double *xJ = xs + 16 * J;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc += tb[half][i][k] * xJ[k];
+        yh[16 * I + i] += acc;
+      } else if (I != J) {
+        const double *xI = xs + 16 * I;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc += tb[half][k][i] * xI[k];
+        yh[16 * J + i] += acc;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void patch_gemv_kernel(Geo g, const int *__restrict__ pxoff,
                                                          const int *__restrict__ pinfo,
                                                          PatchArgs<T> a) {
-  __shared__ double xs[kMaxPatchM];
-  __shared__ double red[2 * kMaxPatchM + 256];
+  constexpr int kPad = (kMaxPatchM + 15) / 16 * 16;
+  constexpr int kMaxTiles = (kPad / 16) * (kPad / 16 + 1) / 2;
+  __shared__ double xs[kPad];
+  __shared__ double yw[8][kPad];
+  __shared__ double tbuf[4][2][16][17];
+  __shared__ unsigned char tI[kMaxTiles], tJ[kMaxTiles];
   const int u = blockIdx.x;
   const int pi = a.nsh + u;
   const int node = a.pnode[pi], kmask = a.pkm[pi];
   int vc[3];
   node_coords(g, node, vc);
-  const int m = a.m, ld = a.ld;
-  for (int k = threadIdx.x; k < m; k += 256)
-    xs[k] = patch_present(g, pinfo[k], kmask, vc) ? (double)a.x[node + pxoff[k]] : 0.0;
-  __syncthreads();
-  const int nch = (m + 3) >> 2;
-  const int nbg = max(1, min(256 / nch, 8));
-  const int c = threadIdx.x % nch, bg = threadIdx.x / nch;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  if (bg < nbg) {
-    const int b0 = (bg * m) / nbg, b1 = ((bg + 1) * m) / nbg;
-    const bool hi = a.matU64 && (!a.u64flag || a.u64flag[u]);
-    if (hi) {
-      const double *M = a.matU64 + (size_t)u * m * ld + 4 * c;
-#pragma unroll 4
-      for (int b = b0; b < b1; ++b) {
-        const double2 v0 = *reinterpret_cast<const double2 *>(M + (size_t)b * ld);
-        const double2 v1 = *reinterpret_cast<const double2 *>(M + (size_t)b * ld + 2);
-        const double xb = xs[b];
-        acc[0] += v0.x * xb;
-        acc[1] += v0.y * xb;
-        acc[2] += v1.x * xb;
-        acc[3] += v1.y * xb;
-      }
-    } else {
-      const T *M = a.matU + (size_t)u * m * ld + 4 * c;
-      if constexpr (std::is_same<T, float>::value) {
-#pragma unroll 4
-        for (int b = b0; b < b1; ++b) {
-          const float4 v = *reinterpret_cast<const float4 *>(M + (size_t)b * ld);
-          const double xb = xs[b];
-          acc[0] += (double)v.x * xb;
-          acc[1] += (double)v.y * xb;
-          acc[2] += (double)v.z * xb;
-          acc[3] += (double)v.w * xb;
-        }
-      } else {
-#pragma unroll 4
-        for (int b = b0; b < b1; ++b) {
-          const double2 v0 = *reinterpret_cast<const double2 *>(M + (size_t)b * ld);
-          const double2 v1 = *reinterpret_cast<const double2 *>(M + (size_t)b * ld + 2);
-          const double xb = xs[b];
-          acc[0] += v0.x * xb;
-          acc[1] += v0.y * xb;
-          acc[2] += v1.x * xb;
-          acc[3] += v1.y * xb;
-        }
-      }
-    }
+  const int m = a.m, nt = a.ntile, mp = 16 * nt;
+  const int ntiles = nt * (nt + 1) / 2;
+  for (int k = threadIdx.x; k < mp; k += 256) {
+    xs[k] = k < m && patch_present(g, pinfo[k], kmask, vc) ? (double)a.x[node + pxoff[k]] : 0.0;
+    for (int w = 0; w < 8; ++w) yw[w][k] = 0.0;
   }
-  // partial sums per slice: red[bg][4c + r]
-  const int ldr = 4 * nch;
-  if (bg < nbg)
-    for (int r = 0; r < 4; ++r) red[bg * ldr + 4 * c + r] = acc[r];
+  for (int t = threadIdx.x; t < ntiles; t += 256) {
+    int I, J;
+    tile_ij(t, nt, I, J);
+    tI[t] = (unsigned char)I;
+    tJ[t] = (unsigned char)J;
+  }
   __syncthreads();
-  for (int r = threadIdx.x; r < m; r += 256) {
-    double s = 0.0;
-    for (int q = 0; q < nbg; ++q) s += red[q * ldr + r];
-    a.Yu[(size_t)u * m + r] = s;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t base = (size_t)u * ntiles * 256;
+  const bool hi = a.matU64 && (!a.u64flag || a.u64flag[u]);
+  if (hi)
+    tile_sweep<double>(a.matU64 + base, ntiles, tI, tJ, xs, tbuf[wave], yw[2 * wave],
+                       yw[2 * wave + 1], wave, lane);
+  else
+    tile_sweep<T>(a.matU + base, ntiles, tI, tJ, xs, tbuf[wave], yw[2 * wave], yw[2 * wave + 1],
+                  wave, lane);
+  __syncthreads();
+  for (int k = threadIdx.x; k < m; k += 256) {
+    double y = 0.0;
+    for (int w = 0; w < 8; ++w) y += yw[w][k];
+    a.Yu[(size_t)u * m + k] = y;
   }
 }
 

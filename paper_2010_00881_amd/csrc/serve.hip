@@ -67,8 +67,8 @@ int64_t footprint_estimate(const fcm_problem &p, const fcm_options &o) {
     for (int q = 2; q <= p.p; ++q) {
       int64_t m = nf;
       for (int ax = 0; ax < d; ++ax) m *= 2 * q + 1;
-      const int64_t ld = (m + 3) & ~3;
-      inv += (nuniq + 128) * m * ld * per;
+      const int64_t ld = (m + 3) & ~3, nt = (m + 15) / 16;
+      inv += 128 * m * ld * per + nuniq * (nt * (nt + 1) / 2) * 256 * per;
       mtop = m;
     }
     inv += G * mtop * 8 + ((int64_t)320 << 20);  // patch products, block scratch
