@@ -121,12 +121,17 @@ __global__ __launch_bounds__(256) void form_patch_blocks_kernel(Geo g, PatchTabl
                                                                 const double *Kcut,
                                                                 double *out) {
   const int blk = blockIdx.y;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m * m) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m * m) return;
+  const int i = e / m, j = e % m;
+  if (j < i) return;
   int vc[3];
   node_coords(g, bnode[blk], vc);
-  out[(size_t)blk * m * m + i] =
-      patch_entry(g, pt, smap, mp, kmat, Kref, Kcut, vc, bkm[blk], i / m, i % m);
+  // the element matrices are symmetric and the element sum runs in the same
+  // order for (i, j) and (j, i): the upper entry is stored at both places
+  const double v = patch_entry(g, pt, smap, mp, kmat, Kref, Kcut, vc, bkm[blk], i, j);
+  out[(size_t)blk * m * m + e] = v;
+  out[(size_t)blk * m * m + (size_t)j * m + i] = v;
 }
 
 void launch_form_patch_blocks(const Geo &g, const Tables &t, const PatchTables &pt, int m,
