@@ -881,7 +881,9 @@ struct PatchScratch {
 
 static int patch_chunk(int m, int nblocks) {
   const size_t per = (size_t)m * m * sizeof(double);
-  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(1024, ((size_t)256 << 20) / per));
+  // up to 1024 blocks (1 GiB of FP64 scratch): large batches keep the sweep
+  // launches of the SPD inverse wide enough to fill the device
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(1024, ((size_t)1024 << 20) / per));
   return std::max(1, std::min(chunk, nblocks));
 }
 

@@ -71,7 +71,7 @@ int64_t footprint_estimate(const fcm_problem &p, const fcm_options &o) {
       inv += 128 * m * ld * per + nuniq * (nt * (nt + 1) / 2) * 256 * per;
       mtop = m;
     }
-    inv += G * mtop * 8 + ((int64_t)320 << 20);  // patch products, block scratch
+    inv += G * mtop * 8 + ((int64_t)1100 << 20);  // patch products, block scratch (setup)
   } else {
     const int64_t nuniq = std::min<int64_t>(E, ncut * (d == 3 ? 4 : 3));
     for (int q = 2; q <= p.p; ++q) {
