@@ -565,9 +565,11 @@ __global__ __launch_bounds__(256) void ml_chol_factor_kernel(double *Ball, const
     const double dj = B[(size_t)j * n + j] - red[0];
     if (tid == 0 && !(dj > 0.0)) atomicOr(flag, 1);
     const double piv = dj > 0.0 ? sqrt(dj) : 1.0;
+    // (the unrolled inner loops keep several loads of a row in flight)
     for (int i = j + 1 + tid; i < n; i += 256) {
       const double *row = B + (size_t)i * n;
       double acc = row[j];
+#pragma unroll 8
       for (int k = 0; k < j; ++k) acc -= row[k] * lj[k];
       B[(size_t)i * n + j] = acc / piv;
     }
@@ -582,6 +584,7 @@ __global__ __launch_bounds__(256) void ml_chol_factor_kernel(double *Ball, const
     for (int i = c; i < n; ++i) {
       const double *row = B + (size_t)i * n;
       double acc = i == c ? 1.0 : 0.0;
+#pragma unroll 8
       for (int k = c; k < i; ++k) acc -= row[k] * wt[k];
       wt[i] = acc / row[i];
     }
