@@ -569,7 +569,7 @@ __global__ __launch_bounds__(256) void ml_chol_factor_kernel(double *Ball, const
     for (int i = j + 1 + tid; i < n; i += 256) {
       const double *row = B + (size_t)i * n;
       double acc = row[j];
-#pragma unroll 8
+#pragma unroll 16
       for (int k = 0; k < j; ++k) acc -= row[k] * lj[k];
       B[(size_t)i * n + j] = acc / piv;
     }
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(256) void ml_chol_factor_kernel(double *Ball, const
     for (int i = c; i < n; ++i) {
       const double *row = B + (size_t)i * n;
       double acc = i == c ? 1.0 : 0.0;
-#pragma unroll 8
+#pragma unroll 16
       for (int k = c; k < i; ++k) acc -= row[k] * wt[k];
       wt[i] = acc / row[i];
     }
