@@ -417,6 +417,21 @@ __global__ __launch_bounds__(256) void ml_integrate_kernel(MlLeafArgs a) {
   }
 }
 
+// sum_j M[j] v[j] over j = lane, lane + 64, ... < n with four independent
+// accumulators (four loads in flight per lane), fixed order
+__device__ inline double ml_row_dot(const double *M, const double *v, int n, int lane) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int j = lane;
+  for (; j + 192 < n; j += 256) {
+    a0 += M[j] * v[j];
+    a1 += M[j + 64] * v[j + 64];
+    a2 += M[j + 128] * v[j + 128];
+    a3 += M[j + 192] * v[j + 192];
+  }
+  for (; j < n; j += 64) a0 += M[j] * v[j];
+  return (a0 + a1) + (a2 + a3);
+}
+
 // ------------------------------------------------------------ operators
 // y += A_l x over the leaves (functions with DOF index >= n_l are absent)
 __global__ __launch_bounds__(256) void ml_apply_kernel(const int *leaf, const int64_t *koff,
@@ -436,8 +451,7 @@ __global__ __launch_bounds__(256) void ml_apply_kernel(const int *leaf, const in
   const int wave = tid >> 6, lane = tid & 63;
   for (int i = wave; i < m; i += 4) {
     if (ds[i] >= nl) continue;
-    double s = 0.0;
-    for (int j = lane; j < m; j += 64) s += K[(size_t)i * m + j] * xs[j];
+    double s = ml_row_dot(K + (size_t)i * m, xs, m, lane);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if (lane == 0) atomicAdd(y + ds[i], s);
   }
@@ -460,8 +474,7 @@ __global__ void ml_coarse_assemble_kernel(const int *leaf, const int64_t *koff, 
 __global__ void ml_gemv_kernel(const double *M, int n, int ld, const double *b, double *x) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (row >= n) return;
-  double s = 0.0;
-  for (int j = lane; j < n; j += 64) s += M[(size_t)row * ld + j] * b[j];
+  double s = ml_row_dot(M + (size_t)row * ld, b, n, lane);
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if (lane == 0) x[row] = s;
 }
@@ -512,8 +525,7 @@ __global__ __launch_bounds__(256) void ml_smooth_kernel(const int *pm, const int
   const int wave = tid >> 6, lane = tid & 63;
   const int row1 = min(mreal, row0 + 64);
   for (int i = row0 + wave; i < row1; i += 4) {
-    double s = 0.0;
-    for (int j = lane; j < mreal; j += 64) s += M[(size_t)i * mb + j] * rs[j];
+    double s = ml_row_dot(M + (size_t)i * mb, rs, mreal, lane);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if (lane == 0) atomicAdd(z + idx[i], s);
   }
