@@ -84,32 +84,48 @@ __device__ double patch_entry(const Geo &g, const PatchTables &pt, const int *sm
     hi[ax] = min(hi_, hj);
     if (lo[ax] > hi[ax]) return 0.0;
   }
-  double sum = 0.0;
-  for (int e2 = lo[2]; e2 <= hi[2]; ++e2)
-    for (int e1 = lo[1]; e1 <= hi[1]; ++e1)
-      for (int e0 = lo[0]; e0 <= hi[0]; ++e0) {
-        const int rel[3] = {e0, e1, e2};
-        int ec[3] = {0, 0, 0};
-        bool in = true;
-        for (int ax = 0; ax < g.d; ++ax) {
-          ec[ax] = vc[ax] + rel[ax];
-          in = in && ec[ax] >= 0 && ec[ax] < g.n[ax];
-        }
-        if (!in) continue;
-        const int kid = kmat[ec[0] + g.n[0] * (ec[1] + g.n[1] * ec[2])];
-        if (kid < 0) continue;
-        int ai[3] = {0, 0, 0}, aj[3] = {0, 0, 0};
-        for (int ax = 0; ax < g.d; ++ax) {
-          // element-local 1D mode: 0 / 1 = hat at the element's left / right
-          // node, t + 1 = bubble of type t
-          ai[ax] = ti[ax] == 0 ? di[ax] - rel[ax] : ti[ax] + 1;
-          aj[ax] = tj[ax] == 0 ? dj[ax] - rel[ax] : tj[ax] + 1;
-        }
-        const int la = smap[(ai[0] + np * (ai[1] + np * ai[2])) * g.nf + mi[3]];
-        const int lb = smap[(aj[0] + np * (aj[1] + np * aj[2])) * g.nf + mj[3]];
-        const double *K = kid == 0 ? Kref : Kcut + (size_t)(kid - 1) * mp * mp;
-        sum += K[(size_t)la * mp + lb];
+  // the (at most 2 per axis) common elements, axis 0 fastest: all element
+  // ids, then all matrix entries (the loads of each pass in flight
+  // together), summed in that order
+  int kid[8];
+  int rel[8][3];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    kid[c] = -1;
+    int ec[3] = {0, 0, 0};
+    bool in = true;
+    for (int ax = 0; ax < 3; ++ax) {
+      rel[c][ax] = lo[ax] + ((c >> ax) & 1);
+      if (ax >= g.d) {
+        in = in && ((c >> ax) & 1) == 0;
+        continue;
       }
+      ec[ax] = vc[ax] + rel[c][ax];
+      in = in && rel[c][ax] <= hi[ax] && ec[ax] >= 0 && ec[ax] < g.n[ax];
+    }
+    if (in) kid[c] = kmat[ec[0] + g.n[0] * (ec[1] + g.n[1] * ec[2])];
+  }
+  double v[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    v[c] = 0.0;
+    if (kid[c] < 0) continue;
+    int ai[3] = {0, 0, 0}, aj[3] = {0, 0, 0};
+    for (int ax = 0; ax < g.d; ++ax) {
+      // element-local 1D mode: 0 / 1 = hat at the element's left / right
+      // node, t + 1 = bubble of type t
+      ai[ax] = ti[ax] == 0 ? di[ax] - rel[c][ax] : ti[ax] + 1;
+      aj[ax] = tj[ax] == 0 ? dj[ax] - rel[c][ax] : tj[ax] + 1;
+    }
+    const int la = smap[(ai[0] + np * (ai[1] + np * ai[2])) * g.nf + mi[3]];
+    const int lb = smap[(aj[0] + np * (aj[1] + np * aj[2])) * g.nf + mj[3]];
+    const double *K = kid[c] == 0 ? Kref : Kcut + (size_t)(kid[c] - 1) * mp * mp;
+    v[c] = K[(size_t)la * mp + lb];
+  }
+  double sum = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if (kid[c] >= 0) sum += v[c];
   return sum;
 }
 
@@ -546,8 +562,14 @@ __global__ __launch_bounds__(256) void patch_gather_kernel(Geo g, const int *__r
   }
   double acc = 0.0;
   if (valid) {
+    // all patch ids first, then all products (the loads of each pass are
+    // independent and in flight together); summed in the fixed order cb
     const int nc = g.d == 3 ? 27 : 9;
-    for (int cb = 0; cb < nc; ++cb) {
+    int pis[27];
+#pragma unroll
+    for (int cb = 0; cb < 27; ++cb) {
+      pis[cb] = -1;
+      if (cb >= nc) continue;
       const int dl[3] = {cb % 3 - 1, (cb / 3) % 3 - 1, g.d == 3 ? cb / 9 - 1 : 0};
       int vcn[3] = {0, 0, 0};
       bool ok = true;
@@ -557,13 +579,21 @@ __global__ __launch_bounds__(256) void patch_gather_kernel(Geo g, const int *__r
         vcn[ax] = gc[ax] - dl[ax];
         ok = ok && vcn[ax] >= 0 && vcn[ax] <= g.n[ax];
       }
-      if (!ok) continue;
-      const int node = vcn[0] + g.gn[0] * (vcn[1] + g.gn[1] * vcn[2]);
-      const int pi = a.pid[node];
+      if (ok) pis[cb] = a.pid[vcn[0] + g.gn[0] * (vcn[1] + g.gn[1] * vcn[2])];
+    }
+    double vals[27];
+#pragma unroll
+    for (int cb = 0; cb < 27; ++cb) {
+      const int pi = pis[cb];
+      vals[cb] = 0.0;
       if (pi < 0) continue;
       const int row = prow[P * 27 + cb];
-      acc += pi < a.nsh ? a.Ys[(size_t)row * a.nsh + pi] : a.Yu[(size_t)(pi - a.nsh) * a.m + row];
+      vals[cb] = pi < a.nsh ? a.Ys[(size_t)row * a.nsh + pi]
+                            : a.Yu[(size_t)(pi - a.nsh) * a.m + row];
     }
+#pragma unroll
+    for (int cb = 0; cb < 27; ++cb)
+      if (pis[cb] >= 0) acc += vals[cb];
   }
   const T val = valid ? (T)acc : T(0);
   const size_t oi = (size_t)P * g.G + gi;
