@@ -108,11 +108,13 @@ typedef struct {
   const double *gauss;        /* [n_gauss][5]: A, w, c_x, c_y, c_z               */
   double f_const;             /* constant scalar source                          */
   double body_force[3];       /* constant body force (elasticity)                */
-  double beta;                /* penalty for u = 0 on the sphere (multi-level hp,
-                                 BALL_INTERIOR; eq. weakform), 0 = none          */
+  double beta;                /* penalty for u = 0 on the sphere (eq. weakform):
+                                 needs refine_levels > 0 and BALL_INTERIOR;
+                                 0 = none                                        */
   int surf_n[2];              /* surface rule of the penalty: Gauss-Legendre
-                                 points in cos(theta) and trapezoid points in phi
-                                 (2D: phi only); 0 = 256 x 512                   */
+                                 points in cos(theta) (<= 4096) and trapezoid
+                                 points in phi (<= 8192; 2D: phi only);
+                                 0 = 256 x 512                                   */
 } fcm_problem;
 
 /* Solver options (Sections 3.3.2 and 4). */

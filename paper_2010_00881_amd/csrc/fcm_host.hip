@@ -218,6 +218,14 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
     return FCM_ERR_ARG;
   }
   if (!std::isfinite(p->beta) || p->beta < 0.0) { set_error("invalid beta"); return FCM_ERR_ARG; }
+  if (p->beta > 0.0 && p->geom != FCM_GEOM_BALL_INTERIOR) {
+    set_error("beta (sphere penalty) needs the ball-interior geometry");
+    return FCM_ERR_ARG;
+  }
+  if (p->surf_n[0] < 0 || p->surf_n[1] < 0 || p->surf_n[0] > 4096 || p->surf_n[1] > 8192) {
+    set_error("surface rule sizes out of range");
+    return FCM_ERR_ARG;
+  }
   for (int ax = 0; ax < p->dim; ++ax) {
     if (p->n[ax] < 1 || p->n[ax] > 4096) { set_error("n[%d] out of range", ax); return FCM_ERR_ARG; }
     if (!(p->hi[ax] > p->lo[ax])) { set_error("empty box on axis %d", ax); return FCM_ERR_ARG; }
