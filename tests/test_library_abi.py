@@ -44,3 +44,31 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(fcm.SolveInfo) == 56
     assert ctypes.sizeof(fcm.Stats) == 64
     assert ctypes.sizeof(fcm.ServerOpts) == 16
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libfcm.so not built")
+@pytest.mark.parametrize("change, opt, msg", [
+    ({"dim": 4}, {}, "dim must be 2 or 3"),
+    ({"refine_levels": 5}, {}, "refine_levels must be in 0..4"),
+    ({"refine_levels": 1}, {"precision": "mixed"}, "FP64 only"),
+    ({"refine_levels": 1}, {"smoother": "elementwise", "omega": 2.0 / 15.0}, "patchwise"),
+    ({"refine_levels": 1, "quad_depth": 4}, {}, "quad_depth must be <= 3"),
+    ({"refine_levels": 0}, {}, "needs refine_levels > 0"),
+    ({"geom": 0}, {}, "ball-interior geometry"),
+    ({"alpha": 0.0}, {}, "alpha must be in (0,1]"),
+    ({"p": 9}, {}, "p must be in 1.."),
+])
+def test_setup_rejects_invalid_problems_before_any_device_call(change, opt, msg):
+    """fcm_setup validates the problem on the host and returns FCM_ERR_ARG with
+    a description before it touches the device (so this runs without a GPU)."""
+    import ctypes
+    import fcm_inputs as fi
+    from paper_2010_00881_amd import fcm
+    d, o = fi.sphere_multilevel(0, n=4, k=1, p=2)
+    d.update(change)
+    pd = fcm._ProblemData(d)
+    opts = fcm.make_options({**o, "precision": "fp64", **opt})
+    h = ctypes.c_void_p()
+    st = fcm.lib().fcm_setup(ctypes.byref(pd.struct), ctypes.byref(opts), None, ctypes.byref(h))
+    assert st == -1 and not h.value
+    assert msg in fcm.lib().fcm_last_error().decode()
