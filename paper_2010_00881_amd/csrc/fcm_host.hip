@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -545,12 +546,18 @@ static fcm_status setup_coarse_alloc(fcm_handle *h) {
   return FCM_OK;
 }
 
+// Make stream cs wait for the work enqueued so far on the handle's stream.
+static fcm_status coarse_fork(fcm_handle *h, hipStream_t cs) {
+  FCM_HIP(hipEventRecord(h->co_ready, h->stream));
+  FCM_HIP(hipStreamWaitEvent(cs, h->co_ready, 0));
+  return FCM_OK;
+}
+
+// Enqueues the block-tridiagonal coarse factorisation on cs (after coarse_fork).
 static fcm_status setup_coarse_launch(fcm_handle *h, hipStream_t cs) {
   const Geo &g = h->geo;
   Coarse &c = h->co;
   const size_t nb2 = (size_t)c.nb * c.nb;
-  FCM_HIP(hipEventRecord(h->co_ready, h->stream));
-  FCM_HIP(hipStreamWaitEvent(cs, h->co_ready, 0));
   launch_coarse_stencils(g, h->tab, c, h->kmat, h->Kref64, h->Kcut64, cs);
   for (int k = 0; k < c.nblk; ++k) {
     double *S = c.Sinv + (size_t)k * nb2;
@@ -922,15 +929,12 @@ static void patch_scratch_free(fcm_handle *h, PatchScratch &ps) {
 // Gauss-Jordan sweep) in chunks.  Class inverses are stored as m x ld (ld = m
 // rounded up to 4, the layout of the class-product kernels), unique inverses
 // as their 16 x 16 tiles on and above the diagonal (symmetric GEMV).
-static fcm_status setup_patch_levels(fcm_handle *h, const std::vector<int> &bnode,
-                                     const std::vector<int> &bkm, const PatchScratch &ps) {
+// dbn, dbk: the nblocks base nodes of the patch blocks and their kinds (device).
+static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *dbk, int nblocks,
+                                     const PatchScratch &ps) {
   const Geo &g = h->geo;
   const bool mixed = h->opt.precision == FCM_MIXED;
-  const int nblocks = (int)bnode.size();
   const int ncls = h->np_classes;
-  int *dbn = nullptr, *dbk = nullptr;
-  TRY(upload(h, &dbn, bnode.empty() ? std::vector<int>{0} : bnode));
-  TRY(upload(h, &dbk, bkm.empty() ? std::vector<int>{0} : bkm));
   std::vector<double> hk(std::max(1, nblocks));
   for (int l = 1; l <= h->L; ++l) {
     Level &L = h->lev[l];
@@ -1017,18 +1021,23 @@ static fcm_status do_setup(fcm_handle *h) {
   FCM_HIP(hipMemsetAsync(h->be, 0, (size_t)g.E * m * sizeof(double), h->stream));
   int *dcut = nullptr;
   if (ncut > 0) TRY(upload(h, &dcut, h->h_cut));
-  launch_integrate(g, h->tab, pr, nullptr, 1, 1, h->Kref64, h->be, h->dflag, h->stream);
-  if (ncut > 0)
-    launch_integrate(g, h->tab, pr, dcut, ncut, 0, h->Kcut64, h->be, h->dflag, h->stream);
-  launch_phys_rhs(g, h->tab, pr, h->state, h->be, h->stream);
-  for (int k = 0; k < pr.n_traction; ++k)
-    launch_traction_rhs(g, h->tab, pr.traction_face[k], &h->prob.tvec[3 * k], h->state, h->be,
-                        h->stream);
   const int L = h->L;
   TRY(dalloc(h, &h->b, (size_t)h->lev[L].npad));
-  launch_assemble_rhs(g, h->tab, h->kmat, h->be, h->b, h->stream);
-  launch_to_f32(h->Kref64, h->Kref32, (int64_t)mm, h->stream);
-  if (ncut > 0) launch_to_f32(h->Kcut64, h->Kcut32, (int64_t)(mm * ncut), h->stream);
+  // Element matrices, loads and the assembled right-hand side.  Enqueued after
+  // every host-built table is uploaded: an upload drains the stream, so one
+  // issued behind these kernels would leave the host waiting for them.
+  auto element_work = [&] {
+    launch_integrate(g, h->tab, pr, nullptr, 1, 1, h->Kref64, h->be, h->dflag, h->stream);
+    if (ncut > 0)
+      launch_integrate(g, h->tab, pr, dcut, ncut, 0, h->Kcut64, h->be, h->dflag, h->stream);
+    launch_phys_rhs(g, h->tab, pr, h->state, h->be, h->stream);
+    for (int k = 0; k < pr.n_traction; ++k)
+      launch_traction_rhs(g, h->tab, pr.traction_face[k], &h->prob.tvec[3 * k], h->state, h->be,
+                          h->stream);
+    launch_assemble_rhs(g, h->tab, h->kmat, h->be, h->b, h->stream);
+    launch_to_f32(h->Kref64, h->Kref32, (int64_t)mm, h->stream);
+    if (ncut > 0) launch_to_f32(h->Kcut64, h->Kcut32, (int64_t)(mm * ncut), h->stream);
+  };
   // Schwarz inverses per level >= 1, coarse factorisation
   for (int l = 0; l <= L; ++l) TRY(build_units(h, l));
   {
@@ -1084,15 +1093,48 @@ static fcm_status do_setup(fcm_handle *h) {
     PatchScratch ps;
     TRY(build_patch_tables(h));
     TRY(build_patches(h, bnode, bkm));
+    int *dbn = nullptr, *dbk = nullptr;
+    TRY(upload(h, &dbn, bnode.empty() ? std::vector<int>{0} : bnode));
+    TRY(upload(h, &dbk, bkm.empty() ? std::vector<int>{0} : bkm));
+    element_work();
     fcm_status sst = patch_scratch_alloc(h, (int)bnode.size(), ps);
-    if (sst == FCM_OK) sst = setup_coarse_launch(h, h->own);
-    if (sst == FCM_OK) sst = setup_patch_levels(h, bnode, bkm, ps);
+    if (sst == FCM_OK) sst = coarse_fork(h, h->own);
+    // The coarse chain is thousands of small serial launches (every block's
+    // inverse is a sweep per 32 pivots); a host thread of its own enqueues
+    // them while this thread enqueues the patch setup on the handle's stream.
+    fcm_status lst = FCM_OK;
+    std::string lerr;
+    std::thread co;
+    if (sst == FCM_OK) {
+      try {
+        co = std::thread([h, &lst, &lerr] {
+          if (hipSetDevice(h->device) != hipSuccess) {
+            lst = FCM_ERR_HIP;
+            lerr = "coarse launch thread: hipSetDevice failed";
+            return;
+          }
+          lst = setup_coarse_launch(h, h->own);
+          if (lst != FCM_OK) lerr = g_err;
+        });
+      } catch (...) {
+        lst = setup_coarse_launch(h, h->own);
+        if (lst != FCM_OK) lerr = g_err;
+      }
+    }
+    if (sst == FCM_OK) sst = setup_patch_levels(h, dbn, dbk, (int)bnode.size(), ps);
+    if (co.joinable()) co.join();
     fcm_status cst = coarse_join(h, h->own);
+    if (lst != FCM_OK && sst == FCM_OK) {
+      sst = lst;
+      set_error("%s", lerr.c_str());
+    }
     patch_scratch_free(h, ps);
     if (sst != FCM_OK) return sst;
     TRY(cst);
   } else {
+    element_work();
     TRY(setup_levels(h));
+    TRY(coarse_fork(h, h->own));
     TRY(setup_coarse_launch(h, h->own));
     TRY(coarse_join(h, h->own));
   }
