@@ -207,6 +207,25 @@ __global__ void ml_classify_kernel(MlGeo g, int k, const int *cells, int ncell, 
 }
 
 // ------------------------------------------------------------ leaf integration
+// Slot of this thread's item among the items that the 256 threads of the
+// workgroup take in this call, in thread order (a deterministic list order,
+// so the quadrature sums over it are reproducible); *total receives their
+// number.  Every thread of the workgroup must call it.
+__device__ inline int ml_ordered_slot(bool take, int *wcnt, int *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const unsigned long long mask = __ballot(take);
+  if (lane == 0) wcnt[w] = __popcll(mask);
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int j = 0; j < 4; ++j) {
+    if (j < w) base += wcnt[j];
+    tot += wcnt[j];
+  }
+  __syncthreads();
+  *total = tot;
+  return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
 // One workgroup per leaf.  Integration cells (the leaf, or the sub-cells of
 // its recursive bisection) are listed in LDS; points are processed in batches
 // whose function values and gradients are staged in LDS; every thread adds
@@ -256,10 +275,13 @@ __global__ __launch_bounds__(256) void ml_integrate_kernel(MlLeafArgs a) {
   // set of sub-boxes at which the recursion stops
   const int D = st == kMlCut ? g.depth : 0;
   const int nfine = 1 << (d * D);
-  for (int f = tid; f < nfine; f += 256) {
+  __shared__ int wcnt[4];
+  int nc = 0;
+  for (int f0 = 0; f0 < nfine; f0 += 256) {
+    const int f = f0 + tid;
     int sdepth = D;
     double slo[3], shi[3];
-    for (int s = 0; s <= D; ++s) {
+    for (int s = 0; s <= D && f < nfine; ++s) {
       // sub-box of depth s containing fine cell f
       for (int ax = 0; ax < 3; ++ax) {
         if (ax >= d) { slo[ax] = llo[ax]; shi[ax] = lhi[ax]; continue; }
@@ -279,17 +301,20 @@ __global__ __launch_bounds__(256) void ml_integrate_kernel(MlLeafArgs a) {
       }
     }
     // f is the representative of its stopping box when its lower bits are 0
-    bool first = true;
+    bool first = f < nfine;
     for (int t = sdepth; t < D; ++t)
       for (int ax = 0; ax < d; ++ax) first = first && (((f >> (d * (D - 1 - t) + ax)) & 1) == 0);
+    int cnt;
+    const int c = nc + ml_ordered_slot(first, wcnt, &cnt);
     if (first) {
-      const int c = atomicAdd(&ncells, 1);
       for (int ax = 0; ax < 3; ++ax) {
         cells[c][ax] = slo[ax];
         cells[c][3 + ax] = shi[ax];
       }
     }
+    nc += cnt;
   }
+  if (tid == 0) ncells = nc;
   __syncthreads();
   int npq = 1;
   for (int ax = 0; ax < d; ++ax) npq *= np1;
@@ -311,7 +336,6 @@ __global__ __launch_bounds__(256) void ml_integrate_kernel(MlLeafArgs a) {
   }
   const int nsurf = scan ? a.nsurf : 0;
   __shared__ int sel[256];
-  __shared__ int nsel;
   double bacc[2] = {0.0, 0.0};
   // one batch of cnt staged points: values/gradients, then K and b updates
   auto process = [&](int cnt) {
@@ -388,16 +412,15 @@ __global__ __launch_bounds__(256) void ml_integrate_kernel(MlLeafArgs a) {
   }
   // surface points of the penalty term inside the half-open leaf box
   for (int s0 = 0; s0 < nsurf; s0 += 256) {
-    if (tid == 0) nsel = 0;
-    __syncthreads();
-    if (s0 + tid < nsurf) {
+    bool in = s0 + tid < nsurf;
+    if (in) {
       const double *sp = a.surf + 4 * (size_t)(s0 + tid);
-      bool in = true;
       for (int ax = 0; ax < d; ++ax) in = in && floor((sp[ax] - g.lo[ax]) / ah[k][ax]) == (double)lf[1 + ax];
-      if (in) sel[atomicAdd(&nsel, 1)] = s0 + tid;
     }
+    int ns;
+    const int slot = ml_ordered_slot(in, wcnt, &ns);
+    if (in) sel[slot] = s0 + tid;
     __syncthreads();
-    const int ns = nsel;
     for (int b0 = 0; b0 < ns; b0 += kMlBatch) {
       const int cnt = min(kMlBatch, ns - b0);
       if (tid < cnt) {

@@ -9,14 +9,20 @@ fictitious leaves have scaled condition numbers up to ~1e14, so individual
 entries of their inverses carry errors ~ cond * eps), and the preconditioned
 CG (iterations, residual, energy-norm distance of the solutions).
 
-Tolerances.  With alpha = 1 and beta = 1 the blocks are well conditioned and
-smoother, V-cycle and solution agree to 1e-6 in the energy norm.  With the
-FCM values alpha = 1e-10, beta = 1e4 the Jacobi-scaled patch blocks reach
-condition numbers of 2e13..5e13 (measured with the oracle), so both sides'
-inverses carry relative errors up to cond * eps ~ 5e-3; the test allows 1e-3
-(measured 3e-5..1e-4).  The solutions of the two CGs, each stopped at a
-relative residual of 1e-10 with cond(A) ~ 1e14, may differ by
-1e-10 sqrt(cond) ~ 1e-3 in the energy norm (measured 4e-5).
+Tolerances. An FP64 inverse of a symmetric positive definite block with
+condition number kappa carries a relative error of about kappa * u (u = eps /
+2, the unit roundoff), so the two sides' inverses may differ by kappa * eps,
+and the smoother of level l is compared to max(1e-6, kappa_l * eps), kappa_l
+the largest condition number of the level's Jacobi-scaled patch blocks
+(computed here from the oracle's blocks), and the V-cycle to the largest of
+these. With alpha = 1 and beta = 1 the blocks are well conditioned (kappa <=
+5e2) and the bound is the 1e-6 floor. With the FCM values alpha = 1e-10, beta
+= 1e4 the blocks with fictitious leaves reach kappa = 2e13..3e14 (bounds
+4e-3..6e-2; measured 3e-5..1.4e-3, varying from run to run with the order of
+the floating-point atomic sums of the leaf quadrature and the load). The
+solutions of the two CGs, each stopped at a relative residual of 1e-10 with
+cond(A) ~ 1e14, may differ by 1e-10 sqrt(cond) ~ 1e-3 in the energy norm
+(measured 4e-5).
 """
 import numpy as np
 import pytest
@@ -47,6 +53,23 @@ CASES = {
 }
 
 _cache = {}
+
+
+_EPS = np.finfo(np.float64).eps
+
+
+def _smoother_tol(H, l):
+    """max(1e-6, kappa * eps) over the Jacobi-scaled patch blocks of level l."""
+    A = H.As[l]
+    kmax = 1.0
+    for I in H.block_sets(l):
+        if I.size == 0:
+            continue
+        Ai = A[I][:, I].toarray()
+        s = 1.0 / np.sqrt(np.diag(Ai))
+        ev = np.linalg.eigvalsh(Ai * s[:, None] * s[None, :])
+        kmax = max(kmax, ev[-1] / ev[0])
+    return max(1e-6, kmax * _EPS)
 
 
 def _tol(name):
@@ -100,6 +123,7 @@ def test_mlhp_smoother_and_vcycle(name):
     s, D, H = _case(name)
     rng = np.random.default_rng(6)
     L = len(D.level_sizes) - 1
+    tols = {}
     for l in range(1, L + 1):
         A = H.As[l]
         r = A @ rng.standard_normal(D.level_sizes[l])
@@ -107,16 +131,19 @@ def test_mlhp_smoother_and_vcycle(name):
         zo = H.smooth(l, r)
         e = z - zo
         err = np.sqrt(e @ (A @ e) / (zo @ (A @ zo)))
-        print(f"[mlhp] {name} smoother level {l}: energy rel err {err:.1e}", flush=True)
-        assert err <= _tol(name)
+        tols[l] = _smoother_tol(H, l)
+        print(f"[mlhp] {name} smoother level {l}: energy rel err {err:.1e} (bound {tols[l]:.1e})",
+              flush=True)
+        assert err <= tols[l]
     A = H.As[L]
     r = A @ rng.standard_normal(D.n_dofs)
     v = s.vcycle(_t(r)).cpu().numpy()
     vo = H.precondition(r)
     e = v - vo
     err = np.sqrt(e @ (A @ e) / (vo @ (A @ vo)))
-    print(f"[mlhp] {name} vcycle: energy rel err {err:.1e}", flush=True)
-    assert err <= _tol(name)
+    print(f"[mlhp] {name} vcycle: energy rel err {err:.1e} (bound {max(tols.values()):.1e})",
+          flush=True)
+    assert err <= max(tols.values())
 
 
 @pytest.mark.parametrize("name", list(CASES))
