@@ -1275,6 +1275,7 @@ static PatchArgs<T> patch_args(fcm_handle *h, int l) {
   a.m = L.mpatch;
   a.ld = L.ldp;
   a.ntile = (L.mpatch + 15) / 16;
+  a.xlen = (int)L.npad;
   a.nP_out = L.nP;
   a.pnode = h->pnode;
   a.pkm = h->pkm;

@@ -292,6 +292,7 @@ void launch_elem_op(const Geo &g, const Tables &t, const OpArgs<T> &a, hipStream
 template <typename T>
 struct PatchArgs {
   const T *x = nullptr;
+  int xlen = 0;                   // length of x (a level vector in the padded plane layout)
   int m = 0, ld = 0;              // level block size, matrix leading dimension (ld % 4 == 0)
   int nP_out = 0;
   const int *pnode = nullptr, *pkm = nullptr, *pid = nullptr;

@@ -493,6 +493,112 @@ __global__ __launch_bounds__(512) void patch_class_mfma32_kernel(Geo g,
   }
 }
 
+// FP32 class products for large blocks (128 < m <= 384): a workgroup computes
+// all m rows for 64 patches of one class, Y[:, q0:q0+64] = A_c X, streaming
+// both operands through LDS in slices of 32 k (A_c from L2, X gathered once
+// per patch instead of once per row group) and prefetching the next slice into
+// registers while the matrix cores work on the current one: waves 0..5 fetch
+// the A slice (row r = thread, 32 k), waves 6 and 7 the X slice.  Wave w owns
+// row tiles w, w + 8, w + 16 and all four 16-patch column tiles (12
+// accumulators).  LDS rows are padded to 16 mod 32 floats so that the four k
+// rows a v_mfma_f32_16x16x4f32 operand read touches fall in distinct banks.
+static_assert(kMaxPatchM <= 384, "class tile kernel covers at most 24 row tiles");
+constexpr int kCT_RS = 384 + 16;   // A slice row stride (floats)
+constexpr int kCT_XS = 64 + 16;    // X slice row stride (floats)
+
+__global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *__restrict__ pxoff,
+                                                                 PatchArgs<float> a) {
+  __shared__ float As[32 * kCT_RS];
+  __shared__ float Xs[32 * kCT_XS];
+  __shared__ int koff[384];            // offset of mode k from the patch node in x
+  __shared__ float kmask[384];         // 1 if mode k is present in the class, else 0
+  const int *ch = a.chk + 3 * blockIdx.y;
+  const int c = ch[0], q0 = ch[1] + 64 * blockIdx.x, qn = min(64, ch[2] - 64 * (int)blockIdx.x);
+  if (qn <= 0) return;
+  const int m = a.m, ld = a.ld;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int n = lane & 15, kq = lane >> 4;
+  const bool fa = wave < 6;            // wave-uniform role in the slice fetch
+  const float *A0 = a.matS32 + (size_t)c * m * ld + min(tid, m - 1);
+  const bool rv = tid < m;
+  const unsigned *pres = a.cpres + (size_t)c * a.pwords;
+  const int pn = fa ? 0 : a.pnode[q0 + min(lane, qn - 1)];
+  const int kx = wave - 6;             // X rows kx, kx + 2, ... of the slice
+  // Every load below is issued unconditionally from a clamped, valid address
+  // and masked afterwards: a load under a branch makes the compiler wait for
+  // it before the branches join, one memory latency per element.
+  float pf[32];
+  auto fetch = [&](int k0) {
+    if (fa) {
+#pragma unroll
+      for (int e = 0; e < 32; ++e) {   // A[r][k] = A0[k * ld + r], r = tid
+        const float v = A0[(size_t)(min(k0 + e, m - 1)) * ld];
+        pf[e] = (rv & (k0 + e < m)) ? v : 0.f;
+      }
+    } else {
+      // The address is clamped into x rather than selected, and absent modes
+      // are scaled by 0: a select on a loaded value is turned back into a
+      // branch around the load.
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int k = k0 + kx + 2 * e, kc = min(k, m - 1);
+        const float mk = ((lane < qn) & (k < m)) ? kmask[kc] : 0.f;
+        pf[e] = a.x[min(max(pn + koff[kc], 0), a.xlen - 1)] * mk;
+      }
+    }
+  };
+  floatx4p acc[3][4];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[i][t] = floatx4p{0.f, 0.f, 0.f, 0.f};
+  for (int k = tid; k < m; k += 512) {
+    koff[k] = pxoff[k];
+    kmask[k] = ((pres[k >> 5] >> (k & 31)) & 1u) ? 1.f : 0.f;
+  }
+  __syncthreads();
+  const int nslice = (m + 31) >> 5;
+  fetch(0);
+  for (int sl = 0; sl < nslice; ++sl) {
+    if (fa) {
+#pragma unroll
+      for (int e = 0; e < 32; ++e) As[e * kCT_RS + tid] = pf[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) Xs[(kx + 2 * e) * kCT_XS + lane] = pf[e];
+    }
+    __syncthreads();
+    if (sl + 1 < nslice) fetch(32 * (sl + 1));
+#pragma unroll
+    for (int k4 = 0; k4 < 8; ++k4) {
+      const int kr = 4 * k4 + kq;
+      float bv[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bv[t] = Xs[kr * kCT_XS + 16 * t + n];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float av = As[kr * kCT_RS + 16 * (wave + 8 * i) + n];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[t], acc[i][t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int q = 16 * t + n;
+      if (q < qn)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int rr = 16 * (wave + 8 * i) + 4 * kq + j;
+          if (rr < m) a.Ys[(size_t)rr * a.nsh + q0 + q] = (double)acc[i][t][j];
+        }
+    }
+}
+
 template <int NKS>
 static void launch_class32_nks(const Geo &g, const PatchTables &pt, const PatchArgs<float> &a,
                                hipStream_t s) {
@@ -506,14 +612,14 @@ static bool launch_class32(const Geo &g, const PatchTables &pt, const PatchArgs<
                            hipStream_t s) {
   if (!a.matS32) return false;
   const int nks = (a.m + 3) / 4;
+  if (a.m > 128) {   // m <= kMaxPatchM = 384
+    patch_class_tile32_kernel<<<dim3(4, a.nchunks), 512, 0, s>>>(pt.pxoff, a);
+    return true;
+  }
   if (nks <= 8) launch_class32_nks<8>(g, pt, a, s);
   else if (nks <= 16) launch_class32_nks<16>(g, pt, a, s);
   else if (nks <= 24) launch_class32_nks<24>(g, pt, a, s);
-  else if (nks <= 32) launch_class32_nks<32>(g, pt, a, s);
-  else if (nks <= 48) launch_class32_nks<48>(g, pt, a, s);
-  else if (nks <= 64) launch_class32_nks<64>(g, pt, a, s);
-  else if (nks <= 88) launch_class32_nks<88>(g, pt, a, s);
-  else launch_class32_nks<96>(g, pt, a, s);
+  else launch_class32_nks<32>(g, pt, a, s);
   return true;
 }
 

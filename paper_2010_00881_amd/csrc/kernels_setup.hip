@@ -863,10 +863,15 @@ __global__ __launch_bounds__(64) void sweep_rows_kernel(double *A, int n, int K,
   const bool panel = l >= kTB;
   const int col = panel ? J * kTJ + (l - kTB) : k0 + l;
   double x[kTB];
+  // unconditional loads from clamped addresses, then a select: a load under a
+  // condition is issued and waited for one row at a time
+  const int cc = min(col, n - 1);
+#pragma unroll
+  for (int r = 0; r < kTB; ++r) x[r] = M[(size_t)min(k0 + r, n - 1) * n + cc];
 #pragma unroll
   for (int r = 0; r < kTB; ++r) {
     const int gr = k0 + r;
-    const double v = (gr < n && col < n) ? M[(size_t)gr * n + col] : (gr == col ? 1.0 : 0.0);
+    const double v = (gr < n && col < n) ? x[r] : (gr == col ? 1.0 : 0.0);
     x[r] = v;
     if (panel && col < n) Rb[(size_t)r * n + col] = v;
   }
@@ -933,22 +938,31 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 2; ++v) acc[u][v] = doublex4s{0.0, 0.0, 0.0, 0.0};
+  // all operand loads first, from clamped addresses (a load under a condition
+  // is waited for before the next one is issued), then the products
+  double av[kTB / 4][2], bv[kTB / 4][2];
 #pragma unroll
   for (int ks = 0; ks < kTB / 4; ++ks) {
     const int kk = 4 * ks + lq;
-    double av[2], bv[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      const int i = i0 + 16 * u + ln;
-      av[u] = i < n ? Rb[(size_t)kk * n + i] : 0.0;        // A[i][kk] = R[kk][i]
-      const int j = j0 + 16 * u + ln;
-      bv[u] = j < n ? Wb[(size_t)kk * n + j] : 0.0;        // B[kk][j] = W[kk][j]
+      av[ks][u] = Rb[(size_t)kk * n + min(i0 + 16 * u + ln, n - 1)];   // A[i][kk] = R[kk][i]
+      bv[ks][u] = Wb[(size_t)kk * n + min(j0 + 16 * u + ln, n - 1)];   // B[kk][j] = W[kk][j]
+    }
+  }
+#pragma unroll
+  for (int ks = 0; ks < kTB / 4; ++ks) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      if (i0 + 16 * u + ln >= n) av[ks][u] = 0.0;
+      if (j0 + 16 * u + ln >= n) bv[ks][u] = 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int v = 0; v < 2; ++v)
-        acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
+        acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][u], bv[ks][v], acc[u][v], 0, 0,
+                                                         0);
   }
   // all loads of the write phase are issued before any store (the output
   // entries are distinct and W is not written here)
