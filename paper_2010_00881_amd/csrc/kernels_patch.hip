@@ -85,47 +85,45 @@ __device__ double patch_entry(const Geo &g, const PatchTables &pt, const int *sm
     if (lo[ax] > hi[ax]) return 0.0;
   }
   // the (at most 2 per axis) common elements, axis 0 fastest: all element
-  // ids, then all matrix entries (the loads of each pass in flight
-  // together), summed in that order
-  int kid[8];
-  int rel[8][3];
+  // ids, then all matrix entries, summed in that order.  Each pass issues
+  // its loads unconditionally from clamped addresses (a load under a
+  // condition is waited for before the next is issued) and masks afterwards.
+  int kid[8], la[8], lb[8];
+  bool in[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    kid[c] = -1;
-    int ec[3] = {0, 0, 0};
-    bool in = true;
+    int ec[3] = {0, 0, 0}, ai[3] = {0, 0, 0}, aj[3] = {0, 0, 0};
+    bool ok = true;
     for (int ax = 0; ax < 3; ++ax) {
-      rel[c][ax] = lo[ax] + ((c >> ax) & 1);
+      const int rel = lo[ax] + ((c >> ax) & 1);
       if (ax >= g.d) {
-        in = in && ((c >> ax) & 1) == 0;
+        ok = ok && ((c >> ax) & 1) == 0;
         continue;
       }
-      ec[ax] = vc[ax] + rel[c][ax];
-      in = in && rel[c][ax] <= hi[ax] && ec[ax] >= 0 && ec[ax] < g.n[ax];
+      ec[ax] = vc[ax] + rel;
+      ok = ok && rel <= hi[ax] && ec[ax] >= 0 && ec[ax] < g.n[ax];
+      ec[ax] = min(max(ec[ax], 0), g.n[ax] - 1);
+      // element-local 1D mode: 0 / 1 = hat at the element's left / right
+      // node, t + 1 = bubble of type t
+      ai[ax] = min(max(ti[ax] == 0 ? di[ax] - rel : ti[ax] + 1, 0), p);
+      aj[ax] = min(max(tj[ax] == 0 ? dj[ax] - rel : tj[ax] + 1, 0), p);
     }
-    if (in) kid[c] = kmat[ec[0] + g.n[0] * (ec[1] + g.n[1] * ec[2])];
+    in[c] = ok;
+    kid[c] = kmat[ec[0] + g.n[0] * (ec[1] + g.n[1] * ec[2])];
+    la[c] = smap[(ai[0] + np * (ai[1] + np * ai[2])) * g.nf + mi[3]];
+    lb[c] = smap[(aj[0] + np * (aj[1] + np * aj[2])) * g.nf + mj[3]];
   }
   double v[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    v[c] = 0.0;
-    if (kid[c] < 0) continue;
-    int ai[3] = {0, 0, 0}, aj[3] = {0, 0, 0};
-    for (int ax = 0; ax < g.d; ++ax) {
-      // element-local 1D mode: 0 / 1 = hat at the element's left / right
-      // node, t + 1 = bubble of type t
-      ai[ax] = ti[ax] == 0 ? di[ax] - rel[c][ax] : ti[ax] + 1;
-      aj[ax] = tj[ax] == 0 ? dj[ax] - rel[c][ax] : tj[ax] + 1;
-    }
-    const int la = smap[(ai[0] + np * (ai[1] + np * ai[2])) * g.nf + mi[3]];
-    const int lb = smap[(aj[0] + np * (aj[1] + np * aj[2])) * g.nf + mj[3]];
-    const double *K = kid[c] == 0 ? Kref : Kcut + (size_t)(kid[c] - 1) * mp * mp;
-    v[c] = K[(size_t)la * mp + lb];
+    const int k = in[c] ? kid[c] : -1;
+    in[c] = k >= 0;
+    const double *K = k <= 0 ? Kref : Kcut + (size_t)(k - 1) * mp * mp;
+    v[c] = K[(size_t)la[c] * mp + lb[c]];
   }
   double sum = 0.0;
 #pragma unroll
-  for (int c = 0; c < 8; ++c)
-    if (kid[c] >= 0) sum += v[c];
+  for (int c = 0; c < 8; ++c) sum += (in[c] ? 1.0 : 0.0) * v[c];
   return sum;
 }
 
@@ -225,23 +223,39 @@ void launch_pack_tiles(const double *src, int m, int nb, double *d64, float *d32
 // Every half-wave adds into its own LDS copy of y in a fixed order, and the
 // eight copies are added in a fixed order, so the result is the same on
 // every run.
-template <typename T>
-__device__ inline void tile_load(const T *p, double v[4]) {
-  if constexpr (std::is_same<T, float>::value) {
-    const float4 q = *reinterpret_cast<const float4 *>(p);
-    v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
-  } else {
-    const double2 q0 = *reinterpret_cast<const double2 *>(p);
-    const double2 q1 = *reinterpret_cast<const double2 *>(p + 2);
-    v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+// A lane's 4 consecutive entries of a stored tile, kept in the storage type
+// while the load is in flight (converted to FP64 when staged in LDS).
+template <typename T> struct TileRaw;
+template <> struct TileRaw<float> {
+  float4 q;
+  __device__ void load(const float *p) { q = *reinterpret_cast<const float4 *>(p); }
+  __device__ double get(int k) const {
+    return k == 0 ? q.x : k == 1 ? q.y : k == 2 ? q.z : q.w;
   }
-}
+};
+template <> struct TileRaw<double> {
+  double2 q0, q1;
+  __device__ void load(const double *p) {
+    q0 = *reinterpret_cast<const double2 *>(p);
+    q1 = *reinterpret_cast<const double2 *>(p + 2);
+  }
+  __device__ double get(int k) const {
+    return k == 0 ? q0.x : k == 1 ? q0.y : k == 2 ? q1.x : q1.y;
+  }
+};
 
 // One wave's share of the tiles, two at a time (t and t + 4 of the wave's
 // sequence t = w, w + 8, ...): each lane loads 4 entries of both tiles and
 // stages them in the wave's LDS buffer (rows padded to 17 doubles); then in
 // each half-wave 16 lanes form the row sums M_IJ x_J and 16 lanes the column
 // sums M_IJ^T x_I of one tile, adding them to that half-wave's copy of y.
+// Each trip issues the loads of kGemvPairs pairs together (unconditionally:
+// a tile index past the end is replaced by the trip's first tile, an L1
+// hit), then stages and computes the pairs in order, waiting only for the
+// pair it needs: kGemvPairs pairs per wave are in flight (the bound is HBM)
+// and no load is pending across trips.
+constexpr int kGemvPairs = 3;
+
 template <typename M>
 __device__ inline void tile_sweep(const M *base, int ntiles, const unsigned char *tI,
                                   const unsigned char *tJ, const double *xs, double (*tb)[16][17],
@@ -250,35 +264,44 @@ __device__ inline void tile_sweep(const M *base, int ntiles, const unsigned char
   const int half = lane >> 5, i = lane & 15;
   const bool rowpart = (lane & 16) == 0;
   double *yh = half ? yh1 : yh0;
-  for (int t0 = wave; t0 < ntiles; t0 += 8) {
-    double va[4], vb[4];
-    tile_load<M>(base + (size_t)t0 * 256 + r * 16 + c0, va);
-    const bool hasb = t0 + 4 < ntiles;
-    if (hasb) tile_load<M>(base + (size_t)(t0 + 4) * 256 + r * 16 + c0, vb);
-    else vb[0] = vb[1] = vb[2] = vb[3] = 0.0;
+  const M *lp = base + r * 16 + c0;
+  for (int t0 = wave; t0 < ntiles; t0 += 8 * kGemvPairs) {
+    TileRaw<M> ta[kGemvPairs], tb2[kGemvPairs];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      tb[0][r][c0 + q] = va[q];
-      tb[1][r][c0 + q] = vb[q];
+    for (int q = 0; q < kGemvPairs; ++q) {
+      const int ta_i = t0 + 8 * q, tb_i = ta_i + 4;
+      ta[q].load(lp + (size_t)(ta_i < ntiles ? ta_i : t0) * 256);
+      tb2[q].load(lp + (size_t)(tb_i < ntiles ? tb_i : t0) * 256);
     }
-    __builtin_amdgcn_wave_barrier();
-    const int t = t0 + 4 * half;
-    if (t < ntiles) {
-      const int I = tI[t], J = tJ[t];
-      double acc = 0.0;
-      if (rowpart) {
-        const double *xJ = xs + 16 * J;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) acc += tb[half][i][k] * xJ[k];
-        yh[16 * I + i] += acc;
-      } else if (I != J) {
-        const double *xI = xs + 16 * I;
+    for (int q = 0; q < kGemvPairs; ++q) {
+      const int tp = t0 + 8 * q;
+      if (tp >= ntiles) break;   // wave-uniform
+      const bool hasb = tp + 4 < ntiles;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) acc += tb[half][k][i] * xI[k];
-        yh[16 * J + i] += acc;
+      for (int e = 0; e < 4; ++e) {
+        tb[0][r][c0 + e] = ta[q].get(e);
+        tb[1][r][c0 + e] = hasb ? tb2[q].get(e) : 0.0;
       }
+      __builtin_amdgcn_wave_barrier();
+      const int t = tp + 4 * half;
+      if (t < ntiles) {
+        const int I = tI[t], J = tJ[t];
+        double acc = 0.0;
+        if (rowpart) {
+          const double *xJ = xs + 16 * J;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) acc += tb[half][i][k] * xJ[k];
+          yh[16 * I + i] += acc;
+        } else if (I != J) {
+          const double *xI = xs + 16 * I;
+#pragma unroll
+          for (int k = 0; k < 16; ++k) acc += tb[half][k][i] * xI[k];
+          yh[16 * J + i] += acc;
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
     }
-    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -493,22 +516,23 @@ __global__ __launch_bounds__(512) void patch_class_mfma32_kernel(Geo g,
   }
 }
 
-// FP32 class products for large blocks (128 < m <= 384): a workgroup computes
-// all m rows for 64 patches of one class, Y[:, q0:q0+64] = A_c X, streaming
-// both operands through LDS in slices of 32 k (A_c from L2, X gathered once
-// per patch instead of once per row group) and prefetching the next slice into
-// registers while the matrix cores work on the current one: waves 0..5 fetch
-// the A slice (row r = thread, 32 k), waves 6 and 7 the X slice.  Wave w owns
-// row tiles w, w + 8, w + 16 and all four 16-patch column tiles (12
-// accumulators).  LDS rows are padded to 16 mod 32 floats so that the four k
-// rows a v_mfma_f32_16x16x4f32 operand read touches fall in distinct banks.
+// FP32 class products: a workgroup computes all m <= 128 NRT rows for 64
+// patches of one class, Y[:, q0:q0+64] = A_c X, streaming both operands
+// through LDS in slices of 32 k (A_c from L2, X gathered once per patch) and
+// prefetching the next slice into registers while the matrix cores work on
+// the current one: threads below 128 NRT fetch the A slice (row r = thread,
+// 32 k), waves 6 and 7 the X slice.  Wave w owns row tiles w, w + 8, ..,
+// w + 8 (NRT - 1) and all four 16-patch column tiles.  LDS rows are padded to
+// 16 mod 32 floats so that the four k rows a v_mfma_f32_16x16x4f32 operand
+// read touches fall in distinct banks.
 static_assert(kMaxPatchM <= 384, "class tile kernel covers at most 24 row tiles");
-constexpr int kCT_RS = 384 + 16;   // A slice row stride (floats)
 constexpr int kCT_XS = 64 + 16;    // X slice row stride (floats)
 
+template <int NRT>
 __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *__restrict__ pxoff,
-                                                                 PatchArgs<float> a) {
-  __shared__ float As[32 * kCT_RS];
+                                                                    PatchArgs<float> a) {
+  constexpr int ROWS = 128 * NRT, RS = ROWS + 16;
+  __shared__ float As[32 * RS];
   __shared__ float Xs[32 * kCT_XS];
   __shared__ int koff[384];            // offset of mode k from the patch node in x
   __shared__ float kmask[384];         // 1 if mode k is present in the class, else 0
@@ -518,11 +542,12 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
   const int m = a.m, ld = a.ld;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n = lane & 15, kq = lane >> 4;
-  const bool fa = wave < 6;            // wave-uniform role in the slice fetch
+  const bool fa = tid < ROWS;          // wave-uniform role in the slice fetch
   const float *A0 = a.matS32 + (size_t)c * m * ld + min(tid, m - 1);
   const bool rv = tid < m;
   const unsigned *pres = a.cpres + (size_t)c * a.pwords;
-  const int pn = fa ? 0 : a.pnode[q0 + min(lane, qn - 1)];
+  const bool fx = wave >= 6;
+  const int pn = fx ? a.pnode[q0 + min(lane, qn - 1)] : 0;
   const int kx = wave - 6;             // X rows kx, kx + 2, ... of the slice
   // Every load below is issued unconditionally from a clamped, valid address
   // and masked afterwards: a load under a branch makes the compiler wait for
@@ -535,7 +560,7 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
         const float v = A0[(size_t)(min(k0 + e, m - 1)) * ld];
         pf[e] = (rv & (k0 + e < m)) ? v : 0.f;
       }
-    } else {
+    } else if (fx) {
       // The address is clamped into x rather than selected, and absent modes
       // are scaled by 0: a select on a loaded value is turned back into a
       // branch around the load.
@@ -547,9 +572,9 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
       }
     }
   };
-  floatx4p acc[3][4];
+  floatx4p acc[NRT][4];
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < NRT; ++i)
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[i][t] = floatx4p{0.f, 0.f, 0.f, 0.f};
   for (int k = tid; k < m; k += 512) {
@@ -562,8 +587,8 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
   for (int sl = 0; sl < nslice; ++sl) {
     if (fa) {
 #pragma unroll
-      for (int e = 0; e < 32; ++e) As[e * kCT_RS + tid] = pf[e];
-    } else {
+      for (int e = 0; e < 32; ++e) As[e * RS + tid] = pf[e];
+    } else if (fx) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) Xs[(kx + 2 * e) * kCT_XS + lane] = pf[e];
     }
@@ -576,8 +601,8 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
 #pragma unroll
       for (int t = 0; t < 4; ++t) bv[t] = Xs[kr * kCT_XS + 16 * t + n];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        const float av = As[kr * kCT_RS + 16 * (wave + 8 * i) + n];
+      for (int i = 0; i < NRT; ++i) {
+        const float av = As[kr * RS + 16 * (wave + 8 * i) + n];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
           acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[t], acc[i][t], 0, 0, 0);
@@ -586,7 +611,7 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < NRT; ++i)
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int q = 16 * t + n;
@@ -612,14 +637,11 @@ static bool launch_class32(const Geo &g, const PatchTables &pt, const PatchArgs<
                            hipStream_t s) {
   if (!a.matS32) return false;
   const int nks = (a.m + 3) / 4;
-  if (a.m > 128) {   // m <= kMaxPatchM = 384
-    patch_class_tile32_kernel<<<dim3(4, a.nchunks), 512, 0, s>>>(pt.pxoff, a);
-    return true;
-  }
-  if (nks <= 8) launch_class32_nks<8>(g, pt, a, s);
-  else if (nks <= 16) launch_class32_nks<16>(g, pt, a, s);
-  else if (nks <= 24) launch_class32_nks<24>(g, pt, a, s);
-  else launch_class32_nks<32>(g, pt, a, s);
+  const dim3 grid(4, a.nchunks);   // chunks hold <= 256 patches; m <= kMaxPatchM = 384
+  if (a.m > 256) patch_class_tile32_kernel<3><<<grid, 512, 0, s>>>(pt.pxoff, a);
+  else if (a.m > 128) patch_class_tile32_kernel<2><<<grid, 512, 0, s>>>(pt.pxoff, a);
+  else if (a.m > 32) patch_class_tile32_kernel<1><<<grid, 512, 0, s>>>(pt.pxoff, a);
+  else launch_class32_nks<8>(g, pt, a, s);   // nks <= 8
   return true;
 }
 
