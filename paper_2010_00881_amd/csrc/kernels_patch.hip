@@ -550,25 +550,21 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
   const int pn = fx ? a.pnode[q0 + min(lane, qn - 1)] : 0;
   const int kx = wave - 6;             // X rows kx, kx + 2, ... of the slice
   // Every load below is issued unconditionally from a clamped, valid address
-  // and masked afterwards: a load under a branch makes the compiler wait for
-  // it before the branches join, one memory latency per element.
+  // (a load under a branch makes the compiler wait for it before the
+  // branches join, one memory latency per element), and the raw values are
+  // masked only when the slice is stored to LDS, one trip later: masking
+  // right after the loads would wait for them before the matrix-core work.
   float pf[32];
   auto fetch = [&](int k0) {
     if (fa) {
 #pragma unroll
-      for (int e = 0; e < 32; ++e) {   // A[r][k] = A0[k * ld + r], r = tid
-        const float v = A0[(size_t)(min(k0 + e, m - 1)) * ld];
-        pf[e] = (rv & (k0 + e < m)) ? v : 0.f;
-      }
+      for (int e = 0; e < 32; ++e)     // A[r][k] = A0[k * ld + r], r = tid
+        pf[e] = A0[(size_t)(min(k0 + e, m - 1)) * ld];
     } else if (fx) {
-      // The address is clamped into x rather than selected, and absent modes
-      // are scaled by 0: a select on a loaded value is turned back into a
-      // branch around the load.
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int k = k0 + kx + 2 * e, kc = min(k, m - 1);
-        const float mk = ((lane < qn) & (k < m)) ? kmask[kc] : 0.f;
-        pf[e] = a.x[min(max(pn + koff[kc], 0), a.xlen - 1)] * mk;
+        const int kc = min(k0 + kx + 2 * e, m - 1);
+        pf[e] = a.x[min(max(pn + koff[kc], 0), a.xlen - 1)];
       }
     }
   };
@@ -585,12 +581,19 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
   const int nslice = (m + 31) >> 5;
   fetch(0);
   for (int sl = 0; sl < nslice; ++sl) {
+    const int k0 = 32 * sl;
     if (fa) {
 #pragma unroll
-      for (int e = 0; e < 32; ++e) As[e * RS + tid] = pf[e];
+      for (int e = 0; e < 32; ++e) As[e * RS + tid] = (rv & (k0 + e < m)) ? pf[e] : 0.f;
     } else if (fx) {
+      // absent modes and missing patches are scaled by 0 (not selected: a
+      // select on a loaded value would be turned back into a branch)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) Xs[(kx + 2 * e) * kCT_XS + lane] = pf[e];
+      for (int e = 0; e < 16; ++e) {
+        const int k = k0 + kx + 2 * e;
+        const float mk = ((lane < qn) & (k < m)) ? kmask[min(k, m - 1)] : 0.f;
+        Xs[(kx + 2 * e) * kCT_XS + lane] = pf[e] * mk;
+      }
     }
     __syncthreads();
     if (sl + 1 < nslice) fetch(32 * (sl + 1));
