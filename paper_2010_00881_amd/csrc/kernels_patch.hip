@@ -536,8 +536,14 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
   __shared__ float Xs[32 * kCT_XS];
   __shared__ int koff[384];            // offset of mode k from the patch node in x
   __shared__ float kmask[384];         // 1 if mode k is present in the class, else 0
-  const int *ch = a.chk + 3 * blockIdx.y;
-  const int c = ch[0], q0 = ch[1] + 64 * blockIdx.x, qn = min(64, ch[2] - 64 * (int)blockIdx.x);
+  // Workgroups are dealt to the 8 XCDs round-robin by id; the four quarters
+  // of a chunk get ids of one residue mod 8, so its class inverse is read
+  // from HBM once into that XCD's L2 and the other quarters hit there.
+  const int L = blockIdx.x, slot = L >> 3;
+  const int chunk = (slot >> 2) * 8 + (L & 7), quarter = slot & 3;
+  if (chunk >= a.nchunks) return;
+  const int *ch = a.chk + 3 * chunk;
+  const int c = ch[0], q0 = ch[1] + 64 * quarter, qn = min(64, ch[2] - 64 * quarter);
   if (qn <= 0) return;
   const int m = a.m, ld = a.ld;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -640,7 +646,8 @@ static bool launch_class32(const Geo &g, const PatchTables &pt, const PatchArgs<
                            hipStream_t s) {
   if (!a.matS32) return false;
   const int nks = (a.m + 3) / 4;
-  const dim3 grid(4, a.nchunks);   // chunks hold <= 256 patches; m <= kMaxPatchM = 384
+  // chunks hold <= 256 patches (four quarters of 64); m <= kMaxPatchM = 384
+  const dim3 grid(4 * ((a.nchunks + 7) / 8 * 8));
   if (a.m > 256) patch_class_tile32_kernel<3><<<grid, 512, 0, s>>>(pt.pxoff, a);
   else if (a.m > 128) patch_class_tile32_kernel<2><<<grid, 512, 0, s>>>(pt.pxoff, a);
   else if (a.m > 32) patch_class_tile32_kernel<1><<<grid, 512, 0, s>>>(pt.pxoff, a);
