@@ -184,3 +184,29 @@ def test_pcg_mixed(name):
     tol_it = 2 if name == "plate40_p3" else 1
     assert abs(info["iterations"] - ito) <= tol_it
     assert eerr <= 1e-7
+
+
+@pytest.mark.parametrize("name", ["plate16_p2", "plate16_p2_patch", "cube7_p3_patch",
+                                  "elast3_p2_patch"])
+def test_mg_solve(name):
+    """The V-cycle as a stand-alone solver (Section 4, eq. contraction)."""
+    desc, opts, s, disc, hier, dm = case(name)
+    xo, ito, ho, rho_o = hier.mg_solve(disc.b)
+    x, info = s.mg_solve()
+    xg, rest = dm.from_gpu(x)
+    err = rel(xg, xo)
+    hg = info["history"]
+    print(f"[parity] {name} mg_solve: it gpu {info['iterations']} oracle {ito}, rho_max gpu "
+          f"{info['rho_max']:.8f} oracle {rho_o:.8f}, rel err {err:.2e}", flush=True)
+    assert info["status"] == 0
+    assert abs(info["iterations"] - ito) <= 1
+    assert err <= 1e-8
+    assert np.all(rest == 0.0)
+    # Contraction numbers of the iterations whose residual is well above the
+    # rounding level of b - A x agree closely; the last ones carry the relative
+    # rounding error of a residual near rtol.
+    k = min(len(hg), len(ho))
+    early = [i for i in range(1, k) if ho[i] > 1e-7]
+    for i in early:
+        assert hg[i] / hg[i - 1] == pytest.approx(ho[i] / ho[i - 1], rel=1e-6), (name, i)
+    assert info["rho_max"] == pytest.approx(rho_o, rel=1e-3)
