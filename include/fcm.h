@@ -73,7 +73,11 @@ typedef enum {
 } fcm_status;
 
 enum { FCM_GEOM_BOX_MINUS_BALLS = 0, FCM_GEOM_BALL_INTERIOR = 1 };
-enum { FCM_FP64 = 0, FCM_MIXED = 1 };           /* V-cycle precision           */
+/* V-cycle precision.  FCM_MIXED streams FP32 copies of the Schwarz inverses
+ * (those whose Jacobi-scaled condition number is at most 1e5) and forms the
+ * patch class products on the FP32 matrix cores; level vectors, residuals,
+ * the coarse solve and the outer CG stay FP64.                              */
+enum { FCM_FP64 = 0, FCM_MIXED = 1 };
 enum { FCM_SMOOTH_ELEMENTWISE = 0, FCM_SMOOTH_PATCHWISE = 1 };  /* Schwarz blocks */
 
 typedef struct fcm_handle fcm_handle;
@@ -127,7 +131,7 @@ typedef struct {
   double omega;               /* relaxation (Section 3.3.2): elementwise 1/3 (2D),
                                  2/15 (3D); patchwise 1/6 (2D), 1/18 (3D)         */
   int n_pre, n_post;          /* smoothing steps per level (5 and 5 in the paper) */
-  int precision;              /* FCM_FP64 or FCM_MIXED (FP32 V-cycle)            */
+  int precision;              /* FCM_FP64 or FCM_MIXED (FP32 smoother matrices)  */
   double rtol;                /* ||r||/||b|| stopping tolerance                  */
   int max_iter;               /* CG iteration cap (500 in the paper)             */
   int use_graphs;             /* 1: replay each CG iteration as a captured HIP
@@ -167,8 +171,9 @@ fcm_status fcm_rhs(fcm_handle *h, double *b_dev, void *stream);
 fcm_status fcm_apply(fcm_handle *h, int level, const double *x, double *y,
                      void *stream);
 
-/* z = M_l^{-1} r (FP64), the elementwise additive Schwarz operator of level
- * l >= 1 (eq. AdditiveSchwarz), without the relaxation factor.              */
+/* z = M_l^{-1} r (FP64), the additive Schwarz operator of level l >= 1 (eq.
+ * AdditiveSchwarz) with the handle's blocks (elementwise or patchwise), in
+ * FP64 arithmetic from the FP64 inverses, without the relaxation factor.    */
 fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z,
                       void *stream);
 
@@ -186,7 +191,7 @@ fcm_status fcm_coarse_solve(fcm_handle *h, const double *b, double *x,
                             void *stream);
 
 /* z = V(0, r): one V-cycle of Alg. 1 on the fine level with zero initial
- * guess, in the handle's precision (FP64, or FP32 with an FP64 coarse solve).
+ * guess, in the handle's precision (FCM_MIXED: FP32 smoother matrices).
  * r and z are fine-level FP64 vectors.                                      */
 fcm_status fcm_vcycle(fcm_handle *h, const double *r_dev, double *z_dev,
                       void *stream);
@@ -227,7 +232,7 @@ typedef struct {
   int64_t n_elements, n_kept, n_cut, n_unique_blocks, n_shared_classes;
   int64_t device_bytes;
   int coarse_blocks, coarse_block_size;
-  int64_t n_fp64_blocks;      /* Schwarz blocks kept in FP64 in the FP32 V-cycle */
+  int64_t n_fp64_blocks;      /* unique Schwarz blocks applied in FP64 (mixed)   */
 } fcm_stats;
 fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s);
 

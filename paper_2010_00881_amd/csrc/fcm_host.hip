@@ -537,10 +537,8 @@ static fcm_status setup_coarse_alloc(fcm_handle *h) {
   TRY(dalloc(h, &c.Gm, nb2 * c.nblk));
   TRY(dalloc(h, &c.Fm, nb2 * c.nblk));
   TRY(dalloc(h, &c.Dst, (size_t)c.nblk * c.nb * 3 * c.no * g.nf));
-  TRY(dalloc(h, &c.xb, (size_t)g.nf * g.G));
   TRY(dalloc(h, &c.xblk, (size_t)c.nblk * c.nb));
   TRY(dalloc(h, &c.bblk, (size_t)c.nblk * c.nb));
-  TRY(dalloc(h, &c.bb, (size_t)g.nf * g.G));
   TRY(pool_alloc((void **)&h->co_scr, spd_inverse_scratch_doubles(c.nb, 1) * sizeof(double),
                  h->stream));
   return FCM_OK;
@@ -946,7 +944,9 @@ static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *d
     const size_t mm = (size_t)m * ld;
     const size_t tp = (size_t)patch_tiles(m) * 256;
     TRY(dalloc(h, &L.invS64, mm * std::max(1, ncls)));
-    if (mixed) TRY(dalloc(h, &L.invS32, mm * std::max(1, ncls)));
+    // FP32 class inverses carry a tail that the class-product kernel may read
+    // past the last row and column (values masked there)
+    if (mixed) TRY(dalloc(h, &L.invS32, mm * std::max(1, ncls) + 32 * ld + 512));
     TRY(dalloc(h, &L.invU64, tp * std::max(1, h->np_unique)));
     if (mixed) TRY(dalloc(h, &L.invU32, tp * std::max(1, h->np_unique)));
     if (nblocks > 0) {
@@ -1014,9 +1014,7 @@ static fcm_status do_setup(fcm_handle *h) {
   const size_t mm = (size_t)m * m;
   const int ncut = (int)h->h_cut.size();
   TRY(dalloc(h, &h->Kref64, mm));
-  TRY(dalloc(h, &h->Kref32, mm));
   TRY(dalloc(h, &h->Kcut64, mm * std::max(1, ncut)));
-  TRY(dalloc(h, &h->Kcut32, mm * std::max(1, ncut)));
   TRY(dalloc(h, &h->be, (size_t)g.E * m));
   FCM_HIP(hipMemsetAsync(h->be, 0, (size_t)g.E * m * sizeof(double), h->stream));
   int *dcut = nullptr;
@@ -1035,8 +1033,6 @@ static fcm_status do_setup(fcm_handle *h) {
       launch_traction_rhs(g, h->tab, pr.traction_face[k], &h->prob.tvec[3 * k], h->state, h->be,
                           h->stream);
     launch_assemble_rhs(g, h->tab, h->kmat, h->be, h->b, h->stream);
-    launch_to_f32(h->Kref64, h->Kref32, (int64_t)mm, h->stream);
-    if (ncut > 0) launch_to_f32(h->Kcut64, h->Kcut32, (int64_t)(mm * ncut), h->stream);
   };
   // Schwarz inverses per level >= 1, coarse factorisation
   for (int l = 0; l <= L; ++l) TRY(build_units(h, l));
@@ -1142,12 +1138,9 @@ static fcm_status do_setup(fcm_handle *h) {
   for (int l = 0; l <= L; ++l) {
     Level &lv = h->lev[l];
     TRY(dalloc(h, &lv.x64, lv.npad));
-    TRY(dalloc(h, &lv.x32, lv.npad));
     if (l >= 1) {
       TRY(dalloc(h, &lv.r64, lv.npad));
       TRY(dalloc(h, &lv.d64, lv.npad));
-      TRY(dalloc(h, &lv.r32, lv.npad));
-      TRY(dalloc(h, &lv.d32, lv.npad));
     }
   }
   const int64_t nf = h->lev[L].npad;
@@ -1155,8 +1148,6 @@ static fcm_status do_setup(fcm_handle *h) {
   TRY(dalloc(h, &h->cg_z, nf));
   TRY(dalloc(h, &h->cg_p, nf));
   TRY(dalloc(h, &h->cg_q, nf));
-  TRY(dalloc(h, &h->vin32, nf));
-  TRY(dalloc(h, &h->vout32, nf));
   TRY(dalloc(h, &h->red, 1024));
   TRY(dalloc(h, &h->scal, 16));
   h->hscal = pinned_get();
@@ -1169,34 +1160,8 @@ static fcm_status do_setup(fcm_handle *h) {
 }
 
 // ------------------------------------------------------------- V-cycle
-template <typename T> struct Prec;
-template <> struct Prec<double> {
-  static double *x(Level &l) { return l.x64; }
-  static double *r(Level &l) { return l.r64; }
-  static double *d(Level &l) { return l.d64; }
-  static const double *invS(Level &l) { return l.invS64; }
-  static const double *invU(Level &l) { return l.invU64; }
-  static const double *Kref(fcm_handle *h) { return h->Kref64; }
-  static const double *Kcut(fcm_handle *h) { return h->Kcut64; }
-};
-template <> struct Prec<float> {
-  static float *x(Level &l) { return l.x32; }
-  static float *r(Level &l) { return l.r32; }
-  static float *d(Level &l) { return l.d32; }
-  static const float *invS(Level &l) { return l.invS32; }
-  static const float *invU(Level &l) { return l.invU32; }
-  static const float *Kref(fcm_handle *h) { return h->Kref32; }
-  static const float *Kcut(fcm_handle *h) { return h->Kcut32; }
-};
-
 static void coarse_solve_t(fcm_handle *h, const double *b, double *x, hipStream_t s) {
   coarse_solve_launch(h->geo, h->co, b, x, s);
-}
-static void coarse_solve_t(fcm_handle *h, const float *b, float *x, hipStream_t s) {
-  const int64_t n = (int64_t)h->geo.nf * h->geo.G;
-  launch_f32_to_f64(b, h->co.bb, n, s);
-  coarse_solve_launch(h->geo, h->co, h->co.bb, h->co.xb, s);
-  launch_f64_to_f32(h->co.xb, x, n, s);
 }
 
 template <typename T>
@@ -1206,9 +1171,9 @@ static OpArgs<T> stiffness_args(fcm_handle *h, int l) {
   a.nP_out = h->lev[l].nP;
   a.ld = h->tab.m;
   a.mid = h->kmat;
-  a.matS = Prec<T>::Kref(h);
+  a.matS = h->Kref64;
   a.nS = 1;
-  a.matU = Prec<T>::Kcut(h);
+  a.matU = h->Kcut64;
   a.m_out = h->lev[l].m;
   a.units = h->lev[l].units;
   a.nunits = h->lev[l].nunits;
@@ -1220,39 +1185,21 @@ static OpArgs<T> stiffness_args(fcm_handle *h, int l) {
   a.nsh = h->n_uncut;
   a.chk = h->uncut_chk;
   a.nchunks = h->n_uncut_chk;
-  set_fp64_parts<T>(h, l, a, false);
   return a;
 }
 
+// mixed: use the FP32 copies of the inverses (FCM_MIXED handles in the V-cycle)
 template <typename T>
-static void set_fp64_parts(fcm_handle *, int, OpArgs<T> &, bool) {}
-template <>
-void set_fp64_parts<float>(fcm_handle *h, int l, OpArgs<float> &a, bool smoother) {
-  if (smoother) {
-    // FP32 storage only where the block is well conditioned; all arithmetic FP64
-    a.matU64 = h->lev[l].invU64;
-    a.u64flag = h->lev[l].hi64;
-    a.matS64 = h->lev[l].invS64;
-  } else {
-    // residual of the FP32 V-cycle: FP64 entries and accumulation for every
-    // element matrix (vectors stay FP32), so that r -= omega A delta cancels
-    a.matU64 = h->Kcut64;
-    a.u64flag = nullptr;
-    a.matS64 = h->Kref64;
-  }
-}
-
-template <typename T>
-static OpArgs<T> smoother_args(fcm_handle *h, int l) {
+static OpArgs<T> smoother_args(fcm_handle *h, int l, bool mixed) {
   Level &L = h->lev[l];
   OpArgs<T> a;
   a.m_in = L.m;
   a.nP_out = L.nP;
   a.ld = L.m;
   a.mid = h->blk;
-  a.matS = Prec<T>::invS(L);
+  a.matS = L.invS64;
   a.nS = h->n_shared;
-  a.matU = Prec<T>::invU(L);
+  a.matU = L.invU64;
   a.m_out = L.m;
   a.units = L.units;
   a.nunits = L.nunits;
@@ -1264,12 +1211,17 @@ static OpArgs<T> smoother_args(fcm_handle *h, int l) {
   a.nsh = h->n_classed;
   a.chk = h->class_chk;
   a.nchunks = h->n_class_chk;
-  set_fp64_parts<T>(h, l, a, true);
+  if (mixed) {
+    // FP32 copies of the well-conditioned unique inverses; class inverses and
+    // all arithmetic in FP64
+    a.matU32 = L.invU32;
+    a.u64flag = L.hi64;
+  }
   return a;
 }
 
 template <typename T>
-static PatchArgs<T> patch_args(fcm_handle *h, int l) {
+static PatchArgs<T> patch_args(fcm_handle *h, int l, bool mixed) {
   Level &L = h->lev[l];
   PatchArgs<T> a;
   a.m = L.mpatch;
@@ -1287,11 +1239,11 @@ static PatchArgs<T> patch_args(fcm_handle *h, int l) {
   a.nsh = h->np_shared;
   a.npu = h->np_unique;
   a.matS64 = L.invS64;
-  a.matU = Prec<T>::invU(L);
-  if (std::is_same<T, float>::value) {
+  a.matU = L.invU64;
+  if (mixed) {
     // FP32 storage where the block is well conditioned, FP64 otherwise; class
     // (uncut) inverses in FP32 on the FP32 matrix cores
-    a.matU64 = L.invU64;
+    a.matU32 = L.invU32;
     a.u64flag = L.hi64;
     a.matS32 = L.invS32;
   }
@@ -1300,12 +1252,14 @@ static PatchArgs<T> patch_args(fcm_handle *h, int l) {
   return a;
 }
 
-// out = M_l^{-1} x; if xs: xs = (first ? 0 : xs) + omega * out.
+// out = M_l^{-1} x; if xs: xs = (first ? 0 : xs) + omega * out.  fp64: use
+// the FP64 inverses even in a mixed-form handle.
 template <typename T>
 static void smooth_launch(fcm_handle *h, int l, const T *x, T *out, T *xs, T omega, int first,
-                          hipStream_t s, bool stored_only = false) {
+                          hipStream_t s, bool stored_only = false, bool fp64 = false) {
+  const bool mixed = h->opt.precision == FCM_MIXED && !fp64;
   if (h->opt.smoother == FCM_SMOOTH_PATCHWISE) {
-    PatchArgs<T> a = patch_args<T>(h, l);
+    PatchArgs<T> a = patch_args<T>(h, l, mixed);
     a.stored_only = stored_only;
     a.x = x;
     a.out = out;
@@ -1315,7 +1269,7 @@ static void smooth_launch(fcm_handle *h, int l, const T *x, T *out, T *xs, T ome
     launch_patch_op<T>(h->geo, h->tab, h->ptab, a, s);
     return;
   }
-  OpArgs<T> a = smoother_args<T>(h, l);
+  OpArgs<T> a = smoother_args<T>(h, l, mixed);
   a.x = x;
   a.out = out;
   a.xs = xs;
@@ -1334,7 +1288,7 @@ static void vcycle_level(fcm_handle *h, int l, const T *b, T *x, hipStream_t s) 
   }
   const Geo &g = h->geo;
   Level &L = h->lev[l];
-  T *r = Prec<T>::r(L), *dl = Prec<T>::d(L);
+  T *r = L.r64, *dl = L.d64;
   const T w = (T)h->opt.omega;
   OpArgs<T> ap = stiffness_args<T>(h, l);
   ap.x = dl;
@@ -1352,7 +1306,7 @@ static void vcycle_level(fcm_handle *h, int l, const T *b, T *x, hipStream_t s) 
   }
   // coarse-grid correction: b_{l-1} = R r (prefix), x += R^T e, r -= A R^T e
   Level &Lc = h->lev[l - 1];
-  T *e = Prec<T>::x(Lc);
+  T *e = Lc.x64;
   vcycle_level<T>(h, l - 1, r, e, s);
   OpArgs<T> pr = stiffness_args<T>(h, l);
   pr.x = e;
@@ -1379,15 +1333,9 @@ static void vcycle_top(fcm_handle *h, const double *r, double *z, hipStream_t s)
     coarse_solve_launch(h->geo, h->co, r, z, s);
     return;
   }
-  if (h->opt.precision == FCM_FP64) {
-    vcycle_level<double>(h, L, r, z, s);
-  } else {
-    // FP32 V-cycle inside the FP64 iteration: cast at entry and exit
-    Level &lv = h->lev[L];
-    launch_f64_to_f32(r, h->vin32, lv.npad, s);
-    vcycle_level<float>(h, L, h->vin32, h->vout32, s);
-    launch_f32_to_f64(h->vout32, z, lv.npad, s);
-  }
+  // both forms keep the level vectors in FP64; the mixed form streams FP32
+  // copies of the smoother's inverses (smoother_args, patch_args)
+  vcycle_level<double>(h, L, r, z, s);
 }
 
 static void apply_fine64(fcm_handle *h, int l, const double *x, double *y, hipStream_t s) {
@@ -1858,7 +1806,7 @@ fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z, void
     set_error("invalid argument");
     return FCM_ERR_ARG;
   }
-  smooth_launch<double>(h, level, r, z, nullptr, 1.0, 0, (hipStream_t)stream);
+  smooth_launch<double>(h, level, r, z, nullptr, 1.0, 0, (hipStream_t)stream, false, true);
   FCM_HIP(hipGetLastError());
   return FCM_OK;
 }
@@ -2005,10 +1953,12 @@ fcm_status fcm_mg_solve(fcm_handle *h, const double *b_dev, double *x_dev, fcm_s
   return st;
 }
 
-// Algorithmic bytes of one smoother / residual launch on level l.
+// Algorithmic bytes of one smoother / residual launch on level l.  Level
+// vectors are FP64 in both forms; the mixed form streams FP32 copies of the
+// well-conditioned unique inverses (and of the patch class inverses).
 static double op_bytes(const fcm_handle *h, int op, int l) {
   const bool mixed = h->opt.precision == FCM_MIXED;
-  const double sv = mixed ? 4.0 : 8.0;
+  const double sm = mixed ? 4.0 : 8.0;
   const fcm::Level &L = h->lev[l];
   const double mm = (double)L.m * L.m;
   const double E = h->geo.E;
@@ -2019,30 +1969,31 @@ static double op_bytes(const fcm_handle *h, int op, int l) {
     const double pm2 = (double)L.mpatch * L.mpatch;
     const double ps2 = 0.5 * L.mpatch * (L.mpatch + 1.0);
     const double nhi = mixed ? L.n_hi64 : 0;
-    const double mats = (h->np_unique - nhi) * ps2 * sv + nhi * ps2 * 8.0 +
-                        (double)h->np_classes * pm2 * 8.0;
-    return 4.0 * L.npad * sv + mats;
+    const double mats = (h->np_unique - nhi) * ps2 * sm + nhi * ps2 * 8.0 +
+                        (double)h->np_classes * pm2 * sm;
+    return 4.0 * L.npad * 8.0 + mats;
   }
   if (op == FCM_OP_SMOOTH) {
-    double nhi = mixed ? L.n_hi64 : 0;
-    double mats = (h->n_shared + h->n_unique - nhi) * mm * sv + nhi * mm * 8.0;
-    return 4.0 * L.npad * sv + mats + 4.0 * E;
+    // class inverses FP64 in both forms
+    const double nhi = mixed ? L.n_hi64 : 0;
+    const double mats = (h->n_unique - nhi) * mm * sm + nhi * mm * 8.0 + h->n_shared * mm * 8.0;
+    return 4.0 * L.npad * 8.0 + mats + 4.0 * E;
   }
-  // residual update: delta, r read, r written; cut matrices (FP64 when mixed)
-  double mats = (double)h->h_cut.size() * mm * 8.0 / (mixed ? 1.0 : 1.0) + mm * sv;
-  return 3.0 * L.npad * sv + mats + 4.0 * E;
+  // residual update: delta, r read, r written; FP64 element matrices
+  const double mats = ((double)h->h_cut.size() + 1.0) * mm * 8.0;
+  return 3.0 * L.npad * 8.0 + mats + 4.0 * E;
 }
 
 // Unique-patch GEMV: every symmetric inverse (m (m + 1) / 2 numbers) streamed
-// once (FP64 where flagged), the gathered inputs read once, the FP64 products
-// written once.
+// once (FP64 where flagged), the gathered FP64 inputs read once, the FP64
+// products written once.
 static double stored_bytes(const fcm_handle *h, int l) {
   const bool mixed = h->opt.precision == FCM_MIXED;
   const fcm::Level &L = h->lev[l];
   const double ps2 = 0.5 * L.mpatch * (L.mpatch + 1.0);
   const double nhi = mixed ? L.n_hi64 : h->np_unique;
   const double mats = (h->np_unique - nhi) * ps2 * 4.0 + nhi * ps2 * 8.0;
-  return mats + (double)h->np_unique * L.mpatch * ((mixed ? 4.0 : 8.0) + 8.0);
+  return mats + (double)h->np_unique * L.mpatch * 16.0;
 }
 
 static double coarse_bytes(const fcm_handle *h) {
@@ -2067,7 +2018,6 @@ fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
     return FCM_ERR_ARG;
   }
   hipStream_t s = (hipStream_t)stream;
-  const bool mixed = h->opt.precision == FCM_MIXED;
   hipEvent_t e0, e1;
   FCM_HIP(hipEventCreate(&e0));
   FCM_HIP(hipEventCreate(&e1));
@@ -2076,31 +2026,14 @@ fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
     if (op == FCM_OP_SMOOTH || op == FCM_OP_RESIDUAL || op == FCM_OP_SMOOTH_STORED) {
       fcm::Level &L = h->lev[level];
       if (op == FCM_OP_SMOOTH) {
-        if (mixed)
-          smooth_launch<float>(h, level, L.r32, L.d32, L.x32, (float)h->opt.omega, 0, s);
-        else
-          smooth_launch<double>(h, level, L.r64, L.d64, L.x64, h->opt.omega, 0, s);
+        smooth_launch<double>(h, level, L.r64, L.d64, L.x64, h->opt.omega, 0, s);
       } else if (op == FCM_OP_SMOOTH_STORED) {
-        if (mixed)
-          smooth_launch<float>(h, level, L.r32, L.d32, L.x32, (float)h->opt.omega, 0, s, true);
-        else
-          smooth_launch<double>(h, level, L.r64, L.d64, L.x64, h->opt.omega, 0, s, true);
-      } else if (mixed) {
-        OpArgs<float> a = op == FCM_OP_SMOOTH ? smoother_args<float>(h, level)
-                                              : stiffness_args<float>(h, level);
-        a.x = op == FCM_OP_SMOOTH ? L.r32 : L.d32;
-        a.out = op == FCM_OP_SMOOTH ? L.d32 : L.r32;
-        if (op == FCM_OP_SMOOTH) {
-          a.xs = L.x32;
-          a.omega = (float)h->opt.omega;
-        } else {
-          a.cvec = L.r32;
-          a.scale = -(float)h->opt.omega;
-        }
-        launch_elem_op<float>(h->geo, h->tab, a, s);
+        smooth_launch<double>(h, level, L.r64, L.d64, L.x64, h->opt.omega, 0, s, true);
       } else {
-        OpArgs<double> a = op == FCM_OP_SMOOTH ? smoother_args<double>(h, level)
-                                               : stiffness_args<double>(h, level);
+        OpArgs<double> a = op == FCM_OP_SMOOTH
+                               ? smoother_args<double>(h, level,
+                                                       h->opt.precision == FCM_MIXED)
+                               : stiffness_args<double>(h, level);
         a.x = op == FCM_OP_SMOOTH ? L.r64 : L.d64;
         a.out = op == FCM_OP_SMOOTH ? L.d64 : L.r64;
         if (op == FCM_OP_SMOOTH) {

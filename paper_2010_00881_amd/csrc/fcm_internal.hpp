@@ -57,13 +57,12 @@ struct Level {
   int64_t npad = 0, ndofs = 0;
   double *invS64 = nullptr, *invU64 = nullptr;
   float *invS32 = nullptr, *invU32 = nullptr;
-  uint8_t *hi64 = nullptr;     // unique blocks applied in FP64 inside the FP32 V-cycle
+  uint8_t *hi64 = nullptr;     // unique blocks applied from FP64 copies in the mixed form
   int n_hi64 = 0;
   int ldp = 0;                 // patchwise: leading dimension of the stored inverses
   int *units = nullptr;        // owner-kernel work units of this level
   int nunits = 0;
   double *x64 = nullptr, *r64 = nullptr, *d64 = nullptr;
-  float *x32 = nullptr, *r32 = nullptr, *d32 = nullptr;
 };
 
 struct Coarse {
@@ -156,11 +155,9 @@ struct fcm_handle {
   double *Yscr = nullptr;                     // stored-matrix products (scratch)
   double *Yshr = nullptr;                     // shared-matrix element products (scratch)
   double *Kref64 = nullptr, *Kcut64 = nullptr, *be = nullptr, *b = nullptr;
-  float *Kref32 = nullptr, *Kcut32 = nullptr;
   fcm::Coarse co;
   // CG work vectors (fine level, FP64) and reduction scratch
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
-  float *vin32 = nullptr, *vout32 = nullptr;  // FP32 V-cycle input/output (fine level)
   double *red = nullptr;                      // partial sums
   double *scal = nullptr;                     // device scalars
   double *hscal = nullptr;                    // pinned host mirror
@@ -262,8 +259,8 @@ struct OpArgs {
   const double *matS64 = nullptr;  // FP64 shared matrices and FP64 accumulation (optional)
   int nS = 0;
   const T *matU = nullptr;    // stored matrices (id - nS)
-  const double *matU64 = nullptr;   // FP32 operator only: FP64 copies of stored matrices,
-  const uint8_t *u64flag = nullptr; //   used for all of them (flag null) or where flag != 0
+  const float *matU32 = nullptr;    // mixed-form smoother: FP32 copies of the stored
+  const uint8_t *u64flag = nullptr; //   matrices, used where u64flag is null or 0
   int m_out = 0;              // rows of the operator (local modes of the output level)
   const int *units = nullptr; // [nunits][12]: vmask, comp, count, planes[8], pad
   int nunits = 0;
@@ -302,12 +299,12 @@ struct PatchArgs {
   const unsigned *cpres = nullptr; // [classes][pwords] mode presence bits per class
   int pwords = 0;
   const double *matS64 = nullptr; // [classes][m][ld]
-  const float *matS32 = nullptr;  // FP32 V-cycle: FP32 class inverses (matrix-core FP32 path)
-  const T *matU = nullptr;        // [npu][tiles][16][16]: symmetric unique inverses, the 16 x 16
+  const float *matS32 = nullptr;  // mixed form: FP32 class inverses (FP32 matrix-core path)
+  const double *matU = nullptr;   // [npu][tiles][16][16]: symmetric unique inverses, the 16 x 16
                                   // tiles on and above the diagonal, I-major
-  const double *matU64 = nullptr; // FP32 V-cycle: FP64 unique inverses where u64flag != 0
+  const float *matU32 = nullptr;  // mixed form: FP32 copies of the unique inverses, used where
+  const uint8_t *u64flag = nullptr; //   u64flag is null or 0 (matU otherwise)
   int ntile = 0;                  // tiles per row of a unique inverse: ceil(m / 16)
-  const uint8_t *u64flag = nullptr;
   double *Ys = nullptr;           // [m][nsh]
   double *Yu = nullptr;           // [npu][m]
   T *out = nullptr;
@@ -343,11 +340,9 @@ void launch_cg_beta(double *scal, int flexible, hipStream_t s);
 void launch_cg_update_p(double *p, const double *z, const double *scal, int64_t n, int first,
                         hipStream_t s);
 void launch_axpby(double *y, const double *x, double a, double b, int64_t n, hipStream_t s);
-void launch_f64_to_f32(const double *x, float *y, int64_t n, hipStream_t s);
 // y = x (x null: y = 0); a kernel, so that it may sit inside a captured graph
 template <typename T>
 void launch_copy(T *y, const T *x, int64_t n, hipStream_t s);
-void launch_f32_to_f64(const float *x, double *y, int64_t n, hipStream_t s);
 
 // Resumable PCG used by fcm_pcg_solve and the server (fcm_host.hip).
 struct CGState {

@@ -335,13 +335,13 @@ __global__ __launch_bounds__(256) void patch_gemv_kernel(Geo g, const int *__res
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const size_t base = (size_t)u * ntiles * 256;
-  const bool hi = a.matU64 && (!a.u64flag || a.u64flag[u]);
-  if (hi)
-    tile_sweep<double>(a.matU64 + base, ntiles, tI, tJ, xs, tbuf[wave], yw[2 * wave],
-                       yw[2 * wave + 1], wave, lane);
+  const bool lo = a.matU32 && !(a.u64flag && a.u64flag[u]);
+  if (lo)
+    tile_sweep<float>(a.matU32 + base, ntiles, tI, tJ, xs, tbuf[wave], yw[2 * wave],
+                      yw[2 * wave + 1], wave, lane);
   else
-    tile_sweep<T>(a.matU + base, ntiles, tI, tJ, xs, tbuf[wave], yw[2 * wave], yw[2 * wave + 1],
-                  wave, lane);
+    tile_sweep<double>(a.matU + base, ntiles, tI, tJ, xs, tbuf[wave], yw[2 * wave],
+                       yw[2 * wave + 1], wave, lane);
   __syncthreads();
   for (int k = threadIdx.x; k < m; k += 256) {
     double y = 0.0;
@@ -440,18 +440,18 @@ __global__ __launch_bounds__(512) void patch_class_mfma_kernel(Geo g,
   }
 }
 
-// FP32 variant for the FP32 V-cycle, used for small blocks (m <= 32; larger
+// FP32 variant for the mixed form, used for small blocks (m <= 32; larger
 // ones go to patch_class_tile32_kernel): class inverses are well conditioned
-// (uncut patches), so their products use v_mfma_f32_16x16x4f32 (FP32 inputs,
-// FP32 accumulation; lane l supplies A[l%16][l/16] and B[l/16][l%16] and holds
-// D[4(l/16)+j][l%16]).  Half-width registers leave room for the next group's
-// prefetch and two accumulation chains.
+// (uncut patches), so their products use v_mfma_f32_16x16x4f32 (inputs
+// rounded to FP32, FP32 accumulation; lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] and holds D[4(l/16)+j][l%16]).  Half-width registers leave
+// room for the next group's prefetch and two accumulation chains.
 typedef float floatx4p __attribute__((ext_vector_type(4)));
 
-template <int NKS>
+template <typename T, int NKS>
 __global__ __launch_bounds__(512) void patch_class_mfma32_kernel(Geo g,
                                                                  const int *__restrict__ pxoff,
-                                                                 PatchArgs<float> a) {
+                                                                 PatchArgs<T> a) {
   extern __shared__ float Xf[];   // [NKS * 4][16]
   constexpr int KP = NKS * 4;
   constexpr int PER = NKS / 8;
@@ -486,7 +486,7 @@ __global__ __launch_bounds__(512) void patch_class_mfma32_kernel(Geo g,
       const int nn = i & 15, k = i >> 4;
       float v = 0.f;
       if (nn < qn && k < m && ((pres[k >> 5] >> (k & 31)) & 1u))
-        v = a.x[a.pnode[q0 + nn] + pxoff[k]];
+        v = (float)a.x[a.pnode[q0 + nn] + pxoff[k]];
       pf[j] = v;
     }
   };
@@ -521,18 +521,24 @@ __global__ __launch_bounds__(512) void patch_class_mfma32_kernel(Geo g,
 // patches of one class, Y[:, q0:q0+64] = A_c X, streaming both operands
 // through LDS in slices of 32 k (A_c from L2, X gathered once per patch) and
 // prefetching the next slice into registers while the matrix cores work on
-// the current one: threads below 128 NRT fetch the A slice (row r = thread,
-// 32 k), waves 6 and 7 the X slice.  Wave w owns row tiles w, w + 8, ..,
+// the current one.  Every thread fetches an equal share of both slices: rows
+// tid % 128 + 128 i and k rows tid / 128 + 4 j of the A slice (coalesced
+// over rows; the class inverses are allocated with a tail of 32 ld + 512
+// floats, so the reads past row or column m need no clamp and are masked when
+// stored) and X rows wave + 8 j (lane = patch).  X stays in its storage type
+// (FP64 level vectors) while the load is in flight and is rounded to FP32
+// when the slice is stored to LDS.  Wave w owns row tiles w, w + 8, ..,
 // w + 8 (NRT - 1) and all four 16-patch column tiles.  LDS rows are padded to
 // 16 mod 32 floats so that the four k rows a v_mfma_f32_16x16x4f32 operand
 // read touches fall in distinct banks.
 static_assert(kMaxPatchM <= 384, "class tile kernel covers at most 24 row tiles");
 constexpr int kCT_XS = 64 + 16;    // X slice row stride (floats)
 
-template <int NRT>
+template <typename T, int NRT>
 __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *__restrict__ pxoff,
-                                                                    PatchArgs<float> a) {
+                                                                    PatchArgs<T> a) {
   constexpr int ROWS = 128 * NRT, RS = ROWS + 16;
+  constexpr int NA = 8 * NRT;          // A entries per thread per slice (32 ROWS / 512)
   __shared__ float As[32 * RS];
   __shared__ float Xs[32 * kCT_XS];
   __shared__ int koff[384];            // offset of mode k from the patch node in x
@@ -549,58 +555,55 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
   const int m = a.m, ld = a.ld;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n = lane & 15, kq = lane >> 4;
-  const bool fa = tid < ROWS;          // wave-uniform role in the slice fetch
-  const float *A0 = a.matS32 + (size_t)c * m * ld + min(tid, m - 1);
-  const bool rv = tid < m;
+  const int ar = tid & 127, ak = tid >> 7;
+  const float *Ab = a.matS32 + (size_t)c * m * ld + (size_t)ak * ld + ar;
   const unsigned *pres = a.cpres + (size_t)c * a.pwords;
-  const bool fx = wave >= 6;
-  const int pn = fx ? a.pnode[q0 + min(lane, qn - 1)] : 0;
-  const int kx = wave - 6;             // X rows kx, kx + 2, ... of the slice
+  const int pn = a.pnode[q0 + min(lane, qn - 1)];
   // Every load below is issued unconditionally from a clamped, valid address
   // (a load under a branch makes the compiler wait for it before the
   // branches join, one memory latency per element), and the raw values are
   // masked only when the slice is stored to LDS, one trip later: masking
   // right after the loads would wait for them before the matrix-core work.
-  float pf[32];
+  float pa[NA];
+  T px[4];
   auto fetch = [&](int k0) {
-    if (fa) {
+    const float *Ak = Ab + (size_t)k0 * ld;   // A[r][k] = A[k][r]: row k of the slice
 #pragma unroll
-      for (int e = 0; e < 32; ++e)     // A[r][k] = A0[k * ld + r], r = tid
-        pf[e] = A0[(size_t)(min(k0 + e, m - 1)) * ld];
-    } else if (fx) {
+    for (int j = 0; j < 8; ++j)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int kc = min(k0 + kx + 2 * e, m - 1);
-        pf[e] = a.x[min(max(pn + koff[kc], 0), a.xlen - 1)];
-      }
-    }
+      for (int i = 0; i < NRT; ++i) pa[j * NRT + i] = Ak[(size_t)(4 * j) * ld + 128 * i];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      px[j] = a.x[min(max(pn + koff[k0 + wave + 8 * j], 0), a.xlen - 1)];
   };
   floatx4p acc[NRT][4];
 #pragma unroll
   for (int i = 0; i < NRT; ++i)
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[i][t] = floatx4p{0.f, 0.f, 0.f, 0.f};
-  for (int k = tid; k < m; k += 512) {
-    koff[k] = pxoff[k];
-    kmask[k] = ((pres[k >> 5] >> (k & 31)) & 1u) ? 1.f : 0.f;
+  for (int k = tid; k < 384; k += 512) {
+    koff[k] = k < m ? pxoff[k] : 0;
+    kmask[k] = k < m && ((pres[k >> 5] >> (k & 31)) & 1u) ? 1.f : 0.f;
   }
   __syncthreads();
   const int nslice = (m + 31) >> 5;
   fetch(0);
   for (int sl = 0; sl < nslice; ++sl) {
     const int k0 = 32 * sl;
-    if (fa) {
 #pragma unroll
-      for (int e = 0; e < 32; ++e) As[e * RS + tid] = (rv & (k0 + e < m)) ? pf[e] : 0.f;
-    } else if (fx) {
-      // absent modes and missing patches are scaled by 0 (not selected: a
-      // select on a loaded value would be turned back into a branch)
+    for (int j = 0; j < 8; ++j)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int k = k0 + kx + 2 * e;
-        const float mk = ((lane < qn) & (k < m)) ? kmask[min(k, m - 1)] : 0.f;
-        Xs[(kx + 2 * e) * kCT_XS + lane] = pf[e] * mk;
+      for (int i = 0; i < NRT; ++i) {
+        const int k = ak + 4 * j, r = ar + 128 * i;
+        As[k * RS + r] = ((r < m) & (k0 + k < m)) ? pa[j * NRT + i] : 0.f;
       }
+    // absent modes and missing patches are scaled by 0 (not selected: a
+    // select on a loaded value would be turned back into a branch)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int kr = wave + 8 * j, k = k0 + kr;
+      const float mk = lane < qn ? kmask[k] : 0.f;
+      Xs[kr * kCT_XS + lane] = (float)px[j] * mk;
     }
     __syncthreads();
     if (sl + 1 < nslice) fetch(32 * (sl + 1));
@@ -634,25 +637,25 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
     }
 }
 
-template <int NKS>
-static void launch_class32_nks(const Geo &g, const PatchTables &pt, const PatchArgs<float> &a,
+template <typename T, int NKS>
+static void launch_class32_nks(const Geo &g, const PatchTables &pt, const PatchArgs<T> &a,
                                hipStream_t s) {
   const int nrt = (a.m + 15) / 16;
   dim3 grid((nrt + 7) / 8, a.nchunks);
-  patch_class_mfma32_kernel<NKS><<<grid, 512, (size_t)NKS * 4 * 16 * sizeof(float), s>>>(
+  patch_class_mfma32_kernel<T, NKS><<<grid, 512, (size_t)NKS * 4 * 16 * sizeof(float), s>>>(
       g, pt.pxoff, a);
 }
 
-static bool launch_class32(const Geo &g, const PatchTables &pt, const PatchArgs<float> &a,
+template <typename T>
+static bool launch_class32(const Geo &g, const PatchTables &pt, const PatchArgs<T> &a,
                            hipStream_t s) {
   if (!a.matS32) return false;
-  const int nks = (a.m + 3) / 4;
   // chunks hold <= 256 patches (four quarters of 64); m <= kMaxPatchM = 384
   const dim3 grid(4 * ((a.nchunks + 7) / 8 * 8));
-  if (a.m > 256) patch_class_tile32_kernel<3><<<grid, 512, 0, s>>>(pt.pxoff, a);
-  else if (a.m > 128) patch_class_tile32_kernel<2><<<grid, 512, 0, s>>>(pt.pxoff, a);
-  else if (a.m > 32) patch_class_tile32_kernel<1><<<grid, 512, 0, s>>>(pt.pxoff, a);
-  else launch_class32_nks<8>(g, pt, a, s);   // nks <= 8
+  if (a.m > 256) patch_class_tile32_kernel<T, 3><<<grid, 512, 0, s>>>(pt.pxoff, a);
+  else if (a.m > 128) patch_class_tile32_kernel<T, 2><<<grid, 512, 0, s>>>(pt.pxoff, a);
+  else if (a.m > 32) patch_class_tile32_kernel<T, 1><<<grid, 512, 0, s>>>(pt.pxoff, a);
+  else launch_class32_nks<T, 8>(g, pt, a, s);   // nks <= 8
   return true;
 }
 
@@ -749,16 +752,12 @@ void launch_patch_op(const Geo &g, const Tables &t, const PatchTables &pt, const
   if (a.npu > 0) patch_gemv_kernel<T><<<a.npu, 256, 0, s>>>(g, pt.pxoff, pt.pinfo, a);
   if (a.stored_only) return;
   if (a.nsh > 0 && a.nchunks > 0) {
-    bool done = false;
-    if constexpr (std::is_same<T, float>::value) done = launch_class32(g, pt, a, s);
-    if (!done) launch_class<T>(g, pt, a, s);
+    if (!launch_class32<T>(g, pt, a, s)) launch_class<T>(g, pt, a, s);
   }
   dim3 grid((g.G + 255) / 256, a.nP_out);
   patch_gather_kernel<T><<<grid, 256, 0, s>>>(g, pt.prow, t.pinfo, a);
 }
 template void launch_patch_op<double>(const Geo &, const Tables &, const PatchTables &,
                                       const PatchArgs<double> &, hipStream_t);
-template void launch_patch_op<float>(const Geo &, const Tables &, const PatchTables &,
-                                     const PatchArgs<float> &, hipStream_t);
 
 }  // namespace fcm

@@ -25,8 +25,26 @@ namespace fcm {
 // Phase A: stored matrices (cut stiffness, unique Schwarz inverses).  One wave
 // per matrix streams it row by row with lanes over the output index (the
 // matrices are symmetric, so row b holds column b contiguously) and writes
-// Y[sid][a] = sum_b M[a][b] x_e[b] in FP64.  FP64 copies are used where the
-// FP32 operator must not round (see set_fp64_parts in the host code).
+// Y[sid][a] = sum_b M[a][b] x_e[b] in FP64.  In the mixed form the smoother
+// streams FP32 copies of the well-conditioned inverses (matU32).
+template <typename M>
+__device__ inline void stored_rows(const M *Mb, int ld, int m_in, const double *xw, int row,
+                                   double &out) {
+  double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+  const M *Mr = Mb + row;
+  int b = 0;
+  // 16 independent coalesced loads in flight per lane (lanes = rows)
+#pragma unroll 4
+  for (; b + 3 < m_in; b += 4) {
+    c0 += (double)Mr[(size_t)b * ld] * xw[b];
+    c1 += (double)Mr[(size_t)(b + 1) * ld] * xw[b + 1];
+    c2 += (double)Mr[(size_t)(b + 2) * ld] * xw[b + 2];
+    c3 += (double)Mr[(size_t)(b + 3) * ld] * xw[b + 3];
+  }
+  for (; b < m_in; ++b) c0 += (double)Mr[(size_t)b * ld] * xw[b];
+  out = (c0 + c1) + (c2 + c3);
+}
+
 template <typename T>
 __device__ void stored_gemv_wg(Geo g, const int *__restrict__ xoff, OpArgs<T> a, int wg,
                                double *scratch) {
@@ -43,36 +61,18 @@ __device__ void stored_gemv_wg(Geo g, const int *__restrict__ xoff, OpArgs<T> a,
   __syncthreads();
   if (!active) return;
   const int ld = a.ld;
-  const bool hi = a.matU64 && (!a.u64flag || a.u64flag[sid]);
+  const bool lo = a.matU32 && !(a.u64flag && a.u64flag[sid]);
+  const size_t off = (size_t)sid * ld * ld;
   const double *xw = xs[wave];
   for (int a0 = 0; a0 < a.m_out; a0 += 64) {
     const int row = a0 + lane;
     if (row >= a.m_out) break;
-    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-    int b = 0;
-    // 16 independent coalesced loads in flight per lane (lanes = rows)
-    if (hi) {
-      const double *M = a.matU64 + (size_t)sid * ld * ld + row;
-#pragma unroll 4
-      for (; b + 3 < a.m_in; b += 4) {
-        c0 += M[(size_t)b * ld] * xw[b];
-        c1 += M[(size_t)(b + 1) * ld] * xw[b + 1];
-        c2 += M[(size_t)(b + 2) * ld] * xw[b + 2];
-        c3 += M[(size_t)(b + 3) * ld] * xw[b + 3];
-      }
-      for (; b < a.m_in; ++b) c0 += M[(size_t)b * ld] * xw[b];
-    } else {
-      const T *M = a.matU + (size_t)sid * ld * ld + row;
-#pragma unroll 4
-      for (; b + 3 < a.m_in; b += 4) {
-        c0 += (double)M[(size_t)b * ld] * xw[b];
-        c1 += (double)M[(size_t)(b + 1) * ld] * xw[b + 1];
-        c2 += (double)M[(size_t)(b + 2) * ld] * xw[b + 2];
-        c3 += (double)M[(size_t)(b + 3) * ld] * xw[b + 3];
-      }
-      for (; b < a.m_in; ++b) c0 += (double)M[(size_t)b * ld] * xw[b];
-    }
-    a.Y[(size_t)sid * a.m_out + row] = (c0 + c1) + (c2 + c3);
+    double y;
+    if (lo)
+      stored_rows<float>(a.matU32 + off, ld, a.m_in, xw, row, y);
+    else
+      stored_rows<T>(a.matU + off, ld, a.m_in, xw, row, y);
+    a.Y[(size_t)sid * a.m_out + row] = y;
   }
 }
 
@@ -411,8 +411,6 @@ void launch_elem_op(const Geo &g, const Tables &t, const OpArgs<T> &a, hipStream
 }
 template void launch_elem_op<double>(const Geo &, const Tables &, const OpArgs<double> &,
                                      hipStream_t);
-template void launch_elem_op<float>(const Geo &, const Tables &, const OpArgs<float> &,
-                                    hipStream_t);
 
 // ------------------------------------------------------------------ vectors
 constexpr int kRedThreads = 256;
@@ -540,26 +538,7 @@ void launch_copy(T *y, const T *x, int64_t n, hipStream_t s) {
   copy_kernel<T><<<blocks, 256, 0, s>>>(y, x, n);
 }
 template void launch_copy<double>(double *, const double *, int64_t, hipStream_t);
-template void launch_copy<float>(float *, const float *, int64_t, hipStream_t);
 
-__global__ void f64_to_f32_kernel(const double *x, float *y, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = (float)x[i];
-}
-__global__ void f32_to_f64_kernel(const float *x, double *y, int64_t n) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = (double)x[i];
-}
-void launch_f64_to_f32(const double *x, float *y, int64_t n, hipStream_t s) {
-  int blocks = (int)std::min<int64_t>((n + 255) / 256, 2048);
-  f64_to_f32_kernel<<<blocks, 256, 0, s>>>(x, y, n);
-}
-void launch_f32_to_f64(const float *x, double *y, int64_t n, hipStream_t s) {
-  int blocks = (int)std::min<int64_t>((n + 255) / 256, 2048);
-  f32_to_f64_kernel<<<blocks, 256, 0, s>>>(x, y, n);
-}
 
 // ------------------------------------------------------------------ coarse
 // Block-local row i of block k -> index in the level-0 padded vector, or -1.
