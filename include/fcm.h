@@ -186,6 +186,19 @@ fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z,
 fcm_status fcm_spd_inverse(double *A_dev, int n, int batch, double *kappa_dev,
                            void *stream);
 
+/* fcm_spd_inverse for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, kernels and results, but the sweep's scratch and pivot flag
+ * live in a static device buffer of 4 Mi doubles (32 MiB) that each GPU the
+ * library runs on holds until the process ends; no hipMalloc, hipFree or
+ * allocating library call is made.  Needs 2*32*n + n + 2 doubles per matrix
+ * (at most 4,194,272 in total); larger requests return FCM_ERR_ARG with
+ * nothing launched.  Calls on one GPU share its buffer: calls that overlap on
+ * one GPU (several streams or threads) race and must be serialised by the
+ * caller.  Synchronises the stream; FCM_ERR_NOT_SPD as fcm_spd_inverse.    */
+fcm_status fcm_spd_inverse_noalloc(double *A_dev, int n, int batch, double *kappa_dev,
+                                   void *stream);
+
 /* x = A_0^{-1} b on the coarsest level (exact FP64 solve).                  */
 fcm_status fcm_coarse_solve(fcm_handle *h, const double *b, double *x,
                             void *stream);

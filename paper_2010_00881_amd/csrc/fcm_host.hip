@@ -1836,6 +1836,78 @@ fcm_status fcm_spd_inverse(double *A, int n, int batch, double *kappa, void *str
   return FCM_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free SPD inverse
+// Scratch of fcm_spd_inverse_noalloc: one file-scope device array, so every
+// GPU the library runs on holds its own copy (kNoAllocDoubles doubles,
+// 32 MiB) until the process ends.  Its last 32 doubles hold the pivot flag.
+// Host code never passes the array's name to a kernel (in host code it is a
+// host-side stand-in, not a device address): the device address of each
+// GPU's copy is looked up once per device with hipGetSymbolAddress.
+constexpr size_t kNoAllocDoubles = size_t(4) << 20;
+constexpr size_t kNoAllocFlagOff = kNoAllocDoubles - 32;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+double *g_noalloc_ptr[kNoAllocDevices] = {};
+
+__global__ void clear_flag_kernel(int *flag) { *flag = 0; }
+
+// Device address of the current device's scratch array (nullptr on error).
+double *noalloc_scratch(int &dev) {
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kNoAllocDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+      set_error("hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+      return nullptr;
+    }
+    g_noalloc_ptr[dev] = static_cast<double *>(p);
+  }
+  return g_noalloc_ptr[dev];
+}
+}  // namespace
+
+extern "C" {
+
+fcm_status fcm_spd_inverse_noalloc(double *A, int n, int batch, double *kappa, void *stream) {
+  if (!A || n < 1 || batch < 1) {
+    set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  const size_t need = spd_inverse_scratch_doubles(n, batch);
+  if (need > kNoAllocFlagOff) {
+    set_error("fcm_spd_inverse_noalloc: n = %d, batch = %d need %zu scratch doubles, more than "
+              "the %zu of the static device buffer (2 * 32 * n + n + 2 doubles per matrix)",
+              n, batch, need, kNoAllocFlagOff);
+    return FCM_ERR_ARG;
+  }
+  int dev = -1;
+  double *scr = noalloc_scratch(dev);
+  if (!scr) {
+    if (dev < 0 || dev >= kNoAllocDevices) set_error("no usable current HIP device (%d)", dev);
+    return FCM_ERR_HIP;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int *flag = reinterpret_cast<int *>(scr + kNoAllocFlagOff);
+  clear_flag_kernel<<<1, 1, 0, s>>>(flag);
+  spd_inverse_batched(A, n, batch, scr, flag, kappa, s);
+  int f = 0;
+  FCM_HIP(hipMemcpyAsync(&f, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  FCM_HIP(hipStreamSynchronize(s));
+  FCM_HIP(hipGetLastError());
+  if (f) {
+    set_error("a pivot was not positive (matrix not SPD in FP64)");
+    return FCM_ERR_NOT_SPD;
+  }
+  return FCM_OK;
+}
+
 fcm_status fcm_coarse_solve(fcm_handle *h, const double *b, double *x, void *stream) {
   if (!h || !b || !x) {
     set_error("invalid argument");

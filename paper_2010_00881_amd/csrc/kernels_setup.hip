@@ -1001,6 +1001,11 @@ size_t spd_inverse_scratch_doubles(int n, int batch) {
   return (size_t)batch * kTB * n * 2 + (size_t)batch * n + 2 * (size_t)batch;
 }
 
+__global__ void zero_doubles_kernel(double *x, size_t n) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
 int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag, double *kappa,
                         hipStream_t s) {
   if (batch <= 0 || n <= 0) return 0;
@@ -1008,7 +1013,9 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
   double *scale = scratch + (size_t)batch * kTB * n * 2;
   const int NB = (n + kTB - 1) / kTB;
   double *nrm = scale + (size_t)batch * n;
-  if (kappa) (void)hipMemsetAsync(nrm, 0, 2 * (size_t)batch * sizeof(double), s);
+  // norm accumulators start at zero (a kernel, not a memset node, so that the
+  // sequence may sit inside a captured graph)
+  if (kappa) zero_doubles_kernel<<<(2 * batch + 255) / 256, 256, 0, s>>>(nrm, 2 * (size_t)batch);
   jacobi_scale_kernel<<<dim3((n + 255) / 256, batch), 256, 0, s>>>(A, n, scale, flag);
   const dim3 sgrid((n + 3) / 4, batch);
   apply_scale_kernel<<<sgrid, 256, 0, s>>>(A, n, scale, 1.0, kappa ? nrm : nullptr);

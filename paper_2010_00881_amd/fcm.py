@@ -89,6 +89,7 @@ SIGNATURES = {
     "fcm_smooth": ([_P, ctypes.c_int, _P, _P, _P], ctypes.c_int),
     "fcm_coarse_solve": ([_P, _P, _P, _P], ctypes.c_int),
     "fcm_spd_inverse": ([_P, ctypes.c_int, ctypes.c_int, _P, _P], ctypes.c_int),
+    "fcm_spd_inverse_noalloc": ([_P, ctypes.c_int, ctypes.c_int, _P, _P], ctypes.c_int),
     "fcm_vcycle": ([_P, _P, _P, _P], ctypes.c_int),
     "fcm_pcg_solve": ([_P, _P, _P, ctypes.POINTER(SolveInfo), _P], ctypes.c_int),
     "fcm_mg_solve": ([_P, _P, _P, ctypes.POINTER(SolveInfo), ctypes.POINTER(ctypes.c_double), _P],
@@ -415,4 +416,15 @@ def spd_inverse(A, kappa=None):
     assert n == n2
     _check(lib().fcm_spd_inverse(_ptr(A), n, b, _ptr(kappa) if kappa is not None else None,
                                  _stream()))
+    return A
+
+
+def spd_inverse_noalloc(A, kappa=None):
+    """spd_inverse through the allocation-free entry point (static device
+    scratch of 4 Mi doubles; see fcm_spd_inverse_noalloc)."""
+    assert A.is_cuda and A.dtype.is_floating_point and A.element_size() == 8 and A.is_contiguous()
+    b, n, n2 = A.shape
+    assert n == n2
+    _check(lib().fcm_spd_inverse_noalloc(_ptr(A), n, b,
+                                         _ptr(kappa) if kappa is not None else None, _stream()))
     return A
