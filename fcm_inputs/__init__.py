@@ -77,6 +77,15 @@ def default_options(dim: int, smoother: str = "elementwise", precision: str = "f
     }
 
 
+def patch_omega(dim: int, n_fields: int = 1) -> float:
+    """Relaxation for patchwise Schwarz blocks: 1/6 (2D) and 1/18 (3D) as in
+    Section 3.3.2; 1/27 for 3D elasticity, whose patchwise lambda_max(M^-1 A)
+    is about 39.5, so that omega * lambda_max stays below 2."""
+    if dim == 2:
+        return 1.0 / 6.0
+    return 1.0 / 27.0 if n_fields > 1 else 1.0 / 18.0
+
+
 def _gaussians(rng, count, dim, c_lo=0.0, c_hi=1.0):
     A = rng.uniform(0.5, 2.0, count)
     w = rng.uniform(0.05, 0.15, count)

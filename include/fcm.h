@@ -127,7 +127,7 @@ typedef struct {
                                  all functions nonzero on it; FCM_SMOOTH_PATCHWISE:
                                  one block per grid node, all functions nonzero on
                                  the kept elements sharing it (Section 3.3.1); the
-                                 patch size n_f (2p+1)^d must not exceed 384      */
+                                 patch size n_f (2p+1)^d must not exceed 2187     */
   double omega;               /* relaxation (Section 3.3.2): elementwise 1/3 (2D),
                                  2/15 (3D); patchwise 1/6 (2D), 1/18 (3D)         */
   int n_pre, n_post;          /* smoothing steps per level (5 and 5 in the paper) */

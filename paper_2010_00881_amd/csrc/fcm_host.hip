@@ -894,9 +894,11 @@ struct PatchScratch {
 
 static int patch_chunk(int m, int nblocks) {
   const size_t per = (size_t)m * m * sizeof(double);
-  // up to 1024 blocks (1 GiB of FP64 scratch): large batches keep the sweep
-  // launches of the SPD inverse wide enough to fill the device
-  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(1024, ((size_t)1024 << 20) / per));
+  // up to 1024 blocks (1 GiB of FP64 scratch; 4 GiB for blocks above
+  // kSmallPatchM): large batches keep the sweep launches of the SPD inverse
+  // wide enough to fill the device
+  const size_t budget = (size_t)(m > kSmallPatchM ? 4096 : 1024) << 20;
+  const int chunk = (int)std::max<size_t>(1, std::min<size_t>(1024, budget / per));
   return std::max(1, std::min(chunk, nblocks));
 }
 
@@ -943,10 +945,11 @@ static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *d
     L.ldp = ld;
     const size_t mm = (size_t)m * ld;
     const size_t tp = (size_t)patch_tiles(m) * 256;
-    TRY(dalloc(h, &L.invS64, mm * std::max(1, ncls)));
-    // FP32 class inverses carry a tail that the class-product kernel may read
-    // past the last row and column (values masked there)
-    if (mixed) TRY(dalloc(h, &L.invS32, mm * std::max(1, ncls) + 32 * ld + 512));
+    // class inverses carry a tail that the class-product kernels may read past
+    // the last row and column (values masked there)
+    const size_t tail = 32 * (size_t)ld + 512;
+    TRY(dalloc(h, &L.invS64, mm * std::max(1, ncls) + tail));
+    if (mixed) TRY(dalloc(h, &L.invS32, mm * std::max(1, ncls) + tail));
     TRY(dalloc(h, &L.invU64, tp * std::max(1, h->np_unique)));
     if (mixed) TRY(dalloc(h, &L.invU32, tp * std::max(1, h->np_unique)));
     if (nblocks > 0) {
@@ -982,6 +985,15 @@ static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *d
   const int mtop = h->lev[h->L].mpatch;
   TRY(dalloc(h, &h->pYs, (size_t)std::max(1, h->np_shared) * mtop));
   TRY(dalloc(h, &h->pYu, (size_t)std::max(1, h->np_unique) * mtop));
+  // band-pair partial products of the large-block unique GEMV
+  size_t nband = 0;
+  for (int l = 1; l <= h->L; ++l) {
+    const int m = h->lev[l].mpatch;
+    if (m <= kSmallPatchM) continue;
+    const int nb = ((m + 15) / 16 + 15) / 16;
+    nband = std::max(nband, (size_t)nb * (nb + 1) / 2 * 512);
+  }
+  if (nband > 0) TRY(dalloc(h, &h->pband, nband * std::max(1, h->np_unique)));
   return check_flag(h, "patch Schwarz block inversion");
 }
 
@@ -1249,6 +1261,7 @@ static PatchArgs<T> patch_args(fcm_handle *h, int l, bool mixed) {
   }
   a.Ys = h->pYs;
   a.Yu = h->pYu;
+  a.Pband = h->pband;
   return a;
 }
 

@@ -32,7 +32,9 @@ constexpr double kKappa64 = 1e5; // scaled kappa_1 above which a Schwarz block s
 constexpr int kSmallInv = 88;
 // Schwarz blocks up to kSmallInv are formed and inverted in LDS (<= 64 KB).
 constexpr int kMaxStoredIn = 1029; // largest element matrix (p = 6 elasticity: 3*7^3)
-constexpr int kMaxPatchM = 384;    // largest patchwise Schwarz block (n_f (2p+1)^d)
+constexpr int kMaxPatchM = 2187;   // largest patchwise Schwarz block (n_f (2p+1)^d: 3D
+                                   // elasticity at p = 4)
+constexpr int kSmallPatchM = 384;  // blocks up to this size: one workgroup per unique patch
 
 enum : uint8_t { kVoid = 0, kPhys = 1, kCut = 2 };
 
@@ -152,6 +154,7 @@ struct fcm_handle {
   std::vector<int> h_pnode, h_pkm;            // host copies (patch order)
   std::vector<int> h_ppinfo;                  // host copy of the patch mode info
   double *pYs = nullptr, *pYu = nullptr;      // patch products (scratch)
+  double *pband = nullptr;                    // band-pair partials of large unique blocks
   double *Yscr = nullptr;                     // stored-matrix products (scratch)
   double *Yshr = nullptr;                     // shared-matrix element products (scratch)
   double *Kref64 = nullptr, *Kcut64 = nullptr, *be = nullptr, *b = nullptr;
@@ -307,6 +310,7 @@ struct PatchArgs {
   int ntile = 0;                  // tiles per row of a unique inverse: ceil(m / 16)
   double *Ys = nullptr;           // [m][nsh]
   double *Yu = nullptr;           // [npu][m]
+  double *Pband = nullptr;        // m > kSmallPatchM: [npu][band pairs][512] partial products
   T *out = nullptr;
   T *xs = nullptr;
   T omega = 0;

@@ -190,27 +190,24 @@ __device__ __host__ inline void tile_ij(int t, int nt, int &I, int &J) {
   J = I + t;
 }
 
-__global__ void pack_tiles_kernel(const double *src, int m, int nb, double *d64, float *d32) {
+// One workgroup per (tile, block): 256 threads copy the 16 x 16 tile.
+__global__ __launch_bounds__(256) void pack_tiles_kernel(const double *src, int m, double *d64,
+                                                         float *d32) {
   const int nt = (m + 15) / 16, tiles = nt * (nt + 1) / 2;
-  const size_t tot = (size_t)nb * tiles * 256;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const size_t b = i / ((size_t)tiles * 256);
-    const int t = (int)((i / 256) % tiles), e = (int)(i % 256);
-    int I, J;
-    tile_ij(t, nt, I, J);
-    const int r = 16 * I + e / 16, c = 16 * J + e % 16;
-    const double v = (r < m && c < m) ? src[b * m * m + (size_t)r * m + c] : 0.0;
-    if (d64) d64[i] = v;
-    if (d32) d32[i] = (float)v;
-  }
+  const int t = blockIdx.x, e = threadIdx.x;
+  const size_t b = blockIdx.y;
+  int I, J;
+  tile_ij(t, nt, I, J);
+  const int r = 16 * I + e / 16, c = 16 * J + e % 16;
+  const double v = (r < m && c < m) ? src[b * m * m + (size_t)r * m + c] : 0.0;
+  const size_t i = (b * tiles + t) * 256 + e;
+  if (d64) d64[i] = v;
+  if (d32) d32[i] = (float)v;
 }
 
 void launch_pack_tiles(const double *src, int m, int nb, double *d64, float *d32, hipStream_t s) {
   if (nb <= 0) return;
-  const size_t tot = (size_t)nb * patch_tiles(m) * 256;
-  const int blocks = (int)std::min<size_t>((tot + 255) / 256, 8192);
-  pack_tiles_kernel<<<blocks, 256, 0, s>>>(src, m, nb, d64, d32);
+  pack_tiles_kernel<<<dim3(patch_tiles(m), nb), 256, 0, s>>>(src, m, d64, d32);
 }
 
 // ---------------------------------------------------------------- apply
@@ -256,10 +253,13 @@ template <> struct TileRaw<double> {
 // and no load is pending across trips.
 constexpr int kGemvPairs = 3;
 
+// toff (LDS, may be null): storage index of the t-th tile of the list
+// (consecutive tiles when null).
 template <typename M>
 __device__ inline void tile_sweep(const M *base, int ntiles, const unsigned char *tI,
-                                  const unsigned char *tJ, const double *xs, double (*tb)[16][17],
-                                  double *yh0, double *yh1, int wave, int lane) {
+                                  const unsigned char *tJ, const int *toff, const double *xs,
+                                  double (*tb)[16][17], double *yh0, double *yh1, int wave,
+                                  int lane) {
   const int r = lane >> 2, c0 = (lane & 3) * 4;
   const int half = lane >> 5, i = lane & 15;
   const bool rowpart = (lane & 16) == 0;
@@ -270,8 +270,9 @@ __device__ inline void tile_sweep(const M *base, int ntiles, const unsigned char
 #pragma unroll
     for (int q = 0; q < kGemvPairs; ++q) {
       const int ta_i = t0 + 8 * q, tb_i = ta_i + 4;
-      ta[q].load(lp + (size_t)(ta_i < ntiles ? ta_i : t0) * 256);
-      tb2[q].load(lp + (size_t)(tb_i < ntiles ? tb_i : t0) * 256);
+      const int ia = ta_i < ntiles ? ta_i : t0, ib = tb_i < ntiles ? tb_i : t0;
+      ta[q].load(lp + (size_t)(toff ? toff[ia] : ia) * 256);
+      tb2[q].load(lp + (size_t)(toff ? toff[ib] : ib) * 256);
     }
 #pragma unroll
     for (int q = 0; q < kGemvPairs; ++q) {
@@ -309,7 +310,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void patch_gemv_kernel(Geo g, const int *__restrict__ pxoff,
                                                          const int *__restrict__ pinfo,
                                                          PatchArgs<T> a) {
-  constexpr int kPad = (kMaxPatchM + 15) / 16 * 16;
+  constexpr int kPad = (kSmallPatchM + 15) / 16 * 16;
   constexpr int kMaxTiles = (kPad / 16) * (kPad / 16 + 1) / 2;
   __shared__ double xs[kPad];
   __shared__ double yw[8][kPad];
@@ -337,10 +338,10 @@ __global__ __launch_bounds__(256) void patch_gemv_kernel(Geo g, const int *__res
   const size_t base = (size_t)u * ntiles * 256;
   const bool lo = a.matU32 && !(a.u64flag && a.u64flag[u]);
   if (lo)
-    tile_sweep<float>(a.matU32 + base, ntiles, tI, tJ, xs, tbuf[wave], yw[2 * wave],
+    tile_sweep<float>(a.matU32 + base, ntiles, tI, tJ, nullptr, xs, tbuf[wave], yw[2 * wave],
                       yw[2 * wave + 1], wave, lane);
   else
-    tile_sweep<double>(a.matU + base, ntiles, tI, tJ, xs, tbuf[wave], yw[2 * wave],
+    tile_sweep<double>(a.matU + base, ntiles, tI, tJ, nullptr, xs, tbuf[wave], yw[2 * wave],
                        yw[2 * wave + 1], wave, lane);
   __syncthreads();
   for (int k = threadIdx.x; k < m; k += 256) {
@@ -348,6 +349,111 @@ __global__ __launch_bounds__(256) void patch_gemv_kernel(Geo g, const int *__res
     for (int w = 0; w < 8; ++w) y += yw[w][k];
     a.Yu[(size_t)u * m + k] = y;
   }
+}
+
+// Unique patches with large blocks (m > kSmallPatchM, e.g. elasticity at
+// p = 3, 4: m = 1029, 2187), whose per-half-wave copies of y would not fit in
+// LDS.  The tile rows are cut into bands of kBandT tiles (256 rows); work item
+// (patch u, band pair a <= b) takes the stored tiles (I, J) with I in band a,
+// J in band b and J >= I, so every stored tile is read by exactly one work
+// item.  Its row sums land in band a and its column sums in band b; the
+// work item keeps both bands of x and eight half-wave copies of both bands of
+// y in LDS (local tile index i for band a, 16 + j for band b, or j when
+// a = b) and writes the two partial bands to P[u][pair][0..511].
+// patch_band_reduce_kernel then adds, for every row of band c, the partials
+// of the pairs (a, c), a < c, then (c, c), then (c, b), b > c -- a fixed
+// order, so the result is the same on every run.
+constexpr int kBandT = 16;
+
+__device__ inline void band_pair(int pr, int nbands, int &A, int &B) {
+  A = 0;
+  while (pr >= nbands - A) {
+    pr -= nbands - A;
+    ++A;
+  }
+  B = A + pr;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void patch_gemv_band_kernel(Geo g, const int *__restrict__ pxoff,
+                                                              const int *__restrict__ pinfo,
+                                                              PatchArgs<T> a, int nbands,
+                                                              int npairs, double *P) {
+  constexpr int R = 16 * kBandT;           // rows per band
+  __shared__ double xs[2 * R];
+  __shared__ double yw[8][2 * R];
+  __shared__ double tbuf[4][2][16][17];
+  __shared__ unsigned char tI[kBandT * kBandT], tJ[kBandT * kBandT];
+  __shared__ int toff[kBandT * kBandT];
+  const int u = blockIdx.x / npairs, pr = blockIdx.x - u * npairs;
+  int A, B;
+  band_pair(pr, nbands, A, B);
+  const bool same = A == B;
+  const int pi = a.nsh + u;
+  const int node = a.pnode[pi], kmask = a.pkm[pi];
+  int vc[3];
+  node_coords(g, node, vc);
+  const int m = a.m, nt = a.ntile;
+  for (int k = threadIdx.x; k < 2 * R; k += 256) {
+    const int row = (k < R ? A : B) * R + (k & (R - 1));
+    const int rc = min(row, m - 1);
+    double v = 0.0;
+    if (row < m && patch_present(g, pinfo[rc], kmask, vc)) v = (double)a.x[node + pxoff[rc]];
+    xs[k] = v;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) yw[w][k] = 0.0;
+  }
+  // the work item's tiles, I-major: a < b all (i, j) of the two bands, a = b
+  // the triangle j >= i
+  const int ni = min(kBandT, nt - kBandT * A), nj = min(kBandT, nt - kBandT * B);
+  const int ntl = same ? ni * (ni + 1) / 2 : ni * nj;
+  for (int t = threadIdx.x; t < ntl; t += 256) {
+    int i, j;
+    if (same) {
+      tile_ij(t, ni, i, j);
+    } else {
+      i = t / nj;
+      j = t - i * nj;
+    }
+    const int I = kBandT * A + i, J = kBandT * B + j;
+    tI[t] = (unsigned char)i;
+    tJ[t] = (unsigned char)(same ? j : kBandT + j);
+    toff[t] = I * nt - I * (I - 1) / 2 + (J - I);
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const size_t base = (size_t)u * (nt * (nt + 1) / 2) * 256;
+  const bool lo = a.matU32 && !(a.u64flag && a.u64flag[u]);
+  if (lo)
+    tile_sweep<float>(a.matU32 + base, ntl, tI, tJ, toff, xs, tbuf[wave], yw[2 * wave],
+                      yw[2 * wave + 1], wave, lane);
+  else
+    tile_sweep<double>(a.matU + base, ntl, tI, tJ, toff, xs, tbuf[wave], yw[2 * wave],
+                       yw[2 * wave + 1], wave, lane);
+  __syncthreads();
+  double *Pw = P + ((size_t)u * npairs + pr) * (2 * R);
+  for (int k = threadIdx.x; k < 2 * R; k += 256) {
+    double y = 0.0;
+#pragma unroll
+    for (int w = 0; w < 8; ++w) y += yw[w][k];
+    Pw[k] = y;
+  }
+}
+
+__global__ __launch_bounds__(256) void patch_band_reduce_kernel(const double *__restrict__ P,
+                                                                int m, int nbands, int npairs,
+                                                                int npu, double *Yu) {
+  constexpr int R = 16 * kBandT;
+  const size_t idx = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (size_t)npu * m) return;
+  const int u = (int)(idx / m), row = (int)(idx - (size_t)u * m);
+  const int c = row / R, k = row - c * R;
+  const double *Pu = P + (size_t)u * npairs * (2 * R);
+  auto pair = [&](int x, int y) { return x * nbands - x * (x - 1) / 2 + (y - x); };
+  double y = 0.0;
+  for (int aa = 0; aa < c; ++aa) y += Pu[(size_t)pair(aa, c) * (2 * R) + R + k];
+  for (int bb = c; bb < nbands; ++bb) y += Pu[(size_t)pair(c, bb) * (2 * R) + k];
+  Yu[idx] = y;
 }
 
 // Class patches on the FP64 matrix cores.  Work item = (8 row tiles of 16,
@@ -517,46 +623,69 @@ __global__ __launch_bounds__(512) void patch_class_mfma32_kernel(Geo g,
   }
 }
 
-// FP32 class products: a workgroup computes all m <= 128 NRT rows for 64
-// patches of one class, Y[:, q0:q0+64] = A_c X, streaming both operands
-// through LDS in slices of 32 k (A_c from L2, X gathered once per patch) and
-// prefetching the next slice into registers while the matrix cores work on
-// the current one.  Every thread fetches an equal share of both slices: rows
-// tid % 128 + 128 i and k rows tid / 128 + 4 j of the A slice (coalesced
-// over rows; the class inverses are allocated with a tail of 32 ld + 512
-// floats, so the reads past row or column m need no clamp and are masked when
-// stored) and X rows wave + 8 j (lane = patch).  X stays in its storage type
-// (FP64 level vectors) while the load is in flight and is rounded to FP32
-// when the slice is stored to LDS.  Wave w owns row tiles w, w + 8, ..,
-// w + 8 (NRT - 1) and all four 16-patch column tiles.  LDS rows are padded to
-// 16 mod 32 floats so that the four k rows a v_mfma_f32_16x16x4f32 operand
-// read touches fall in distinct banks.
-static_assert(kMaxPatchM <= 384, "class tile kernel covers at most 24 row tiles");
-constexpr int kCT_XS = 64 + 16;    // X slice row stride (floats)
+// Class products with both operands streamed through LDS: a workgroup
+// computes ROWS = 128 NRT rows (row block blockIdx.y) for 64 patches of one
+// class, Y[r0:r0+ROWS, q0:q0+64] = A_c[r0:r0+ROWS, :] X, in slices of 32 k
+// (A_c from L2, X gathered once per patch and row block), prefetching the
+// next slice into registers while the matrix cores work on the current one.
+// C is the arithmetic type: float (mixed form, v_mfma_f32_16x16x4f32, lane l
+// holds D[4(l/16) + j][l%16]) or double (v_mfma_f64_16x16x4f64, D[4j +
+// l/16][l%16]); both take A[l%16][l/16] and B[l/16][l%16].  Every thread
+// fetches an equal share of both slices: rows tid % 128 + 128 i and k rows
+// tid / 128 + 4 j of the A slice (coalesced over rows; the class inverses are
+// allocated with a tail of 32 ld + 512 entries, so the reads past row or
+// column m need no clamp and are masked when stored) and X rows wave + 8 j
+// (lane = patch).  X stays in its storage type (FP64 level vectors) while
+// the load is in flight.  Wave w owns row tiles w, w + 8, .., w + 8 (NRT -
+// 1) and all four 16-patch column tiles.  LDS rows are padded so that the
+// four k rows an MFMA operand read touches fall in distinct banks.
+constexpr int kKTab = ((kMaxPatchM + 31) / 32) * 32;   // mode tables of the class kernel
 
-template <typename T, int NRT>
-__global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *__restrict__ pxoff,
-                                                                    PatchArgs<T> a) {
-  constexpr int ROWS = 128 * NRT, RS = ROWS + 16;
-  constexpr int NA = 8 * NRT;          // A entries per thread per slice (32 ROWS / 512)
-  __shared__ float As[32 * RS];
-  __shared__ float Xs[32 * kCT_XS];
-  __shared__ int koff[384];            // offset of mode k from the patch node in x
-  __shared__ float kmask[384];         // 1 if mode k is present in the class, else 0
+template <typename C> struct ClassMfma;
+template <> struct ClassMfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static constexpr int kPadA = 16, kPadX = 16;
+  __device__ static v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int j, int kq) { return 4 * kq + j; }
+  template <typename A> __device__ static const float *mat(const A &a) { return a.matS32; }
+};
+template <> struct ClassMfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static constexpr int kPadA = 8, kPadX = 8;
+  __device__ static v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int j, int kq) { return 4 * j + kq; }
+  template <typename A> __device__ static const double *mat(const A &a) { return a.matS64; }
+};
+
+template <typename T, typename C, int NRT, int KTAB>
+__global__ __launch_bounds__(512, 4) void patch_class_tile_kernel(const int *__restrict__ pxoff,
+                                                                  PatchArgs<T> a) {
+  typedef ClassMfma<C> MM;
+  typedef typename MM::v4 v4;
+  constexpr int ROWS = 128 * NRT, RS = ROWS + MM::kPadA, XS = 64 + MM::kPadX;
+  __shared__ C As[32 * RS];
+  __shared__ C Xs[32 * XS];
+  __shared__ int koff[KTAB];           // offset of mode k from the patch node in x
+  __shared__ C kmask[KTAB];            // 1 if mode k is present in the class, else 0
   // Workgroups are dealt to the 8 XCDs round-robin by id; the four quarters
-  // of a chunk get ids of one residue mod 8, so its class inverse is read
-  // from HBM once into that XCD's L2 and the other quarters hit there.
+  // of a chunk get ids of one residue mod 8 (gridDim.x is a multiple of 32),
+  // so its class inverse is read from HBM once into that XCD's L2 and the
+  // other quarters hit there.
   const int L = blockIdx.x, slot = L >> 3;
   const int chunk = (slot >> 2) * 8 + (L & 7), quarter = slot & 3;
   if (chunk >= a.nchunks) return;
   const int *ch = a.chk + 3 * chunk;
   const int c = ch[0], q0 = ch[1] + 64 * quarter, qn = min(64, ch[2] - 64 * quarter);
   if (qn <= 0) return;
-  const int m = a.m, ld = a.ld;
+  const int m = a.m, ld = a.ld, r0 = ROWS * blockIdx.y;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int n = lane & 15, kq = lane >> 4;
   const int ar = tid & 127, ak = tid >> 7;
-  const float *Ab = a.matS32 + (size_t)c * m * ld + (size_t)ak * ld + ar;
+  const C *Ab = MM::mat(a) + (size_t)c * m * ld + (size_t)ak * ld + r0 + ar;
   const unsigned *pres = a.cpres + (size_t)c * a.pwords;
   const int pn = a.pnode[q0 + min(lane, qn - 1)];
   // Every load below is issued unconditionally from a clamped, valid address
@@ -564,10 +693,10 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
   // branches join, one memory latency per element), and the raw values are
   // masked only when the slice is stored to LDS, one trip later: masking
   // right after the loads would wait for them before the matrix-core work.
-  float pa[NA];
+  C pa[8 * NRT];
   T px[4];
   auto fetch = [&](int k0) {
-    const float *Ak = Ab + (size_t)k0 * ld;   // A[r][k] = A[k][r]: row k of the slice
+    const C *Ak = Ab + (size_t)k0 * ld;   // A[r][k] = A[k][r]: row k of the slice
 #pragma unroll
     for (int j = 0; j < 8; ++j)
 #pragma unroll
@@ -576,14 +705,14 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
     for (int j = 0; j < 4; ++j)
       px[j] = a.x[min(max(pn + koff[k0 + wave + 8 * j], 0), a.xlen - 1)];
   };
-  floatx4p acc[NRT][4];
+  v4 acc[NRT][4];
 #pragma unroll
   for (int i = 0; i < NRT; ++i)
 #pragma unroll
-    for (int t = 0; t < 4; ++t) acc[i][t] = floatx4p{0.f, 0.f, 0.f, 0.f};
-  for (int k = tid; k < 384; k += 512) {
+    for (int t = 0; t < 4; ++t) acc[i][t] = v4{0, 0, 0, 0};
+  for (int k = tid; k < KTAB; k += 512) {
     koff[k] = k < m ? pxoff[k] : 0;
-    kmask[k] = k < m && ((pres[k >> 5] >> (k & 31)) & 1u) ? 1.f : 0.f;
+    kmask[k] = k < m && ((pres[k >> 5] >> (k & 31)) & 1u) ? C(1) : C(0);
   }
   __syncthreads();
   const int nslice = (m + 31) >> 5;
@@ -595,30 +724,29 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
 #pragma unroll
       for (int i = 0; i < NRT; ++i) {
         const int k = ak + 4 * j, r = ar + 128 * i;
-        As[k * RS + r] = ((r < m) & (k0 + k < m)) ? pa[j * NRT + i] : 0.f;
+        As[k * RS + r] = ((r0 + r < m) & (k0 + k < m)) ? pa[j * NRT + i] : C(0);
       }
     // absent modes and missing patches are scaled by 0 (not selected: a
     // select on a loaded value would be turned back into a branch)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const int kr = wave + 8 * j, k = k0 + kr;
-      const float mk = lane < qn ? kmask[k] : 0.f;
-      Xs[kr * kCT_XS + lane] = (float)px[j] * mk;
+      const C mk = lane < qn ? kmask[k] : C(0);
+      Xs[kr * XS + lane] = (C)px[j] * mk;
     }
     __syncthreads();
     if (sl + 1 < nslice) fetch(32 * (sl + 1));
 #pragma unroll
     for (int k4 = 0; k4 < 8; ++k4) {
       const int kr = 4 * k4 + kq;
-      float bv[4];
+      C bv[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) bv[t] = Xs[kr * kCT_XS + 16 * t + n];
+      for (int t = 0; t < 4; ++t) bv[t] = Xs[kr * XS + 16 * t + n];
 #pragma unroll
       for (int i = 0; i < NRT; ++i) {
-        const float av = As[kr * RS + 16 * (wave + 8 * i) + n];
+        const C av = As[kr * RS + 16 * (wave + 8 * i) + n];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[t], acc[i][t], 0, 0, 0);
+        for (int t = 0; t < 4; ++t) acc[i][t] = MM::mma(av, bv[t], acc[i][t]);
       }
     }
     __syncthreads();
@@ -631,7 +759,7 @@ __global__ __launch_bounds__(512, 4) void patch_class_tile32_kernel(const int *_
       if (q < qn)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int rr = 16 * (wave + 8 * i) + 4 * kq + j;
+          const int rr = r0 + 16 * (wave + 8 * i) + MM::row(j, kq);
           if (rr < m) a.Ys[(size_t)rr * a.nsh + q0 + q] = (double)acc[i][t][j];
         }
     }
@@ -646,15 +774,32 @@ static void launch_class32_nks(const Geo &g, const PatchTables &pt, const PatchA
       g, pt.pxoff, a);
 }
 
+template <typename T, typename C, int NRT>
+static void launch_class_tile(const Geo &g, const PatchTables &pt, const PatchArgs<T> &a,
+                              hipStream_t s) {
+  (void)g;
+  // chunks hold <= 256 patches (four quarters of 64)
+  const dim3 grid(4 * ((a.nchunks + 7) / 8 * 8), (a.m + 128 * NRT - 1) / (128 * NRT));
+  if (a.m <= kSmallPatchM)
+    patch_class_tile_kernel<T, C, NRT, 384><<<grid, 512, 0, s>>>(pt.pxoff, a);
+  else
+    patch_class_tile_kernel<T, C, NRT, kKTab><<<grid, 512, 0, s>>>(pt.pxoff, a);
+}
+
+// Mixed form: FP32 class products (m <= 32 on the register-tile kernel).
+// FP64 form: register-resident inverse rows for m <= kSmallPatchM, the
+// LDS-streamed FP64 kernel above that.
 template <typename T>
 static bool launch_class32(const Geo &g, const PatchTables &pt, const PatchArgs<T> &a,
                            hipStream_t s) {
-  if (!a.matS32) return false;
-  // chunks hold <= 256 patches (four quarters of 64); m <= kMaxPatchM = 384
-  const dim3 grid(4 * ((a.nchunks + 7) / 8 * 8));
-  if (a.m > 256) patch_class_tile32_kernel<T, 3><<<grid, 512, 0, s>>>(pt.pxoff, a);
-  else if (a.m > 128) patch_class_tile32_kernel<T, 2><<<grid, 512, 0, s>>>(pt.pxoff, a);
-  else if (a.m > 32) patch_class_tile32_kernel<T, 1><<<grid, 512, 0, s>>>(pt.pxoff, a);
+  if (!a.matS32) {
+    if (a.m <= kSmallPatchM) return false;
+    launch_class_tile<T, double, 1>(g, pt, a, s);
+    return true;
+  }
+  if (a.m > 256) launch_class_tile<T, float, 3>(g, pt, a, s);
+  else if (a.m > 128) launch_class_tile<T, float, 2>(g, pt, a, s);
+  else if (a.m > 32) launch_class_tile<T, float, 1>(g, pt, a, s);
   else launch_class32_nks<T, 8>(g, pt, a, s);   // nks <= 8
   return true;
 }
@@ -749,7 +894,18 @@ __global__ __launch_bounds__(256) void patch_gather_kernel(Geo g, const int *__r
 template <typename T>
 void launch_patch_op(const Geo &g, const Tables &t, const PatchTables &pt, const PatchArgs<T> &a,
                      hipStream_t s) {
-  if (a.npu > 0) patch_gemv_kernel<T><<<a.npu, 256, 0, s>>>(g, pt.pxoff, pt.pinfo, a);
+  if (a.npu > 0) {
+    if (a.m <= kSmallPatchM) {
+      patch_gemv_kernel<T><<<a.npu, 256, 0, s>>>(g, pt.pxoff, pt.pinfo, a);
+    } else {
+      const int nbands = (a.ntile + kBandT - 1) / kBandT, npairs = nbands * (nbands + 1) / 2;
+      patch_gemv_band_kernel<T><<<a.npu * npairs, 256, 0, s>>>(g, pt.pxoff, pt.pinfo, a, nbands,
+                                                               npairs, a.Pband);
+      const size_t rows = (size_t)a.npu * a.m;
+      patch_band_reduce_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, s>>>(
+          a.Pband, a.m, nbands, npairs, a.npu, a.Yu);
+    }
+  }
   if (a.stored_only) return;
   if (a.nsh > 0 && a.nchunks > 0) {
     if (!launch_class32<T>(g, pt, a, s)) launch_class<T>(g, pt, a, s);

@@ -9,9 +9,10 @@ positive Schwarz smoothers and V-cycle, convergence of the preconditioned CG
 to the requested tolerance, and agreement of the FP32-V-cycle and plain FP64
 solutions in the energy norm.
 
-Workloads: the 32^3 p = 3 voided cube (Poisson, patchwise Schwarz, 848,071
-unknowns, the benchmark) and the 24^3 p = 4 voided cube (elasticity,
-elementwise Schwarz, 2,690,520 unknowns), generator seed 0.
+Workloads: the 32^3 p = 3 voided cube (Poisson, 848,071 unknowns) and the
+24^3 p = 4 voided cube (elasticity, 2,690,520 unknowns, patch blocks of 2187
+unknowns), both with patchwise Schwarz blocks, generator seed 0.  Only one
+solver handle is alive at a time (the elasticity handle holds ~100-150 GB).
 """
 import numpy as np
 import pytest
@@ -21,17 +22,12 @@ from tests.parity_utils import DofMap, local_perm
 
 pytestmark = pytest.mark.gpu
 
-# (descriptor, options), smoother, omega, iteration bound, residual reached.  The
-# elasticity case runs the elementwise smoother (patchwise blocks would hold
-# 2187 unknowns); on these voided cubes with alpha = 1e-10 it does not reach
-# rtol 1e-10 within 500 iterations, the same limitation of elementwise blocks
-# that the Poisson benchmark avoids with patchwise ones, so for it the test
-# asks for steady progress (relative residual below 1e-5) instead.
+# (descriptor, options), smoother, omega, iteration bound, true residual reached
 CASES = {
     "cube32_p3_patch": lambda: (fi.voided_cube_poisson(0, n=32, p=3), "patchwise", 1.0 / 18.0,
                                 12, 1e-9),
-    "elast24_p4": lambda: (fi.voided_cube_elasticity(0, n=24, p=4), "elementwise", 2.0 / 15.0,
-                           500, 1e-5),
+    "elast24_p4_patch": lambda: (fi.voided_cube_elasticity(0, n=24, p=4), "patchwise",
+                                 fi.patch_omega(3, 3), 40, 1e-9),
 }
 
 _cache = {}
@@ -41,7 +37,7 @@ def _case(name, precision):
     key = (name, precision)
     if key in _cache:
         return _cache[key]
-    for k in [k for k in _cache if k[0] != name and k[1] != "oracle"]:
+    for k in [k for k in _cache if k[1] != "oracle"]:
         _cache.pop(k)[0].close()
     from oracle import fcm
     from paper_2010_00881_amd import Solver
@@ -141,19 +137,20 @@ def test_fullsize_operator_rows(name):
 def test_fullsize_pcg_and_sampled_residual(name):
     import torch
     sols = {}
-    converged = True
+    its = {}
     for prec in ("mixed", "fp64"):
         s, disc, dm, max_it, res_ok = _case(name, prec)
         x, info = s.pcg()
         torch.cuda.synchronize()
         print(f"[fullsize] {name} {prec}: status {info['status']} it {info['iterations']} rel res "
               f"{info['rel_res']:.2e} true {info['true_rel_res']:.2e}", flush=True)
-        assert info["status"] in (0, 1) and info["iterations"] <= max_it
+        assert info["status"] == 0 and info["iterations"] <= max_it
         assert info["true_rel_res"] <= res_ok
-        converged = converged and info["status"] == 0
+        its[prec] = info["iterations"]
         xo, rest = dm.from_gpu(x)
         assert np.all(rest == 0.0)
         sols[prec] = (x.clone(), xo, info["true_rel_res"])
+    assert abs(its["mixed"] - its["fp64"]) <= 1
     # b - A x at sampled DOFs, with A and b from oracle element systems
     rng = np.random.default_rng(13)
     dofs = rng.choice(disc.n_dofs, 300, replace=False)
@@ -162,8 +159,6 @@ def test_fullsize_pcg_and_sampled_residual(name):
     res = np.abs(b - ax).max() / bmax
     print(f"[fullsize] {name}: sampled |b - A x| / max|b| = {res:.2e}", flush=True)
     assert res <= max(1e-7, 1e3 * sols["fp64"][2])
-    if not converged:
-        return
     # FP32 V-cycle and plain FP64 solutions agree in the energy norm
     s = _cache[(name, "fp64")][0]
     L = s.n_levels - 1

@@ -8,8 +8,10 @@ the exact coarse solve, one V-cycle (Alg. 1) and the full MG-preconditioned
 CG (Section 4) in the plain FP64 and the FP32-V-cycle forms.
 
 Cases span 2D/3D, Poisson/elasticity, orders 2..4, several tiles of the
-element grid with ragged tails, single- and multi-block coarse levels, and
-Schwarz blocks inverted in LDS (m <= 88) and by the blocked sweep (m > 88).
+element grid with ragged tails, single- and multi-block coarse levels,
+Schwarz blocks inverted in LDS (m <= 88) and by the blocked sweep (m > 88),
+and patch blocks applied by one workgroup per patch (m <= 384) or by band
+pairs with row-blocked class products (elasticity, m = 1029 and 2187).
 """
 import numpy as np
 import pytest
@@ -33,12 +35,22 @@ CASES = {
     "cube7_p3_patch": lambda: _patch(fi.voided_cube_poisson(0, n=7, p=3)),
     "cube13_p2_patch": lambda: _patch(fi.voided_cube_poisson(2, n=13, p=2)),
     "elast3_p2_patch": lambda: _patch(fi.voided_cube_elasticity(1, n=3, p=2)),
+    # large patch blocks: m = 375, 1029, 2187 (all patches unique) and a single
+    # void on 5^3 at p = 3, whose uncut region gives class patches of m = 1029
+    "elast3_p4_patch": lambda: _patch(fi.voided_cube_elasticity(1, n=3, p=4)),
+    "elast5_p3_patch_void1": lambda: _patch(_one_void(fi.voided_cube_elasticity(0, n=5, p=3))),
 }
 
 
 def _patch(case_):
     desc, opts = case_
-    return desc, dict(opts, smoother="patchwise", omega=1 / 6 if desc["dim"] == 2 else 1 / 18)
+    return desc, dict(opts, smoother="patchwise",
+                      omega=fi.patch_omega(desc["dim"], desc.get("n_fields", 1)))
+
+
+def _one_void(case_):
+    desc, opts = case_
+    return dict(desc, ball_c=desc["ball_c"][:1], ball_r=desc["ball_r"][:1]), opts
 
 _cache = {}
 
