@@ -1,25 +1,31 @@
 #!/usr/bin/env python3
 """MG-PCG throughput of the FCM p-multigrid solver on one MI355X.
 
-Workload: 3D Poisson on the unit cube minus 8 seeded spherical voids, 32^3
-cells, integrated-Legendre tensor basis p = 3 (848k unknowns for seed 0),
-alpha = 1e-10, octree depth 3, u = 0 on the box faces, f = 1; FP32 V-cycle
-inside FP64 CG (rtol 1e-10), patchwise additive Schwarz smoothing (one block
-per grid node, omega = 1/18, Section 3.3).  One step = one complete solve of
-a fresh seeded problem: classification, cut-cell integration, loads, Schwarz
-inverses, coarse factorisation (setup) and the MG-preconditioned CG.  Step k
-uses generator seed k; warm-up steps use seeds 1000+.
+Default workload (the largest single-GPU configuration): 3D linear elasticity
+(E = 1, nu = 0.3) on the unit cube minus 8 seeded spherical voids, 24^3
+cells, integrated-Legendre tensor basis p = 4 (2,690,520 unknowns for seed
+0), alpha = 1e-10, octree depth 3, clamped at z = 0, traction (0,0,-1) on
+z = 1; patchwise additive Schwarz smoothing (blocks of up to 2187 unknowns,
+omega = 1/27), FP32 smoother matrices inside the FP64 V-cycle and CG, rtol
+1e-10.  One step = one complete solve of a fresh seeded problem:
+classification, cut-cell integration, loads, Schwarz inverses, coarse
+factorisation (setup) and the MG-preconditioned CG.  Step k uses generator
+seed k; warm-up steps use seeds 1000+.  The plain FP64 form is timed on the
+same seeds, and the 32^3 p = 3 Poisson cube (848,071 unknowns) is reported
+beside it under "poisson_32".
 
 Prints one JSON line.  `value` is solves/s over the timed steps; p50/p99 are
 per-solve latencies; the V-cycle throughput and the roofline of the dominant
 V-cycle kernel (the finest-level GEMV over the unique patch inverses, HBM
-bound) are timed with HIP events on the stream the library launches on,
-after the timed region.
+bound) are timed with HIP events on the stream the library launches on, on
+the seed-0 problem, outside the timed region.
 """
 import argparse
 import json
 import os
+import platform
 import statistics
+import subprocess
 import sys
 import time
 
@@ -28,33 +34,76 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MG-PCG solves/s + V-cycle DOF/s (%HBM roofline) at rel. err 1e-8; p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
-# HBM traffic of one launch of the finest-level unique-patch GEMV on the seed-0
-# 32^3 p = 3 problem, FP32 V-cycle: rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
-# dispatch) of `bench.py --steps 1 --warmup 0 --no-cpu-baseline --pmc-calibration`,
-# each scaled by the reading of a 1 GiB elementwise copy (see
-# profiles/patch_gemv_cube32_p3_traffic.md).  Valid for the kernel as profiled.
-GEMV_TRAFFIC = {"bytes": 2.215e9}
+# HBM traffic per launch of the dominant kernel, from the committed rocprofv3
+# counter profiles (FETCH_SIZE + WRITE_SIZE, KiB per dispatch, each scaled by
+# the reading of a 1 GiB elementwise copy); constants of the kernels as
+# profiled, reported as null for any other configuration.
+GEMV_TRAFFIC = {
+    "elasticity": None,   # profiles/patch_gemv_band_elast24_p4_traffic.md
+    "poisson": 2.215e9,   # profiles/patch_gemv_cube32_p3_traffic.md
+}
 
 
-def cpu_baseline(n_sample=6):
-    """Oracle (FP64 NumPy/SciPy) MG-PCG, setup + solve, on the workload's geometry
-    at a reduced grid; scaled to the full workload by the ratio of fine DOFs."""
-    import fcm_inputs as fi
-    from oracle import fcm, mg
-    desc, opts = fi.voided_cube_poisson(0, n=n_sample, p=3)
-    opts = dict(opts, smoother="patchwise", omega=1.0 / 18.0)
-    t0 = time.perf_counter()
-    disc = fcm.Discretization(desc)
-    hier = mg.Hierarchy(disc, opts)
-    _, it, _ = hier.pcg(disc.b)
-    t = time.perf_counter() - t0
-    full = 848071
-    scale = full / disc.n_dofs
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / (t * scale), "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": (f"oracle setup+MG-PCG (patchwise) of the same seeded voided cube at {n_sample}^3 cells, "
-                       f"p=3 ({disc.n_dofs} DOFs, {it} iterations, {t:.1f} s), scaled by fine DOFs "
-                       f"x{scale:.1f} to the 32^3 workload")}
+def _cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return platform.processor() or "unknown"
+
+
+def _oracle_time(kind, n, threads):
+    """Wall time of one oracle setup + MG-PCG (patchwise) of the seed-0
+    problem at n^3 cells, with the BLAS thread count fixed, in a child
+    process (thread counts are fixed at BLAS load)."""
+    code = (
+        "import sys, time; sys.path.insert(0, %r)\n"
+        "import fcm_inputs as fi\n"
+        "from oracle import fcm, mg\n"
+        "if %r == 'elasticity':\n"
+        "    d, o = fi.voided_cube_elasticity(0, n=%d, p=4)\n"
+        "    o = dict(o, smoother='patchwise', omega=fi.patch_omega(3, 3))\n"
+        "else:\n"
+        "    d, o = fi.voided_cube_poisson(0, n=%d, p=3)\n"
+        "    o = dict(o, smoother='patchwise', omega=fi.patch_omega(3, 1))\n"
+        "t = time.perf_counter()\n"
+        "disc = fcm.Discretization(d)\n"
+        "h = mg.Hierarchy(disc, o)\n"
+        "x, it, hist = h.pcg(disc.b)\n"
+        "print(time.perf_counter() - t, disc.n_dofs, it)\n" % (ROOT, kind, n, n))
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[k] = str(threads)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                       timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr[-2000:])
+    t, dofs, it = r.stdout.split()
+    return float(t), int(dofs), int(it)
+
+
+def cpu_baseline(kind, full_dofs, sizes, cores):
+    """The oracle (FP64 NumPy/SciPy, patchwise) timed on the host at small
+    grids of the same seeded workload, with all `cores` BLAS threads and with
+    one; the time per solve is extrapolated to the full workload along the
+    power law t ~ dofs^beta fitted to the two largest all-core samples."""
+    import math
+    pts = [(n,) + _oracle_time(kind, n, cores) for n in sizes]
+    t1, d1, _ = _oracle_time(kind, sizes[0], 1)
+    (na, ta, da, _), (nb, tb, db, _) = pts[-2], pts[-1]
+    beta = math.log(tb / ta) / math.log(db / da)
+    t_full = tb * (full_dofs / db) ** beta
+    t_full1 = t1 * (pts[-1][1] / pts[0][1]) * (full_dofs / db) ** beta
+    return {"value": 1.0 / t_full, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "cpu": _cpu_model(),
+            "one_core_value": 1.0 / t_full1,
+            "sample": ("oracle setup+MG-PCG (patchwise, FP64) of the seed-0 workload at " +
+                       ", ".join(f"{n}^3 ({d} DOFs, {it} it, {t:.1f} s)" for n, t, d, it in pts) +
+                       f" on {cores} threads, {sizes[0]}^3 on 1 thread {t1:.1f} s; extrapolated to "
+                       f"{full_dofs} DOFs with t ~ dofs^{beta:.2f} fitted to the two largest samples")}
 
 
 def serve_bench(args):
@@ -169,20 +218,118 @@ def mlhp_bench(args):
     return 0
 
 
+def _problem(kind, seed, n, precision, smoother="patchwise"):
+    import fcm_inputs as fi
+    if kind == "elasticity":
+        d, o = fi.voided_cube_elasticity(seed, n=n, p=4)
+        nf = 3
+    else:
+        d, o = fi.voided_cube_poisson(seed, n=n, p=3)
+        nf = 1
+    omega = fi.patch_omega(3, nf) if smoother == "patchwise" else 2.0 / 15.0
+    return d, dict(o, precision=precision, smoother=smoother, omega=omega)
+
+
+def _run_steps(kind, n, seeds, precision, smoother="patchwise"):
+    """Complete solves (setup + MG-PCG) of fresh problems; per-solve records."""
+    import torch
+    from paper_2010_00881_amd import Solver
+    recs = []
+    for sd in seeds:
+        t = time.perf_counter()
+        s = Solver(*_problem(kind, sd, n, precision, smoother))
+        x, info = s.pcg()
+        torch.cuda.synchronize()
+        lat = (time.perf_counter() - t) * 1e3
+        s.close()
+        del x
+        if info["status"] != 0:
+            raise RuntimeError(f"{kind} solve of seed {sd} ({precision}) did not converge: {info}")
+        recs.append({"lat": lat, "it": info["iterations"], "setup": info["t_setup_ms"],
+                     "solve": info["t_solve_ms"], "res": info["true_rel_res"]})
+    return recs
+
+
+def _kernel_figures(kind, n, precision, smoother="patchwise"):
+    """V-cycle and dominant-kernel timings (HIP events on the library's
+    stream) on the seed-0 problem."""
+    import torch
+    from paper_2010_00881_amd import Solver
+    s = Solver(*_problem(kind, 0, n, precision, smoother))
+    torch.cuda.synchronize()
+    L = s.n_levels - 1
+    n_fine = s.n_dofs[-1]
+    reps = 3 if kind == "elasticity" else 10
+    ms_v, bytes_v = s.time_op("vcycle", reps=reps)
+    ms_s, bytes_s = s.time_op("smooth", level=L, reps=5 * reps)
+    ms_r, bytes_r = s.time_op("residual", level=L, reps=5 * reps)
+    ms_c, bytes_c = s.time_op("coarse", reps=reps)
+    if smoother == "patchwise":
+        ms_k, bytes_k = s.time_op("smooth_stored", level=L, reps=5 * reps)
+        dom = ("patch_gemv_band_kernel (finest level, unique patch inverses, band pairs)"
+               if kind == "elasticity" else
+               "patch_gemv_kernel (finest level, unique patch inverses)")
+    else:
+        ms_k, bytes_k = ms_s, bytes_s
+        dom = "finest-level elementwise smoother"
+    st = s.stats()
+    s.close()
+    torch.cuda.empty_cache()
+    achieved = bytes_k / (ms_k * 1e-3) / 1e9
+    traffic = GEMV_TRAFFIC.get(kind) if (precision == "mixed" and smoother == "patchwise"
+                                         and n == (24 if kind == "elasticity" else 32)) else None
+    return {
+        "dofs": n_fine,
+        "vcycle_ms": ms_v,
+        "vcycle_gdof_s": n_fine / (ms_v * 1e-3) / 1e9,
+        "vcycle_hbm_frac": bytes_v / (ms_v * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "kernels": {
+            "smooth_fine": {"ms": ms_s, "bytes": bytes_s, "gbs": bytes_s / (ms_s * 1e-3) / 1e9},
+            "stored_gemv_fine": {"ms": ms_k, "bytes": bytes_k},
+            "residual_fine": {"ms": ms_r, "bytes": bytes_r, "gbs": bytes_r / (ms_r * 1e-3) / 1e9},
+            "coarse_solve": {"ms": ms_c, "bytes": bytes_c, "gbs": bytes_c / (ms_c * 1e-3) / 1e9},
+        },
+        "problem": {k: st[k] for k in ("n_cut", "n_unique_blocks", "n_fp64_blocks",
+                                        "coarse_blocks", "coarse_block_size", "device_bytes")},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic / 1e9 if traffic is not None else None,
+                     "traffic_unit": "GB per launch (calibrated FETCH_SIZE + WRITE_SIZE of the "
+                                     "committed counter profile)",
+                     "algorithmic_gb": bytes_k / 1e9},
+    }
+
+
+def _summary(recs):
+    lat = [r["lat"] for r in recs]
+    return {
+        "p50_ms": statistics.median(lat),
+        "p99_ms": sorted(lat)[max(0, int(round(0.99 * len(lat))) - 1)],
+        "setup_ms_median": statistics.median(r["setup"] for r in recs),
+        "solve_ms_median": statistics.median(r["solve"] for r in recs),
+        "iterations": [r["it"] for r in recs],
+        "max_true_rel_res": max(r["res"] for r in recs),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
-    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--workload", default="elasticity",
+                    choices=["elasticity", "poisson", "serving", "mlhp"],
+                    help="elasticity: the 24^3 p = 4 solve benchmark (default); poisson: the "
+                         "32^3 p = 3 cube; serving: the request stream; mlhp: the multi-level "
+                         "hp sphere problem")
+    ap.add_argument("--n", type=int, default=None, help="cells per axis (24 / 32)")
     ap.add_argument("--smoother", default="patchwise", choices=["patchwise", "elementwise"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--compare-fp64", action="store_true",
-                    help="also time the plain FP64 form one problem at a time")
-    ap.add_argument("--workload", default="cube", choices=["cube", "serving", "mlhp"],
-                    help="cube: the 32^3 solve benchmark; serving: the request stream; "
-                         "mlhp: the multi-level hp sphere problem")
+    ap.add_argument("--no-fp64", action="store_true",
+                    help="skip the plain FP64 form (one problem at a time)")
+    ap.add_argument("--no-poisson", action="store_true",
+                    help="skip the 32^3 Poisson figures beside the elasticity line")
     ap.add_argument("--mlhp-k", type=int, default=1)
     ap.add_argument("--mlhp-p", type=int, default=3)
     ap.add_argument("--requests", type=int, default=64)
@@ -203,66 +350,24 @@ def main():
         return mlhp_bench(args)
 
     import torch
-    import fcm_inputs as fi
-    from paper_2010_00881_amd import Solver
+    kind = args.workload
+    n = args.n or (24 if kind == "elasticity" else 32)
+    label = (f"cube_voids_elasticity_{n}^3_p4" if kind == "elasticity"
+             else f"cube_voids_poisson_{n}^3_p3")
 
-    def problem(seed, precision):
-        d, o = fi.voided_cube_poisson(seed, n=args.n, p=3)
-        return d, dict(o, precision=precision, smoother=args.smoother,
-                       omega=1.0 / 18.0 if args.smoother == "patchwise" else 2.0 / 15.0)
-
-    def run_steps(seeds, precision, keep_first=False):
-        lat, its, setup, solve, errs = [], [], [], [], []
-        first = None
-        for sd in seeds:
-            t = time.perf_counter()
-            s = Solver(*problem(sd, precision))
-            x, info = s.pcg()
-            torch.cuda.synchronize()
-            lat.append((time.perf_counter() - t) * 1e3)
-            its.append(info["iterations"])
-            setup.append(info["t_setup_ms"])
-            solve.append(info["t_solve_ms"])
-            errs.append(info["true_rel_res"])
-            if info["status"] != 0:
-                raise RuntimeError(f"solve of seed {sd} did not converge: {info}")
-            if keep_first and sd == seeds[0]:
-                first = s
-            else:
-                s.close()
-            del x
-        return lat, its, setup, solve, errs, first
-
-    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    run_steps([1000 + w for w in range(args.warmup)], args.precision)
+    print(f"[bench] {label}: warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    _run_steps(kind, n, [1000 + w for w in range(args.warmup)], args.precision, args.smoother)
+    print("[bench] kernel figures on the seed-0 problem", file=sys.stderr, flush=True)
+    kf = _kernel_figures(kind, n, args.precision, args.smoother)
     torch.cuda.synchronize()
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    lat, its, setup, solve, errs, s = run_steps(list(range(args.steps)), args.precision,
-                                                keep_first=True)
+    recs = _run_steps(kind, n, list(range(args.steps)), args.precision, args.smoother)
     torch.cuda.synchronize()
     T = time.perf_counter() - t0
-    value = args.steps / T
-
-    # V-cycle throughput and dominant kernel on the seed-0 problem (the one the
-    # committed counter profile covers), HIP events on the library's stream
-    L = s.n_levels - 1
-    n_fine = s.n_dofs[-1]
-    ms_v, bytes_v = s.time_op("vcycle", reps=10)
-    ms_s, bytes_s = s.time_op("smooth", level=L, reps=50)
-    ms_r, bytes_r = s.time_op("residual", level=L, reps=50)
-    ms_c, bytes_c = s.time_op("coarse", reps=10)
-    if args.smoother == "patchwise":
-        ms_k, bytes_k = s.time_op("smooth_stored", level=L, reps=50)
-        dom = "patch_gemv_kernel (finest level, unique patch inverses)"
-    else:
-        ms_k, bytes_k = ms_s, bytes_s
-        dom = "finest-level elementwise smoother"
-    achieved = bytes_k / (ms_k * 1e-3) / 1e9
-    st = s.stats()
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": args.steps / T,
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -273,49 +378,39 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic (seeded voided cube, seeds 0..steps-1)",
-        "config": {"workload": f"cube_voids_poisson_{args.n}^3_p3", "n": args.n, "p": 3,
-                   "dofs": n_fine, "precision": args.precision, "smoother": args.smoother,
-                   "alpha": 1e-10,
-                   "quad_depth": 3, "rtol": 1e-10, "parallelism": "none (1 GPU)"},
-        "p50_ms": statistics.median(lat),
-        "p99_ms": sorted(lat)[max(0, int(round(0.99 * len(lat))) - 1)],
-        "setup_ms_median": statistics.median(setup),
-        "solve_ms_median": statistics.median(solve),
-        "iterations": its,
-        "max_true_rel_res": max(errs),
-        "vcycle_ms": ms_v,
-        "vcycle_gdof_s": n_fine / (ms_v * 1e-3) / 1e9,
-        "vcycle_hbm_frac": bytes_v / (ms_v * 1e-3) / 1e9 / HBM_PEAK_GBS,
-        "kernels": {
-            "smooth_fine": {"ms": ms_s, "bytes": bytes_s,
-                            "gbs": bytes_s / (ms_s * 1e-3) / 1e9},
-            "stored_gemv_fine": {"ms": ms_k, "bytes": bytes_k},
-            "residual_fine": {"ms": ms_r, "bytes": bytes_r,
-                              "gbs": bytes_r / (ms_r * 1e-3) / 1e9},
-            "coarse_solve": {"ms": ms_c, "bytes": bytes_c,
-                             "gbs": bytes_c / (ms_c * 1e-3) / 1e9},
-        },
-        "problem": {k: st[k] for k in ("n_cut", "n_unique_blocks", "n_fp64_blocks",
-                                        "coarse_blocks", "coarse_block_size", "device_bytes")},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (GEMV_TRAFFIC["bytes"] / 1e9
-                                 if GEMV_TRAFFIC["bytes"] is not None and args.n == 32
-                                 and args.smoother == "patchwise" and args.precision == "mixed"
-                                 else None),
-                     "traffic_unit": "GB per launch (calibrated FETCH_SIZE + WRITE_SIZE)",
-                     "algorithmic_gb": bytes_k / 1e9},
+        "config": {"workload": label, "n": n, "p": 4 if kind == "elasticity" else 3,
+                   "fields": 3 if kind == "elasticity" else 1, "dofs": kf["dofs"],
+                   "precision": args.precision, "smoother": args.smoother,
+                   "omega": _problem(kind, 0, n, args.precision, args.smoother)[1]["omega"],
+                   "alpha": 1e-10, "quad_depth": 3, "rtol": 1e-10,
+                   "parallelism": "none (1 GPU)"},
     }
-    s.close()
-    if args.compare_fp64:
+    out.update(_summary(recs))
+    out.update({k: kf[k] for k in ("vcycle_ms", "vcycle_gdof_s", "vcycle_hbm_frac", "kernels",
+                                   "problem", "roofline")})
+    if not args.no_fp64 and args.precision == "mixed":
         print("[bench] plain FP64 form, one problem at a time", file=sys.stderr, flush=True)
         t1 = time.perf_counter()
-        lat64, *_ = run_steps(list(range(args.steps)), "fp64")
+        r64 = _run_steps(kind, n, list(range(args.steps)), "fp64", args.smoother)
         torch.cuda.synchronize()
         out["fp64_form_solves_s"] = args.steps / (time.perf_counter() - t1)
+        out["fp64_form"] = _summary(r64)
+        out["mixed_over_fp64"] = out["value"] / out["fp64_form_solves_s"]
+    if kind == "elasticity" and not args.no_poisson:
+        print("[bench] 32^3 p = 3 Poisson cube", file=sys.stderr, flush=True)
+        _run_steps("poisson", 32, [1000, 1001], args.precision)
+        pk = _kernel_figures("poisson", 32, args.precision)
+        t2 = time.perf_counter()
+        rp = _run_steps("poisson", 32, list(range(8)), args.precision)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t2
+        out["poisson_32"] = dict({"workload": "cube_voids_poisson_32^3_p3",
+                                  "solves_s": 8 / tp, "steps": 8}, **_summary(rp), **pk)
     if not args.no_cpu_baseline:
-        print("[bench] CPU oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline()
+        print("[bench] CPU oracle samples", file=sys.stderr, flush=True)
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        sizes = (2, 3) if kind == "elasticity" else (4, 6)
+        out["cpu_baseline"] = cpu_baseline(kind, kf["dofs"], sizes, cores)
     if args.pmc_calibration:
         a = torch.ones(256 * 2**20, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)

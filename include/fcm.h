@@ -191,7 +191,7 @@ fcm_status fcm_spd_inverse(double *A_dev, int n, int batch, double *kappa_dev,
  * same arguments, kernels and results, but the sweep's scratch and pivot flag
  * live in a static device buffer of 4 Mi doubles (32 MiB) that each GPU the
  * library runs on holds until the process ends; no hipMalloc, hipFree or
- * allocating library call is made.  Needs 2*32*n + n + 2 doubles per matrix
+ * allocating library call is made.  Needs 385*n + 2 doubles per matrix
  * (at most 4,194,272 in total); larger requests return FCM_ERR_ARG with
  * nothing launched.  Calls on one GPU share its buffer: calls that overlap on
  * one GPU (several streams or threads) race and must be serialised by the

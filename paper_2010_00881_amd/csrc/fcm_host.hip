@@ -1896,7 +1896,7 @@ fcm_status fcm_spd_inverse_noalloc(double *A, int n, int batch, double *kappa, v
   const size_t need = spd_inverse_scratch_doubles(n, batch);
   if (need > kNoAllocFlagOff) {
     set_error("fcm_spd_inverse_noalloc: n = %d, batch = %d need %zu scratch doubles, more than "
-              "the %zu of the static device buffer (2 * 32 * n + n + 2 doubles per matrix)",
+              "the %zu of the static device buffer (385 n + 2 doubles per matrix)",
               n, batch, need, kNoAllocFlagOff);
     return FCM_ERR_ARG;
   }

@@ -789,13 +789,30 @@ void launch_form_blocks(const Geo &g, const Tables &t, int q, int m, const int *
 }
 
 // --------------------------------------------- batched blocked SPD inverse
-// In-place symmetric Gauss-Jordan sweep by blocks of 32 pivots: sweeping
-// pivot block K maps [[A_KK, A_KJ],[A_IK, A_IJ]] to
-// [[-P, P A_KJ],[A_IK P, A_IJ - A_IK P A_KJ]] with P = A_KK^{-1}; after all
-// K the matrix holds -A^{-1}.  Two launches per pivot block (pivot rows,
-// symmetric trailing update on the FP64 matrix cores); the matrix is
-// Jacobi-scaled first.
+// In-place symmetric Gauss-Jordan sweep: sweeping pivot block K maps
+// [[A_KK, A_KJ],[A_IK, A_IJ]] to [[-P, P A_KJ],[A_IK P, A_IJ - A_IK P A_KJ]]
+// with P = A_KK^{-1}; after all K the matrix holds -A^{-1}.  Two levels of
+// pivot blocks: the rows of an outer block of kPB = 128 pivots (the panel,
+// copied to scratch) are swept in four steps of kTB = 32 pivots -- the pivot
+// rows pivot by pivot in registers (product form), then the other panel
+// rows by the same rank-32 step -- and the rest of the matrix then takes the
+// four rank-32 updates of those steps at once, as one symmetric rank-128
+// update on the FP64 matrix cores: sum_s R_s^T W_s with R_s and W_s the rows
+// of step s as they were before and after that step (stacked, kPB rows).
+// This is the step-by-step sweep with the updates of the rows outside the
+// panel deferred and summed; only the order of the additions changes.  (The
+// Schur-complement form R_K^T W_K with the panel before and after all four
+// steps is equal in exact arithmetic but amounts to an explicit inverse of
+// the 128 x 128 pivot block: on cut-cell patch blocks of scaled condition
+// 1e12 and more it loses positivity.)  The matrix is Jacobi-scaled first.
 constexpr int kTB = 32;
+constexpr int kPB = 128;
+// Batches of at least kTwoLevelBatch matrices larger than kTwoLevelN take the
+// 128-pivot panels; the rest one trailing update per 32 pivots (fewer
+// dependent launches for single coarse blocks, and no gain below ~400: the
+// 343 x 343 patch blocks of the p = 3 Poisson cube set up 15 % faster that way).
+constexpr int kTwoLevelBatch = 8;
+constexpr int kTwoLevelN = 384;
 
 __global__ void jacobi_scale_kernel(double *A, int n, double *scale, int *flag) {
   const int b = blockIdx.y;
@@ -840,26 +857,36 @@ __global__ void kappa_product_kernel(const double *nrm, int batch, double *kappa
   if (b < batch) kappa[b] = nrm[b] * nrm[batch + b];
 }
 
-// Pivot rows of block K: one wave per workgroup (J, b).  Lanes 0..31 hold
-// the columns of the 32 x 32 pivot tile (a private copy, needed for the
-// pivot columns), lanes 32..63 the panel columns [32 J, 32 J + 32), each a
-// column of 32 rows in registers; the wave sweeps them pivot by pivot
-// (product form: the unblocked sweep restricted to the rows of block K),
-// the pivot column being broadcast from its lane through LDS.  Rows past n
-// of a partial last block are identity rows.  It writes the swept rows W and
-// the rows before the sweep R of its panel columns.  Because the swept
-// matrix stays symmetric, the block column is A_IK = R^T, so the update
-// kernel needs nothing that another workgroup of the same launch writes.
+// Panel of outer block [k0, k0 + kb): Wp = rows k0.. of the matrix (kPB x n
+// per matrix, rows past kb zero).
+__global__ __launch_bounds__(256) void panel_copy_kernel(const double *A, int n, int k0, int kb,
+                                                         double *Wp) {
+  const int b = blockIdx.y;
+  const size_t tot = (size_t)kPB * n;
+  const double *M = A + (size_t)b * n * n + (size_t)k0 * n;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < tot; i += (size_t)gridDim.x * 256)
+    Wp[(size_t)b * tot + i] = i < (size_t)kb * n ? M[i] : 0.0;
+}
+
+// Pivot rows of one inner block (kTB pivots, global index k0 of the first):
+// one wave per workgroup (J, b).  P points at the block's rows (row r at P +
+// b pstride + r n); W and R receive them at + b wstride + r n.  Lanes 0..31 hold the columns of the 32 x 32 pivot tile
+// (a private copy, needed for the pivot columns), lanes 32..63 the panel
+// columns [32 J, 32 J + 32), each a column of 32 rows in registers; the wave
+// sweeps them pivot by pivot (product form), the pivot column being
+// broadcast from its lane through LDS.  Rows past n of a partial last block
+// are identity rows.  It writes the swept rows W and the rows before the
+// sweep R of its panel columns.
 constexpr int kTJ = 32;
 
-__global__ __launch_bounds__(64) void sweep_rows_kernel(double *A, int n, int K, double *W,
-                                                        double *Rg, int *flag) {
+__global__ __launch_bounds__(64) void sweep_rows_kernel(const double *P, size_t pstride, int n,
+                                                        int k0, double *W, double *Rg,
+                                                        size_t wstride, int *flag) {
   __shared__ double bc[2][kTB];
   const int J = blockIdx.x, b = blockIdx.y, l = threadIdx.x;
-  const double *M = A + (size_t)b * n * n;
-  double *Wb = W + (size_t)b * kTB * n;
-  double *Rb = Rg + (size_t)b * kTB * n;
-  const int k0 = K * kTB;
+  const double *M = P + (size_t)b * pstride;
+  double *Wb = W + (size_t)b * wstride;
+  double *Rb = Rg + (size_t)b * wstride;
   const bool panel = l >= kTB;
   const int col = panel ? J * kTJ + (l - kTB) : k0 + l;
   double x[kTB];
@@ -867,7 +894,7 @@ __global__ __launch_bounds__(64) void sweep_rows_kernel(double *A, int n, int K,
   // condition is issued and waited for one row at a time
   const int cc = min(col, n - 1);
 #pragma unroll
-  for (int r = 0; r < kTB; ++r) x[r] = M[(size_t)min(k0 + r, n - 1) * n + cc];
+  for (int r = 0; r < kTB; ++r) x[r] = M[(size_t)min(r, n - 1 - k0) * n + cc];
 #pragma unroll
   for (int r = 0; r < kTB; ++r) {
     const int gr = k0 + r;
@@ -904,20 +931,78 @@ __global__ __launch_bounds__(64) void sweep_rows_kernel(double *A, int n, int K,
   }
 }
 
-// M_IJ -= R_KI^T W_KJ for I, J outside block K; rows of K <- W; columns of K
-// <- W^T.  Only the upper triangle is computed and every value is stored at
-// (i, j) and (j, i): the swept matrix is symmetric in exact arithmetic, and
-// keeping it exactly symmetric matters for cut-cell blocks whose scaled
-// condition reaches 1e12 or more, where R^T (A_KK^{-1} R) and its mirror
-// image differ by the pivot-block solve error.  64 x 64 output tile (ti <= tj)
-// per workgroup, wave w owns the 32 x 32 quarter (w / 2, w % 2) as 2 x 2
-// v_mfma_f64_16x16x4f64 tiles (lane l supplies A[l%16][l/16] and
-// B[l/16][l%16], holds D[4j + l/16][l%16]).
+// The inner step [s0, s0 + kTB) applied to the other rows of the panel
+// (global rows k0p + t, t < kb): entries in the inner block's columns <- the
+// swept rows' transposes, the rest -= R_S^T W_S; the inner block's own rows
+// <- W_S.  Workgroup (column group, row group, matrix): 64 columns x 16
+// panel rows, the step's W_S columns and the R_S entries of the 16 rows
+// staged in LDS, wave w takes rows 16 g + w, + 4, + 8, + 12.  Within the panel's own columns (the K x K block, the pivot tiles
+// of the next steps) only the upper triangle is computed and each value is
+// also stored at its mirror position, so that block stays exactly symmetric
+// (as the trailing update keeps the whole matrix); the mirror targets are
+// entries no thread computes.  Ws, Rs: the step's rows in the stacks
+// (matrix stride kPB n).
+__global__ __launch_bounds__(256) void sweep_panel_kernel(double *Wp, int n, int k0p, int kb,
+                                                          int s0, const double *Ws,
+                                                          const double *Rs) {
+  __shared__ double wt[kTB][64];
+  __shared__ double rt[kTB][16];
+  const int b = blockIdx.z;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * 64 + lane;
+  double *Wb = Wp + (size_t)b * kPB * n;
+  const double *Wsb = Ws + (size_t)b * kPB * n;
+  const double *Rsb = Rs + (size_t)b * kPB * n;
+  const int jc = min(j, n - 1);
+  for (int k = wave; k < kTB; k += 4) wt[k][lane] = Wsb[(size_t)k * n + jc];
+  for (int e = threadIdx.x; e < kTB * 16; e += 256) {
+    const int k = e >> 4, r = e & 15;
+    rt[k][r] = Rsb[(size_t)k * n + min(k0p + 16 * (int)blockIdx.y + r, n - 1)];
+  }
+  __syncthreads();
+  if (j >= n) return;
+  const bool jin = j >= s0 && j < s0 + kTB;
+  const int jl = j - k0p, sl = s0 - k0p;
+  const bool jK = jl >= 0 && jl < kb;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = 16 * blockIdx.y + wave + 4 * q;
+    if (t >= kb || (jK && t > jl)) continue;   // K block: rows on and above the diagonal
+    const int tg = k0p + t;
+    double v;
+    if (t >= sl && t < sl + kTB) {
+      v = wt[t - sl][lane];
+    } else if (jin) {
+      v = Wsb[(size_t)(j - s0) * n + tg];
+    } else {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < kTB; ++k) acc += rt[k][t - 16 * blockIdx.y] * wt[k][lane];
+      v = Wb[(size_t)t * n + j] - acc;
+    }
+    Wb[(size_t)t * n + j] = v;
+    if (jK && t < jl) Wb[(size_t)jl * n + tg] = v;
+  }
+}
+
+// M_IJ -= sum_s R_s,I^T W_s,J = Rst_KI^T Wst_KJ (the stacked rows of the
+// four steps) for I, J outside the outer block K = [k0, k0 + kb); rows of K
+// <- Wp (the swept panel); columns of K <- Wp^T.  Only the upper triangle is computed
+// and every value is stored at (i, j) and (j, i): the swept matrix is
+// symmetric in exact arithmetic, and keeping it exactly symmetric matters for
+// cut-cell blocks whose scaled condition reaches 1e12 or more, where R^T (P R)
+// and its mirror image differ by the pivot-block solve error.  64 x 64 output
+// tile (ti <= tj) per workgroup, wave w owns the 32 x 32 quarter (w / 2, w %
+// 2) as 2 x 2 v_mfma_f64_16x16x4f64 tiles (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16], holds D[4j + l/16][l%16]); the kPB-deep sum runs in chunks of
+// 16 k, the loads of the next chunk in flight while the current one is on the
+// matrix cores.
 typedef double doublex4s __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n, int K,
-                                                                const double *W,
-                                                                const double *Rg, int ntile) {
+__global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n, int k0, int kb,
+                                                                const double *Wp,
+                                                                const double *Wst,
+                                                                const double *Rst, int ntile) {
   const int b = blockIdx.y;
   int ti = 0, rem = blockIdx.x;
   while (rem >= ntile - ti) {
@@ -926,9 +1011,10 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
   }
   const int tj = ti + rem;
   double *M = A + (size_t)b * n * n;
-  const double *Wb = W + (size_t)b * kTB * n;
-  const double *Rb = Rg + (size_t)b * kTB * n;
-  const int k0 = K * kTB, k1 = min(n, k0 + kTB);
+  const double *Wb = Wp + (size_t)b * kPB * n;
+  const double *Sw = Wst + (size_t)b * kPB * n;
+  const double *Sr = Rst + (size_t)b * kPB * n;
+  const int k1 = k0 + kb;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ln = lane & 15, lq = lane >> 4;
   const int i0 = ti * 64 + (wave >> 1) * 32, j0 = tj * 64 + (wave & 1) * 32;
@@ -938,34 +1024,49 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 2; ++v) acc[u][v] = doublex4s{0.0, 0.0, 0.0, 0.0};
-  // all operand loads first, from clamped addresses (a load under a condition
-  // is waited for before the next one is issued), then the products
-  double av[kTB / 4][2], bv[kTB / 4][2];
+  const int ic[2] = {min(i0 + ln, n - 1), min(i0 + 16 + ln, n - 1)};
+  const int jc[2] = {min(j0 + ln, n - 1), min(j0 + 16 + ln, n - 1)};
+  const double mi[2] = {i0 + ln < n ? 1.0 : 0.0, i0 + 16 + ln < n ? 1.0 : 0.0};
+  const double mj[2] = {j0 + ln < n ? 1.0 : 0.0, j0 + 16 + ln < n ? 1.0 : 0.0};
+  // operand loads from clamped addresses (stack rows kb.. up to the next
+  // multiple of 32 are the zero rows of a partial last step), masked by a
+  // multiply once they have arrived
+  double av[2][4][2], bv[2][4][2];
+  auto load = [&](int c, int buf) {
 #pragma unroll
-  for (int ks = 0; ks < kTB / 4; ++ks) {
-    const int kk = 4 * ks + lq;
+    for (int ks = 0; ks < 4; ++ks) {
+      const size_t kk = (size_t)(c + 4 * ks + lq) * n;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      av[ks][u] = Rb[(size_t)kk * n + min(i0 + 16 * u + ln, n - 1)];   // A[i][kk] = R[kk][i]
-      bv[ks][u] = Wb[(size_t)kk * n + min(j0 + 16 * u + ln, n - 1)];   // B[kk][j] = W[kk][j]
+      for (int u = 0; u < 2; ++u) {
+        av[buf][ks][u] = Sr[kk + ic[u]];   // A[i][k] = R[k][i]
+        bv[buf][ks][u] = Sw[kk + jc[u]];   // B[k][j] = W[k][j]
+      }
     }
-  }
+  };
+  const int nk = (kb + 15) & ~15;
+  load(0, 0);
 #pragma unroll
-  for (int ks = 0; ks < kTB / 4; ++ks) {
+  for (int c = 0; c < kPB; c += 16) {
+    if (c >= nk) break;   // wave-uniform
+    const int cur = (c >> 4) & 1;
+    if (c + 16 < nk) load(c + 16, cur ^ 1);
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      if (i0 + 16 * u + ln >= n) av[ks][u] = 0.0;
-      if (j0 + 16 * u + ln >= n) bv[ks][u] = 0.0;
+    for (int ks = 0; ks < 4; ++ks) {
+      double a[2], bb[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        a[u] = av[cur][ks][u] * mi[u];
+        bb[u] = bv[cur][ks][u] * mj[u];
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bb[v], acc[u][v], 0, 0, 0);
     }
-#pragma unroll
-    for (int u = 0; u < 2; ++u)
-#pragma unroll
-      for (int v = 0; v < 2; ++v)
-        acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][u], bv[ks][v], acc[u][v], 0, 0,
-                                                         0);
   }
   // all loads of the write phase are issued before any store (the output
-  // entries are distinct and W is not written here)
+  // entries are distinct and Wp is not written here)
   double old[2][2][4];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -997,8 +1098,9 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
 }
 
 size_t spd_inverse_scratch_doubles(int n, int batch) {
-  // W and R of kTB rows, scale, two norms per matrix
-  return (size_t)batch * kTB * n * 2 + (size_t)batch * n + 2 * (size_t)batch;
+  // the panel (Wp) and the stacked rows after (Wst) and before (Rst) each
+  // step, kPB x n each; scale; two norms per matrix
+  return (size_t)batch * n * (3 * kPB + 1) + 2 * (size_t)batch;
 }
 
 __global__ void zero_doubles_kernel(double *x, size_t n) {
@@ -1009,21 +1111,40 @@ __global__ void zero_doubles_kernel(double *x, size_t n) {
 int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag, double *kappa,
                         hipStream_t s) {
   if (batch <= 0 || n <= 0) return 0;
-  double *W = scratch;
-  double *scale = scratch + (size_t)batch * kTB * n * 2;
-  const int NB = (n + kTB - 1) / kTB;
-  double *nrm = scale + (size_t)batch * n;
+  const size_t bn = (size_t)batch * n;
+  double *Wp = scratch, *Wst = Wp + bn * kPB, *Rst = Wst + bn * kPB;
+  double *scale = Rst + bn * kPB;
+  double *nrm = scale + bn;
   // norm accumulators start at zero (a kernel, not a memset node, so that the
   // sequence may sit inside a captured graph)
   if (kappa) zero_doubles_kernel<<<(2 * batch + 255) / 256, 256, 0, s>>>(nrm, 2 * (size_t)batch);
   jacobi_scale_kernel<<<dim3((n + 255) / 256, batch), 256, 0, s>>>(A, n, scale, flag);
   const dim3 sgrid((n + 3) / 4, batch);
   apply_scale_kernel<<<sgrid, 256, 0, s>>>(A, n, scale, 1.0, kappa ? nrm : nullptr);
-  double *R = W + (size_t)batch * kTB * n;
   const int nt = (n + 63) / 64;
-  for (int K = 0; K < NB; ++K) {
-    sweep_rows_kernel<<<dim3((n + kTJ - 1) / kTJ, batch), 64, 0, s>>>(A, n, K, W, R, flag);
-    sweep_update_mfma_kernel<<<dim3(nt * (nt + 1) / 2, batch), 256, 0, s>>>(A, n, K, W, R, nt);
+  const int pc_blocks = (int)std::min<size_t>(((size_t)kPB * n + 255) / 256, 1024);
+  const dim3 ugrid(nt * (nt + 1) / 2, batch);
+  if (batch < kTwoLevelBatch || n <= kTwoLevelN) {
+    // one trailing update per 32 pivots, straight from the matrix rows
+    for (int k0 = 0; k0 < n; k0 += kTB) {
+      const int kb = std::min(kTB, n - k0);
+      sweep_rows_kernel<<<dim3((n + kTJ - 1) / kTJ, batch), 64, 0, s>>>(
+          A + (size_t)k0 * n, (size_t)n * n, n, k0, Wst, Rst, (size_t)kPB * n, flag);
+      sweep_update_mfma_kernel<<<ugrid, 256, 0, s>>>(A, n, k0, kb, Wst, Wst, Rst, nt);
+    }
+  } else {
+    for (int k0 = 0; k0 < n; k0 += kPB) {
+      const int kb = std::min(kPB, n - k0);
+      panel_copy_kernel<<<dim3(pc_blocks, batch), 256, 0, s>>>(A, n, k0, kb, Wp);
+      for (int t0 = 0; t0 < kb; t0 += kTB) {
+        const size_t off = (size_t)t0 * n;
+        sweep_rows_kernel<<<dim3((n + kTJ - 1) / kTJ, batch), 64, 0, s>>>(
+            Wp + off, (size_t)kPB * n, n, k0 + t0, Wst + off, Rst + off, (size_t)kPB * n, flag);
+        sweep_panel_kernel<<<dim3((n + 63) / 64, (kb + 15) / 16, batch), 256, 0, s>>>(
+            Wp, n, k0, kb, k0 + t0, Wst + off, Rst + off);
+      }
+      sweep_update_mfma_kernel<<<ugrid, 256, 0, s>>>(A, n, k0, kb, Wp, Wst, Rst, nt);
+    }
   }
   apply_scale_kernel<<<sgrid, 256, 0, s>>>(A, n, scale, -1.0, kappa ? nrm + batch : nullptr);
   if (kappa) kappa_product_kernel<<<(batch + 255) / 256, 256, 0, s>>>(nrm, batch, kappa);

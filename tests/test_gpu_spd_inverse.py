@@ -4,7 +4,10 @@ The routine inverts every Schwarz block and the coarse Schur complements, so
 it is checked directly against numpy's LU-based inverse on seeded SPD
 matrices with scaled condition numbers up to ~1e7: sizes cover the one-tile
 case, the panel-wide path with a ragged last pivot block and the tiled path
-(n > 384); batches cover one matrix and a full chunk of distinct matrices.
+(n > 384); batches below 8 and sizes up to 384 take one trailing update per
+32 pivots, the rest the 128-pivot panels (ragged last panels of 116 and 5
+pivots at n = 500, 1029); batches cover one matrix and a full chunk of
+distinct matrices.
 Error bound: ||X - A^-1||_max / ||A^-1||_max <= 1e-14 * n * kappa(scaled)."""
 import numpy as np
 import pytest
@@ -25,7 +28,7 @@ def _spd_batch(n, batch, seed):
 
 
 @pytest.mark.parametrize("n,batch", [(25, 3), (49, 7), (125, 40), (343, 1), (343, 272),
-                                     (375, 5), (500, 2)])
+                                     (375, 5), (500, 2), (500, 9), (1029, 8)])
 def test_batched_spd_inverse(n, batch):
     import torch
     from paper_2010_00881_amd.fcm import spd_inverse

@@ -48,7 +48,7 @@ def test_noalloc_matches_allocating_entry_point():
 def test_noalloc_rejects_oversized_request():
     import torch
     from paper_2010_00881_amd.fcm import FcmError, spd_inverse_noalloc
-    # 2 * 32 * 1000 + 1000 + 2 doubles per matrix: 65 matrices exceed 4 Mi doubles
-    A = torch.zeros((65, 1000, 1000), dtype=torch.float64, device="cuda")
+    # 385 * 1000 + 2 doubles per matrix: 11 matrices exceed 4 Mi doubles
+    A = torch.zeros((11, 1000, 1000), dtype=torch.float64, device="cuda")
     with pytest.raises(FcmError, match="static device buffer"):
         spd_inverse_noalloc(A)
