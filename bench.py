@@ -39,8 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # the reading of a 1 GiB elementwise copy); constants of the kernels as
 # profiled, reported as null for any other configuration.
 GEMV_TRAFFIC = {
-    "elasticity": None,   # profiles/patch_gemv_band_elast24_p4_traffic.md
-    "poisson": 2.215e9,   # profiles/patch_gemv_cube32_p3_traffic.md
+    "elasticity": 53.682e9,   # profiles/patch_gemv_band_elast24_p4_traffic.md
+    "poisson": None,          # profiles/patch_gemv_cube32_p3_traffic.md (re-measured below)
 }
 
 
@@ -247,6 +247,9 @@ def _run_steps(kind, n, seeds, precision, smoother="patchwise"):
             raise RuntimeError(f"{kind} solve of seed {sd} ({precision}) did not converge: {info}")
         recs.append({"lat": lat, "it": info["iterations"], "setup": info["t_setup_ms"],
                      "solve": info["t_solve_ms"], "res": info["true_rel_res"]})
+        print(f"[bench] {kind} seed {sd} {precision}: {lat:.0f} ms (setup {info['t_setup_ms']:.0f}, "
+              f"solve {info['t_solve_ms']:.0f}, {info['iterations']} it)", file=sys.stderr,
+              flush=True)
     return recs
 
 
@@ -303,6 +306,7 @@ def _kernel_figures(kind, n, precision, smoother="patchwise"):
 def _summary(recs):
     lat = [r["lat"] for r in recs]
     return {
+        "latency_ms": lat,
         "p50_ms": statistics.median(lat),
         "p99_ms": sorted(lat)[max(0, int(round(0.99 * len(lat))) - 1)],
         "setup_ms_median": statistics.median(r["setup"] for r in recs),

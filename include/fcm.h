@@ -252,7 +252,7 @@ fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s);
 /* Benchmark hook: launch one operator of the solve `reps` times between two
  * HIP events recorded on `stream` and report the average time per launch and
  * the algorithmic bytes one launch must move (inputs read once, outputs
- * written once, matrices streamed once; see the design notes).
+ * written once, matrices streamed once).
  * op: FCM_OP_SMOOTH (Schwarz smoother of `level`, handle precision),
  *     FCM_OP_RESIDUAL (residual update r -= omega A delta of `level`),
  *     FCM_OP_COARSE (one exact coarse solve), FCM_OP_VCYCLE (one V-cycle,

@@ -901,6 +901,7 @@ void launch_patch_op(const Geo &g, const Tables &t, const PatchTables &pt, const
       const int nbands = (a.ntile + kBandT - 1) / kBandT, npairs = nbands * (nbands + 1) / 2;
       patch_gemv_band_kernel<T><<<a.npu * npairs, 256, 0, s>>>(g, pt.pxoff, pt.pinfo, a, nbands,
                                                                npairs, a.Pband);
+      if (a.stored_only) return;   // timing hook: the band kernel alone
       const size_t rows = (size_t)a.npu * a.m;
       patch_band_reduce_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, s>>>(
           a.Pband, a.m, nbands, npairs, a.npu, a.Yu);
