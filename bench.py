@@ -40,7 +40,7 @@ HBM_PEAK_GBS = 8000.0
 # profiled, reported as null for any other configuration.
 GEMV_TRAFFIC = {
     "elasticity": 53.682e9,   # profiles/patch_gemv_band_elast24_p4_traffic.md
-    "poisson": None,          # profiles/patch_gemv_cube32_p3_traffic.md (re-measured below)
+    "poisson": 2.231e9,       # profiles/patch_gemv_cube32_p3_traffic.md
 }
 
 
