@@ -136,6 +136,10 @@ typedef struct {
   int max_iter;               /* CG iteration cap (500 in the paper)             */
   int use_graphs;             /* 1: replay each CG iteration as a captured HIP
                                  graph on a library-owned stream (0: eager)     */
+  int autotune;               /* 1: at setup, time the launch variants of the
+                                 patchwise smoother on this problem's data and
+                                 keep the fastest (cached per problem shape in
+                                 the process); 0: fixed heuristics            */
 } fcm_options;
 
 typedef struct {
@@ -216,6 +220,23 @@ fcm_status fcm_vcycle(fcm_handle *h, const double *r_dev, double *z_dev,
 fcm_status fcm_pcg_solve(fcm_handle *h, const double *b_dev, double *x_dev,
                          fcm_solve_info *info, void *stream);
 
+/* Batched MG-PCG (systems batching, not in the paper): solves the n problems
+ * of the handles hs[0..n-1] (sizes, orders and dimensions may differ;
+ * uniform grids only, every handle set up with use_graphs = 1), each with
+ * its assembled right-hand side, into x_dev[i] (caller-owned device vectors
+ * of the handle's fine-level padded length).  After every problem's first
+ * iteration, each CG step of all unfinished problems is ONE hipGraphLaunch of
+ * a graph whose child graphs are the problems' captured CG iterations; the
+ * graph is rebuilt when a problem finishes.  Per problem the arithmetic is
+ * that of fcm_pcg_solve (same kernels in the same order: identical iterates).
+ * infos[i] (may be NULL) as fcm_pcg_solve with t_solve_ms = the batch's wall
+ * time; status[i] (may be NULL) each problem's status.  Returns the worst
+ * status (a negative one, else FCM_NOT_CONVERGED if any, else FCM_OK); a
+ * handle that is null, multi-level, repeated or without graphs is
+ * FCM_ERR_ARG with nothing launched.  Synchronises the handles' streams.   */
+fcm_status fcm_pcg_solve_batched(fcm_handle *const *hs, int n, double *const *x_dev,
+                                 fcm_solve_info *infos, fcm_status *status, void *stream);
+
 /* The V-cycle as a stand-alone solver: x <- x + V(b - A x) (Section 4,
  * eq. contraction).  *rho_max receives the largest contraction number.     */
 fcm_status fcm_mg_solve(fcm_handle *h, const double *b_dev, double *x_dev,
@@ -248,6 +269,19 @@ typedef struct {
   int64_t n_fp64_blocks;      /* unique Schwarz blocks applied in FP64 (mixed)   */
 } fcm_stats;
 fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s);
+
+/* Launch variants of the patchwise smoother of level l >= 1 (set at setup by
+ * the autotuner, or by the heuristics when options.autotune = 0):
+ * class_rows = rows of the class inverse per workgroup of the class-product
+ * kernel divided by 128 (1, 2 or 3; mixed form, blocks above 32), gemv_band =
+ * 1 when the unique-patch inverses are streamed by band pairs, 0 one
+ * workgroup per patch.  fcm_set_tuning overrides them (0 < class_rows <= 3,
+ * gemv_band 0 or 1; band pairs are the only kernel above 384 unknowns; -1
+ * keeps a value); every variant computes the same products (class rows:
+ * identical bits; band pairs: the row sums in another order).               */
+fcm_status fcm_get_tuning(const fcm_handle *h, int level, int *class_rows, int *gemv_band,
+                          double *tune_ms);
+fcm_status fcm_set_tuning(fcm_handle *h, int level, int class_rows, int gemv_band);
 
 /* Benchmark hook: launch one operator of the solve `reps` times between two
  * HIP events recorded on `stream` and report the average time per launch and

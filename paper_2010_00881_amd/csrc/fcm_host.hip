@@ -13,6 +13,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -627,6 +628,8 @@ static fcm_status build_units(fcm_handle *h, int l) {
   return upload(h, &h->lev[l].units, units);
 }
 
+static fcm_status autotune_levels(fcm_handle *h);
+
 static fcm_status setup_levels(fcm_handle *h) {
   const Geo &g = h->geo;
   int *belems = nullptr;
@@ -985,11 +988,11 @@ static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *d
   const int mtop = h->lev[h->L].mpatch;
   TRY(dalloc(h, &h->pYs, (size_t)std::max(1, h->np_shared) * mtop));
   TRY(dalloc(h, &h->pYu, (size_t)std::max(1, h->np_unique) * mtop));
-  // band-pair partial products of the large-block unique GEMV
+  // band-pair partial products of the unique GEMV (every level: the
+  // autotuner may pick band pairs below kSmallPatchM too)
   size_t nband = 0;
   for (int l = 1; l <= h->L; ++l) {
     const int m = h->lev[l].mpatch;
-    if (m <= kSmallPatchM) continue;
     const int nb = ((m + 15) / 16 + 15) / 16;
     nband = std::max(nband, (size_t)nb * (nb + 1) / 2 * 512);
   }
@@ -1167,6 +1170,7 @@ static fcm_status do_setup(fcm_handle *h) {
     set_error("pinned host allocation failed");
     return FCM_ERR_OOM;
   }
+  if (h->opt.smoother == FCM_SMOOTH_PATCHWISE) TRY(autotune_levels(h));
   FCM_HIP(hipStreamSynchronize(h->stream));
   return FCM_OK;
 }
@@ -1262,6 +1266,8 @@ static PatchArgs<T> patch_args(fcm_handle *h, int l, bool mixed) {
   a.Ys = h->pYs;
   a.Yu = h->pYu;
   a.Pband = h->pband;
+  a.class_rows = L.class_rows;
+  a.gemv_band = L.gemv_band;
   return a;
 }
 
@@ -1338,6 +1344,112 @@ static void vcycle_level(fcm_handle *h, int l, const T *b, T *x, hipStream_t s) 
       launch_elem_op<T>(g, h->tab, ap, s);
     }
   }
+}
+
+// ----------------------------------------------------------- autotuner
+// Launch variants of the patchwise smoother per level: the rows of the class
+// inverse per class-product workgroup (128, 256 or 384; mixed form, blocks
+// above 32) and, for blocks up to kSmallPatchM, the unique-patch GEMV by one
+// workgroup per patch or by band pairs.  With options.autotune the first
+// handle of a problem shape times every candidate on its own data (three
+// event-timed smoother launches after one warm-up, on the handle's stream,
+// class rows first, then the GEMV kind with the best class rows) and keeps
+// the fastest; the choice is cached per shape (dimension, fields, level
+// order, form, and the numbers of class and unique patches to a factor of
+// two) for the rest of the process.
+namespace {
+struct TuneKey {
+  int d, nf, q, mixed, lsh, lsu;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(d, nf, q, mixed, lsh, lsu) < std::tie(o.d, o.nf, o.q, o.mixed, o.lsh, o.lsu);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;
+
+int ilog2(int v) {
+  int r = 0;
+  while (v > 1) {
+    v >>= 1;
+    ++r;
+  }
+  return r;
+}
+}  // namespace
+
+static fcm_status autotune_levels(fcm_handle *h) {
+  const bool mixed = h->opt.precision == FCM_MIXED;
+  hipStream_t s = h->stream;
+  for (int l = 1; l <= h->L; ++l) {
+    Level &L = h->lev[l];
+    const int m = L.mpatch;
+    L.class_rows = m > 256 ? 3 : m > 128 ? 2 : 1;
+    L.gemv_band = m > kSmallPatchM ? 1 : 0;
+    L.tune_ms = 0.0;
+    if (!h->opt.autotune) continue;
+    const TuneKey key{h->geo.d, h->geo.nf, L.q, mixed ? 1 : 0, ilog2(h->np_shared + 1),
+                      ilog2(h->np_unique + 1)};
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end()) {
+        L.class_rows = it->second.first;
+        L.gemv_band = it->second.second;
+        continue;
+      }
+    }
+    auto t_start = std::chrono::steady_clock::now();
+    launch_copy<double>(L.r64, nullptr, L.npad, s);
+    launch_copy<double>(L.x64, nullptr, L.npad, s);
+    hipEvent_t e0, e1;
+    FCM_HIP(hipEventCreate(&e0));
+    FCM_HIP(hipEventCreate(&e1));
+    auto time_smoother = [&]() {
+      smooth_launch<double>(h, l, L.r64, L.d64, L.x64, h->opt.omega, 0, s);
+      hipEventRecord(e0, s);
+      for (int i = 0; i < 3; ++i) smooth_launch<double>(h, l, L.r64, L.d64, L.x64, h->opt.omega, 0, s);
+      hipEventRecord(e1, s);
+      hipEventSynchronize(e1);
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      return ms;
+    };
+    if (mixed && m > 32 && h->np_shared > 0) {
+      int best = L.class_rows;
+      float tbest = 1e30f;
+      for (int c = 1; c <= 3; ++c) {
+        L.class_rows = c;
+        const float t = time_smoother();
+        if (t < tbest) {
+          tbest = t;
+          best = c;
+        }
+      }
+      L.class_rows = best;
+    }
+    if (m <= kSmallPatchM && h->np_unique > 0) {
+      int best = L.gemv_band;
+      float tbest = 1e30f;
+      for (int b = 0; b <= 1; ++b) {
+        L.gemv_band = b;
+        const float t = time_smoother();
+        if (t < tbest) {
+          tbest = t;
+          best = b;
+        }
+      }
+      L.gemv_band = best;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    FCM_HIP(hipGetLastError());
+    L.tune_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+            .count();
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = {L.class_rows, L.gemv_band};
+  }
+  return FCM_OK;
 }
 
 static void vcycle_top(fcm_handle *h, const double *r, double *z, hipStream_t s) {
@@ -1791,6 +1903,42 @@ fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s) {
   return FCM_OK;
 }
 
+fcm_status fcm_get_tuning(const fcm_handle *h, int level, int *class_rows, int *gemv_band,
+                          double *tune_ms) {
+  if (!h || h->ml || h->opt.smoother != FCM_SMOOTH_PATCHWISE || level < 1 || level > h->L) {
+    set_error("fcm_get_tuning: needs a uniform-grid patchwise handle and 1 <= level <= %d",
+              h ? h->L : 0);
+    return FCM_ERR_ARG;
+  }
+  const fcm::Level &L = h->lev[level];
+  if (class_rows) *class_rows = L.class_rows;
+  if (gemv_band) *gemv_band = L.gemv_band;
+  if (tune_ms) *tune_ms = L.tune_ms;
+  return FCM_OK;
+}
+
+fcm_status fcm_set_tuning(fcm_handle *h, int level, int class_rows, int gemv_band) {
+  if (!h || h->ml || h->opt.smoother != FCM_SMOOTH_PATCHWISE || level < 1 || level > h->L ||
+      class_rows == 0 || class_rows > 3 || class_rows < -1 || gemv_band < -1 || gemv_band > 1) {
+    set_error("fcm_set_tuning: invalid handle, level or variant");
+    return FCM_ERR_ARG;
+  }
+  fcm::Level &L = h->lev[level];
+  if (gemv_band == 0 && L.mpatch > kSmallPatchM) {
+    set_error("fcm_set_tuning: blocks of %d unknowns take band pairs only", L.mpatch);
+    return FCM_ERR_ARG;
+  }
+  if (class_rows > 0) L.class_rows = class_rows;
+  if (gemv_band >= 0) L.gemv_band = gemv_band;
+  if (h->cg_exec) {   // a captured iteration holds the old launch parameters
+    hipGraphExecDestroy(h->cg_exec);
+    hipGraphDestroy(h->cg_graph);
+    h->cg_exec = nullptr;
+    h->cg_graph = nullptr;
+  }
+  return FCM_OK;
+}
+
 fcm_status fcm_rhs(fcm_handle *h, double *b_dev, void *stream) {
   if (!h || !b_dev) {
     set_error("null argument");
@@ -1978,6 +2126,104 @@ fcm_status fcm_pcg_solve(fcm_handle *h, const double *b_dev, double *x_dev, fcm_
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   return (fcm_status)cg.status;
+}
+
+fcm_status fcm_pcg_solve_batched(fcm_handle *const *hs, int n, double *const *x_dev,
+                                 fcm_solve_info *infos, fcm_status *status, void *stream) {
+  if (!hs || n < 1 || !x_dev) {
+    set_error("invalid argument");
+    return FCM_ERR_ARG;
+  }
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i] || !x_dev[i] || hs[i]->ml || !hs[i]->opt.use_graphs || !hs[i]->own) {
+      set_error("batched solve: handle %d is null, multi-level hp or without captured graphs", i);
+      return FCM_ERR_ARG;
+    }
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) {
+        set_error("batched solve: handle %d appears twice", i);
+        return FCM_ERR_ARG;
+      }
+  }
+  auto t0 = std::chrono::steady_clock::now();
+  FCM_HIP(hipStreamSynchronize((hipStream_t)stream));   // after the caller's work
+  std::vector<CGState> cg(n);
+  std::vector<fcm_status> st(n, FCM_OK);
+  for (int i = 0; i < n; ++i) {
+    st[i] = cg_begin(hs[i], cg[i], nullptr, x_dev[i], hs[i]->own);
+    if (st[i] < 0) cg[i].done = true;
+  }
+  // the first iteration (no beta) of every problem, each on its own stream
+  for (int i = 0; i < n; ++i)
+    if (!cg[i].done) cg_issue(hs[i], cg[i], hs[i]->own);
+  for (int i = 0; i < n; ++i)
+    if (!cg[i].done) {
+      FCM_HIP(hipStreamSynchronize(hs[i]->own));
+      cg_finish(hs[i], cg[i]);
+      if (!cg[i].done) {
+        st[i] = cg_capture(hs[i], cg[i], hs[i]->own);
+        if (st[i] < 0) cg[i].done = true;
+      }
+    }
+  // steady iterations: the captured iterations of all unfinished problems are
+  // the child graphs of one parent graph, launched once per step; the parent
+  // is rebuilt whenever a problem finishes
+  hipStream_t ls = hs[0]->own;
+  hipGraph_t pg = nullptr;
+  hipGraphExec_t pexec = nullptr;
+  std::vector<int> act, built;
+  fcm_status gst = FCM_OK;
+  for (;;) {
+    act.clear();
+    for (int i = 0; i < n; ++i)
+      if (!cg[i].done) act.push_back(i);
+    if (act.empty()) break;
+    if (act != built) {
+      if (pexec) hipGraphExecDestroy(pexec);
+      if (pg) hipGraphDestroy(pg);
+      pexec = nullptr;
+      pg = nullptr;
+      hipError_t e = hipGraphCreate(&pg, 0);
+      for (size_t k = 0; e == hipSuccess && k < act.size(); ++k) {
+        hipGraphNode_t node;
+        e = hipGraphAddChildGraphNode(&node, pg, nullptr, 0, hs[act[k]]->cg_graph);
+      }
+      if (e == hipSuccess) e = hipGraphInstantiate(&pexec, pg, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        set_error("batched solve: building the step graph failed: %s", hipGetErrorString(e));
+        gst = FCM_ERR_HIP;
+        break;
+      }
+      built = act;
+    }
+    hipError_t e = hipGraphLaunch(pexec, ls);
+    if (e == hipSuccess) e = hipStreamSynchronize(ls);
+    if (e != hipSuccess) {
+      set_error("batched solve: step graph failed: %s", hipGetErrorString(e));
+      gst = FCM_ERR_HIP;
+      break;
+    }
+    for (int i : act) cg_finish(hs[i], cg[i]);
+  }
+  if (pexec) hipGraphExecDestroy(pexec);
+  if (pg) hipGraphDestroy(pg);
+  if (gst < 0) return gst;
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  fcm_status worst = FCM_OK;
+  for (int i = 0; i < n; ++i) {
+    if (st[i] >= 0) st[i] = (fcm_status)cg[i].status;
+    if (infos && st[i] >= 0) {
+      fcm_status rs = cg_report(hs[i], cg[i], &infos[i], hs[i]->own);
+      if (rs < 0) st[i] = rs;
+      infos[i].t_solve_ms = ms;
+    }
+    if (status) status[i] = st[i];
+    if (st[i] < 0 && (worst >= 0 || st[i] < worst)) worst = st[i];
+    else if (worst >= 0 && st[i] == FCM_NOT_CONVERGED) worst = FCM_NOT_CONVERGED;
+  }
+  for (int i = 0; i < n; ++i) FCM_HIP(hipStreamSynchronize(hs[i]->own));
+  return worst;
 }
 
 fcm_status fcm_mg_solve(fcm_handle *h, const double *b_dev, double *x_dev, fcm_solve_info *info,

@@ -62,6 +62,9 @@ struct Level {
   uint8_t *hi64 = nullptr;     // unique blocks applied from FP64 copies in the mixed form
   int n_hi64 = 0;
   int ldp = 0;                 // patchwise: leading dimension of the stored inverses
+  int class_rows = 0;          // patchwise launch variants (autotuner): class-product rows
+  int gemv_band = 0;           //   per workgroup / 128, unique GEMV by band pairs
+  double tune_ms = 0.0;        //   (time the autotuner spent on this level)
   int *units = nullptr;        // owner-kernel work units of this level
   int nunits = 0;
   double *x64 = nullptr, *r64 = nullptr, *d64 = nullptr;
@@ -316,6 +319,8 @@ struct PatchArgs {
   T omega = 0;
   int first = 0;
   int stored_only = 0;            // timing hook: launch only the unique-patch GEMV
+  int class_rows = 0;             // class-product rows per workgroup / 128 (0: by m)
+  int gemv_band = 0;              // 1: unique GEMV by band pairs (always for m > kSmallPatchM)
 };
 template <typename T>
 void launch_patch_op(const Geo &g, const Tables &t, const PatchTables &pt, const PatchArgs<T> &a,

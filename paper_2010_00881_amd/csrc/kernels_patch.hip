@@ -797,10 +797,14 @@ static bool launch_class32(const Geo &g, const PatchTables &pt, const PatchArgs<
     launch_class_tile<T, double, 1>(g, pt, a, s);
     return true;
   }
-  if (a.m > 256) launch_class_tile<T, float, 3>(g, pt, a, s);
-  else if (a.m > 128) launch_class_tile<T, float, 2>(g, pt, a, s);
-  else if (a.m > 32) launch_class_tile<T, float, 1>(g, pt, a, s);
-  else launch_class32_nks<T, 8>(g, pt, a, s);   // nks <= 8
+  if (a.m <= 32) {
+    launch_class32_nks<T, 8>(g, pt, a, s);   // nks <= 8
+    return true;
+  }
+  const int rows = a.class_rows > 0 ? a.class_rows : a.m > 256 ? 3 : a.m > 128 ? 2 : 1;
+  if (rows >= 3) launch_class_tile<T, float, 3>(g, pt, a, s);
+  else if (rows == 2) launch_class_tile<T, float, 2>(g, pt, a, s);
+  else launch_class_tile<T, float, 1>(g, pt, a, s);
   return true;
 }
 
@@ -895,7 +899,7 @@ template <typename T>
 void launch_patch_op(const Geo &g, const Tables &t, const PatchTables &pt, const PatchArgs<T> &a,
                      hipStream_t s) {
   if (a.npu > 0) {
-    if (a.m <= kSmallPatchM) {
+    if (a.m <= kSmallPatchM && !a.gemv_band) {
       patch_gemv_kernel<T><<<a.npu, 256, 0, s>>>(g, pt.pxoff, pt.pinfo, a);
     } else {
       const int nbands = (a.ntile + kBandT - 1) / kBandT, npairs = nbands * (nbands + 1) / 2;

@@ -49,7 +49,8 @@ class Options(ctypes.Structure):
     _fields_ = [("smoother", ctypes.c_int), ("omega", ctypes.c_double),
                 ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
                 ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
-                ("max_iter", ctypes.c_int), ("use_graphs", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("use_graphs", ctypes.c_int),
+                ("autotune", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -92,6 +93,9 @@ SIGNATURES = {
     "fcm_spd_inverse_noalloc": ([_P, ctypes.c_int, ctypes.c_int, _P, _P], ctypes.c_int),
     "fcm_vcycle": ([_P, _P, _P, _P], ctypes.c_int),
     "fcm_pcg_solve": ([_P, _P, _P, ctypes.POINTER(SolveInfo), _P], ctypes.c_int),
+    "fcm_pcg_solve_batched": ([ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(_P),
+                               ctypes.POINTER(SolveInfo), ctypes.POINTER(ctypes.c_int), _P],
+                              ctypes.c_int),
     "fcm_mg_solve": ([_P, _P, _P, ctypes.POINTER(SolveInfo), ctypes.POINTER(ctypes.c_double), _P],
                      ctypes.c_int),
     "fcm_dof_keys": ([_P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -99,6 +103,9 @@ SIGNATURES = {
     "fcm_element": ([_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "fcm_get_stats": ([_P, ctypes.POINTER(Stats)], ctypes.c_int),
+    "fcm_get_tuning": ([_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                        ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "fcm_set_tuning": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "fcm_time_op": ([_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, _P, ctypes.POINTER(ctypes.c_double),
                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "fcm_destroy": ([_P], None),
@@ -208,6 +215,7 @@ def make_options(opts):
     o.rtol = float(opts.get("rtol", 1e-10))
     o.max_iter = int(opts.get("max_iter", 500))
     o.use_graphs = int(opts.get("use_graphs", 1))
+    o.autotune = int(opts.get("autotune", 1))
     return o
 
 
@@ -349,6 +357,16 @@ class Solver:
                                  ctypes.byref(by)))
         return ms.value, by.value
 
+    def tuning(self, level):
+        """Launch variants of the patchwise smoother of a level (autotuner)."""
+        cr, gb, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+        _check(lib().fcm_get_tuning(self.h, int(level), ctypes.byref(cr), ctypes.byref(gb),
+                                    ctypes.byref(ms)))
+        return {"class_rows": cr.value, "gemv_band": gb.value, "tune_ms": ms.value}
+
+    def set_tuning(self, level, class_rows=-1, gemv_band=-1):
+        _check(lib().fcm_set_tuning(self.h, int(level), int(class_rows), int(gemv_band)))
+
     def stats(self):
         s = Stats()
         _check(lib().fcm_get_stats(self.h, ctypes.byref(s)))
@@ -403,6 +421,24 @@ class Server:
 def trim_pool():
     """Return the cached, unused device memory of the library's pool."""
     _check(lib().fcm_trim_pool())
+
+
+def pcg_batched(solvers):
+    """MG-PCG of several problems, each CG step of all of them one graph launch
+    (fcm_pcg_solve_batched).  Returns [(x, info), ...] in the order given."""
+    n = len(solvers)
+    xs = [s._new() for s in solvers]
+    hs = (_P * n)(*[s.h for s in solvers])
+    xp = (_P * n)(*[_ptr(x) for x in xs])
+    infos = (SolveInfo * n)()
+    sts = (ctypes.c_int * n)()
+    _check(lib().fcm_pcg_solve_batched(hs, n, xp, infos, sts, _stream()))
+    out = []
+    for i in range(n):
+        d = infos[i].to_dict()
+        d["status"] = sts[i]
+        out.append((xs[i], d))
+    return out
 
 
 def spd_inverse(A, kappa=None):

@@ -40,7 +40,7 @@ def test_struct_layouts_match_header():
     import ctypes
     from paper_2010_00881_amd import fcm
     # the C structs are plain; sizes follow the C alignment rules for x86-64
-    assert ctypes.sizeof(fcm.Options) == 48  # 7 fields + use_graphs in the tail padding
+    assert ctypes.sizeof(fcm.Options) == 56  # 7 fields, then use_graphs and autotune
     assert ctypes.sizeof(fcm.SolveInfo) == 56
     assert ctypes.sizeof(fcm.Stats) == 64
     assert ctypes.sizeof(fcm.ServerOpts) == 16
