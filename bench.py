@@ -108,8 +108,10 @@ def cpu_baseline(kind, full_dofs, sizes, cores):
 
 def serve_bench(args):
     """Serving stream: seeded requests of mixed grids and orders arriving as a
-    Poisson process, admitted by device-memory footprint and advanced together
-    (one CG iteration per tick); compared with one-at-a-time plain FP64 solves."""
+    Poisson process at each rate of --rate, admitted by device-memory footprint
+    and advanced together (each admitted solve has one CG iteration in flight,
+    replayed from its captured graph, on one of several streams); compared with
+    the same requests solved one at a time in the plain FP64 form."""
     import numpy as np
     import torch
     import fcm_inputs as fi
@@ -117,48 +119,119 @@ def serve_bench(args):
 
     R = args.requests
     reqs = [fi.serving_request(i) for i in range(R)]
-    arrivals = fi.arrival_times(args.rate, R)
-    print(f"[bench] serving {R} requests at {args.rate}/s", file=sys.stderr, flush=True)
-    srv = Server(memory_budget_bytes=int(args.budget_gb * (1 << 30)), max_active=args.slots,
-                 n_streams=4)
-    ids = []
-    t0 = time.perf_counter()
-    for i, (d, o) in enumerate(reqs):
-        now = time.perf_counter() - t0
-        if arrivals[i] > now:
-            time.sleep(arrivals[i] - now)
-        ids.append((srv.submit(d, dict(o, precision="mixed")), time.perf_counter() - t0))
-    done = {}
-    while len(done) < R:
-        for k, (rid, ts) in enumerate(ids):
-            if k not in done:
-                r = srv.poll(rid, 0)
-                if r is not None:
-                    done[k] = (r, ts)
-        time.sleep(0.002)
-    srv.close()
-    lat = [done[k][0]["latency_ms"] for k in range(R)]
-    t_end = max(done[k][1] + done[k][0]["latency_ms"] / 1e3 for k in range(R))
-    failed = [k for k in range(R) if done[k][0]["status"] != 0]
-    served = R / t_end
+    rates = [float(r) for r in str(args.rate).split(",")]
+    runs = []
+    for rate in rates:
+        arrivals = fi.arrival_times(rate, R)
+        print(f"[bench] serving {R} requests at {rate}/s", file=sys.stderr, flush=True)
+        srv = Server(memory_budget_bytes=int(args.budget_gb * (1 << 30)), max_active=args.slots,
+                     n_streams=4)
+        ids = []
+        t0 = time.perf_counter()
+        for i, (d, o) in enumerate(reqs):
+            now = time.perf_counter() - t0
+            if arrivals[i] > now:
+                time.sleep(arrivals[i] - now)
+            ids.append((srv.submit(d, dict(o, precision="mixed")), time.perf_counter() - t0))
+        done = {}
+        while len(done) < R:
+            for k, (rid, ts) in enumerate(ids):
+                if k not in done:
+                    r = srv.poll(rid, 0)
+                    if r is not None:
+                        done[k] = (r, ts)
+                        if len(done) % 64 == 0:
+                            print(f"[bench] {len(done)} of {R} done", file=sys.stderr, flush=True)
+            time.sleep(0.002)
+        srv.close()
+        lat = [done[k][0]["latency_ms"] for k in range(R)]
+        t_end = max(done[k][1] + done[k][0]["latency_ms"] / 1e3 for k in range(R))
+        runs.append({"rate_per_s": rate, "solves_s": R / t_end, "makespan_s": t_end,
+                     "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)),
+                     "failed_requests": [k for k in range(R) if done[k][0]["status"] != 0],
+                     "iterations": [done[k][0]["iterations"] for k in range(R)]})
     print("[bench] one-at-a-time plain FP64", file=sys.stderr, flush=True)
     t1 = time.perf_counter()
-    its = []
-    for d, o in reqs:
+    its, lat1 = [], []
+    for k, (d, o) in enumerate(reqs):
+        t = time.perf_counter()
         s = Solver(d, dict(o, precision="fp64", use_graphs=0))
         _, info = s.pcg()
         torch.cuda.synchronize()
         its.append(info["iterations"])
         s.close()
+        lat1.append((time.perf_counter() - t) * 1e3)
+        if (k + 1) % 64 == 0:
+            print(f"[bench] {k + 1} of {R} alone", file=sys.stderr, flush=True)
     alone = R / (time.perf_counter() - t1)
     out = {
         "metric": "served MG-PCG solves/s (p50/p99 latency) vs one-at-a-time plain FP64",
-        "value": served, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
-        "config": {"workload": f"serving_stream_{R}_requests", "rate_per_s": args.rate,
-                   "slots": args.slots, "budget_gb": args.budget_gb},
-        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-        "one_at_a_time_fp64_solves_s": alone, "speedup": served / alone,
-        "failed_requests": failed, "iterations_fp64": its,
+        "value": runs[0]["solves_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "config": {"workload": f"serving_stream_{R}_requests", "rates_per_s": rates,
+                   "slots": args.slots, "budget_gb": args.budget_gb, "precision": "mixed"},
+        "runs": runs,
+        "one_at_a_time_fp64_solves_s": alone,
+        "one_at_a_time_fp64_p50_ms": float(np.percentile(lat1, 50)),
+        "one_at_a_time_fp64_p99_ms": float(np.percentile(lat1, 99)),
+        "speedup": [r["solves_s"] / alone for r in runs],
+        "iterations_fp64": its,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def batch_bench(args):
+    """Throughput batch of the 16^2 p = 2 plate (856 unknowns each, seeds
+    0..B-1): one problem at a time in the plain FP64 form against all B set up
+    and then solved together, every CG step of all of them one graph launch
+    (mixed form)."""
+    import torch
+    import fcm_inputs as fi
+    from paper_2010_00881_amd import Solver
+    from paper_2010_00881_amd.fcm import pcg_batched
+    B = args.batch
+
+    def prob(sd, prec):
+        d, o = fi.plate_with_hole(sd)
+        return d, dict(o, precision=prec)
+
+    for sd in range(1000, 1000 + max(1, args.warmup)):   # warm-up: tuner, pool, code objects
+        s = Solver(*prob(sd, "mixed"))
+        s.pcg()
+        s.close()
+    print(f"[bench] batch of {B}: one at a time, FP64", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    solve1 = 0.0
+    for sd in range(B):
+        s = Solver(*prob(sd, "fp64"))
+        _, info = s.pcg()
+        solve1 += info["t_solve_ms"]
+        s.close()
+    torch.cuda.synchronize()
+    t_alone = time.perf_counter() - t0
+    print(f"[bench] batch of {B}: batched, mixed", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    solvers = [Solver(*prob(sd, "mixed")) for sd in range(B)]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t1
+    t2 = time.perf_counter()
+    res = pcg_batched(solvers)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t2
+    bad = [k for k, (_, i) in enumerate(res) if i["status"] != 0]
+    for s in solvers:
+        s.close()
+    out = {
+        "metric": "batched MG-PCG solves/s (one graph launch per CG step) vs one at a time",
+        "value": B / (t_setup + t_solve), "unit": "solves/s", "n_gpus": 1,
+        "higher_is_better": True,
+        "config": {"workload": f"plate16_p2_batch_{B}", "dofs_each": 856, "precision": "mixed"},
+        "batched_solve_phase_s": t_solve, "batched_setup_phase_s": t_setup,
+        "one_at_a_time_fp64_solves_s": B / t_alone,
+        "one_at_a_time_fp64_solve_phase_s": solve1 / 1e3,
+        "solve_phase_speedup": (solve1 / 1e3) / t_solve,
+        "iterations": [i["iterations"] for _, i in res], "failed": bad,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -323,7 +396,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--workload", default="elasticity",
-                    choices=["elasticity", "poisson", "serving", "mlhp"],
+                    choices=["elasticity", "poisson", "serving", "batch", "mlhp"],
                     help="elasticity: the 24^3 p = 4 solve benchmark (default); poisson: the "
                          "32^3 p = 3 cube; serving: the request stream; mlhp: the multi-level "
                          "hp sphere problem")
@@ -337,7 +410,8 @@ def main():
     ap.add_argument("--mlhp-k", type=int, default=1)
     ap.add_argument("--mlhp-p", type=int, default=3)
     ap.add_argument("--requests", type=int, default=64)
-    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--rate", default="200", help="arrival rate(s) per s, comma separated")
+    ap.add_argument("--batch", type=int, default=64, help="problems of the batch workload")
     ap.add_argument("--slots", type=int, default=16)
     ap.add_argument("--budget-gb", type=float, default=96.0)
     ap.add_argument("--pmc-calibration", action="store_true",
@@ -350,6 +424,8 @@ def main():
 
     if args.workload == "serving":
         return serve_bench(args)
+    if args.workload == "batch":
+        return batch_bench(args)
     if args.workload == "mlhp":
         return mlhp_bench(args)
 

@@ -108,6 +108,20 @@ def plate_with_hole(seed: int = 0, n: int = 16, p: int = 2):
     return d, o
 
 
+def island_plate(p: int = 2):
+    """5 x 5 cells on the unit square, u = 0 on the box edges, f as the seed-0
+    plate; holes of radius 0.15 centred on the 8 cells around the centre cell
+    fill those cells (void) and cut the centre cell, which is then enclosed by
+    void cells: an island touching no Dirichlet edge (no random draws beyond
+    the plate's sources)."""
+    d, o = plate_with_hole(0, n=5, p=p)
+    d["ball_c"] = [[0.1 + 0.2 * i, 0.1 + 0.2 * j] for i in (1, 2, 3) for j in (1, 2, 3)
+                   if (i, j) != (2, 2)]
+    d["ball_r"] = [0.15] * 8
+    d["name"] = f"island_plate_5x5_p{p}"
+    return d, o
+
+
 def _voids(rng, count=8):
     centres = rng.uniform(0.15, 0.85, (count, 3))
     radii = rng.uniform(0.05, 0.12, count)

@@ -222,17 +222,17 @@ fcm_status fcm_pcg_solve(fcm_handle *h, const double *b_dev, double *x_dev,
 
 /* Batched MG-PCG (systems batching, not in the paper): solves the n problems
  * of the handles hs[0..n-1] (sizes, orders and dimensions may differ;
- * uniform grids only, every handle set up with use_graphs = 1), each with
- * its assembled right-hand side, into x_dev[i] (caller-owned device vectors
- * of the handle's fine-level padded length).  After every problem's first
- * iteration, each CG step of all unfinished problems is ONE hipGraphLaunch of
- * a graph whose child graphs are the problems' captured CG iterations; the
- * graph is rebuilt when a problem finishes.  Per problem the arithmetic is
- * that of fcm_pcg_solve (same kernels in the same order: identical iterates).
- * infos[i] (may be NULL) as fcm_pcg_solve with t_solve_ms = the batch's wall
- * time; status[i] (may be NULL) each problem's status.  Returns the worst
- * status (a negative one, else FCM_NOT_CONVERGED if any, else FCM_OK); a
- * handle that is null, multi-level, repeated or without graphs is
+ * uniform grids only), each with its assembled right-hand side, into x_dev[i]
+ * (caller-owned device vectors of the handle's fine-level padded length).
+ * After every problem's first iteration, each CG step of all unfinished
+ * problems is ONE hipGraphLaunch of a graph holding their iterations as
+ * independent branches (captured with each problem on its own stream); the
+ * graph is captured again when a problem finishes.  Per problem the
+ * arithmetic is that of fcm_pcg_solve (same kernels in the same order:
+ * identical iterates).  infos[i] (may be NULL) as fcm_pcg_solve with
+ * t_solve_ms = the batch's wall time; status[i] (may be NULL) each problem's
+ * status.  Returns the worst status (a negative one, else FCM_NOT_CONVERGED
+ * if any, else FCM_OK); a handle that is null, multi-level or repeated is
  * FCM_ERR_ARG with nothing launched.  Synchronises the handles' streams.   */
 fcm_status fcm_pcg_solve_batched(fcm_handle *const *hs, int n, double *const *x_dev,
                                  fcm_solve_info *infos, fcm_status *status, void *stream);

@@ -103,6 +103,7 @@ class Discretization:
             idx = tuple(reversed(e))
             lo, hi = self.elem_box(idx)
             state[e] = classify_box(self.desc, lo, hi)
+        self._drop_floating(state)
         self.state = state
         flat = state.reshape(-1)                         # axis 0 fastest
         self.kept = np.nonzero(flat != VOID)[0]
@@ -114,6 +115,31 @@ class Discretization:
             idx[:, ax] = rem % self.n[ax]
             rem //= self.n[ax]
         self.kept_idx = idx
+
+    def _drop_floating(self, state):
+        """Kept elements whose component (elements sharing a node) touches no
+        Dirichlet face are dropped like void ones: constants on such an island
+        have zero energy, so the system would be singular (reading R23).  Only
+        overlapping holes that enclose cells produce them; problems without
+        Dirichlet faces are left as they are."""
+        from scipy import ndimage
+        faces = int(self.desc.get("dirichlet_faces", 0))
+        if faces == 0:
+            return
+        d = self.dim
+        kept = state != VOID                              # indexed [e_{d-1}, ..., e_0]
+        labels, count = ndimage.label(kept, structure=np.ones((3,) * d, dtype=bool))
+        anchored = set()
+        for ax in range(d):
+            arr_ax = d - 1 - ax                            # array axis of grid axis ax
+            for side in (0, 1):
+                if faces >> (2 * ax + side) & 1:
+                    sl = [slice(None)] * d
+                    sl[arr_ax] = 0 if side == 0 else -1
+                    anchored.update(np.unique(labels[tuple(sl)]).tolist())
+        anchored.discard(0)
+        floating = kept & ~np.isin(labels, list(anchored))
+        state[floating] = VOID
 
     # ---------------------------------------------------------------------- DOFs
     def _entity_codes(self, e_idx):

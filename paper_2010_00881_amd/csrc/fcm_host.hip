@@ -500,6 +500,52 @@ static void build_blocks(fcm_handle *h) {
   h->h_block_elems.insert(h->h_block_elems.end(), uniq.begin(), uniq.end());
 }
 
+// Kept elements whose component (elements sharing a grid node) touches no
+// Dirichlet face are dropped like void ones: constants on such an island have
+// zero energy and would make the system singular.  Only overlapping holes
+// that enclose cells produce them; without Dirichlet faces nothing changes.
+// Returns whether an element was dropped.
+static bool drop_floating(const Geo &g, std::vector<uint8_t> &state) {
+  if (g.dir == 0) return false;
+  std::vector<uint8_t> reach(g.E, 0);
+  std::vector<int> stack;
+  for (int e = 0; e < g.E; ++e) {
+    if (state[e] == kVoid) continue;
+    const int c[3] = {e % g.n[0], (e / g.n[0]) % g.n[1], e / (g.n[0] * g.n[1])};
+    bool face = false;
+    for (int ax = 0; ax < g.d; ++ax) {
+      if (c[ax] == 0 && ((g.dir >> (2 * ax)) & 1)) face = true;
+      if (c[ax] == g.n[ax] - 1 && ((g.dir >> (2 * ax + 1)) & 1)) face = true;
+    }
+    if (face) {
+      reach[e] = 1;
+      stack.push_back(e);
+    }
+  }
+  while (!stack.empty()) {
+    const int e = stack.back();
+    stack.pop_back();
+    const int c[3] = {e % g.n[0], (e / g.n[0]) % g.n[1], e / (g.n[0] * g.n[1])};
+    for (int dz = (g.d == 3 ? -1 : 0); dz <= (g.d == 3 ? 1 : 0); ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int x = c[0] + dx, y = c[1] + dy, z = c[2] + dz;
+          if (x < 0 || y < 0 || z < 0 || x >= g.n[0] || y >= g.n[1] || z >= g.n[2]) continue;
+          const int f = x + g.n[0] * (y + g.n[1] * z);
+          if (state[f] == kVoid || reach[f]) continue;
+          reach[f] = 1;
+          stack.push_back(f);
+        }
+  }
+  bool dropped = false;
+  for (int e = 0; e < g.E; ++e)
+    if (state[e] != kVoid && !reach[e]) {
+      state[e] = kVoid;
+      dropped = true;
+    }
+  return dropped;
+}
+
 static fcm_status check_flag(fcm_handle *h, const char *what) {
   int f = 0;
   FCM_HIP(hipMemcpyAsync(&f, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -1013,6 +1059,8 @@ static fcm_status do_setup(fcm_handle *h) {
   h->h_state.resize(g.E);
   FCM_HIP(hipMemcpyAsync(h->h_state.data(), h->state, g.E, hipMemcpyDeviceToHost, h->stream));
   FCM_HIP(hipStreamSynchronize(h->stream));
+  if (drop_floating(g, h->h_state))
+    FCM_HIP(hipMemcpyAsync(h->state, h->h_state.data(), g.E, hipMemcpyHostToDevice, h->stream));
   h->h_kmat.assign(g.E, -1);
   h->h_cut.clear();
   for (int e = 0; e < g.E; ++e) {
@@ -2135,8 +2183,8 @@ fcm_status fcm_pcg_solve_batched(fcm_handle *const *hs, int n, double *const *x_
     return FCM_ERR_ARG;
   }
   for (int i = 0; i < n; ++i) {
-    if (!hs[i] || !x_dev[i] || hs[i]->ml || !hs[i]->opt.use_graphs || !hs[i]->own) {
-      set_error("batched solve: handle %d is null, multi-level hp or without captured graphs", i);
+    if (!hs[i] || !x_dev[i] || hs[i]->ml || !hs[i]->own) {
+      set_error("batched solve: handle %d is null or multi-level hp", i);
       return FCM_ERR_ARG;
     }
     for (int j = 0; j < i; ++j)
@@ -2160,18 +2208,17 @@ fcm_status fcm_pcg_solve_batched(fcm_handle *const *hs, int n, double *const *x_
     if (!cg[i].done) {
       FCM_HIP(hipStreamSynchronize(hs[i]->own));
       cg_finish(hs[i], cg[i]);
-      if (!cg[i].done) {
-        st[i] = cg_capture(hs[i], cg[i], hs[i]->own);
-        if (st[i] < 0) cg[i].done = true;
-      }
     }
-  // steady iterations: the captured iterations of all unfinished problems are
-  // the child graphs of one parent graph, launched once per step; the parent
-  // is rebuilt whenever a problem finishes
+  // steady iterations: one graph holds the iterations of all unfinished
+  // problems as independent branches (captured from the launch stream, each
+  // problem forked onto its own stream and joined back), launched once per
+  // step; it is captured again whenever a problem finishes
   hipStream_t ls = hs[0]->own;
   hipGraph_t pg = nullptr;
   hipGraphExec_t pexec = nullptr;
   std::vector<int> act, built;
+  std::vector<hipEvent_t> ev(n + 1, nullptr);
+  for (auto &e : ev) FCM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   fcm_status gst = FCM_OK;
   for (;;) {
     act.clear();
@@ -2183,11 +2230,24 @@ fcm_status fcm_pcg_solve_batched(fcm_handle *const *hs, int n, double *const *x_
       if (pg) hipGraphDestroy(pg);
       pexec = nullptr;
       pg = nullptr;
-      hipError_t e = hipGraphCreate(&pg, 0);
+      // the launch stream is hs[0]->own: problem 0 runs on it directly
+      hipError_t e = hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) e = hipEventRecord(ev[n], ls);
       for (size_t k = 0; e == hipSuccess && k < act.size(); ++k) {
-        hipGraphNode_t node;
-        e = hipGraphAddChildGraphNode(&node, pg, nullptr, 0, hs[act[k]]->cg_graph);
+        const int i = act[k];
+        hipStream_t si = hs[i]->own;
+        if (si != ls) e = hipStreamWaitEvent(si, ev[n], 0);
+        if (e != hipSuccess) break;
+        CGState steady = cg[i];
+        steady.first = false;
+        cg_issue_body(hs[i], steady, si);
+        if (si != ls) {
+          e = hipEventRecord(ev[i], si);
+          if (e == hipSuccess) e = hipStreamWaitEvent(ls, ev[i], 0);
+        }
       }
+      hipError_t e2 = hipStreamEndCapture(ls, &pg);
+      if (e == hipSuccess) e = e2;
       if (e == hipSuccess) e = hipGraphInstantiate(&pexec, pg, nullptr, nullptr, 0);
       if (e != hipSuccess) {
         set_error("batched solve: building the step graph failed: %s", hipGetErrorString(e));
@@ -2205,6 +2265,7 @@ fcm_status fcm_pcg_solve_batched(fcm_handle *const *hs, int n, double *const *x_
     }
     for (int i : act) cg_finish(hs[i], cg[i]);
   }
+  for (auto &e : ev) hipEventDestroy(e);
   if (pexec) hipGraphExecDestroy(pexec);
   if (pg) hipGraphDestroy(pg);
   if (gst < 0) return gst;

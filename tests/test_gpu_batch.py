@@ -66,8 +66,9 @@ def test_batched_rejects_bad_handles():
     s = Solver(d, o)
     with pytest.raises(FcmError, match="appears twice"):
         pcg_batched([s, s])
-    g = Solver(d, dict(o, use_graphs=0))
-    with pytest.raises(FcmError, match="without captured graphs"):
+    dm, om = fi.sphere_multilevel(0, n=4, k=1, p=2)
+    g = Solver(dict(dm, quad_depth=2), dict(om, precision="fp64"))
+    with pytest.raises(FcmError, match="multi-level hp"):
         pcg_batched([s, g])
     s.close()
     g.close()

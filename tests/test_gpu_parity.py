@@ -39,6 +39,8 @@ CASES = {
     # void on 5^3 at p = 3, whose uncut region gives class patches of m = 1029
     "elast3_p4_patch": lambda: _patch(fi.voided_cube_elasticity(1, n=3, p=4)),
     "elast5_p3_patch_void1": lambda: _patch(_one_void(fi.voided_cube_elasticity(0, n=5, p=3))),
+    # a kept cell enclosed by void cells (dropped, reading R23)
+    "island5_p3_patch": lambda: _patch(fi.island_plate(p=3)),
 }
 
 

@@ -644,3 +644,25 @@ def test_p15_ball_interior_measure_converges(dim):
         errs.append(abs(vol - exact) / exact)
     assert errs[-1] < (2e-3 if dim == 2 else 2e-2), errs
     assert errs[-1] < errs[0] / 4, errs
+
+
+def test_floating_island_is_dropped_and_system_is_spd():
+    """R23: a kept cell enclosed by void cells carries a constant of zero
+    energy (singular A); it is dropped like a void cell, and A is SPD."""
+    import fcm_inputs as fi
+    from oracle import fcm
+    from oracle.geometry import CUT, classify_box
+    d, _ = fi.island_plate()
+    assert classify_box(d, [0.4, 0.4], [0.6, 0.6]) == CUT       # the island cell itself
+    for i, j in [(1, 1), (1, 2), (2, 1), (3, 3)]:
+        assert classify_box(d, [0.2 * i, 0.2 * j], [0.2 * i + 0.2, 0.2 * j + 0.2]) == 0   # VOID
+    disc = fcm.Discretization(d)
+    kept = {tuple(int(c) for c in e) for e in disc.kept_idx}
+    assert (2, 2) not in kept
+    assert len(kept) == 25 - 9
+    A = disc.A.toarray()
+    np.linalg.cholesky(A)                                         # SPD
+    # without the rule the island's hats would add a zero-energy constant
+    d2 = dict(d, dirichlet_faces=0)                               # no anchor: nothing is dropped
+    disc2 = fcm.Discretization(d2)
+    assert (2, 2) in {tuple(int(c) for c in e) for e in disc2.kept_idx}
