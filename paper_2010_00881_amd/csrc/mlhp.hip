@@ -51,6 +51,8 @@ struct MlPatches {                // Schwarz blocks of one multigrid level
   int *pair_leaf = nullptr;       // per pair: leaf
   int64_t *pair_map = nullptr;    // per pair: offset into map
   int *map = nullptr;             // per pair and leaf function: block row or -1
+  int *pg_ptr = nullptr, *pg_slot = nullptr;  // per DOF: its patch rows (slots into pidx)
+  double *pc = nullptr;           // per patch row: the smoother product (gathered per DOF)
   double *inv = nullptr;
   int64_t inv_doubles = 0;
   std::vector<std::pair<int64_t, std::pair<int, int>>> buckets;  // (inv offset, (count, mb))
@@ -71,6 +73,11 @@ struct MlhpState {
   int *leaf = nullptr;
   int64_t *koff = nullptr;
   int *fdof = nullptr, *fdesc = nullptr;
+  int *lg_ptr = nullptr, *lg_slot = nullptr;  // per DOF: its leaf-function slots (into fdof)
+  double *lc = nullptr;                       // per leaf function: load / product contribution
+  int64_t *ce_tgt = nullptr, *ce_src = nullptr;  // coarse matrix: entries and Kl sources
+  int *ce_ptr = nullptr;
+  int n_ce = 0;
   double *Kl = nullptr, *b = nullptr;
   double *surf = nullptr;
   int nsurf = 0;
@@ -113,6 +120,20 @@ static fcm_status ml_upload(fcm_handle *h, T **p, const std::vector<T> &v) {
     fcm_status s_ = (x);         \
     if (s_ != FCM_OK) return s_; \
   } while (0)
+
+// Gather table: for every target t < nt, the slots s with tgt[s] == t in
+// increasing s (targets outside [0, nt) are skipped).
+static void gather_csr(const std::vector<int> &tgt, int64_t nt, std::vector<int> &ptr,
+                       std::vector<int> &slot) {
+  ptr.assign(nt + 1, 0);
+  for (int t : tgt)
+    if (t >= 0 && t < nt) ptr[t + 1]++;
+  for (int64_t t = 0; t < nt; ++t) ptr[t + 1] += ptr[t];
+  slot.assign(ptr[nt], 0);
+  std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+  for (size_t s = 0; s < tgt.size(); ++s)
+    if (tgt[s] >= 0 && tgt[s] < nt) slot[fill[tgt[s]]++] = (int)s;
+}
 
 // ------------------------------------------------------------ device helpers
 struct MlGeo {
@@ -238,8 +259,7 @@ struct MlLeafArgs {
   const double *gx;       // nodes[p+1], weights[p+1]
   const double *surf;     // x, y, z, w
   int nsurf;
-  double *Kl, *b;
-  const int *fdof;
+  double *Kl, *lc;        // leaf matrices, per leaf-function load contributions
 };
 
 __global__ __launch_bounds__(256) void ml_integrate_kernel(MlLeafArgs a) {
@@ -436,7 +456,7 @@ __global__ __launch_bounds__(256) void ml_integrate_kernel(MlLeafArgs a) {
   }
   for (int u = 0; u < 2; ++u) {
     const int i = tid + 256 * u;
-    if (i < m) atomicAdd(a.b + a.fdof[foff + i], bacc[u]);
+    if (i < m) a.lc[foff + i] = bacc[u];
   }
 }
 
@@ -459,7 +479,7 @@ __device__ inline double ml_row_dot(const double *M, const double *v, int n, int
 // y += A_l x over the leaves (functions with DOF index >= n_l are absent)
 __global__ __launch_bounds__(256) void ml_apply_kernel(const int *leaf, const int64_t *koff,
                                                        const int *fdof, const double *Kl,
-                                                       int64_t nl, const double *x, double *y) {
+                                                       int64_t nl, const double *x, double *lc) {
   const int L = blockIdx.x, tid = threadIdx.x;
   const int foff = leaf[7 * L + 4], m = leaf[7 * L + 5];
   __shared__ double xs[kMlMaxM];
@@ -476,20 +496,33 @@ __global__ __launch_bounds__(256) void ml_apply_kernel(const int *leaf, const in
     if (ds[i] >= nl) continue;
     double s = ml_row_dot(K + (size_t)i * m, xs, m, lane);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) atomicAdd(y + ds[i], s);
+    if (lane == 0) lc[foff + i] = s;
   }
 }
 
-// dense level-0 matrix from the leaf matrices (functions with DOF < n0)
-__global__ void ml_coarse_assemble_kernel(const int *leaf, const int64_t *koff, const int *fdof,
-                                          const double *Kl, int n0, int ld, double *A0) {
-  const int L = blockIdx.x;
-  const int foff = leaf[7 * L + 4], m = leaf[7 * L + 5];
-  const double *K = Kl + koff[L];
-  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
-    const int i = fdof[foff + e / m], j = fdof[foff + e % m];
-    if (i < n0 && j < n0) atomicAdd(A0 + (size_t)i * ld + j, K[e]);
+// Owner gather: y[t] = sum of c[slot[k]], ptr[t] <= k < ptr[t + 1], in that
+// (fixed) order, for every t < n.  Replaces atomic scatters: the leaves' and
+// patches' contributions land in per-slot buffers and every DOF adds its own,
+// so the sums are the same on every run.
+__global__ void ml_gather_kernel(int64_t n, const int *ptr, const int *slot, const double *c,
+                                 double *y) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int k = ptr[t]; k < ptr[t + 1]; ++k) v += c[slot[k]];
+    y[t] = v;
   }
+}
+
+// dense level-0 matrix from the leaf matrices (functions with DOF < n0): entry
+// tgt[e] = the sum of Kl[src[k]], ptr[e] <= k < ptr[e + 1], in leaf order
+__global__ void ml_coarse_assemble_kernel(int ne, const int64_t *tgt, const int *ptr,
+                                          const int64_t *src, const double *Kl, double *A0) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double v = 0.0;
+  for (int k = ptr[e]; k < ptr[e + 1]; ++k) v += Kl[src[k]];
+  A0[tgt[e]] = v;
 }
 
 // x = M b for the leading n x n block of a matrix with leading dimension ld
@@ -535,7 +568,7 @@ __global__ __launch_bounds__(256) void ml_form_blocks_kernel(
 __global__ __launch_bounds__(256) void ml_smooth_kernel(const int *pm, const int64_t *pinv,
                                                         const int64_t *poff, const int *pidx,
                                                         const double *inv, const double *r,
-                                                        double *z) {
+                                                        double *pc) {
   const int P = blockIdx.x, tid = threadIdx.x;
   const int mb = pm[2 * P], mreal = pm[2 * P + 1];
   const int row0 = 64 * blockIdx.y;
@@ -550,7 +583,7 @@ __global__ __launch_bounds__(256) void ml_smooth_kernel(const int *pm, const int
   for (int i = row0 + wave; i < row1; i += 4) {
     double s = ml_row_dot(M + (size_t)i * mb, rs, mreal, lane);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-    if (lane == 0) atomicAdd(z + idx[i], s);
+    if (lane == 0) pc[poff[P] + i] = s;
   }
 }
 
@@ -694,7 +727,8 @@ __global__ void ml_sub_kernel(int64_t n, const double *b, const double *y, doubl
     r[i] = b[i] - y[i];
 }
 
-__global__ void ml_dot_kernel(int64_t n, const double *x, const double *y, double *out) {
+// per-block partial sums (fixed tree order), added in block order by ml_sum_kernel
+__global__ void ml_dot_kernel(int64_t n, const double *x, const double *y, double *partial) {
   __shared__ double red[256];
   double s = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -706,7 +740,15 @@ __global__ void ml_dot_kernel(int64_t n, const double *x, const double *y, doubl
     if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void ml_sum_kernel(int nb, const double *partial, double *out) {
+  if (threadIdx.x == 0) {
+    double v = 0.0;
+    for (int b = 0; b < nb; ++b) v += partial[b];
+    *out = v;
+  }
 }
 
 static int ml_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
@@ -1086,6 +1128,14 @@ static fcm_status ml_patches(Builder &B, int l, const std::vector<int> &fdof,
     }
   }
   P.inv_doubles = inv_off;
+  {
+    // per DOF of the level: its patch rows (padding rows carry -1)
+    std::vector<int> gptr, gslot;
+    gather_csr(pidx, S->level_size[l], gptr, gslot);
+    ML_TRY(ml_upload(h, &P.pg_ptr, gptr));
+    ML_TRY(ml_upload(h, &P.pg_slot, gslot));
+    ML_TRY(ml_alloc(h, &P.pc, pidx.size()));
+  }
   ML_TRY(ml_upload(h, &P.pidx, pidx));
   ML_TRY(ml_upload(h, &P.poff, poff));
   ML_TRY(ml_upload(h, &P.pm, pm));
@@ -1154,6 +1204,46 @@ fcm_status mlhp_setup(fcm_handle *h) {
   std::vector<int64_t> koff;
   ML_TRY(ml_leaf_functions(B, dof_of, fdof, fdesc, koff));
   ML_TRY(ml_upload(h, &S->leaf, S->h_leaf));
+  {
+    std::vector<int> gptr, gslot;
+    gather_csr(fdof, S->ndof, gptr, gslot);
+    ML_TRY(ml_upload(h, &S->lg_ptr, gptr));
+    ML_TRY(ml_upload(h, &S->lg_slot, gslot));
+    ML_TRY(ml_alloc(h, &S->lc, fdof.size()));
+    // level-0 matrix entries: per (i, j) with i, j < n0 the leaf-matrix entries
+    // that add to it, in leaf order
+    const int n0 = (int)S->level_size[0], n0p = (n0 + 31) / 32 * 32;
+    std::vector<std::pair<int64_t, int64_t>> ent;
+    for (int L = 0; L < S->nleaf; ++L) {
+      const int foff = S->h_leaf[7 * L + 4], m = S->h_leaf[7 * L + 5];
+      for (int a = 0; a < m; ++a) {
+        const int i = fdof[foff + a];
+        if (i >= n0) continue;
+        for (int b = 0; b < m; ++b) {
+          const int j = fdof[foff + b];
+          if (j < n0) ent.push_back({(int64_t)i * n0p + j, koff[L] + (int64_t)a * m + b});
+        }
+      }
+    }
+    std::stable_sort(ent.begin(), ent.end(),
+                     [](const std::pair<int64_t, int64_t> &x, const std::pair<int64_t, int64_t> &y) {
+                       return x.first < y.first;
+                     });
+    std::vector<int64_t> tgt, src;
+    std::vector<int> ptr;
+    for (size_t k = 0; k < ent.size(); ++k) {
+      if (k == 0 || ent[k].first != ent[k - 1].first) {
+        tgt.push_back(ent[k].first);
+        ptr.push_back((int)k);
+      }
+      src.push_back(ent[k].second);
+    }
+    ptr.push_back((int)ent.size());
+    S->n_ce = (int)tgt.size();
+    ML_TRY(ml_upload(h, &S->ce_tgt, tgt));
+    ML_TRY(ml_upload(h, &S->ce_ptr, ptr));
+    ML_TRY(ml_upload(h, &S->ce_src, src));
+  }
   ML_TRY(ml_upload(h, &S->fdof, fdof));
   ML_TRY(ml_upload(h, &S->fdesc, fdesc));
   ML_TRY(ml_upload(h, &S->koff, koff));
@@ -1205,9 +1295,10 @@ fcm_status mlhp_setup(fcm_handle *h) {
     a.surf = S->surf;
     a.nsurf = S->nsurf;
     a.Kl = S->Kl;
-    a.b = S->b;
-    a.fdof = S->fdof;
+    a.lc = S->lc;
     ml_integrate_kernel<<<S->nleaf, 256, 0, h->stream>>>(a);
+    ml_gather_kernel<<<ml_grid(S->ndof), 256, 0, h->stream>>>(S->ndof, S->lg_ptr, S->lg_slot,
+                                                              S->lc, S->b);
     FCM_HIP(hipGetLastError());
   }
   // coarse level: dense inverse of A_0
@@ -1220,9 +1311,9 @@ fcm_status mlhp_setup(fcm_handle *h) {
     for (int i = S->n0; i < S->n0p; ++i) eye[(size_t)i * S->n0p + i] = 1.0;
     FCM_HIP(hipMemcpyAsync(S->A0, eye.data(), nn * sizeof(double), hipMemcpyHostToDevice,
                            h->stream));
-    if (S->nleaf > 0)
-      ml_coarse_assemble_kernel<<<S->nleaf, 256, 0, h->stream>>>(S->leaf, S->koff, S->fdof,
-                                                                S->Kl, S->n0, S->n0p, S->A0);
+    if (S->n_ce > 0)
+      ml_coarse_assemble_kernel<<<(S->n_ce + 255) / 256, 256, 0, h->stream>>>(
+          S->n_ce, S->ce_tgt, S->ce_ptr, S->ce_src, S->Kl, S->A0);
     if (S->n0p > kMlMaxPatch) {
       set_error("multi-level hp: %d coarse unknowns (limit %d)", S->n0, kMlMaxPatch);
       return FCM_ERR_ARG;
@@ -1286,7 +1377,7 @@ fcm_status mlhp_setup(fcm_handle *h) {
   ML_TRY(ml_alloc(h, &S->cg_z, (size_t)S->ndof));
   ML_TRY(ml_alloc(h, &S->cg_p, (size_t)S->ndof));
   ML_TRY(ml_alloc(h, &S->cg_q, (size_t)S->ndof));
-  ML_TRY(ml_alloc(h, &S->red, 4));
+  ML_TRY(ml_alloc(h, &S->red, 2049));   // result, then up to 2048 block partials
   int f = 0;
   FCM_HIP(hipMemcpyAsync(&f, S->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   FCM_HIP(hipStreamSynchronize(h->stream));
@@ -1305,18 +1396,18 @@ void mlhp_free(fcm_handle *h) {
 // ------------------------------------------------------------ operators
 static void ml_apply(MlhpState *S, int l, const double *x, double *y, hipStream_t s) {
   const int64_t n = S->level_size[l];
-  (void)hipMemsetAsync(y, 0, n * sizeof(double), s);
   if (S->nleaf > 0)
-    ml_apply_kernel<<<S->nleaf, 256, 0, s>>>(S->leaf, S->koff, S->fdof, S->Kl, n, x, y);
+    ml_apply_kernel<<<S->nleaf, 256, 0, s>>>(S->leaf, S->koff, S->fdof, S->Kl, n, x, S->lc);
+  ml_gather_kernel<<<ml_grid(n), 256, 0, s>>>(n, S->lg_ptr, S->lg_slot, S->lc, y);
 }
 
 static void ml_smooth(MlhpState *S, int l, const double *r, double *z, hipStream_t s) {
   const int64_t n = S->level_size[l];
-  (void)hipMemsetAsync(z, 0, n * sizeof(double), s);
   const MlPatches &P = S->pl[l];
   if (P.npatch > 0)
     ml_smooth_kernel<<<dim3(P.npatch, (P.max_mb + 63) / 64), 256, 0, s>>>(P.pm, P.pinv, P.poff,
-                                                                          P.pidx, P.inv, r, z);
+                                                                          P.pidx, P.inv, r, P.pc);
+  ml_gather_kernel<<<ml_grid(n), 256, 0, s>>>(n, P.pg_ptr, P.pg_slot, P.pc, z);
 }
 
 static void ml_coarse(MlhpState *S, const double *b, double *x, hipStream_t s) {
@@ -1352,8 +1443,9 @@ static void ml_vcycle(fcm_handle *h, int l, const double *b, double *x, hipStrea
 }
 
 static double ml_dot(MlhpState *S, int64_t n, const double *x, const double *y, hipStream_t s) {
-  (void)hipMemsetAsync(S->red, 0, sizeof(double), s);
-  ml_dot_kernel<<<ml_grid(n), 256, 0, s>>>(n, x, y, S->red);
+  const int nb = ml_grid(n);
+  ml_dot_kernel<<<nb, 256, 0, s>>>(n, x, y, S->red + 1);
+  ml_sum_kernel<<<1, 64, 0, s>>>(nb, S->red + 1, S->red);
   double v = 0.0;
   hipMemcpyAsync(&v, S->red, sizeof(double), hipMemcpyDeviceToHost, s);
   hipStreamSynchronize(s);
