@@ -547,7 +547,7 @@ __global__ __launch_bounds__(512) void patch_class_mfma_kernel(Geo g,
 }
 
 // FP32 variant for the mixed form, used for small blocks (m <= 32; larger
-// ones go to patch_class_tile32_kernel): class inverses are well conditioned
+// ones go to patch_class_tile_kernel): class inverses are well conditioned
 // (uncut patches), so their products use v_mfma_f32_16x16x4f32 (inputs
 // rounded to FP32, FP32 accumulation; lane l supplies A[l%16][l/16] and
 // B[l/16][l%16] and holds D[4(l/16)+j][l%16]).  Half-width registers leave

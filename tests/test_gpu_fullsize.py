@@ -6,7 +6,7 @@ sampled cut and uncut elements, and sampled rows of A x and of b - A x
 rebuilt from oracle element matrices and loads through the DOF map.  The
 rest is checked through properties that hold at any size: symmetric and
 positive Schwarz smoothers and V-cycle, convergence of the preconditioned CG
-to the requested tolerance, and agreement of the FP32-V-cycle and plain FP64
+to the requested tolerance, and agreement of the mixed (FP32 smoother matrices) and plain FP64
 solutions in the energy norm.
 
 Workloads: the 32^3 p = 3 voided cube (Poisson, 848,071 unknowns) and the
@@ -159,7 +159,7 @@ def test_fullsize_pcg_and_sampled_residual(name):
     res = np.abs(b - ax).max() / bmax
     print(f"[fullsize] {name}: sampled |b - A x| / max|b| = {res:.2e}", flush=True)
     assert res <= max(1e-7, 1e3 * sols["fp64"][2])
-    # FP32 V-cycle and plain FP64 solutions agree in the energy norm
+    # mixed-form and plain FP64 solutions agree in the energy norm
     s = _cache[(name, "fp64")][0]
     L = s.n_levels - 1
     e = sols["mixed"][0] - sols["fp64"][0]

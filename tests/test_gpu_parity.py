@@ -5,7 +5,7 @@ oracle on the same seeded inputs: element matrices and loads of cut cells,
 the assembled right-hand side, the level operators A_l (eq.
 hierarchicalMatrices), the additive Schwarz smoothers (eq. AdditiveSchwarz),
 the exact coarse solve, one V-cycle (Alg. 1) and the full MG-preconditioned
-CG (Section 4) in the plain FP64 and the FP32-V-cycle forms.
+CG (Section 4) in the plain FP64 and the mixed (FP32 smoother matrices) forms.
 
 Cases span 2D/3D, Poisson/elasticity, orders 2..4, several tiles of the
 element grid with ragged tails, single- and multi-block coarse levels,
