@@ -12,7 +12,9 @@ Follows Section 3 of the paper:
   * damped update x <- x + omega M^{-1} r (Section 3.1); the residual is
     recomputed after every smoothing step;
   * V-cycle of Alg. 1 with n_s pre- and post-smoothing steps, exact solve on
-    l = 0 (the p = 1 problem);
+    l = 0 (the p = 1 problem), or, with options["coarse"] == "hmg", one cycle
+    over geometric h-levels below it (remark at the end of Section 3.2;
+    oracle/hmg.py);
   * CG preconditioned by one V-cycle, stopped on ||r||/||b|| < rtol (Section 4),
     and the V-cycle as a stand-alone solver with contraction numbers
     rho_i = ||r_i|| / ||r_{i-1}|| (eq. contraction).
@@ -67,7 +69,12 @@ class Hierarchy:
         self.As = [A[:n, :n].tocsr() for n in self.sizes]
         self.scaled_blocks = scaled_blocks
         self.blocks = [None] + [self._build_blocks(l) for l in range(1, self.L + 1)]
-        self._build_coarse()
+        self.hmg = None
+        if options.get("coarse", "blocktri") == "hmg":
+            from .hmg import HLevels
+            self.hmg = HLevels(disc, self.As[0], options, scaled_blocks)
+        else:
+            self._build_coarse()
 
     # ------------------------------------------------------------- smoother
     def block_sets(self, l):
@@ -114,6 +121,8 @@ class Hierarchy:
             self.coarse_lu = spla.splu(A0.tocsc())
 
     def coarse_solve(self, b):
+        if self.hmg is not None:
+            return self.hmg.cycle(0, b)
         if self.coarse_dense is not None:
             return sla.cho_solve(self.coarse_dense, b)
         return self.coarse_lu.solve(b)
