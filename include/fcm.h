@@ -79,6 +79,12 @@ enum { FCM_GEOM_BOX_MINUS_BALLS = 0, FCM_GEOM_BALL_INTERIOR = 1 };
  * the coarse solve and the outer CG stay FP64.                              */
 enum { FCM_FP64 = 0, FCM_MIXED = 1 };
 enum { FCM_SMOOTH_ELEMENTWISE = 0, FCM_SMOOTH_PATCHWISE = 1 };  /* Schwarz blocks */
+/* Solve on the p = 1 level: FCM_COARSE_BLOCKTRI factorises it exactly
+ * (block LDL^T over layers of grid points); FCM_COARSE_HMG coarsens it
+ * further by geometric h-levels (remark closing Section 3.2): d-linear
+ * interpolation, Galerkin matrices P^T A P, patchwise additive Schwarz on
+ * every h-level, a dense inverse on the coarsest.                          */
+enum { FCM_COARSE_BLOCKTRI = 0, FCM_COARSE_HMG = 1 };
 
 typedef struct fcm_handle fcm_handle;
 typedef struct fcm_server fcm_server;
@@ -140,6 +146,11 @@ typedef struct {
                                  patchwise smoother on this problem's data and
                                  keep the fastest (cached per problem shape in
                                  the process); 0: fixed heuristics            */
+  int coarse;                 /* FCM_COARSE_BLOCKTRI or FCM_COARSE_HMG (uniform
+                                 grids only)                                   */
+  int coarse_dense_max;       /* HMG: an h-level with at most this many DOFs is
+                                 the coarsest (solved by a dense inverse);
+                                 0 = 2048, at most 8192                        */
 } fcm_options;
 
 typedef struct {
@@ -171,15 +182,26 @@ fcm_status fcm_sizes(const fcm_handle *h, int *n_levels, int64_t *n_dofs,
 /* Copy the assembled right-hand side b (fine level, FP64) to b_dev.         */
 fcm_status fcm_rhs(fcm_handle *h, double *b_dev, void *stream);
 
-/* y = A_l x (FP64) on level l (eq. hierarchicalMatrices); x, y level-l vectors. */
+/* y = A_l x (FP64) on level l (eq. hierarchicalMatrices); x, y level-l vectors.
+ * With FCM_COARSE_HMG, level = -k (k >= 1) applies the Galerkin matrix of
+ * h-level k to vectors of n_f (n_k+1)^d entries (fcm_hlevels).              */
 fcm_status fcm_apply(fcm_handle *h, int level, const double *x, double *y,
                      void *stream);
 
 /* z = M_l^{-1} r (FP64), the additive Schwarz operator of level l >= 1 (eq.
  * AdditiveSchwarz) with the handle's blocks (elementwise or patchwise), in
- * FP64 arithmetic from the FP64 inverses, without the relaxation factor.    */
+ * FP64 arithmetic from the FP64 inverses, without the relaxation factor.
+ * With FCM_COARSE_HMG, level = 0 and level = -k give the patchwise operator
+ * of h-level 0 (the p = 1 level) and h-level k (not the coarsest).          */
 fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z,
                       void *stream);
+
+/* Geometric h-levels of a handle set up with FCM_COARSE_HMG: *count = number
+ * of h-levels J+1 (h-level 0 = the p = 1 level, J the coarsest), 0 without
+ * them; cells (may be NULL, room for 3 * 12 ints) receives the cells per axis
+ * of each (1 on unused axes).  A level-k vector holds n_f planes of
+ * (n_0+1)(n_1+1)(n_2+1) grid points, axis 0 fastest, zero where no DOF is. */
+fcm_status fcm_hlevels(const fcm_handle *h, int *count, int *cells);
 
 /* Test hook for the batched SPD inversion used by the Schwarz blocks and the
  * coarse factorisation: A_dev (device, `batch` row-major n x n FP64 SPD
@@ -203,7 +225,8 @@ fcm_status fcm_spd_inverse(double *A_dev, int n, int batch, double *kappa_dev,
 fcm_status fcm_spd_inverse_noalloc(double *A_dev, int n, int batch, double *kappa_dev,
                                    void *stream);
 
-/* x = A_0^{-1} b on the coarsest level (exact FP64 solve).                  */
+/* x = A_0^{-1} b on the coarsest level (exact FP64 solve); with
+ * FCM_COARSE_HMG, x = one h-cycle applied to b (its approximation).         */
 fcm_status fcm_coarse_solve(fcm_handle *h, const double *b, double *x,
                             void *stream);
 
@@ -265,7 +288,10 @@ fcm_status fcm_element(const fcm_handle *h, int64_t e, int *state, double *K,
 typedef struct {
   int64_t n_elements, n_kept, n_cut, n_unique_blocks, n_shared_classes;
   int64_t device_bytes;
-  int coarse_blocks, coarse_block_size;
+  int coarse_blocks, coarse_block_size;  /* layer blocks of the exact coarse
+                                 factorisation and their size; with
+                                 FCM_COARSE_HMG: h-levels below p = 1 and the
+                                 DOFs of the coarsest                         */
   int64_t n_fp64_blocks;      /* unique Schwarz blocks applied in FP64 (mixed)   */
 } fcm_stats;
 fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s);
@@ -289,7 +315,7 @@ fcm_status fcm_set_tuning(fcm_handle *h, int level, int class_rows, int gemv_ban
  * written once, matrices streamed once).
  * op: FCM_OP_SMOOTH (Schwarz smoother of `level`, handle precision),
  *     FCM_OP_RESIDUAL (residual update r -= omega A delta of `level`),
- *     FCM_OP_COARSE (one exact coarse solve), FCM_OP_VCYCLE (one V-cycle,
+ *     FCM_OP_COARSE (one coarse solve or h-cycle), FCM_OP_VCYCLE (one V-cycle,
  *     bytes = sum over its launches), FCM_OP_SMOOTH_STORED (patchwise only:
  *     the kernel that streams the unique patch inverses of `level`, alone).  Work vectors of the handle are used;
  * their contents are overwritten.                                          */

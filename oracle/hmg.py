@@ -19,8 +19,9 @@ uniform grid, in the plainest form:
   * A_{k+1} = P_k^T A_k P_k (Galerkin);
   * smoother on every h-level: additive Schwarz with the patchwise blocks of
     Section 3.3.1 for p = 1 (block v = the DOFs of the vertices of the kept
-    cells around node v), damped by the problem's omega, the residual
-    recomputed after every step (as on the p-levels);
+    cells around node v), damped by omega_h = 1 / (c 3^(d-1)), c = 2 for
+    scalar and 3 for vector problems (1/6, 1/9 in 2D; 1/18, 1/27 in 3D),
+    the residual recomputed after every step (as on the p-levels);
   * the coarsest h-level (at most `coarse_dense_max` DOFs, or no axis left
     to halve) is solved exactly (dense Cholesky);
   * one h-cycle (Alg. 1 on the h-levels) replaces the exact p = 1 solve.
@@ -35,6 +36,11 @@ import itertools
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
+
+
+def h_omega(dim, n_fields):
+    """Relaxation of the h-level smoothers (see the module docstring)."""
+    return 1.0 / ((2.0 if n_fields == 1 else 3.0) * 3.0 ** (dim - 1))
 
 
 def decode_vertex_keys(disc, keys):
@@ -76,7 +82,7 @@ class HLevels:
         self.d = disc.dim
         self.nf = disc.nf
         self.faces = int(disc.desc.get("dirichlet_faces", 0))
-        self.omega = float(options["omega"])
+        self.omega = h_omega(self.d, self.nf)
         self.n_pre = int(options.get("n_pre", 5))
         self.n_post = int(options.get("n_post", 5))
         self.dense_max = int(options.get("coarse_dense_max", 2048))

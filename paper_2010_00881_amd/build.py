@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfcm.so")
 SOURCES = ["kernels_setup.hip", "kernels_solve.hip", "kernels_patch.hip", "fcm_host.hip",
-           "serve.hip", "mlhp.hip"]
+           "serve.hip", "mlhp.hip", "hlevels.hip"]
 ARCH = os.environ.get("FCM_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

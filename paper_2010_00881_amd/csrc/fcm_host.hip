@@ -161,32 +161,6 @@ void pinned_put(double *b) {
   g_pinned_free.push_back(b);
 }
 
-template <typename T>
-static fcm_status dalloc(fcm_handle *h, T **p, size_t n) {
-  *p = nullptr;
-  if (n == 0) n = 1;
-  TRY(pool_alloc((void **)p, n * sizeof(T), h->stream));
-  h->allocs.push_back(*p);
-  h->bytes += (int64_t)(n * sizeof(T));
-  hipError_t e = hipMemsetAsync(*p, 0, n * sizeof(T), h->stream);
-  if (e != hipSuccess) {
-    set_error("hipMemsetAsync failed: %s", hipGetErrorString(e));
-    return FCM_ERR_HIP;
-  }
-  return FCM_OK;
-}
-
-template <typename T>
-static fcm_status upload(fcm_handle *h, T **p, const std::vector<T> &v) {
-  fcm_status st = dalloc(h, p, v.size());
-  if (st != FCM_OK) return st;
-  // ordered on the handle's stream (which may be non-blocking) and drained
-  // before v can go out of scope
-  FCM_HIP(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
-  FCM_HIP(hipStreamSynchronize(h->stream));
-  return FCM_OK;
-}
-
 // ------------------------------------------------------------ validation
 static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
   if (!p || !o) { set_error("null problem or options"); return FCM_ERR_ARG; }
@@ -200,8 +174,20 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
     set_error("refine_levels must be in 0..4");
     return FCM_ERR_ARG;
   }
+  if (o->coarse != FCM_COARSE_BLOCKTRI && o->coarse != FCM_COARSE_HMG) {
+    set_error("coarse must be FCM_COARSE_BLOCKTRI or FCM_COARSE_HMG");
+    return FCM_ERR_ARG;
+  }
+  if (o->coarse_dense_max < 0 || o->coarse_dense_max > 8192) {
+    set_error("coarse_dense_max must be in 0..8192");
+    return FCM_ERR_ARG;
+  }
   if (p->refine_levels > 0) {
     if (p->n_fields != 1) { set_error("multi-level hp: Poisson only"); return FCM_ERR_ARG; }
+    if (o->coarse != FCM_COARSE_BLOCKTRI) {
+      set_error("multi-level hp: the coarse level is solved exactly");
+      return FCM_ERR_ARG;
+    }
     if (o->precision != FCM_FP64) {
       set_error("multi-level hp: the V-cycle runs in FP64 only");
       return FCM_ERR_ARG;
@@ -430,19 +416,19 @@ static fcm_status build_tables(fcm_handle *h) {
       }
     }
   }
-  TRY(upload(h, &t.lm, lm));
-  TRY(upload(h, &t.xoff, xoff));
-  TRY(upload(h, &t.rows, rows));
-  TRY(upload(h, &t.pinfo, pinfo));
-  TRY(upload(h, &t.smap, smap));
-  TRY(upload(h, &t.tab1d, tab1d));
-  TRY(upload(h, &t.gxw, gxw));
-  TRY(upload(h, &t.vgauss, vg));
+  TRY(device_upload(h, &t.lm, lm));
+  TRY(device_upload(h, &t.xoff, xoff));
+  TRY(device_upload(h, &t.rows, rows));
+  TRY(device_upload(h, &t.pinfo, pinfo));
+  TRY(device_upload(h, &t.smap, smap));
+  TRY(device_upload(h, &t.tab1d, tab1d));
+  TRY(device_upload(h, &t.gxw, gxw));
+  TRY(device_upload(h, &t.vgauss, vg));
   std::vector<double> ball = h->prob.ball, gs = h->prob.gsrc;
   if (ball.empty()) ball.assign(4, 0.0);
   if (gs.empty()) gs.assign(5, 0.0);
-  TRY(upload(h, &t.ball, ball));
-  TRY(upload(h, &t.gsrc, gs));
+  TRY(device_upload(h, &t.ball, ball));
+  TRY(device_upload(h, &t.gsrc, gs));
   return FCM_OK;
 }
 
@@ -580,12 +566,12 @@ static fcm_status setup_coarse_alloc(fcm_handle *h) {
   c.nb = g.nf * w * c.PP;
   c.no = g.d == 3 ? 9 : 3;
   const size_t nb2 = (size_t)c.nb * c.nb;
-  TRY(dalloc(h, &c.Sinv, nb2 * c.nblk));
-  TRY(dalloc(h, &c.Gm, nb2 * c.nblk));
-  TRY(dalloc(h, &c.Fm, nb2 * c.nblk));
-  TRY(dalloc(h, &c.Dst, (size_t)c.nblk * c.nb * 3 * c.no * g.nf));
-  TRY(dalloc(h, &c.xblk, (size_t)c.nblk * c.nb));
-  TRY(dalloc(h, &c.bblk, (size_t)c.nblk * c.nb));
+  TRY(device_alloc(h, &c.Sinv, nb2 * c.nblk));
+  TRY(device_alloc(h, &c.Gm, nb2 * c.nblk));
+  TRY(device_alloc(h, &c.Fm, nb2 * c.nblk));
+  TRY(device_alloc(h, &c.Dst, (size_t)c.nblk * c.nb * 3 * c.no * g.nf));
+  TRY(device_alloc(h, &c.xblk, (size_t)c.nblk * c.nb));
+  TRY(device_alloc(h, &c.bblk, (size_t)c.nblk * c.nb));
   TRY(pool_alloc((void **)&h->co_scr, spd_inverse_scratch_doubles(c.nb, 1) * sizeof(double),
                  h->stream));
   return FCM_OK;
@@ -598,8 +584,10 @@ static fcm_status coarse_fork(fcm_handle *h, hipStream_t cs) {
   return FCM_OK;
 }
 
-// Enqueues the block-tridiagonal coarse factorisation on cs (after coarse_fork).
+// Enqueues the block-tridiagonal coarse factorisation (or the h-level setup)
+// on cs (after coarse_fork).
 static fcm_status setup_coarse_launch(fcm_handle *h, hipStream_t cs) {
+  if (h->hmg) return hmg_launch(h, cs);
   const Geo &g = h->geo;
   Coarse &c = h->co;
   const size_t nb2 = (size_t)c.nb * c.nb;
@@ -671,7 +659,7 @@ static fcm_status build_units(fcm_handle *h, int l) {
       }
     }
   h->lev[l].nunits = (int)units.size() / 12;
-  return upload(h, &h->lev[l].units, units);
+  return device_upload(h, &h->lev[l].units, units);
 }
 
 static fcm_status autotune_levels(fcm_handle *h);
@@ -679,7 +667,7 @@ static fcm_status autotune_levels(fcm_handle *h);
 static fcm_status setup_levels(fcm_handle *h) {
   const Geo &g = h->geo;
   int *belems = nullptr;
-  TRY(upload(h, &belems, h->h_block_elems));
+  TRY(device_upload(h, &belems, h->h_block_elems));
   const int nblocks = (int)h->h_block_elems.size();
   double *kappa = nullptr;
   TRY(pool_alloc((void **)&kappa, std::max(1, nblocks) * sizeof(double), h->stream));
@@ -688,8 +676,8 @@ static fcm_status setup_levels(fcm_handle *h) {
     Level &L = h->lev[l];
     const int m = L.m;
     const size_t mm = (size_t)m * m;
-    TRY(dalloc(h, &L.invS64, mm * nblocks));
-    TRY(dalloc(h, &L.invS32, mm * nblocks));
+    TRY(device_alloc(h, &L.invS64, mm * nblocks));
+    TRY(device_alloc(h, &L.invS32, mm * nblocks));
     L.invU64 = L.invS64 + mm * h->n_shared;
     L.invU32 = L.invS32 + mm * h->n_shared;
     if (m <= kSmallInv) {
@@ -721,7 +709,7 @@ static fcm_status setup_levels(fcm_handle *h) {
         fl[u] = 1;
         L.n_hi64++;
       }
-    TRY(upload(h, &L.hi64, fl));
+    TRY(device_upload(h, &L.hi64, fl));
   }
   pool_free(kappa, h->stream);
   return check_flag(h, "Schwarz block inversion");
@@ -802,10 +790,10 @@ static fcm_status build_patch_tables(fcm_handle *h) {
       if (!ok) continue;
       prow[(size_t)P * 27 + cb] = kmap.at(((sl[0] + S * (sl[1] + S * sl[2])) * nf) + pt[4 * P + 3]);
     }
-  TRY(upload(h, &h->ptab.pm, pm));
-  TRY(upload(h, &h->ptab.pxoff, pxoff));
-  TRY(upload(h, &h->ptab.pinfo, pinfo));
-  TRY(upload(h, &h->ptab.prow, prow));
+  TRY(device_upload(h, &h->ptab.pm, pm));
+  TRY(device_upload(h, &h->ptab.pxoff, pxoff));
+  TRY(device_upload(h, &h->ptab.pinfo, pinfo));
+  TRY(device_upload(h, &h->ptab.prow, prow));
   return FCM_OK;
 }
 
@@ -925,11 +913,11 @@ static fcm_status build_patches(fcm_handle *h, std::vector<int> &bnode, std::vec
     pkm.push_back(0);
   }
   if (chk.empty()) chk.assign(3, 0);
-  TRY(upload(h, &h->pnode, pnode));
-  TRY(upload(h, &h->pkm, pkm));
-  TRY(upload(h, &h->pchk, chk));
-  TRY(upload(h, &h->pcpres, cpres));
-  TRY(upload(h, &h->pid, pid));
+  TRY(device_upload(h, &h->pnode, pnode));
+  TRY(device_upload(h, &h->pkm, pkm));
+  TRY(device_upload(h, &h->pchk, chk));
+  TRY(device_upload(h, &h->pcpres, cpres));
+  TRY(device_upload(h, &h->pid, pid));
   return FCM_OK;
 }
 
@@ -997,10 +985,10 @@ static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *d
     // class inverses carry a tail that the class-product kernels may read past
     // the last row and column (values masked there)
     const size_t tail = 32 * (size_t)ld + 512;
-    TRY(dalloc(h, &L.invS64, mm * std::max(1, ncls) + tail));
-    if (mixed) TRY(dalloc(h, &L.invS32, mm * std::max(1, ncls) + tail));
-    TRY(dalloc(h, &L.invU64, tp * std::max(1, h->np_unique)));
-    if (mixed) TRY(dalloc(h, &L.invU32, tp * std::max(1, h->np_unique)));
+    TRY(device_alloc(h, &L.invS64, mm * std::max(1, ncls) + tail));
+    if (mixed) TRY(device_alloc(h, &L.invS32, mm * std::max(1, ncls) + tail));
+    TRY(device_alloc(h, &L.invU64, tp * std::max(1, h->np_unique)));
+    if (mixed) TRY(device_alloc(h, &L.invU32, tp * std::max(1, h->np_unique)));
     if (nblocks > 0) {
       const int cb = patch_chunk(m, nblocks);
       for (int b0 = 0; b0 < nblocks; b0 += cb) {
@@ -1029,11 +1017,11 @@ static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *d
         fl[u] = 1;
         L.n_hi64++;
       }
-    TRY(upload(h, &L.hi64, fl));
+    TRY(device_upload(h, &L.hi64, fl));
   }
   const int mtop = h->lev[h->L].mpatch;
-  TRY(dalloc(h, &h->pYs, (size_t)std::max(1, h->np_shared) * mtop));
-  TRY(dalloc(h, &h->pYu, (size_t)std::max(1, h->np_unique) * mtop));
+  TRY(device_alloc(h, &h->pYs, (size_t)std::max(1, h->np_shared) * mtop));
+  TRY(device_alloc(h, &h->pYu, (size_t)std::max(1, h->np_unique) * mtop));
   // band-pair partial products of the unique GEMV (every level: the
   // autotuner may pick band pairs below kSmallPatchM too)
   size_t nband = 0;
@@ -1042,7 +1030,7 @@ static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *d
     const int nb = ((m + 15) / 16 + 15) / 16;
     nband = std::max(nband, (size_t)nb * (nb + 1) / 2 * 512);
   }
-  if (nband > 0) TRY(dalloc(h, &h->pband, nband * std::max(1, h->np_unique)));
+  if (nband > 0) TRY(device_alloc(h, &h->pband, nband * std::max(1, h->np_unique)));
   return check_flag(h, "patch Schwarz block inversion");
 }
 
@@ -1051,10 +1039,10 @@ static fcm_status do_setup(fcm_handle *h) {
   const fcm_problem &pr = h->prob.pr;
   TRY(build_tables(h));
   const int m = h->tab.m;
-  TRY(dalloc(h, &h->dflag, 1));
-  TRY(dalloc(h, &h->dflag_co, 1));
+  TRY(device_alloc(h, &h->dflag, 1));
+  TRY(device_alloc(h, &h->dflag_co, 1));
   // classification
-  TRY(dalloc(h, &h->state, (size_t)g.E));
+  TRY(device_alloc(h, &h->state, (size_t)g.E));
   launch_classify(g, h->tab.ball, h->state, h->stream);
   h->h_state.resize(g.E);
   FCM_HIP(hipMemcpyAsync(h->h_state.data(), h->state, g.E, hipMemcpyDeviceToHost, h->stream));
@@ -1071,19 +1059,19 @@ static fcm_status do_setup(fcm_handle *h) {
     }
   }
   build_blocks(h);
-  TRY(upload(h, &h->kmat, h->h_kmat));
-  TRY(upload(h, &h->blk, h->h_blk));
+  TRY(device_upload(h, &h->kmat, h->h_kmat));
+  TRY(device_upload(h, &h->blk, h->h_blk));
   // element matrices and loads
   const size_t mm = (size_t)m * m;
   const int ncut = (int)h->h_cut.size();
-  TRY(dalloc(h, &h->Kref64, mm));
-  TRY(dalloc(h, &h->Kcut64, mm * std::max(1, ncut)));
-  TRY(dalloc(h, &h->be, (size_t)g.E * m));
+  TRY(device_alloc(h, &h->Kref64, mm));
+  TRY(device_alloc(h, &h->Kcut64, mm * std::max(1, ncut)));
+  TRY(device_alloc(h, &h->be, (size_t)g.E * m));
   FCM_HIP(hipMemsetAsync(h->be, 0, (size_t)g.E * m * sizeof(double), h->stream));
   int *dcut = nullptr;
-  if (ncut > 0) TRY(upload(h, &dcut, h->h_cut));
+  if (ncut > 0) TRY(device_upload(h, &dcut, h->h_cut));
   const int L = h->L;
-  TRY(dalloc(h, &h->b, (size_t)h->lev[L].npad));
+  TRY(device_alloc(h, &h->b, (size_t)h->lev[L].npad));
   // Element matrices, loads and the assembled right-hand side.  Enqueued after
   // every host-built table is uploaded: an upload drains the stream, so one
   // issued behind these kernels would leave the host waiting for them.
@@ -1102,12 +1090,12 @@ static fcm_status do_setup(fcm_handle *h) {
   {
     std::vector<int> ue(h->h_block_elems.begin() + h->n_shared, h->h_block_elems.end());
     if (ue.empty()) ue.push_back(0);
-    TRY(upload(h, &h->uniq_elems, ue));
+    TRY(device_upload(h, &h->uniq_elems, ue));
     std::vector<int> ce = h->h_cut;
     if (ce.empty()) ce.push_back(0);
-    TRY(upload(h, &h->cut_elems, ce));
-    TRY(dalloc(h, &h->Yscr, (size_t)std::max(1, std::max(ncut, h->n_unique)) * m));
-    TRY(dalloc(h, &h->Yshr, (size_t)g.E * m));
+    TRY(device_upload(h, &h->cut_elems, ce));
+    TRY(device_alloc(h, &h->Yscr, (size_t)std::max(1, std::max(ncut, h->n_unique)) * m));
+    TRY(device_alloc(h, &h->Yshr, (size_t)g.E * m));
     std::vector<int> ul, cl;
     for (int e = 0; e < g.E; ++e)
       if (h->h_kmat[e] == 0) ul.push_back(e);
@@ -1137,12 +1125,13 @@ static fcm_status do_setup(fcm_handle *h) {
     h->n_class_chk = cl.empty() ? 0 : (int)cck.size() / 3;
     if (ul.empty()) ul.push_back(0);
     if (cl.empty()) cl.push_back(0);
-    TRY(upload(h, &h->uncut_list, ul));
-    TRY(upload(h, &h->class_list, cl));
-    TRY(upload(h, &h->uncut_chk, uck));
-    TRY(upload(h, &h->class_chk, cck));
+    TRY(device_upload(h, &h->uncut_list, ul));
+    TRY(device_upload(h, &h->class_list, cl));
+    TRY(device_upload(h, &h->uncut_chk, uck));
+    TRY(device_upload(h, &h->class_chk, cck));
   }
-  TRY(setup_coarse_alloc(h));
+  if (h->opt.coarse == FCM_COARSE_HMG) TRY(hmg_alloc(h));
+  else TRY(setup_coarse_alloc(h));
   FCM_HIP(hipStreamCreateWithFlags(&h->own, hipStreamNonBlocking));
   FCM_HIP(hipEventCreateWithFlags(&h->co_ready, hipEventDisableTiming));
   if (h->opt.smoother == FCM_SMOOTH_PATCHWISE) {
@@ -1153,8 +1142,8 @@ static fcm_status do_setup(fcm_handle *h) {
     TRY(build_patch_tables(h));
     TRY(build_patches(h, bnode, bkm));
     int *dbn = nullptr, *dbk = nullptr;
-    TRY(upload(h, &dbn, bnode.empty() ? std::vector<int>{0} : bnode));
-    TRY(upload(h, &dbk, bkm.empty() ? std::vector<int>{0} : bkm));
+    TRY(device_upload(h, &dbn, bnode.empty() ? std::vector<int>{0} : bnode));
+    TRY(device_upload(h, &dbk, bkm.empty() ? std::vector<int>{0} : bkm));
     element_work();
     fcm_status sst = patch_scratch_alloc(h, (int)bnode.size(), ps);
     if (sst == FCM_OK) sst = coarse_fork(h, h->own);
@@ -1200,19 +1189,19 @@ static fcm_status do_setup(fcm_handle *h) {
   // work vectors
   for (int l = 0; l <= L; ++l) {
     Level &lv = h->lev[l];
-    TRY(dalloc(h, &lv.x64, lv.npad));
+    TRY(device_alloc(h, &lv.x64, lv.npad));
     if (l >= 1) {
-      TRY(dalloc(h, &lv.r64, lv.npad));
-      TRY(dalloc(h, &lv.d64, lv.npad));
+      TRY(device_alloc(h, &lv.r64, lv.npad));
+      TRY(device_alloc(h, &lv.d64, lv.npad));
     }
   }
   const int64_t nf = h->lev[L].npad;
-  TRY(dalloc(h, &h->cg_r, nf));
-  TRY(dalloc(h, &h->cg_z, nf));
-  TRY(dalloc(h, &h->cg_p, nf));
-  TRY(dalloc(h, &h->cg_q, nf));
-  TRY(dalloc(h, &h->red, 1024));
-  TRY(dalloc(h, &h->scal, 16));
+  TRY(device_alloc(h, &h->cg_r, nf));
+  TRY(device_alloc(h, &h->cg_z, nf));
+  TRY(device_alloc(h, &h->cg_p, nf));
+  TRY(device_alloc(h, &h->cg_q, nf));
+  TRY(device_alloc(h, &h->red, 1024));
+  TRY(device_alloc(h, &h->scal, 16));
   h->hscal = pinned_get();
   if (!h->hscal) {
     set_error("pinned host allocation failed");
@@ -1225,7 +1214,8 @@ static fcm_status do_setup(fcm_handle *h) {
 
 // ------------------------------------------------------------- V-cycle
 static void coarse_solve_t(fcm_handle *h, const double *b, double *x, hipStream_t s) {
-  coarse_solve_launch(h->geo, h->co, b, x, s);
+  if (h->hmg) hmg_cycle(h, b, x, s);
+  else coarse_solve_launch(h->geo, h->co, b, x, s);
 }
 
 template <typename T>
@@ -1503,7 +1493,7 @@ static fcm_status autotune_levels(fcm_handle *h) {
 static void vcycle_top(fcm_handle *h, const double *r, double *z, hipStream_t s) {
   const int L = h->L;
   if (L == 0) {
-    coarse_solve_launch(h->geo, h->co, r, z, s);
+    coarse_solve_t(h, r, z, s);
     return;
   }
   // both forms keep the level vectors in FP64; the mixed form streams FP32
@@ -1717,7 +1707,20 @@ void fcm_destroy(fcm_handle *h) {
   if (h->co_ready) hipEventDestroy(h->co_ready);
   if (h->own) hipStreamDestroy(h->own);
   pinned_put(h->hscal);
+  delete h->hmg;
   delete h;
+}
+
+fcm_status fcm_hlevels(const fcm_handle *h, int *count, int *cells) {
+  if (!h || !count) {
+    set_error("null argument");
+    return FCM_ERR_ARG;
+  }
+  *count = h->hmg ? h->hmg->J + 1 : 0;
+  if (cells)
+    for (int k = 0; k < *count; ++k)
+      for (int ax = 0; ax < 3; ++ax) cells[3 * k + ax] = h->hmg->lev[k].n[ax];
+  return FCM_OK;
 }
 
 fcm_status fcm_trim_pool(void) {
@@ -1944,8 +1947,8 @@ fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s) {
   s->n_unique_blocks = patch ? h->np_unique : h->n_unique;
   s->n_shared_classes = patch ? h->np_classes : h->n_shared;
   s->device_bytes = h->bytes;
-  s->coarse_blocks = h->co.nblk;
-  s->coarse_block_size = h->co.nb;
+  s->coarse_blocks = h->hmg ? h->hmg->J : h->co.nblk;
+  s->coarse_block_size = h->hmg ? h->hmg->nd : h->co.nb;
   s->n_fp64_blocks = 0;
   for (int l = 1; l <= h->L; ++l) s->n_fp64_blocks += h->lev[l].n_hi64;
   return FCM_OK;
@@ -2000,6 +2003,7 @@ fcm_status fcm_rhs(fcm_handle *h, double *b_dev, void *stream) {
 
 fcm_status fcm_apply(fcm_handle *h, int level, const double *x, double *y, void *stream) {
   if (h && h->ml && x && y) return mlhp_apply(h, level, x, y, (hipStream_t)stream);
+  if (h && h->hmg && x && y && level < 0) return hmg_apply(h, -level, x, y, (hipStream_t)stream);
   if (!h || !x || !y || level < 0 || level > h->L) {
     set_error("invalid argument");
     return FCM_ERR_ARG;
@@ -2011,6 +2015,8 @@ fcm_status fcm_apply(fcm_handle *h, int level, const double *x, double *y, void 
 
 fcm_status fcm_smooth(fcm_handle *h, int level, const double *r, double *z, void *stream) {
   if (h && h->ml && r && z) return mlhp_smooth(h, level, r, z, (hipStream_t)stream);
+  if (h && h->hmg && r && z && level <= 0)
+    return hmg_smooth(h, -level, r, z, (hipStream_t)stream);
   if (!h || !r || !z || level < 1 || level > h->L) {
     set_error("invalid argument");
     return FCM_ERR_ARG;
@@ -2123,7 +2129,7 @@ fcm_status fcm_coarse_solve(fcm_handle *h, const double *b, double *x, void *str
     return FCM_ERR_ARG;
   }
   if (h->ml) return mlhp_coarse_solve(h, b, x, (hipStream_t)stream);
-  coarse_solve_launch(h->geo, h->co, b, x, (hipStream_t)stream);
+  coarse_solve_t(h, b, x, (hipStream_t)stream);
   FCM_HIP(hipGetLastError());
   return FCM_OK;
 }
@@ -2389,6 +2395,7 @@ static double stored_bytes(const fcm_handle *h, int l) {
 }
 
 static double coarse_bytes(const fcm_handle *h) {
+  if (h->hmg) return hmg_cycle_bytes(h);
   const fcm::Coarse &c = h->co;
   // S_k^{-1} (all blocks), G_k (k >= 1) and F_k (k < K-1) are each read once
   return (3.0 * c.nblk - 2.0) * c.nb * c.nb * 8.0 + 3.0 * (double)c.nblk * c.nb * 8.0;
@@ -2438,7 +2445,7 @@ fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
         launch_elem_op<double>(h->geo, h->tab, a, s);
       }
     } else if (op == FCM_OP_COARSE) {
-      coarse_solve_launch(h->geo, h->co, h->b, h->lev[0].x64, s);
+      coarse_solve_t(h, h->b, h->lev[0].x64, s);
     } else {
       vcycle_top(h, h->b, h->cg_z, s);
     }

@@ -85,6 +85,38 @@ struct Coarse {
   double *xblk = nullptr, *bblk = nullptr;  // [nblk][nb] block-layout sweep vectors
 };
 
+// Geometric h-levels below the p = 1 level (hlevels.hip).  h-level 0 is the
+// p = 1 level itself (its vectors are the level-0 vectors of the p-hierarchy:
+// n_f vertex planes of G points); h-level k+1 has ceil(n_k / 2) cells per
+// axis and the Galerkin matrix P^T A_k P of the d-linear interpolation P.
+// Every h-level's matrix is held as a 3^d-point stencil per row, vectors as
+// n_f planes of its grid points (axis 0 fastest), absent DOFs zero.
+constexpr int kMaxH = 12;
+struct HLev {
+  int n[3] = {1, 1, 1}, gn[3] = {1, 1, 1};   // cells and grid points per axis
+  int64_t G = 1, len = 0;                    // points, vector length n_f G
+  int ndof = 0;                              // DOFs (present entries)
+  int *pres = nullptr;                       // [len] 1 = DOF
+  double *S = nullptr;                       // [len][3^d][n_f] stencil rows
+  int np = 0;                                // Schwarz patches (nodes with a kept cell)
+  int *pidx = nullptr;                       // [G] patch of a node, -1 none
+  int *pmem = nullptr;                       // [np][m] vector index of patch slot, -1 none
+  double *Binv = nullptr;                    // [np][m][m] patch inverses
+  double *Y = nullptr;                       // [np][m] patch products
+  double *x = nullptr, *b = nullptr;         // level vectors (level 0: the p-level's)
+  double *r = nullptr, *dl = nullptr, *e = nullptr;
+};
+struct HMG {
+  int J = 0;                                 // coarsest h-level (exact dense solve)
+  int m = 0;                                 // patch slots n_f 3^d
+  HLev lev[kMaxH];
+  int nd = 0;                                // DOFs of the coarsest level
+  int *didx = nullptr;                       // [nd] their vector indices
+  double *Ainv = nullptr;                    // [nd][nd] inverse of the coarsest matrix
+  double *scr = nullptr;                     // setup scratch (SPD inverse)
+  size_t scr_doubles = 0;
+};
+
 struct Problem {
   fcm_problem pr;
   std::vector<double> ball;    // [nballs][4]: cx, cy, cz, r
@@ -162,6 +194,7 @@ struct fcm_handle {
   double *Yshr = nullptr;                     // shared-matrix element products (scratch)
   double *Kref64 = nullptr, *Kcut64 = nullptr, *be = nullptr, *b = nullptr;
   fcm::Coarse co;
+  fcm::HMG *hmg = nullptr;                    // set when options.coarse = FCM_COARSE_HMG
   // CG work vectors (fine level, FP64) and reduction scratch
   double *cg_r = nullptr, *cg_z = nullptr, *cg_p = nullptr, *cg_q = nullptr;
   double *red = nullptr;                      // partial sums
@@ -221,6 +254,44 @@ void pool_free(void *p, hipStream_t s);
 double *pinned_get();
 void pinned_put(double *b);
 
+// Zero-filled device memory owned by the handle (freed by fcm_destroy), and
+// a host vector copied into such memory (the copy is complete on return).
+template <typename T>
+fcm_status device_alloc(fcm_handle *h, T **p, size_t n) {
+  *p = nullptr;
+  if (n == 0) n = 1;
+  fcm_status st = pool_alloc((void **)p, n * sizeof(T), h->stream);
+  if (st != FCM_OK) return st;
+  h->allocs.push_back(*p);
+  h->bytes += (int64_t)(n * sizeof(T));
+  FCM_HIP(hipMemsetAsync(*p, 0, n * sizeof(T), h->stream));
+  return FCM_OK;
+}
+
+template <typename T>
+fcm_status device_upload(fcm_handle *h, T **p, const std::vector<T> &v) {
+  fcm_status st = device_alloc(h, p, v.size());
+  if (st != FCM_OK) return st;
+  if (!v.empty()) {
+    FCM_HIP(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
+    FCM_HIP(hipStreamSynchronize(h->stream));
+  }
+  return FCM_OK;
+}
+
+// Geometric h-levels (hlevels.hip).  hmg_alloc builds the host tables and
+// allocates everything on the handle's stream (after the element matrices
+// exist); hmg_launch enqueues the level-0 stencil, the Galerkin products, the
+// patch blocks and all inverses on stream cs; hmg_cycle applies one h-cycle
+// (Alg. 1 over the h-levels, x = 0 on entry) to the level-0 right-hand side.
+fcm_status hmg_alloc(fcm_handle *h);
+fcm_status hmg_launch(fcm_handle *h, hipStream_t cs);
+void hmg_cycle(fcm_handle *h, const double *b, double *x, hipStream_t s);
+// Test hooks: y = A_k x (k >= 1) and z = M_k^{-1} r (k >= 0) on h-level k.
+fcm_status hmg_apply(fcm_handle *h, int k, const double *x, double *y, hipStream_t s);
+fcm_status hmg_smooth(fcm_handle *h, int k, const double *r, double *z, hipStream_t s);
+double hmg_cycle_bytes(const fcm_handle *h);
+
 // ------------------------------------------------------- kernel launchers
 // Setup (kernels_setup.hip).
 void launch_classify(const Geo &g, const double *ball, uint8_t *state, hipStream_t s);
@@ -233,6 +304,8 @@ void launch_traction_rhs(const Geo &g, const Tables &t, int face, const double *
                          const uint8_t *state, double *be_all, hipStream_t s);
 void launch_assemble_rhs(const Geo &g, const Tables &t, const int *kmat, const double *be_all,
                          double *b, hipStream_t s);
+void launch_hstencil0(const Geo &g, const Tables &t, const int *kmat, const double *Kref,
+                      const double *Kcut, const int *pres, double *S, hipStream_t s);
 void launch_form_invert_small(const Geo &g, const Tables &t, int q, int m, const int *belems,
                               int nblocks, const int *kmat, const double *Kref,
                               const double *Kcut, double *inv64, float *inv32, int *flag,

@@ -1269,6 +1269,42 @@ void launch_coarse_stencils(const Geo &g, const Tables &t, const Coarse &c, cons
                                                             c.Dst);
 }
 
+// 3^d-point stencil of the p = 1 matrix for the geometric h-levels: row
+// (c, node) holds, for offset o = (dx+1) + 3 (dy+1) + 9 (dz+1) and component
+// c', the entry of the vertex DOF (c', node + off(o)); rows and columns of
+// absent DOFs (pres = 0) are zero.
+__global__ void hstencil0_kernel(Geo g, const int *smap, int mp, const int *kmat,
+                                 const double *Kref, const double *Kcut, const int *pres,
+                                 double *S) {
+  const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= (int64_t)g.nf * g.G) return;
+  const int no = g.d == 3 ? 27 : 9;
+  const int ca = (int)(row / g.G);
+  const int pt = (int)(row % g.G);
+  int ga[3] = {pt % g.gn[0], (pt / g.gn[0]) % g.gn[1], pt / (g.gn[0] * g.gn[1])};
+  double *out = S + row * (no * g.nf);
+  const bool ok = pres[row] != 0;
+  for (int o = 0; o < no; ++o) {
+    int gb[3] = {ga[0] + o % 3 - 1, ga[1] + (o / 3) % 3 - 1, ga[2] + (g.d == 3 ? o / 9 - 1 : 0)};
+    bool in = true;
+    for (int ax = 0; ax < 3; ++ax) in = in && gb[ax] >= 0 && gb[ax] < g.gn[ax];
+    const int pb = in ? gb[0] + g.gn[0] * (gb[1] + g.gn[1] * gb[2]) : 0;
+    for (int cb = 0; cb < g.nf; ++cb) {
+      double v = 0.0;
+      if (ok && in && pres[(int64_t)cb * g.G + pb])
+        v = coarse_entry(g, smap, mp, kmat, Kref, Kcut, ga, ca, gb, cb);
+      out[o * g.nf + cb] = v;
+    }
+  }
+}
+
+void launch_hstencil0(const Geo &g, const Tables &t, const int *kmat, const double *Kref,
+                      const double *Kcut, const int *pres, double *S, hipStream_t s) {
+  const int64_t rows = (int64_t)g.nf * g.G;
+  hstencil0_kernel<<<(unsigned)((rows + 127) / 128), 128, 0, s>>>(g, t.smap, t.m, kmat, Kref,
+                                                                   Kcut, pres, S);
+}
+
 // Neighbour of block-local row i at (so, o, c') -> block-local index in the
 // block of that layer, and which block (-1, 0, +1 relative), or -1 if none.
 __device__ inline int coarse_nbr(const Geo &g, const Coarse &c, int i, int so, int o, int cb,

@@ -92,29 +92,6 @@ struct MlhpState {
   std::vector<double> hist;
 };
 
-template <typename T>
-static fcm_status ml_alloc(fcm_handle *h, T **p, size_t n) {
-  *p = nullptr;
-  if (n == 0) n = 1;
-  fcm_status st = pool_alloc((void **)p, n * sizeof(T), h->stream);
-  if (st != FCM_OK) return st;
-  h->allocs.push_back(*p);
-  h->bytes += (int64_t)(n * sizeof(T));
-  FCM_HIP(hipMemsetAsync(*p, 0, n * sizeof(T), h->stream));
-  return FCM_OK;
-}
-
-template <typename T>
-static fcm_status ml_upload(fcm_handle *h, T **p, const std::vector<T> &v) {
-  fcm_status st = ml_alloc(h, p, v.size());
-  if (st != FCM_OK) return st;
-  if (!v.empty()) {
-    FCM_HIP(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, h->stream));
-    FCM_HIP(hipStreamSynchronize(h->stream));
-  }
-  return FCM_OK;
-}
-
 #define ML_TRY(x)                \
   do {                           \
     fcm_status s_ = (x);         \
@@ -1132,19 +1109,19 @@ static fcm_status ml_patches(Builder &B, int l, const std::vector<int> &fdof,
     // per DOF of the level: its patch rows (padding rows carry -1)
     std::vector<int> gptr, gslot;
     gather_csr(pidx, S->level_size[l], gptr, gslot);
-    ML_TRY(ml_upload(h, &P.pg_ptr, gptr));
-    ML_TRY(ml_upload(h, &P.pg_slot, gslot));
-    ML_TRY(ml_alloc(h, &P.pc, pidx.size()));
+    ML_TRY(device_upload(h, &P.pg_ptr, gptr));
+    ML_TRY(device_upload(h, &P.pg_slot, gslot));
+    ML_TRY(device_alloc(h, &P.pc, pidx.size()));
   }
-  ML_TRY(ml_upload(h, &P.pidx, pidx));
-  ML_TRY(ml_upload(h, &P.poff, poff));
-  ML_TRY(ml_upload(h, &P.pm, pm));
-  ML_TRY(ml_upload(h, &P.pinv, pinv));
-  ML_TRY(ml_upload(h, &P.plf, plf));
-  ML_TRY(ml_upload(h, &P.pair_leaf, pair_leaf));
-  ML_TRY(ml_upload(h, &P.pair_map, pair_map));
-  ML_TRY(ml_upload(h, &P.map, map));
-  ML_TRY(ml_alloc(h, &P.inv, (size_t)std::max<int64_t>(1, inv_off)));
+  ML_TRY(device_upload(h, &P.pidx, pidx));
+  ML_TRY(device_upload(h, &P.poff, poff));
+  ML_TRY(device_upload(h, &P.pm, pm));
+  ML_TRY(device_upload(h, &P.pinv, pinv));
+  ML_TRY(device_upload(h, &P.plf, plf));
+  ML_TRY(device_upload(h, &P.pair_leaf, pair_leaf));
+  ML_TRY(device_upload(h, &P.pair_map, pair_map));
+  ML_TRY(device_upload(h, &P.map, map));
+  ML_TRY(device_alloc(h, &P.inv, (size_t)std::max<int64_t>(1, inv_off)));
   return FCM_OK;
 }
 
@@ -1179,8 +1156,8 @@ fcm_status mlhp_setup(fcm_handle *h) {
     g.h0[ax] = S->h0[ax];
   }
   double *dball = nullptr, *dgauss = nullptr;
-  ML_TRY(ml_upload(h, &dball, h->prob.ball));
-  ML_TRY(ml_upload(h, &dgauss, h->prob.gsrc));
+  ML_TRY(device_upload(h, &dball, h->prob.ball));
+  ML_TRY(device_upload(h, &dgauss, h->prob.gsrc));
   g.ball = dball;
   g.gauss = dgauss;
   // modes of an element, axis 0 fastest
@@ -1203,13 +1180,13 @@ fcm_status mlhp_setup(fcm_handle *h) {
   std::vector<int> fdof, fdesc;
   std::vector<int64_t> koff;
   ML_TRY(ml_leaf_functions(B, dof_of, fdof, fdesc, koff));
-  ML_TRY(ml_upload(h, &S->leaf, S->h_leaf));
+  ML_TRY(device_upload(h, &S->leaf, S->h_leaf));
   {
     std::vector<int> gptr, gslot;
     gather_csr(fdof, S->ndof, gptr, gslot);
-    ML_TRY(ml_upload(h, &S->lg_ptr, gptr));
-    ML_TRY(ml_upload(h, &S->lg_slot, gslot));
-    ML_TRY(ml_alloc(h, &S->lc, fdof.size()));
+    ML_TRY(device_upload(h, &S->lg_ptr, gptr));
+    ML_TRY(device_upload(h, &S->lg_slot, gslot));
+    ML_TRY(device_alloc(h, &S->lc, fdof.size()));
     // level-0 matrix entries: per (i, j) with i, j < n0 the leaf-matrix entries
     // that add to it, in leaf order
     const int n0 = (int)S->level_size[0], n0p = (n0 + 31) / 32 * 32;
@@ -1240,23 +1217,23 @@ fcm_status mlhp_setup(fcm_handle *h) {
     }
     ptr.push_back((int)ent.size());
     S->n_ce = (int)tgt.size();
-    ML_TRY(ml_upload(h, &S->ce_tgt, tgt));
-    ML_TRY(ml_upload(h, &S->ce_ptr, ptr));
-    ML_TRY(ml_upload(h, &S->ce_src, src));
+    ML_TRY(device_upload(h, &S->ce_tgt, tgt));
+    ML_TRY(device_upload(h, &S->ce_ptr, ptr));
+    ML_TRY(device_upload(h, &S->ce_src, src));
   }
-  ML_TRY(ml_upload(h, &S->fdof, fdof));
-  ML_TRY(ml_upload(h, &S->fdesc, fdesc));
-  ML_TRY(ml_upload(h, &S->koff, koff));
-  ML_TRY(ml_alloc(h, &S->Kl, (size_t)koff[S->nleaf]));
-  ML_TRY(ml_alloc(h, &S->b, (size_t)S->ndof));
-  ML_TRY(ml_alloc(h, &S->flag, 1));
+  ML_TRY(device_upload(h, &S->fdof, fdof));
+  ML_TRY(device_upload(h, &S->fdesc, fdesc));
+  ML_TRY(device_upload(h, &S->koff, koff));
+  ML_TRY(device_alloc(h, &S->Kl, (size_t)koff[S->nleaf]));
+  ML_TRY(device_alloc(h, &S->b, (size_t)S->ndof));
+  ML_TRY(device_alloc(h, &S->flag, 1));
   // Gauss rule and surface rule
   {
     std::vector<double> x, w, gw;
     gauss_legendre(np1, x, w);
     gw = x;
     gw.insert(gw.end(), w.begin(), w.end());
-    ML_TRY(ml_upload(h, &S->gx, gw));
+    ML_TRY(device_upload(h, &S->gx, gw));
     std::vector<double> sp;
     if (pr.beta != 0.0) {
       const int nt = pr.surf_n[0] > 0 ? pr.surf_n[0] : 256;
@@ -1282,7 +1259,7 @@ fcm_status mlhp_setup(fcm_handle *h) {
       }
     }
     S->nsurf = (int)sp.size() / 4;
-    ML_TRY(ml_upload(h, &S->surf, sp));
+    ML_TRY(device_upload(h, &S->surf, sp));
   }
   // leaf matrices and load
   if (S->nleaf > 0) {
@@ -1306,7 +1283,7 @@ fcm_status mlhp_setup(fcm_handle *h) {
   S->n0p = (S->n0 + 31) / 32 * 32;
   {
     const size_t nn = (size_t)S->n0p * S->n0p;
-    ML_TRY(ml_alloc(h, &S->A0, nn));
+    ML_TRY(device_alloc(h, &S->A0, nn));
     std::vector<double> eye(nn, 0.0);
     for (int i = S->n0; i < S->n0p; ++i) eye[(size_t)i * S->n0p + i] = 1.0;
     FCM_HIP(hipMemcpyAsync(S->A0, eye.data(), nn * sizeof(double), hipMemcpyHostToDevice,
@@ -1323,8 +1300,8 @@ fcm_status mlhp_setup(fcm_handle *h) {
     int64_t *cpinv = nullptr;
     ML_TRY(pool_alloc((void **)&s1, nn * sizeof(double), h->stream));
     ML_TRY(pool_alloc((void **)&s2, nn * sizeof(double), h->stream));
-    ML_TRY(ml_upload(h, &cpm, std::vector<int>{S->n0p, S->n0}));
-    ML_TRY(ml_upload(h, &cpinv, std::vector<int64_t>{0}));
+    ML_TRY(device_upload(h, &cpm, std::vector<int>{S->n0p, S->n0}));
+    ML_TRY(device_upload(h, &cpinv, std::vector<int64_t>{0}));
     ML_TRY(ml_spd_inverse(S->A0, 1, cpm, cpinv, {{0, {1, S->n0p}}}, s1, s2, S->flag,
                           h->stream));
     FCM_HIP(hipStreamSynchronize(h->stream));
@@ -1368,16 +1345,16 @@ fcm_status mlhp_setup(fcm_handle *h) {
   S->vz.assign(S->nlev, nullptr);
   for (int l = 0; l < S->nlev; ++l) {
     const size_t n = (size_t)S->level_size[l];
-    ML_TRY(ml_alloc(h, &S->vx[l], n));
-    ML_TRY(ml_alloc(h, &S->vr[l], n));
-    ML_TRY(ml_alloc(h, &S->vy[l], n));
-    ML_TRY(ml_alloc(h, &S->vz[l], n));
+    ML_TRY(device_alloc(h, &S->vx[l], n));
+    ML_TRY(device_alloc(h, &S->vr[l], n));
+    ML_TRY(device_alloc(h, &S->vy[l], n));
+    ML_TRY(device_alloc(h, &S->vz[l], n));
   }
-  ML_TRY(ml_alloc(h, &S->cg_r, (size_t)S->ndof));
-  ML_TRY(ml_alloc(h, &S->cg_z, (size_t)S->ndof));
-  ML_TRY(ml_alloc(h, &S->cg_p, (size_t)S->ndof));
-  ML_TRY(ml_alloc(h, &S->cg_q, (size_t)S->ndof));
-  ML_TRY(ml_alloc(h, &S->red, 2049));   // result, then up to 2048 block partials
+  ML_TRY(device_alloc(h, &S->cg_r, (size_t)S->ndof));
+  ML_TRY(device_alloc(h, &S->cg_z, (size_t)S->ndof));
+  ML_TRY(device_alloc(h, &S->cg_p, (size_t)S->ndof));
+  ML_TRY(device_alloc(h, &S->cg_q, (size_t)S->ndof));
+  ML_TRY(device_alloc(h, &S->red, 2049));   // result, then up to 2048 block partials
   int f = 0;
   FCM_HIP(hipMemcpyAsync(&f, S->flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   FCM_HIP(hipStreamSynchronize(h->stream));

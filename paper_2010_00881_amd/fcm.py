@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfcm.so")
 
 FCM_FP64, FCM_MIXED = 0, 1
 FCM_SMOOTH_ELEMENTWISE, FCM_SMOOTH_PATCHWISE = 0, 1
+FCM_COARSE_BLOCKTRI, FCM_COARSE_HMG = 0, 1
 STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "out of device memory",
           -3: "HIP error", -4: "not SPD", -5: "CG breakdown", -6: "non-finite value", -7: "busy"}
 
@@ -50,7 +51,8 @@ class Options(ctypes.Structure):
                 ("n_pre", ctypes.c_int), ("n_post", ctypes.c_int),
                 ("precision", ctypes.c_int), ("rtol", ctypes.c_double),
                 ("max_iter", ctypes.c_int), ("use_graphs", ctypes.c_int),
-                ("autotune", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("coarse", ctypes.c_int),
+                ("coarse_dense_max", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -110,6 +112,7 @@ SIGNATURES = {
                      ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "fcm_destroy": ([_P], None),
     "fcm_trim_pool": ([], ctypes.c_int),
+    "fcm_hlevels": ([_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
     "fcm_server_create": ([ctypes.POINTER(ServerOpts), ctypes.POINTER(_P)], ctypes.c_int),
     "fcm_serve_submit": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Options),
                           ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -216,6 +219,11 @@ def make_options(opts):
     o.max_iter = int(opts.get("max_iter", 500))
     o.use_graphs = int(opts.get("use_graphs", 1))
     o.autotune = int(opts.get("autotune", 1))
+    co = opts.get("coarse", "blocktri")
+    if co not in ("blocktri", "hmg"):
+        raise ValueError(f"unknown coarse solve {co!r}")
+    o.coarse = FCM_COARSE_HMG if co == "hmg" else FCM_COARSE_BLOCKTRI
+    o.coarse_dense_max = int(opts.get("coarse_dense_max", 0))
     return o
 
 
@@ -235,6 +243,7 @@ class Solver:
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("libfcm needs a GPU (torch.cuda.is_available() is False)")
+        self.desc = desc
         self._pd = _ProblemData(desc)
         self._opts = make_options(opts)
         h = ctypes.c_void_p()
@@ -292,6 +301,33 @@ class Solver:
     def smooth(self, level, r):
         z = self._new(level)
         _check(lib().fcm_smooth(self.h, level, _ptr(r), _ptr(z), _stream()))
+        return z
+
+    def hlevels(self):
+        """Cells per axis of the geometric h-levels (h-level 0 = the p = 1 level);
+        empty without them."""
+        cnt = ctypes.c_int(0)
+        cells = (ctypes.c_int * 36)()
+        _check(lib().fcm_hlevels(self.h, ctypes.byref(cnt), cells))
+        return [tuple(cells[3 * k + a] for a in range(3)) for k in range(cnt.value)]
+
+    def _hnew(self, k):
+        import torch
+        n = self.hlevels()[k]
+        nf = int(self.desc.get("n_fields", 1))
+        return torch.zeros(nf * (n[0] + 1) * (n[1] + 1) * (n[2] + 1), dtype=torch.float64,
+                           device="cuda")
+
+    def happly(self, k, x):
+        """y = A_k x on h-level k >= 1 (Galerkin matrix)."""
+        y = self._hnew(k)
+        _check(lib().fcm_apply(self.h, -k, _ptr(x), _ptr(y), _stream()))
+        return y
+
+    def hsmooth(self, k, r):
+        """z = M_k^{-1} r, the patchwise Schwarz operator of h-level k."""
+        z = self._hnew(k)
+        _check(lib().fcm_smooth(self.h, -k, _ptr(r), _ptr(z), _stream()))
         return z
 
     def coarse_solve(self, b):

@@ -1,0 +1,162 @@
+"""GPU parity of the geometric h-levels below p = 1 (options coarse = "hmg").
+
+Against the oracle (oracle/hmg.py) on the same seeded problems: the cells of
+every h-level, the Galerkin operators A_k x (k >= 1) entry by entry, the
+patchwise Schwarz operators of every h-level but the coarsest, one h-cycle
+(the coarse solve), one V-cycle and the MG-preconditioned CG in both forms.
+Cases cover 2D/3D, Poisson/elasticity, odd cell counts (13 -> 7 -> 4), p = 1
+(the V-cycle is the h-cycle), both p-level smoothers, and 1 to 3 h-levels
+below p = 1 (small dense limits so that the small grids coarsen).
+
+Tolerances: operators 1e-12 (sums of the same products in another order);
+smoothers, cycles and solutions 1e-8 as for the p-levels (both sides invert
+Jacobi-scaled FP64 blocks by different algorithms); mixed-form CG 1e-7 and
+the oracle's iteration count +-1.
+"""
+import numpy as np
+import pytest
+
+import fcm_inputs as fi
+from tests.parity_utils import DofMap, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _patch(case_, dense=64):
+    desc, opts = case_
+    return desc, dict(opts, smoother="patchwise",
+                      omega=fi.patch_omega(desc["dim"], desc.get("n_fields", 1)),
+                      coarse="hmg", coarse_dense_max=dense)
+
+
+CASES = {
+    "plate16_p2_patch": lambda: _patch(fi.plate_with_hole(0)),
+    "plate40_p3_patch": lambda: _patch(fi.plate_with_hole(1, n=40, p=3)),
+    "plate16_p1_patch": lambda: _patch(fi.plate_with_hole(0, p=1), dense=40),
+    "cube13_p2_patch": lambda: _patch(fi.voided_cube_poisson(2, n=13, p=2)),
+    "elast4_p2_patch": lambda: _patch(fi.voided_cube_elasticity(0, n=4, p=2)),
+    "cube7_p3_elem": lambda: (lambda d, o: (d, dict(o, coarse="hmg", coarse_dense_max=40)))(
+        *fi.voided_cube_poisson(0, n=7, p=3)),
+}
+
+_cache = {}
+
+
+def case(name, precision="fp64"):
+    key = (name, precision)
+    if key not in _cache:
+        from oracle import fcm, mg
+        from paper_2010_00881_amd import Solver
+        desc, opts = CASES[name]()
+        okey = (name, "oracle")
+        if okey not in _cache:
+            print(f"[hmg] oracle for {name}", flush=True)
+            disc = fcm.Discretization(desc)
+            _cache[okey] = (disc, mg.Hierarchy(disc, opts, scaled_blocks=True))
+        disc, hier = _cache[okey]
+        print(f"[hmg] setting up {name} ({precision}) on cuda:0", flush=True)
+        s = Solver(desc, dict(opts, precision=precision))
+        _cache[key] = (s, disc, hier, DofMap(s, disc))
+    return _cache[key]
+
+
+def _hidx(s, lv):
+    """GPU vector index of each oracle DOF of an h-level (comp-major planes)."""
+    n = np.asarray(lv.n)
+    gn = np.ones(3, dtype=np.int64)
+    gn[:n.size] = n + 1
+    node = np.zeros((lv.size, 3), dtype=np.int64)
+    node[:, :lv.node.shape[1]] = lv.node
+    G = int(np.prod(gn))
+    return lv.comp * G + node[:, 0] + gn[0] * (node[:, 1] + gn[1] * node[:, 2]), G
+
+
+def _to(s, k, lv, v):
+    import torch
+    idx, G = _hidx(s, lv)
+    out = np.zeros(int(s.desc.get("n_fields", 1)) * G)
+    out[idx] = v
+    return torch.from_numpy(out).cuda()
+
+
+def _from(s, lv, t):
+    idx, _ = _hidx(s, lv)
+    a = t.cpu().numpy()
+    mask = np.ones(a.size, dtype=bool)
+    mask[idx] = False
+    return a[idx], a[mask]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hlevel_grids(name):
+    s, disc, hier, dm = case(name)
+    cells = s.hlevels()
+    H = hier.hmg
+    assert len(cells) == H.J + 1
+    for k, lv in enumerate(H.levels):
+        assert list(cells[k][:disc.dim]) == [int(v) for v in lv.n], (name, k)
+    print(f"[hmg] {name}: h-level sizes {[lv.size for lv in H.levels]}", flush=True)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hlevel_operators(name):
+    s, disc, hier, dm = case(name)
+    H = hier.hmg
+    rng = np.random.default_rng(31)
+    for k in range(1, H.J + 1):
+        lv = H.levels[k]
+        x = rng.standard_normal(lv.size)
+        y, rest = _from(s, lv, s.happly(k, _to(s, k, lv, x)))
+        assert np.all(rest == 0.0)
+        err = rel(y, lv.A @ x)
+        print(f"[hmg] {name} h-level {k}: A x rel err {err:.1e}", flush=True)
+        assert err <= 1e-12, (name, k, err)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hlevel_smoothers(name):
+    s, disc, hier, dm = case(name)
+    H = hier.hmg
+    rng = np.random.default_rng(32)
+    for k in range(H.J):
+        lv = H.levels[k]
+        r = rng.standard_normal(lv.size)
+        z, rest = _from(s, lv, s.hsmooth(k, _to(s, k, lv, r)))
+        assert np.all(rest == 0.0)
+        err = rel(z, H.smooth(k, r))
+        print(f"[hmg] {name} h-level {k} smoother: rel err {err:.1e}", flush=True)
+        assert err <= 1e-8, (name, k, err)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hcycle_and_vcycle(name):
+    s, disc, hier, dm = case(name)
+    rng = np.random.default_rng(33)
+    b = rng.standard_normal(disc.level_sizes[0])
+    x, rest = dm.from_gpu(s.coarse_solve(dm.to_gpu(b, 0)), 0)
+    assert np.all(rest == 0.0)
+    err = rel(x, hier.coarse_solve(b))
+    print(f"[hmg] {name} h-cycle: rel err {err:.1e}", flush=True)
+    assert err <= 1e-8
+    r = rng.standard_normal(disc.n_dofs)
+    z, rest = dm.from_gpu(s.vcycle(dm.to_gpu(r)))
+    assert np.all(rest == 0.0)
+    err = rel(z, hier.precondition(r))
+    print(f"[hmg] {name} vcycle: rel err {err:.1e}", flush=True)
+    assert err <= 1e-8
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_hmg_pcg(name, precision):
+    s, disc, hier, dm = case(name, precision)
+    xo, ito, _ = hier.pcg(disc.b)
+    x, info = s.pcg()
+    xg, rest = dm.from_gpu(x)
+    err = rel(xg, xo)
+    print(f"[hmg] {name} pcg {precision}: it gpu {info['iterations']} oracle {ito}, "
+          f"rel err {err:.1e}, true res {info['true_rel_res']:.1e}", flush=True)
+    assert info["status"] == 0
+    assert abs(info["iterations"] - ito) <= 1
+    assert err <= (1e-8 if precision == "fp64" else 1e-7)
+    assert np.all(rest == 0.0)

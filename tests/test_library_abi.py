@@ -40,7 +40,8 @@ def test_struct_layouts_match_header():
     import ctypes
     from paper_2010_00881_amd import fcm
     # the C structs are plain; sizes follow the C alignment rules for x86-64
-    assert ctypes.sizeof(fcm.Options) == 56  # 7 fields, then use_graphs and autotune
+    # 7 fields, then use_graphs, autotune, coarse and coarse_dense_max
+    assert ctypes.sizeof(fcm.Options) == 64
     assert ctypes.sizeof(fcm.SolveInfo) == 56
     assert ctypes.sizeof(fcm.Stats) == 64
     assert ctypes.sizeof(fcm.ServerOpts) == 16
@@ -57,6 +58,9 @@ def test_struct_layouts_match_header():
     ({"geom": 0}, {}, "ball-interior geometry"),
     ({"alpha": 0.0}, {}, "alpha must be in (0,1]"),
     ({"p": 9}, {}, "p must be in 1.."),
+    ({"refine_levels": 1}, {"coarse": "hmg"}, "coarse level is solved exactly"),
+    ({"refine_levels": 0, "beta": 0.0}, {"coarse": "hmg", "coarse_dense_max": 9000},
+     "coarse_dense_max must be in 0..8192"),
 ])
 def test_setup_rejects_invalid_problems_before_any_device_call(change, opt, msg):
     """fcm_setup validates the problem on the host and returns FCM_ERR_ARG with

@@ -7,8 +7,8 @@ What the mathematics fixes, independent of the oracle's own formulas:
     elasticity 3D);
   * P has full column rank and the coarse matrices are SPD also for odd cell
     counts and voided domains; no coarse DOF sits on a Dirichlet face;
-  * the patchwise Schwarz operators are SPD and omega * lambda_max(M^-1 A) < 2
-    (the damped smoother converges);
+  * the patchwise Schwarz operators are SPD and omega_h * lambda_max(M^-1 A)
+    < 2 (the damped smoother converges) for 2D/3D Poisson and elasticity;
   * the h-cycle is a symmetric operator; as a stand-alone solver of the p = 1
     problem it contracts with h-independent rates (textbook geometric
     multigrid); when the p = 1 level is small enough to be the coarsest, the
@@ -75,8 +75,14 @@ def test_coarse_levels_are_spd_and_respect_dirichlet_faces(case):
         assert np.linalg.eigvalsh(Ac).min() > 0.0
 
 
+def _plate_elasticity():
+    d, o = fi.plate_with_hole(1, n=16, p=1)
+    return dict(d, n_fields=2, E=1.0, nu=0.3, body_force=[0.0, -1.0], gauss=[], f_const=0.0), o
+
+
 @pytest.mark.parametrize("case, omega", [
     (fi.plate_with_hole(1, n=40, p=3), 1.0 / 6.0),
+    (_plate_elasticity(), 1.0 / 9.0),
     (fi.voided_cube_poisson(2, n=13, p=2), 1.0 / 18.0),
     (fi.voided_cube_elasticity(0, n=4, p=2), 1.0 / 27.0),
 ])
@@ -84,8 +90,8 @@ def test_smoothers_spd_and_damping_converges(case, omega):
     d, o = case
     disc = fcm.Discretization(d)
     n0 = disc.level_sizes[0]
-    H = HLevels(disc, disc.A.tocsr()[:n0, :n0], dict(o, omega=omega, coarse_dense_max=64),
-                scaled_blocks=True)
+    H = HLevels(disc, disc.A.tocsr()[:n0, :n0], dict(o, coarse_dense_max=64), scaled_blocks=True)
+    assert H.omega == pytest.approx(omega)
     for k in range(H.J):
         A = H.levels[k].A.toarray()
         n = A.shape[0]
@@ -100,13 +106,13 @@ def test_hcycle_symmetric_and_exact_when_coarsest():
     d, o = fi.plate_with_hole(0, n=16, p=1)
     disc = fcm.Discretization(d)
     A = disc.A.tocsr()
-    H = HLevels(disc, A, dict(o, omega=1.0 / 6.0, coarse_dense_max=40))
+    H = HLevels(disc, A, dict(o, coarse_dense_max=40))
     assert H.J >= 2
     rng = np.random.default_rng(3)
     r1, r2 = rng.standard_normal((2, A.shape[0]))
     a, b = r2 @ H.cycle(0, r1), r1 @ H.cycle(0, r2)
     assert abs(a - b) <= 1e-12 * abs(a)
-    E = HLevels(disc, A, dict(o, omega=1.0 / 6.0, coarse_dense_max=10 ** 6))
+    E = HLevels(disc, A, dict(o, coarse_dense_max=10 ** 6))
     assert E.J == 0
     x = E.cycle(0, r1)
     assert np.linalg.norm(A @ x - r1) <= 1e-12 * np.linalg.norm(r1)
@@ -118,7 +124,7 @@ def test_hcycle_contraction_is_h_independent():
         d, o = fi.plate_with_hole(0, n=n, p=1)
         disc = fcm.Discretization(dict(d, ball_c=[], ball_r=[]))
         A, b = disc.A.tocsr(), disc.b
-        H = HLevels(disc, A, dict(o, omega=1.0 / 6.0, coarse_dense_max=30))
+        H = HLevels(disc, A, dict(o, coarse_dense_max=30))
         x = np.zeros_like(b)
         hist = [np.linalg.norm(b)]
         for _ in range(8):
