@@ -291,6 +291,9 @@ def mlhp_bench(args):
     return 0
 
 
+COARSE = "blocktri"        # exact layer-block factorisation, or "hmg" (h-levels below p = 1)
+
+
 def _problem(kind, seed, n, precision, smoother="patchwise"):
     import fcm_inputs as fi
     if kind == "elasticity":
@@ -300,7 +303,7 @@ def _problem(kind, seed, n, precision, smoother="patchwise"):
         d, o = fi.voided_cube_poisson(seed, n=n, p=3)
         nf = 1
     omega = fi.patch_omega(3, nf) if smoother == "patchwise" else 2.0 / 15.0
-    return d, dict(o, precision=precision, smoother=smoother, omega=omega)
+    return d, dict(o, precision=precision, smoother=smoother, omega=omega, coarse=COARSE)
 
 
 def _run_steps(kind, n, seeds, precision, smoother="patchwise"):
@@ -402,6 +405,8 @@ def main():
                          "hp sphere problem")
     ap.add_argument("--n", type=int, default=None, help="cells per axis (24 / 32)")
     ap.add_argument("--smoother", default="patchwise", choices=["patchwise", "elementwise"])
+    ap.add_argument("--coarse", default="blocktri", choices=["blocktri", "hmg"],
+                    help="p = 1 level: exact layer-block factorisation or geometric h-levels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the plain FP64 form (one problem at a time)")
@@ -417,9 +422,11 @@ def main():
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="finish with a 1 GiB elementwise copy (counter calibration)")
     args = ap.parse_args()
+    global COARSE
+    COARSE = args.coarse
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU path is not "
+              "built", file=sys.stderr)
         return 2
 
     if args.workload == "serving":
@@ -461,6 +468,7 @@ def main():
         "config": {"workload": label, "n": n, "p": 4 if kind == "elasticity" else 3,
                    "fields": 3 if kind == "elasticity" else 1, "dofs": kf["dofs"],
                    "precision": args.precision, "smoother": args.smoother,
+                   "coarse": args.coarse,
                    "omega": _problem(kind, 0, n, args.precision, args.smoother)[1]["omega"],
                    "alpha": 1e-10, "quad_depth": 3, "rtol": 1e-10,
                    "parallelism": "none (1 GPU)"},
@@ -486,6 +494,23 @@ def main():
         tp = time.perf_counter() - t2
         out["poisson_32"] = dict({"workload": "cube_voids_poisson_32^3_p3",
                                   "solves_s": 8 / tp, "steps": 8}, **_summary(rp), **pk)
+    if kind == "elasticity" and not args.no_poisson and args.coarse == "blocktri":
+        # h-levels below p = 1 against the exact layer-block solve on a grid
+        # where the latter's dense layer blocks (4225 unknowns) dominate
+        big = {}
+        for co in ("hmg", "blocktri"):
+            COARSE = co
+            print(f"[bench] 64^3 p = 3 Poisson cube, coarse {co}", file=sys.stderr, flush=True)
+            _run_steps("poisson", 64, [1000], args.precision)
+            t3 = time.perf_counter()
+            r = _run_steps("poisson", 64, [0, 1], args.precision)
+            torch.cuda.synchronize()
+            big[co] = dict({"solves_s": 2 / (time.perf_counter() - t3)}, **_summary(r))
+        COARSE = args.coarse
+        out["poisson_64_coarse"] = {"workload": "cube_voids_poisson_64^3_p3", "steps": 2,
+                                    "hmg": big["hmg"], "blocktri": big["blocktri"],
+                                    "hmg_over_blocktri": big["hmg"]["solves_s"] /
+                                    big["blocktri"]["solves_s"]}
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle samples", file=sys.stderr, flush=True)
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))

@@ -160,3 +160,38 @@ def test_hmg_pcg(name, precision):
     assert abs(info["iterations"] - ito) <= 1
     assert err <= (1e-8 if precision == "fp64" else 1e-7)
     assert np.all(rest == 0.0)
+
+
+def test_hmg_fullsize_cube32_matches_exact_coarse_solve():
+    """The 32^3 p = 3 voided Poisson cube (848,071 unknowns, patchwise, seed 0)
+    with h-levels below p = 1 (33^3 -> 17^3 -> 9^3 points, dense on the last):
+    CG converges to rtol 1e-10 in at most 10 iterations, and its solution
+    agrees with the one preconditioned by the exact p = 1 solve to 1e-7 in the
+    energy norm (both stop at a relative residual of 1e-10)."""
+    import torch
+    from paper_2010_00881_amd import Solver
+    for k in list(_cache):
+        if k[1] != "oracle":
+            _cache.pop(k)[0].close()
+    d, o = fi.voided_cube_poisson(0, n=32, p=3)
+    o = dict(o, smoother="patchwise", omega=fi.patch_omega(3, 1), precision="mixed")
+    sols, its = {}, {}
+    for coarse in ("blocktri", "hmg"):
+        s = Solver(d, dict(o, coarse=coarse))
+        x, info = s.pcg()
+        torch.cuda.synchronize()
+        print(f"[hmg] cube32 {coarse}: it {info['iterations']} true res "
+              f"{info['true_rel_res']:.1e} setup {info['t_setup_ms']:.0f} ms solve "
+              f"{info['t_solve_ms']:.0f} ms h-levels {s.hlevels()}", flush=True)
+        assert info["status"] == 0 and info["true_rel_res"] <= 1e-9
+        sols[coarse], its[coarse] = x.clone(), info["iterations"]
+        if coarse == "hmg":
+            assert [c[0] for c in s.hlevels()] == [32, 16, 8]
+            e = sols["hmg"] - sols["blocktri"]
+            L = s.n_levels - 1
+            ee = float(e @ s.apply(L, e))
+            xx = float(sols["blocktri"] @ s.apply(L, sols["blocktri"]))
+            print(f"[hmg] cube32: energy diff {np.sqrt(ee / xx):.1e}", flush=True)
+            assert np.sqrt(ee / xx) <= 1e-7
+        s.close()
+    assert its["hmg"] <= 10
