@@ -3,7 +3,9 @@
 Implements, in the plainest form:
   * the FCM weak form with indicator alpha (Section 2.1, eq. weakform) for the
     Poisson equation (-kappa Lap u = f) and isotropic linear elasticity;
-  * the tensor-product integrated Legendre basis (Section 2.1);
+  * the tensor-product integrated Legendre basis (Section 2.1), or its trunk
+    subspace (modes whose bubble degrees sum to at most p; Table
+    tab::upperbound, trunk column);
   * cut-cell integration by recursive bisection of cut cells to a fixed depth,
     with a (p+1)^d Gauss rule on every leaf sub-cell and alpha evaluated per
     point (quadtree/octree integration, Section 4.3.1);
@@ -36,9 +38,32 @@ from . import basis
 from .geometry import CUT, PHYS, VOID, alpha_at, classify_box
 
 
-def local_modes(p: int, dim: int):
-    """All per-axis mode tuples (a_0, ..., a_{d-1}), a_ax in 0..p, axis 0 fastest."""
-    return [tuple(reversed(t)) for t in itertools.product(range(p + 1), repeat=dim)]
+def trunk_degree(t):
+    """Order of the trunk space that first contains the mode tuple t: the sum of
+    the degrees of its bubble factors (1D modes a >= 2 have degree a), at
+    least 1 (Table tab::upperbound, trunk column)."""
+    return max(1, sum(a for a in t if a >= 2))
+
+
+def local_modes(p: int, dim: int, space: str = "tensor"):
+    """Per-axis mode tuples (a_0, ..., a_{d-1}), a_ax in 0..p, axis 0 fastest:
+    all of them for the tensor-product space, those with trunk_degree <= p for
+    the trunk space (vertex modes, edge modes up to degree p, face and
+    interior modes whose bubble degrees sum to at most p)."""
+    modes = [tuple(reversed(t)) for t in itertools.product(range(p + 1), repeat=dim)]
+    if space == "trunk":
+        modes = [t for t in modes if trunk_degree(t) <= p]
+    elif space != "tensor":
+        raise ValueError(f"unknown space {space!r}")
+    return modes
+
+
+def mode_level_degree(t, space: str = "tensor"):
+    """Order q of the first hierarchical level containing mode tuple t: the
+    largest factor degree (tensor space), the trunk degree (trunk space)."""
+    if space == "trunk":
+        return trunk_degree(t)
+    return max(basis.mode_degree(a) for a in t)
 
 
 def source(desc, x):
@@ -79,10 +104,11 @@ class Discretization:
         self.hi = np.array(desc["hi"][:d], dtype=np.float64)
         self.h = (self.hi - self.lo) / self.n
         self.depth = int(desc.get("quad_depth", 3))
-        self.modes = local_modes(p, d)                    # scalar mode tuples
+        self.space = desc.get("space", "tensor")
+        self.modes = local_modes(p, d, self.space)        # scalar mode tuples
         self.m_scalar = len(self.modes)
         self.m = self.m_scalar * self.nf                  # local index = mode*nf + comp
-        self.mode_deg = np.array([max(basis.mode_degree(a) for a in t) for t in self.modes])
+        self.mode_deg = np.array([mode_level_degree(t, self.space) for t in self.modes])
         self.local_deg = np.repeat(self.mode_deg, self.nf)
         self._classify()
         self._number_dofs()
