@@ -292,6 +292,7 @@ def mlhp_bench(args):
 
 
 COARSE = "blocktri"        # exact layer-block factorisation, or "hmg" (h-levels below p = 1)
+SPACE = "tensor"           # element basis: tensor-product or trunk space
 
 
 def _problem(kind, seed, n, precision, smoother="patchwise"):
@@ -303,6 +304,7 @@ def _problem(kind, seed, n, precision, smoother="patchwise"):
         d, o = fi.voided_cube_poisson(seed, n=n, p=3)
         nf = 1
     omega = fi.patch_omega(3, nf) if smoother == "patchwise" else 2.0 / 15.0
+    d = dict(d, space=SPACE)
     return d, dict(o, precision=precision, smoother=smoother, omega=omega, coarse=COARSE)
 
 
@@ -356,6 +358,7 @@ def _kernel_figures(kind, n, precision, smoother="patchwise"):
     torch.cuda.empty_cache()
     achieved = bytes_k / (ms_k * 1e-3) / 1e9
     traffic = GEMV_TRAFFIC.get(kind) if (precision == "mixed" and smoother == "patchwise"
+                                         and SPACE == "tensor"
                                          and n == (24 if kind == "elasticity" else 32)) else None
     return {
         "dofs": n_fine,
@@ -405,6 +408,9 @@ def main():
                          "hp sphere problem")
     ap.add_argument("--n", type=int, default=None, help="cells per axis (24 / 32)")
     ap.add_argument("--smoother", default="patchwise", choices=["patchwise", "elementwise"])
+    ap.add_argument("--space", default="tensor", choices=["tensor", "trunk"],
+                    help="element basis (the trunk space keeps the modes whose bubble degrees "
+                         "sum to at most p)")
     ap.add_argument("--coarse", default="blocktri", choices=["blocktri", "hmg"],
                     help="p = 1 level: exact layer-block factorisation or geometric h-levels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -422,8 +428,9 @@ def main():
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="finish with a 1 GiB elementwise copy (counter calibration)")
     args = ap.parse_args()
-    global COARSE
+    global COARSE, SPACE
     COARSE = args.coarse
+    SPACE = args.space
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); a multi-GPU path is not "
               "built", file=sys.stderr)
@@ -468,7 +475,7 @@ def main():
         "config": {"workload": label, "n": n, "p": 4 if kind == "elasticity" else 3,
                    "fields": 3 if kind == "elasticity" else 1, "dofs": kf["dofs"],
                    "precision": args.precision, "smoother": args.smoother,
-                   "coarse": args.coarse,
+                   "coarse": args.coarse, "space": args.space,
                    "omega": _problem(kind, 0, n, args.precision, args.smoother)[1]["omega"],
                    "alpha": 1e-10, "quad_depth": 3, "rtol": 1e-10,
                    "parallelism": "none (1 GPU)"},
@@ -494,6 +501,18 @@ def main():
         tp = time.perf_counter() - t2
         out["poisson_32"] = dict({"workload": "cube_voids_poisson_32^3_p3",
                                   "solves_s": 8 / tp, "steps": 8}, **_summary(rp), **pk)
+    if kind == "elasticity" and not args.no_poisson and args.space == "tensor":
+        # the same problems in the trunk space (the paper's 3D element)
+        SPACE = "trunk"
+        print("[bench] 24^3 p = 4 elasticity cube, trunk space", file=sys.stderr, flush=True)
+        _run_steps(kind, n, [1000], args.precision, args.smoother)
+        t4 = time.perf_counter()
+        rt = _run_steps(kind, n, list(range(args.steps)), args.precision, args.smoother)
+        torch.cuda.synchronize()
+        out["elasticity_trunk"] = dict({"workload": "cube_voids_elasticity_24^3_p4_trunk",
+                                        "solves_s": args.steps / (time.perf_counter() - t4),
+                                        "steps": args.steps}, **_summary(rt))
+        SPACE = args.space
     if kind == "elasticity" and not args.no_poisson and args.coarse == "blocktri":
         # h-levels below p = 1 against the exact layer-block solve on a grid
         # where the latter's dense layer blocks (4225 unknowns) dominate

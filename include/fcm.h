@@ -73,6 +73,11 @@ typedef enum {
 } fcm_status;
 
 enum { FCM_GEOM_BOX_MINUS_BALLS = 0, FCM_GEOM_BALL_INTERIOR = 1 };
+/* Element basis: the tensor-product integrated Legendre space, or its trunk
+ * subspace (Table tab::upperbound, trunk column): the products whose bubble
+ * factors' degrees sum to at most p; level q of the p-hierarchy holds the
+ * modes whose sum (at least 1) is at most q.                               */
+enum { FCM_SPACE_TENSOR = 0, FCM_SPACE_TRUNK = 1 };
 /* V-cycle precision.  FCM_MIXED streams FP32 copies of the Schwarz inverses
  * (those whose Jacobi-scaled condition number is at most 1e5) and forms the
  * patch class products on the FP32 matrix cores; level vectors, residuals,
@@ -125,6 +130,8 @@ typedef struct {
                                  points in cos(theta) (<= 4096) and trapezoid
                                  points in phi (<= 8192; 2D: phi only);
                                  0 = 256 x 512                                   */
+  int space;                  /* FCM_SPACE_TENSOR or FCM_SPACE_TRUNK (uniform
+                                 grids only)                                   */
 } fcm_problem;
 
 /* Solver options (Sections 3.3.2 and 4). */

@@ -90,6 +90,44 @@ static void modes1d_host(int p, double xi, double *v, double *dv) {
 static int deg1(int a) { return a < 2 ? 1 : a; }      // local 1D mode -> degree
 static int tdeg(int t) { return t == 0 ? 1 : t + 1; }  // slot type -> degree
 
+// Level order q of a product of 1D functions of degrees dg[0..d-1] (1 for a
+// linear factor): the largest degree in the tensor-product space; in the
+// trunk space the sum of the degrees above 1, at least 1.
+static int prod_degree(bool trunk, int d, const int *dg) {
+  int mx = 1, sum = 0;
+  for (int ax = 0; ax < d; ++ax) {
+    mx = std::max(mx, dg[ax]);
+    if (dg[ax] > 1) sum += dg[ax];
+  }
+  return trunk ? std::max(1, sum) : mx;
+}
+static int mode_degree(const Geo &g, int a0, int a1, int a2) {
+  const int dg[3] = {deg1(a0), deg1(a1), deg1(a2)};
+  return prod_degree(g.trunk, g.d, dg);
+}
+static int plane_degree(const Geo &g, int t0, int t1, int t2) {
+  const int dg[3] = {tdeg(t0), tdeg(t1), tdeg(t2)};
+  return prod_degree(g.trunk, g.d, dg);
+}
+// Patch-local functions of level q (per-axis slots 0..2p: hats at 0, p, 2p,
+// bubbles of degree t+1 at slots t and p+t), times n_f.
+static int patch_size(bool trunk, int d, int nf, int p, int q) {
+  int cnt = 0;
+  const int S = 2 * p + 1;
+  for (int s2 = 0; s2 < (d == 3 ? S : 1); ++s2)
+    for (int s1 = 0; s1 < S; ++s1)
+      for (int s0 = 0; s0 < S; ++s0) {
+        const int sl[3] = {s0, s1, s2};
+        int dg[3];
+        for (int ax = 0; ax < 3; ++ax) {
+          const int t = sl[ax] % p;          // 0 for the hats, else the bubble type
+          dg[ax] = tdeg(t);
+        }
+        if (prod_degree(trunk, d, dg) <= q) ++cnt;
+      }
+  return cnt * nf;
+}
+
 #define TRY(x)                         \
   do {                                 \
     fcm_status s_ = (x);               \
@@ -265,12 +303,19 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
     set_error("invalid options");
     return FCM_ERR_ARG;
   }
+  if (p->space != FCM_SPACE_TENSOR && p->space != FCM_SPACE_TRUNK) {
+    set_error("space must be FCM_SPACE_TENSOR or FCM_SPACE_TRUNK");
+    return FCM_ERR_ARG;
+  }
+  if (p->space == FCM_SPACE_TRUNK && p->refine_levels > 0) {
+    set_error("multi-level hp: tensor-product space only");
+    return FCM_ERR_ARG;
+  }
   if (o->smoother == FCM_SMOOTH_PATCHWISE) {
-    int mpatch = p->n_fields;
-    for (int ax = 0; ax < p->dim; ++ax) mpatch *= 2 * p->p + 1;
+    const int mpatch =
+        patch_size(p->space == FCM_SPACE_TRUNK, p->dim, p->n_fields, p->p, p->p);
     if (mpatch > kMaxPatchM) {
-      set_error("patchwise blocks of size %d exceed the supported %d (n_f (2p+1)^d)", mpatch,
-                kMaxPatchM);
+      set_error("patchwise blocks of size %d exceed the supported %d", mpatch, kMaxPatchM);
       return FCM_ERR_ARG;
     }
   }
@@ -286,8 +331,7 @@ static void plane_types(const fcm_handle *h, std::vector<int> &pt) {
     for (int t2 = 0; t2 < (d == 3 ? p : 1); ++t2)
       for (int t1 = 0; t1 < p; ++t1)
         for (int t0 = 0; t0 < p; ++t0) {
-          int dg = std::max(tdeg(t0), tdeg(t1));
-          if (d == 3) dg = std::max(dg, tdeg(t2));
+          const int dg = plane_degree(g, t0, t1, t2);
           if (dg != s) continue;
           for (int c = 0; c < nf; ++c) {
             pt.push_back(t0);
@@ -324,8 +368,7 @@ static fcm_status build_tables(fcm_handle *h) {
     for (int a2 = 0; a2 < (d == 3 ? np : 1); ++a2)
       for (int a1 = 0; a1 < np; ++a1)
         for (int a0 = 0; a0 < np; ++a0) {
-          int dg = std::max(deg1(a0), deg1(a1));
-          if (d == 3) dg = std::max(dg, deg1(a2));
+          const int dg = mode_degree(g, a0, a1, a2);
           if (dg != s) continue;
           for (int c = 0; c < nf; ++c) {
             int idx = (int)lm.size() / 4;
@@ -345,8 +388,7 @@ static fcm_status build_tables(fcm_handle *h) {
     for (int t2 = 0; t2 < (d == 3 ? p : 1); ++t2)
       for (int t1 = 0; t1 < p; ++t1)
         for (int t0 = 0; t0 < p; ++t0) {
-          int dg = std::max(tdeg(t0), tdeg(t1));
-          if (d == 3) dg = std::max(dg, tdeg(t2));
+          const int dg = plane_degree(g, t0, t1, t2);
           if (dg != s) continue;
           for (int c = 0; c < nf; ++c) {
             pidx[(t0 + p * (t1 + p * t2)) * nf + c] = (int)ptype.size() / 4;
@@ -629,8 +671,7 @@ static fcm_status build_units(fcm_handle *h, int l) {
     for (int t2 = 0; t2 < (d == 3 ? p : 1); ++t2)
       for (int t1 = 0; t1 < p; ++t1)
         for (int t0 = 0; t0 < p; ++t0) {
-          int dg = std::max(tdeg(t0), tdeg(t1));
-          if (d == 3) dg = std::max(dg, tdeg(t2));
+          const int dg = plane_degree(g, t0, t1, t2);
           if (dg != s) continue;
           for (int c = 0; c < nf; ++c) {
             pt.push_back(t0);
@@ -732,15 +773,17 @@ static fcm_status build_patch_tables(fcm_handle *h) {
     patch_slot_host(sl, p, t, dl);
     return t == 0 ? 1 : t + 1;
   };
+  auto pdeg = [&](int s0, int s1, int s2) {
+    const int dg[3] = {sdeg(s0), sdeg(s1), sdeg(s2)};
+    return prod_degree(g.trunk, d, dg);
+  };
   std::vector<int> pm;
   std::map<int, int> kmap;
   for (int q = 1; q <= p; ++q)
     for (int s2 = (d == 3 ? 0 : p); s2 <= (d == 3 ? 2 * p : p); ++s2)
       for (int s1 = 0; s1 < S; ++s1)
         for (int s0 = 0; s0 < S; ++s0) {
-          int dg = std::max(sdeg(s0), sdeg(s1));
-          if (d == 3) dg = std::max(dg, sdeg(s2));
-          if (dg != q) continue;
+          if (pdeg(s0, s1, s2) != q) continue;
           for (int c = 0; c < nf; ++c) {
             kmap[((s0 + S * (s1 + S * s2)) * nf) + c] = (int)pm.size() / 4;
             pm.push_back(s0);
@@ -927,6 +970,7 @@ static fcm_status build_patches(fcm_handle *h, std::vector<int> &bnode, std::vec
 struct PatchScratch {
   double *blk = nullptr, *scr = nullptr, *kappa = nullptr;
   int chunk = 0;
+  size_t nblk = 0, nscr = 0;          // capacities in doubles
 };
 
 static int patch_chunk(int m, int nblocks) {
@@ -943,14 +987,16 @@ static fcm_status patch_scratch_alloc(fcm_handle *h, int nblocks, PatchScratch &
   const Geo &g = h->geo;
   size_t nblk = 1, nscr = 1;
   for (int l = 1; l <= h->L; ++l) {
-    int m = g.nf;
-    for (int ax = 0; ax < g.d; ++ax) m *= 2 * h->lev[l].q + 1;
+    // the same block size and chunk as setup_patch_levels uses
+    const int m = patch_size(g.trunk, g.d, g.nf, g.p, h->lev[l].q);
     const int cb = patch_chunk(m, std::max(1, nblocks));
     nblk = std::max(nblk, (size_t)cb * m * m);
     nscr = std::max(nscr, spd_inverse_scratch_doubles(m, cb));
   }
   TRY(pool_alloc((void **)&ps.blk, nblk * sizeof(double), h->stream));
   TRY(pool_alloc((void **)&ps.scr, nscr * sizeof(double), h->stream));
+  ps.nblk = nblk;
+  ps.nscr = nscr;
   TRY(pool_alloc((void **)&ps.kappa, std::max(1, nblocks) * sizeof(double), h->stream));
   return FCM_OK;
 }
@@ -975,8 +1021,7 @@ static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *d
   std::vector<double> hk(std::max(1, nblocks));
   for (int l = 1; l <= h->L; ++l) {
     Level &L = h->lev[l];
-    int m = g.nf;
-    for (int ax = 0; ax < g.d; ++ax) m *= 2 * L.q + 1;
+    const int m = patch_size(g.trunk, g.d, g.nf, g.p, L.q);
     const int ld = (m + 3) & ~3;
     L.mpatch = m;
     L.ldp = ld;
@@ -991,6 +1036,10 @@ static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *d
     if (mixed) TRY(device_alloc(h, &L.invU32, tp * std::max(1, h->np_unique)));
     if (nblocks > 0) {
       const int cb = patch_chunk(m, nblocks);
+      if ((size_t)cb * m * m > ps.nblk || spd_inverse_scratch_doubles(m, cb) > ps.nscr) {
+        set_error("internal: patch block scratch too small for %d blocks of %d", cb, m);
+        return FCM_ERR_ARG;
+      }
       for (int b0 = 0; b0 < nblocks; b0 += cb) {
         const int nb = std::min(cb, nblocks - b0);
         launch_form_patch_blocks(g, h->tab, h->ptab, m, dbn + b0, dbk + b0, nb, h->kmat,
@@ -1779,17 +1828,22 @@ fcm_status fcm_setup(const fcm_problem *pr, const fcm_options *op, void *stream,
   g.nballs = pr->n_balls;
   g.alpha = pr->alpha;
   g.depth = pr->quad_depth;
+  g.trunk = pr->space == FCM_SPACE_TRUNK;
   h->L = pr->p - 1;
   for (int l = 0; l <= h->L; ++l) {
     Level &lv = h->lev[l];
     lv.q = l + 1;
-    int q1 = 1, qq = 1;
-    for (int ax = 0; ax < g.d; ++ax) {
-      q1 *= (lv.q + 1);
-      qq *= lv.q;
-    }
-    lv.m = g.nf * q1;
-    lv.nP = g.nf * qq;
+    // local modes (per-axis 1D modes 0..p) and planes (per-axis slot types
+    // 0..p-1) of level order <= q, times n_f
+    int nm = 0, np = 0;
+    for (int a2 = 0; a2 < (g.d == 3 ? g.p + 1 : 1); ++a2)
+      for (int a1 = 0; a1 <= g.p; ++a1)
+        for (int a0 = 0; a0 <= g.p; ++a0) {
+          if (mode_degree(g, a0, a1, a2) <= lv.q) ++nm;
+          if (a0 < g.p && a1 < g.p && a2 < g.p && plane_degree(g, a0, a1, a2) <= lv.q) ++np;
+        }
+    lv.m = g.nf * nm;
+    lv.nP = g.nf * np;
     lv.npad = (int64_t)lv.nP * g.G;
   }
   if ((int64_t)h->lev[h->L].npad >= (1ll << 31) - 1) {

@@ -50,6 +50,7 @@ struct Geo {
   int geom, nballs;
   double alpha;
   int depth;
+  int trunk;     // 1: trunk-space basis (FCM_SPACE_TRUNK)
 };
 
 // Per-level Schwarz data and work vectors.

@@ -271,6 +271,7 @@ __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
       for (int a0 = 0; a0 < NP; ++a0)
         for (int b0 = 0; b0 < NP; ++b0) {
           const int sa = a0 + NP * (a1 + NP * a2), sb = b0 + NP * (b1 + NP * b2);
+          if (A.smap[sa * nf] < 0 || A.smap[sb * nf] < 0) continue;   // not a trunk mode
           for (int ci = 0; ci < nf; ++ci)
             for (int cj = 0; cj < nf; ++cj)
               Kel[(size_t)A.smap[sa * nf + ci] * m + A.smap[sb * nf + cj]] = 0.0;
@@ -399,6 +400,8 @@ __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
           for (int b0 = 0; b0 < NP; ++b0) {
             const double G = acc[a0 * NP + b0];
             const int sa = a0 + NP * (a1 + NP * a2), sb = b0 + NP * (b1 + NP * b2);
+            // tuples outside the trunk space have no local index
+            if (A.smap[sa * nf] < 0 || A.smap[sb * nf] < 0) continue;
             if (!A.elastic) {
               Kel[(size_t)A.smap[sa] * m + A.smap[sb]] = A.kappa * G;
             } else {
@@ -415,7 +418,7 @@ __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
   if (!want_load) return;
   for (int k = 0; k < 2; ++k) {
     const int sidx = tid + k * kIntThreads;
-    if (sidx >= ms) continue;
+    if (sidx >= ms || A.smap[sidx * nf] < 0) continue;
     double *be = A.be_all + (size_t)e * m;
     if (!A.elastic) be[A.smap[sidx]] = bacc[k];
     else
@@ -498,6 +501,7 @@ __global__ __launch_bounds__(64) void phys_rhs_kernel(Geo g, const double *gxw,
   __syncthreads();
   double *be = be_all + (size_t)e * m;
   for (int s = threadIdx.x; s < ms; s += 64) {
+    if (smap[s * g.nf] < 0) continue;    // not a trunk mode
     int sc[3] = {s % np, (s / np) % np, s / np2};
     double sum = 0.0;
     for (int q = 0; q < Q; ++q) {
@@ -556,6 +560,7 @@ __global__ void traction_kernel(Geo g, const double *gxw, const double *vgauss, 
   }
   const double tv[3] = {t0, t1, t2};
   double *be = be_all + (size_t)e * m;
+  if (smap[s * g.nf] < 0) return;        // not a trunk mode
   for (int c = 0; c < g.nf; ++c) be[smap[s * g.nf + c]] += tv[c] * val;
 }
 

@@ -65,7 +65,7 @@ int64_t footprint_estimate(const fcm_problem &p, const fcm_options &o) {
     const int64_t nuniq = std::min<int64_t>(G, ncut * (d == 3 ? 5 : 4));
     int64_t mtop = 0;
     for (int q = 2; q <= p.p; ++q) {
-      int64_t m = nf;
+      int64_t m = nf;    // tensor-space block size (an upper bound for the trunk space)
       for (int ax = 0; ax < d; ++ax) m *= 2 * q + 1;
       const int64_t ld = (m + 3) & ~3, nt = (m + 15) / 16;
       inv += 128 * m * ld * per + nuniq * (nt * (nt + 1) / 2) * 256 * per;

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfcm.so")
 FCM_FP64, FCM_MIXED = 0, 1
 FCM_SMOOTH_ELEMENTWISE, FCM_SMOOTH_PATCHWISE = 0, 1
 FCM_COARSE_BLOCKTRI, FCM_COARSE_HMG = 0, 1
+FCM_SPACE_TENSOR, FCM_SPACE_TRUNK = 0, 1
 STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "out of device memory",
           -3: "HIP error", -4: "not SPD", -5: "CG breakdown", -6: "non-finite value", -7: "busy"}
 
@@ -42,7 +43,7 @@ class Problem(ctypes.Structure):
         ("traction_vec", ctypes.POINTER(ctypes.c_double)),
         ("n_gauss", ctypes.c_int), ("gauss", ctypes.POINTER(ctypes.c_double)),
         ("f_const", ctypes.c_double), ("body_force", ctypes.c_double * 3),
-        ("beta", ctypes.c_double), ("surf_n", ctypes.c_int * 2),
+        ("beta", ctypes.c_double), ("surf_n", ctypes.c_int * 2), ("space", ctypes.c_int),
     ]
 
 
@@ -201,6 +202,10 @@ class _ProblemData:
         P.beta = float(desc.get("beta", 0.0))
         sn = desc.get("surface_rule", (0, 0))
         P.surf_n[0], P.surf_n[1] = int(sn[0]), int(sn[1])
+        sp = desc.get("space", "tensor")
+        if sp not in ("tensor", "trunk"):
+            raise ValueError(f"unknown space {sp!r}")
+        P.space = 1 if sp == "trunk" else 0
         self.struct = P
 
 

@@ -7,8 +7,9 @@ hierarchicalMatrices), the additive Schwarz smoothers (eq. AdditiveSchwarz),
 the exact coarse solve, one V-cycle (Alg. 1) and the full MG-preconditioned
 CG (Section 4) in the plain FP64 and the mixed (FP32 smoother matrices) forms.
 
-Cases span 2D/3D, Poisson/elasticity, orders 2..4, several tiles of the
-element grid with ragged tails, single- and multi-block coarse levels,
+Cases span 2D/3D, Poisson/elasticity, orders 2..4, tensor-product and trunk
+spaces, several tiles of the element grid with ragged tails, single- and
+multi-block coarse levels,
 Schwarz blocks inverted in LDS (m <= 88) and by the blocked sweep (m > 88),
 and patch blocks applied by one workgroup per patch (m <= 384) or by band
 pairs with row-blocked class products (elasticity, m = 1029 and 2187).
@@ -41,7 +42,18 @@ CASES = {
     "elast5_p3_patch_void1": lambda: _patch(_one_void(fi.voided_cube_elasticity(0, n=5, p=3))),
     # a kept cell enclosed by void cells (dropped, reading R23)
     "island5_p3_patch": lambda: _patch(fi.island_plate(p=3)),
+    # trunk-space basis (Table tab::upperbound, trunk column): elements of 32 / 50
+    # scalar modes, patch blocks of 135 (p = 3) and 675 (elasticity p = 4)
+    "cube7_p3_trunk": lambda: _trunk(fi.voided_cube_poisson(0, n=7, p=3)),
+    "plate16_p4_trunk_patch": lambda: _patch(_trunk(fi.plate_with_hole(0, p=4))),
+    "cube6_p4_trunk_patch": lambda: _patch(_trunk(fi.voided_cube_poisson(1, n=6, p=4))),
+    "elast3_p4_trunk_patch": lambda: _patch(_trunk(fi.voided_cube_elasticity(1, n=3, p=4))),
 }
+
+
+def _trunk(case_):
+    desc, opts = case_
+    return dict(desc, space="trunk"), opts
 
 
 def _patch(case_):

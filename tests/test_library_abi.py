@@ -43,6 +43,7 @@ def test_struct_layouts_match_header():
     # 7 fields, then use_graphs, autotune, coarse and coarse_dense_max
     assert ctypes.sizeof(fcm.Options) == 64
     assert ctypes.sizeof(fcm.SolveInfo) == 56
+    assert ctypes.sizeof(fcm.Problem) == 240     # ..., beta, surf_n[2], space
     assert ctypes.sizeof(fcm.Stats) == 64
     assert ctypes.sizeof(fcm.ServerOpts) == 16
 
@@ -59,6 +60,7 @@ def test_struct_layouts_match_header():
     ({"alpha": 0.0}, {}, "alpha must be in (0,1]"),
     ({"p": 9}, {}, "p must be in 1.."),
     ({"refine_levels": 1}, {"coarse": "hmg"}, "coarse level is solved exactly"),
+    ({"refine_levels": 1, "space": "trunk"}, {}, "tensor-product space only"),
     ({"refine_levels": 0, "beta": 0.0}, {"coarse": "hmg", "coarse_dense_max": 9000},
      "coarse_dense_max must be in 0..8192"),
 ])
