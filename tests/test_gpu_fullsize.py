@@ -11,7 +11,8 @@ solutions in the energy norm.
 
 Workloads: the 32^3 p = 3 voided cube (Poisson, 848,071 unknowns) and the
 24^3 p = 4 voided cube (elasticity, 2,690,520 unknowns, patch blocks of 2187
-unknowns), both with patchwise Schwarz blocks, generator seed 0.  Only one
+unknowns; in the trunk space 565,143 unknowns, blocks of 675), all with
+patchwise Schwarz blocks, generator seed 0.  Only one
 solver handle is alive at a time (the elasticity handle holds ~100-150 GB).
 """
 import numpy as np
@@ -28,7 +29,14 @@ CASES = {
                                 12, 1e-9),
     "elast24_p4_patch": lambda: (fi.voided_cube_elasticity(0, n=24, p=4), "patchwise",
                                  fi.patch_omega(3, 3), 40, 1e-9),
+    "elast24_p4_trunk_patch": lambda: (_trunk(fi.voided_cube_elasticity(0, n=24, p=4)),
+                                       "patchwise", fi.patch_omega(3, 3), 20, 1e-9),
 }
+
+
+def _trunk(case_):
+    desc, opts = case_
+    return dict(desc, space="trunk"), opts
 
 _cache = {}
 
