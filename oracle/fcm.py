@@ -35,7 +35,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import basis
-from .geometry import CUT, PHYS, VOID, alpha_at, classify_box
+from .geometry import CUT, PHYS, SQUARE, VOID, alpha_at, classify_box, square_corners, square_frame
 
 
 def trunk_degree(t):
@@ -74,7 +74,17 @@ def source(desc, x):
     for A, w, c in desc.get("gauss", []):
         d2 = np.sum((x - np.asarray(c)) ** 2, axis=1)
         f += A * np.exp(-d2 / (w * w))
+    if desc.get("trig_src"):
+        f += trig(desc, desc["trig_src"], x)
     return f
+
+
+def trig(desc, coef, x):
+    """A cos(a x') sin(a y') in the rotated square's frame (Section 4.1: the
+    manufactured solution and its source), coef = (A, a)."""
+    A, a = float(coef[0]), float(coef[1])
+    xr = square_frame(desc, x)
+    return A * np.cos(a * xr[:, 0]) * np.sin(a * xr[:, 1])
 
 
 def elasticity_C(dim, E, nu):
@@ -113,6 +123,7 @@ class Discretization:
         self._classify()
         self._number_dofs()
         self._kref = None
+        self.penalty = self._edge_points() if self._has_edge_penalty() else {}
         if assemble:
             self.assemble()
 
@@ -316,11 +327,65 @@ class Discretization:
         return lo, x, w, alpha_at(self.desc, x), len(leaves)
 
     def element_system(self, e):
-        """(K_e, b_e) of element e in the oracle's local order (mode*nf + comp)."""
+        """(K_e, b_e) of element e in the oracle's local order (mode*nf + comp),
+        with the boundary penalty of the element's edge pieces."""
         lo, x, w, a, _ = self.element_quadrature(e)
         val, grad = self._shape(lo, x)
         wa = w * a
-        return self._stiffness(grad, wa), self._load(val, x, wa)
+        K, b = self._stiffness(grad, wa), self._load(val, x, wa)
+        Kp, bp = self.penalty_system(e)
+        return K + Kp, b + bp
+
+    # --------------------------------------------------------- edge penalty
+    def _has_edge_penalty(self):
+        return self.desc["geom"] == SQUARE and float(self.desc.get("beta", 0.0)) > 0.0
+
+    def _edge_points(self):
+        """Quadrature of the penalty term on the square's edges (eq. weakform):
+        every edge is cut where it crosses a grid line; each piece gets a
+        Gauss rule of 2p+2 points and belongs to the cell that contains its
+        midpoint (floor((x - lo)/h), clamped to the grid).  Returns
+        {element multi-index: (points, weights, Dirichlet data g)}."""
+        gx, gw = basis.gauss(2 * self.p + 2)
+        corners = square_corners(self.desc)
+        coef = self.desc.get("trig_dir")
+        out = {}
+        for i in range(4):
+            a, b = corners[i], corners[(i + 1) % 4]
+            ts = {0.0, 1.0}
+            for ax in range(2):
+                if b[ax] != a[ax]:
+                    for k in range(int(self.n[ax]) + 1):
+                        t = (self.lo[ax] + k * self.h[ax] - a[ax]) / (b[ax] - a[ax])
+                        if 0.0 < t < 1.0:
+                            ts.add(float(t))
+            ts = sorted(ts)
+            length = float(np.linalg.norm(b - a))
+            for t0, t1 in zip(ts[:-1], ts[1:]):
+                if t1 <= t0:
+                    continue
+                mid = a + 0.5 * (t0 + t1) * (b - a)
+                cell = tuple(int(min(max(np.floor((mid[ax] - self.lo[ax]) / self.h[ax]), 0),
+                                     self.n[ax] - 1)) for ax in range(2))
+                tq = t0 + 0.5 * (gx + 1.0) * (t1 - t0)
+                x = a[None, :] + tq[:, None] * (b - a)[None, :]
+                w = 0.5 * gw * (t1 - t0) * length
+                g = trig(self.desc, coef, x) if coef else np.zeros(x.shape[0])
+                px, pw, pg = out.get(cell, (np.zeros((0, 2)), np.zeros(0), np.zeros(0)))
+                out[cell] = (np.vstack([px, x]), np.concatenate([pw, w]), np.concatenate([pg, g]))
+        return out
+
+    def penalty_system(self, e):
+        """beta sum_q w N_a N_b and beta sum_q w g N_a over the element's edge
+        pieces (zero for elements without any)."""
+        e = tuple(int(c) for c in e)
+        if e not in self.penalty:
+            return np.zeros((self.m, self.m)), np.zeros(self.m)
+        x, w, g = self.penalty[e]
+        beta = float(self.desc["beta"])
+        lo, _ = self.elem_box(e)
+        val, _ = self._shape(lo, x)
+        return beta * (val.T * w) @ val, beta * val.T @ (w * g)
 
     def reference_stiffness(self):
         """K_e of an uncut element (alpha = 1 everywhere): one Gauss rule per element."""
@@ -375,7 +440,7 @@ class Discretization:
         ne = self.kept.size
         Ks = np.empty((ne, m, m))
         bs = np.empty((ne, m))
-        const_f = (self.nf == 1 and not self.desc.get("gauss")
+        const_f = (self.nf == 1 and not self.desc.get("gauss") and not self.desc.get("trig_src")
                    and not callable(self.desc.get("source_fn"))) or self.nf > 1
         phys_b = None
         self.cut_elems = []
@@ -389,6 +454,10 @@ class Discretization:
                     bs[k] = phys_b
                 else:
                     bs[k] = self.phys_load(e)
+                if e in self.penalty:
+                    Kp, bp = self.penalty_system(e)
+                    Ks[k] = Ks[k] + Kp
+                    bs[k] = bs[k] + bp
             else:
                 Ks[k], bs[k] = self.element_system(e)
                 self.cut_elems.append(k)
