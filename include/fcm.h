@@ -72,7 +72,10 @@ typedef enum {
   FCM_ERR_BUSY = -7
 } fcm_status;
 
-enum { FCM_GEOM_BOX_MINUS_BALLS = 0, FCM_GEOM_BALL_INTERIOR = 1 };
+/* Physical domain: the box minus balls, the interior of one ball, or (2D,
+ * Section 4.1) the square of side ball_r[0] centred at ball_c[0] and rotated
+ * by psi (counter-clockwise) about its centre.                              */
+enum { FCM_GEOM_BOX_MINUS_BALLS = 0, FCM_GEOM_BALL_INTERIOR = 1, FCM_GEOM_SQUARE = 2 };
 /* Element basis: the tensor-product integrated Legendre space, or its trunk
  * subspace (Table tab::upperbound, trunk column): the products whose bubble
  * factors' degrees sum to at most p; level q of the p-hierarchy holds the
@@ -123,15 +126,24 @@ typedef struct {
   const double *gauss;        /* [n_gauss][5]: A, w, c_x, c_y, c_z               */
   double f_const;             /* constant scalar source                          */
   double body_force[3];       /* constant body force (elasticity)                */
-  double beta;                /* penalty for u = 0 on the sphere (eq. weakform):
-                                 needs refine_levels > 0 and BALL_INTERIOR;
-                                 0 = none                                        */
+  double beta;                /* penalty of the Dirichlet condition on an immersed
+                                 boundary (eq. weakform): u = 0 on the sphere
+                                 (refine_levels > 0, BALL_INTERIOR) or u = g on
+                                 the edges of the square (FCM_GEOM_SQUARE, g
+                                 from trig_dir); 0 = none                       */
   int surf_n[2];              /* surface rule of the penalty: Gauss-Legendre
                                  points in cos(theta) (<= 4096) and trapezoid
                                  points in phi (<= 8192; 2D: phi only);
                                  0 = 256 x 512                                   */
   int space;                  /* FCM_SPACE_TENSOR or FCM_SPACE_TRUNK (uniform
                                  grids only)                                   */
+  double psi;                 /* FCM_GEOM_SQUARE: rotation in radians            */
+  double trig_src[2];         /* source += A cos(a x') sin(a y') with (A, a) =
+                                 trig_src, (x', y') the square's frame (origin
+                                 at its centre, axes along its edges); A = 0:
+                                 none; FCM_GEOM_SQUARE only                    */
+  double trig_dir[2];         /* Dirichlet data g = A cos(a x') sin(a y') on the
+                                 square's edges, (A, a) = trig_dir             */
 } fcm_problem;
 
 /* Solver options (Sections 3.3.2 and 4). */

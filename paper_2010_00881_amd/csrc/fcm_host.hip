@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -239,13 +240,29 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
       return FCM_ERR_ARG;
     }
     if (p->p > 3) { set_error("multi-level hp: p must be <= 3"); return FCM_ERR_ARG; }
-  } else if (p->beta != 0.0) {
+  } else if (p->beta != 0.0 && p->geom != FCM_GEOM_SQUARE) {
     set_error("beta (sphere penalty) needs refine_levels > 0");
     return FCM_ERR_ARG;
   }
   if (!std::isfinite(p->beta) || p->beta < 0.0) { set_error("invalid beta"); return FCM_ERR_ARG; }
-  if (p->beta > 0.0 && p->geom != FCM_GEOM_BALL_INTERIOR) {
+  if (p->beta > 0.0 && p->geom != FCM_GEOM_BALL_INTERIOR && p->geom != FCM_GEOM_SQUARE) {
     set_error("beta (sphere penalty) needs the ball-interior geometry");
+    return FCM_ERR_ARG;
+  }
+  if (p->geom == FCM_GEOM_SQUARE) {
+    if (p->dim != 2 || p->n_fields != 1 || p->refine_levels != 0 || p->n_balls != 1) {
+      set_error("the square geometry needs a 2D Poisson problem on a uniform grid with one "
+                "centre (ball_c) and side (ball_r)");
+      return FCM_ERR_ARG;
+    }
+    if (!std::isfinite(p->psi) || !std::isfinite(p->trig_src[0]) ||
+        !std::isfinite(p->trig_src[1]) || !std::isfinite(p->trig_dir[0]) ||
+        !std::isfinite(p->trig_dir[1])) {
+      set_error("invalid square rotation or trigonometric data");
+      return FCM_ERR_ARG;
+    }
+  } else if (p->trig_src[0] != 0.0 || p->trig_dir[0] != 0.0) {
+    set_error("trigonometric source and Dirichlet data need the square geometry");
     return FCM_ERR_ARG;
   }
   if (p->surf_n[0] < 0 || p->surf_n[1] < 0 || p->surf_n[0] > 4096 || p->surf_n[1] > 8192) {
@@ -261,7 +278,8 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
     set_error("quad_depth must be in 0..%d", kMaxDepth);
     return FCM_ERR_ARG;
   }
-  if (p->geom != FCM_GEOM_BOX_MINUS_BALLS && p->geom != FCM_GEOM_BALL_INTERIOR) {
+  if (p->geom != FCM_GEOM_BOX_MINUS_BALLS && p->geom != FCM_GEOM_BALL_INTERIOR &&
+      p->geom != FCM_GEOM_SQUARE) {
     set_error("unknown geometry");
     return FCM_ERR_ARG;
   }
@@ -488,7 +506,8 @@ static void build_blocks(fcm_handle *h) {
       for (int x = 0; x < g.n[0]; ++x) {
         int e = elin(g, x, y, z);
         if (h->h_state[e] == kVoid) continue;
-        bool unique = h->h_state[e] == kCut;
+        // uncut = shares K_ref (an uncut element with an edge penalty does not)
+        bool unique = h->h_kmat[e] != 0;
         int c[3] = {x, y, z};
         for (int o = 0; o < 27 && !unique; ++o) {
           int off[3] = {o % 3 - 1, (o / 3) % 3 - 1, o / 9 - 1};
@@ -499,7 +518,7 @@ static void build_blocks(fcm_handle *h) {
             nc[ax] = c[ax] + off[ax];
             in = in && nc[ax] >= 0 && nc[ax] < g.n[ax];
           }
-          if (in && h->h_state[elin(g, nc[0], nc[1], nc[2])] != kPhys) unique = true;
+          if (in && h->h_kmat[elin(g, nc[0], nc[1], nc[2])] != 0) unique = true;
         }
         if (unique) {
           uniq.push_back(e);
@@ -874,7 +893,7 @@ static fcm_status build_patches(fcm_handle *h, std::vector<int> &bnode, std::vec
         for (int ez = lo[2]; ez <= hi[2] && shared; ++ez)
           for (int ey = lo[1]; ey <= hi[1] && shared; ++ey)
             for (int ex = lo[0]; ex <= hi[0] && shared; ++ex)
-              if (h->h_state[elin(g, ex, ey, ez)] != kPhys) shared = false;
+              if (h->h_kmat[elin(g, ex, ey, ez)] != 0) shared = false;
         if (!shared) continue;
         int k = 0;
         for (int ax = d - 1; ax >= 0; --ax)
@@ -1083,6 +1102,71 @@ static fcm_status setup_patch_levels(fcm_handle *h, const int *dbn, const int *d
   return check_flag(h, "patch Schwarz block inversion");
 }
 
+// Quadrature of the penalty on the square's edges (FCM_GEOM_SQUARE, beta >
+// 0): each edge, corner to corner counter-clockwise, is cut at every
+// crossing with a grid line; a piece gets the (2p+2)-point Gauss rule and
+// belongs to the element containing its midpoint (floor((x - lo) / h),
+// clamped to the grid).  Output per element with points (increasing element
+// index): pel, ptr (CSR) and pts [x, y, weight, Dirichlet data g].
+static void edge_penalty_points(const fcm_handle *h, std::vector<int> &pel,
+                                std::vector<int> &ptr, std::vector<double> &pts) {
+  const Geo &g = h->geo;
+  const fcm_problem &pr = h->prob.pr;
+  std::vector<double> gx, gw;
+  gauss_legendre(2 * g.p + 2, gx, gw);
+  const double hs = g.sq[2], cs = g.sq[3], sn = g.sq[4];
+  const int sgn[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+  double cx[4], cy[4];
+  for (int i = 0; i < 4; ++i) {
+    cx[i] = g.sq[0] + hs * (sgn[i][0] * cs - sgn[i][1] * sn);
+    cy[i] = g.sq[1] + hs * (sgn[i][0] * sn + sgn[i][1] * cs);
+  }
+  std::map<int, std::vector<double>> per;   // element -> points
+  for (int i = 0; i < 4; ++i) {
+    const double a[2] = {cx[i], cy[i]}, b[2] = {cx[(i + 1) % 4], cy[(i + 1) % 4]};
+    std::set<double> ts = {0.0, 1.0};
+    for (int ax = 0; ax < 2; ++ax) {
+      if (b[ax] == a[ax]) continue;
+      for (int k = 0; k <= g.n[ax]; ++k) {
+        const double t = (g.lo[ax] + k * g.h[ax] - a[ax]) / (b[ax] - a[ax]);
+        if (t > 0.0 && t < 1.0) ts.insert(t);
+      }
+    }
+    const double len = std::hypot(b[0] - a[0], b[1] - a[1]);
+    std::vector<double> tv(ts.begin(), ts.end());
+    for (size_t j = 0; j + 1 < tv.size(); ++j) {
+      const double t0 = tv[j], t1 = tv[j + 1];
+      if (!(t1 > t0)) continue;
+      int cell[2];
+      for (int ax = 0; ax < 2; ++ax) {
+        const double mid = a[ax] + 0.5 * (t0 + t1) * (b[ax] - a[ax]);
+        const double f = std::floor((mid - g.lo[ax]) / g.h[ax]);
+        cell[ax] = (int)std::min(std::max(f, 0.0), (double)(g.n[ax] - 1));
+      }
+      std::vector<double> &out = per[cell[0] + g.n[0] * cell[1]];
+      for (size_t q = 0; q < gx.size(); ++q) {
+        const double tq = t0 + 0.5 * (gx[q] + 1.0) * (t1 - t0);
+        const double x = a[0] + tq * (b[0] - a[0]), y = a[1] + tq * (b[1] - a[1]);
+        const double rx = x - g.sq[0], ry = y - g.sq[1];
+        const double xr = cs * rx + sn * ry, yr = -sn * rx + cs * ry;
+        out.push_back(x);
+        out.push_back(y);
+        out.push_back(0.5 * gw[q] * (t1 - t0) * len);
+        out.push_back(pr.trig_dir[0] * std::cos(pr.trig_dir[1] * xr) *
+                      std::sin(pr.trig_dir[1] * yr));
+      }
+    }
+  }
+  pel.clear();
+  ptr.assign(1, 0);
+  pts.clear();
+  for (auto &kv : per) {
+    pel.push_back(kv.first);
+    pts.insert(pts.end(), kv.second.begin(), kv.second.end());
+    ptr.push_back((int)(pts.size() / 4));
+  }
+}
+
 static fcm_status do_setup(fcm_handle *h) {
   Geo &g = h->geo;
   const fcm_problem &pr = h->prob.pr;
@@ -1098,14 +1182,35 @@ static fcm_status do_setup(fcm_handle *h) {
   FCM_HIP(hipStreamSynchronize(h->stream));
   if (drop_floating(g, h->h_state))
     FCM_HIP(hipMemcpyAsync(h->state, h->h_state.data(), g.E, hipMemcpyHostToDevice, h->stream));
+  // penalty of immersed edges: those elements get stored matrices
+  std::vector<int> pen_el, pen_ptr;
+  std::vector<double> pen_pts;
+  std::vector<uint8_t> pen(g.E, 0);
+  if (g.geom == FCM_GEOM_SQUARE && pr.beta > 0.0) {
+    edge_penalty_points(h, pen_el, pen_ptr, pen_pts);
+    for (int e : pen_el) {
+      if (h->h_state[e] == kVoid) {
+        set_error("edge penalty points in a void element");
+        return FCM_ERR_ARG;
+      }
+      pen[e] = 1;
+    }
+  }
   h->h_kmat.assign(g.E, -1);
   h->h_cut.clear();
   for (int e = 0; e < g.E; ++e) {
-    if (h->h_state[e] == kPhys) h->h_kmat[e] = 0;
-    else if (h->h_state[e] == kCut) {
+    if (h->h_state[e] == kPhys && !pen[e]) h->h_kmat[e] = 0;
+    else if (h->h_state[e] != kVoid) {
       h->h_kmat[e] = 1 + (int)h->h_cut.size();
       h->h_cut.push_back(e);
     }
+  }
+  int *dpel = nullptr, *dpptr = nullptr;
+  double *dppts = nullptr;
+  if (!pen_el.empty()) {
+    TRY(device_upload(h, &dpel, pen_el));
+    TRY(device_upload(h, &dpptr, pen_ptr));
+    TRY(device_upload(h, &dppts, pen_pts));
   }
   build_blocks(h);
   TRY(device_upload(h, &h->kmat, h->h_kmat));
@@ -1129,6 +1234,8 @@ static fcm_status do_setup(fcm_handle *h) {
     if (ncut > 0)
       launch_integrate(g, h->tab, pr, dcut, ncut, 0, h->Kcut64, h->be, h->dflag, h->stream);
     launch_phys_rhs(g, h->tab, pr, h->state, h->be, h->stream);
+    launch_edge_penalty(g, h->tab, dpel, (int)pen_el.size(), dpptr, dppts, pr.beta, h->kmat,
+                        h->Kcut64, h->be, h->stream);
     for (int k = 0; k < pr.n_traction; ++k)
       launch_traction_rhs(g, h->tab, pr.traction_face[k], &h->prob.tvec[3 * k], h->state, h->be,
                           h->stream);
@@ -1826,6 +1933,16 @@ fcm_status fcm_setup(const fcm_problem *pr, const fcm_options *op, void *stream,
   g.dir = pr->dirichlet_faces;
   g.geom = pr->geom;
   g.nballs = pr->n_balls;
+  for (int k = 0; k < 5; ++k) g.sq[k] = 0.0;
+  if (g.geom == FCM_GEOM_SQUARE) {
+    g.sq[0] = pr->ball_c[0];
+    g.sq[1] = pr->ball_c[1];
+    g.sq[2] = 0.5 * pr->ball_r[0];
+    g.sq[3] = std::cos(pr->psi);
+    g.sq[4] = std::sin(pr->psi);
+  }
+  g.trig[0] = pr->trig_src[0];
+  g.trig[1] = pr->trig_src[1];
   g.alpha = pr->alpha;
   g.depth = pr->quad_depth;
   g.trunk = pr->space == FCM_SPACE_TRUNK;
@@ -1996,7 +2113,8 @@ fcm_status fcm_get_stats(const fcm_handle *h, fcm_stats *s) {
   int64_t kept = 0;
   for (auto v : h->h_state) kept += v != kVoid;
   s->n_kept = kept;
-  s->n_cut = (int64_t)h->h_cut.size();
+  s->n_cut = 0;   // cut elements (stored matrices also serve uncut penalty elements)
+  for (uint8_t st : h->h_state) s->n_cut += st == kCut;
   const bool patch = h->opt.smoother == FCM_SMOOTH_PATCHWISE;
   s->n_unique_blocks = patch ? h->np_unique : h->n_unique;
   s->n_shared_classes = patch ? h->np_classes : h->n_shared;

@@ -51,6 +51,8 @@ struct Geo {
   double alpha;
   int depth;
   int trunk;     // 1: trunk-space basis (FCM_SPACE_TRUNK)
+  double sq[5];  // FCM_GEOM_SQUARE: centre x, y, half side, cos psi, sin psi
+  double trig[2];  // source A cos(a x') sin(a y'): A, a (A = 0: none)
 };
 
 // Per-level Schwarz data and work vectors.
@@ -301,6 +303,12 @@ void launch_integrate(const Geo &g, const Tables &t, const fcm_problem &pr, cons
                       hipStream_t s);
 void launch_phys_rhs(const Geo &g, const Tables &t, const fcm_problem &pr, const uint8_t *state,
                      double *be_all, hipStream_t s);
+// Penalty of the Dirichlet data on immersed edges (FCM_GEOM_SQUARE): for the
+// elements pel[0..nel) with points ptr[k]..ptr[k+1] of pts ([x, y, w, g]),
+// K_e += beta sum w N N^T and b_e += beta sum w g N, in point order.
+void launch_edge_penalty(const Geo &g, const Tables &t, const int *pel, int nel, const int *ptr,
+                         const double *pts, double beta, const int *kmat, double *Kcut,
+                         double *be_all, hipStream_t s);
 void launch_traction_rhs(const Geo &g, const Tables &t, int face, const double *tvec,
                          const uint8_t *state, double *be_all, hipStream_t s);
 void launch_assemble_rhs(const Geo &g, const Tables &t, const int *kmat, const double *be_all,

@@ -20,8 +20,56 @@
 namespace fcm {
 
 // ------------------------------------------------------------ device helpers
+// Square of FCM_GEOM_SQUARE: point in its frame.
+__device__ inline void square_frame_dev(const Geo &g, const double *x, double *xr) {
+  const double rx = x[0] - g.sq[0], ry = x[1] - g.sq[1];
+  xr[0] = g.sq[3] * rx + g.sq[4] * ry;
+  xr[1] = -g.sq[4] * rx + g.sq[3] * ry;
+}
+
+__device__ inline bool inside_square_dev(const Geo &g, const double *x) {
+  double xr[2];
+  square_frame_dev(g, x, xr);
+  return fabs(xr[0]) <= g.sq[2] && fabs(xr[1]) <= g.sq[2];
+}
+
+// Box against the (convex) square: kPhys if all four corners are inside,
+// kVoid if an axis of the box or of the square separates the two (touching
+// counts as separated), kCut otherwise.
+__device__ inline int classify_square_dev(const Geo &g, const double *lo, const double *hi) {
+  const double bx[4] = {lo[0], hi[0], hi[0], lo[0]}, by[4] = {lo[1], lo[1], hi[1], hi[1]};
+  bool all = true;
+  for (int i = 0; i < 4; ++i) {
+    const double x[2] = {bx[i], by[i]};
+    all = all && inside_square_dev(g, x);
+  }
+  if (all) return kPhys;
+  const double cx = g.sq[0], cy = g.sq[1], hs = g.sq[2], cs = g.sq[3], sn = g.sq[4];
+  const double ux = cs, uy = sn, vx = -sn, vy = cs;
+  double sx[4], sy[4];
+  const int sgn[4][2] = {{-1, -1}, {1, -1}, {1, 1}, {-1, 1}};
+  for (int i = 0; i < 4; ++i) {
+    sx[i] = cx + hs * (sgn[i][0] * ux + sgn[i][1] * vx);
+    sy[i] = cy + hs * (sgn[i][0] * uy + sgn[i][1] * vy);
+  }
+  const double ax[4] = {1.0, 0.0, ux, vx}, ay[4] = {0.0, 1.0, uy, vy};
+  for (int k = 0; k < 4; ++k) {
+    double bmin = 1e300, bmax = -1e300, smin = 1e300, smax = -1e300;
+    for (int i = 0; i < 4; ++i) {
+      const double pb = bx[i] * ax[k] + by[i] * ay[k], ps = sx[i] * ax[k] + sy[i] * ay[k];
+      bmin = fmin(bmin, pb);
+      bmax = fmax(bmax, pb);
+      smin = fmin(smin, ps);
+      smax = fmax(smax, ps);
+    }
+    if (bmax <= smin || smax <= bmin) return kVoid;
+  }
+  return kCut;
+}
+
 __device__ inline int classify_box_dev(const Geo &g, const double *ball, const double *lo,
                                        const double *hi) {
+  if (g.geom == FCM_GEOM_SQUARE) return classify_square_dev(g, lo, hi);
   if (g.geom == FCM_GEOM_BOX_MINUS_BALLS) {
     bool any = false;
     for (int j = 0; j < g.nballs; ++j) {
@@ -56,6 +104,7 @@ __device__ inline int classify_box_dev(const Geo &g, const double *ball, const d
 }
 
 __device__ inline bool inside_phys_dev(const Geo &g, const double *ball, const double *x) {
+  if (g.geom == FCM_GEOM_SQUARE) return inside_square_dev(g, x);
   if (g.geom == FCM_GEOM_BOX_MINUS_BALLS) {
     for (int j = 0; j < g.nballs; ++j) {
       const double *b = ball + 4 * j;
@@ -94,9 +143,14 @@ __device__ inline void modes1d_dev(int p, double xi, double *v, double *dv) {
   }
 }
 
-__device__ inline double source_dev(const double *gsrc, int ngauss, double fconst,
+__device__ inline double source_dev(const Geo &g, const double *gsrc, int ngauss, double fconst,
                                     const double *x, int d) {
   double f = fconst;
+  if (g.trig[0] != 0.0) {
+    double xr[2];
+    square_frame_dev(g, x, xr);
+    f += g.trig[0] * cos(g.trig[1] * xr[0]) * sin(g.trig[1] * xr[1]);
+  }
   for (int k = 0; k < ngauss; ++k) {
     const double *s = gsrc + 5 * k;
     double d2 = 0.0;
@@ -192,9 +246,10 @@ __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
   const int e = A.ref_mode ? 0 : A.elist[blockIdx.x];
   int ec[3];
   elem_coords(g, e, ec);
-  double elo[3];
+  double elo[3], ehi[3];
   for (int ax = 0; ax < 3; ++ax) elo[ax] = g.lo[ax] + ec[ax] * g.h[ax];
   if (A.ref_mode) elo[0] = elo[1] = elo[2] = 0.0;
+  for (int ax = 0; ax < 3; ++ax) ehi[ax] = elo[ax] + g.h[ax];
 
   // ---- enumerate leaves
   if (tid == 0) {
@@ -204,6 +259,12 @@ __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
       s_ncur = 0;
     } else if (g.depth == 0) {
       leaves[0] = leaf_pack(0, kCut, 0, 0, 0);
+      s_nleaf = 1;
+      s_ncur = 0;
+    } else if (classify_box_dev(g, A.ball, elo, ehi) == kPhys) {
+      // an uncut element with a stored matrix (an immersed edge's penalty
+      // lies on it): one Gauss rule over the element, as for K_ref
+      leaves[0] = leaf_pack(0, kPhys, 0, 0, 0);
       s_nleaf = 1;
       s_ncur = 0;
     } else {
@@ -316,7 +377,7 @@ __global__ __launch_bounds__(kIntThreads) void integrate_kernel(IntegArgs A) {
           else al = inside_phys_dev(g, A.ball, x) ? 1.0 : g.alpha;
           W[q] = w * al;
           if (do_load)
-            Wf[q] = w * al * (A.elastic ? 1.0 : source_dev(A.gsrc, A.ngauss, A.fconst, x, d));
+            Wf[q] = w * al * (A.elastic ? 1.0 : source_dev(g, A.gsrc, A.ngauss, A.fconst, x, d));
         }
         __syncthreads();
         // phase B: pair tables of axes 0, 1 and the q2-contraction T1
@@ -496,7 +557,7 @@ __global__ __launch_bounds__(64) void phys_rhs_kernel(Geo g, const double *gxw,
       x[ax] = g.lo[ax] + ec[ax] * g.h[ax] + 0.5 * (gx[qc[ax]] + 1.0) * g.h[ax];
       w *= gw[qc[ax]] * 0.5 * g.h[ax];
     }
-    fw[q] = w * (elastic ? 1.0 : source_dev(gsrc, ngauss, fconst, x, d));
+    fw[q] = w * (elastic ? 1.0 : source_dev(g, gsrc, ngauss, fconst, x, d));
   }
   __syncthreads();
   double *be = be_all + (size_t)e * m;
@@ -527,6 +588,68 @@ void launch_phys_rhs(const Geo &g, const Tables &t, const fcm_problem &pr, const
 }
 
 // Box-face traction t on face (axis, side): int_face N_a t dA, closed form per mode.
+// Penalty of the Dirichlet data on the square's edges (eq. weakform): one
+// workgroup per element with edge points; the mode values of up to 32
+// points at a time are staged in LDS, then thread (a, b) adds
+// beta sum_q w_q N_a N_b to K_e and thread a adds beta sum_q w_q g_q N_a to
+// b_e, points in their stored order.
+constexpr int kPenPts = 32;
+__global__ __launch_bounds__(256) void edge_penalty_kernel(Geo g, const int *lm, int m,
+                                                           const int *pel, const int *ptr,
+                                                           const double *pts, double beta,
+                                                           const int *kmat, double *Kcut,
+                                                           double *be_all) {
+  __shared__ double N[kPenPts * 64];
+  __shared__ double W[kPenPts], Gv[kPenPts];
+  const int e = pel[blockIdx.x];
+  const int kid = kmat[e];
+  if (kid <= 0) return;   // the host gives every penalty element a stored matrix
+  int ec[3];
+  elem_coords(g, e, ec);
+  double *K = Kcut + (size_t)(kid - 1) * m * m;
+  double *be = be_all + (size_t)e * m;
+  const int np = g.p + 1;
+  for (int q0 = ptr[blockIdx.x]; q0 < ptr[blockIdx.x + 1]; q0 += kPenPts) {
+    const int nq = min(kPenPts, ptr[blockIdx.x + 1] - q0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nq * m; i += blockDim.x) {
+      const int q = i / m, a = i % m;
+      const double *pt = pts + 4 * (size_t)(q0 + q);
+      double val = 1.0;
+      for (int ax = 0; ax < g.d; ++ax) {
+        const double xi = 2.0 * (pt[ax] - (g.lo[ax] + ec[ax] * g.h[ax])) / g.h[ax] - 1.0;
+        double v[kMaxP + 1], dv[kMaxP + 1];
+        modes1d_dev(np - 1, xi, v, dv);
+        val *= v[lm[4 * a + ax]];
+      }
+      N[q * 64 + a] = val;
+      if (a == 0) {
+        W[q] = pt[2];
+        Gv[q] = pt[3];
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < m * m; i += blockDim.x) {
+      const int a = i / m, b = i % m;
+      double s = 0.0;
+      for (int q = 0; q < nq; ++q) s += W[q] * N[q * 64 + a] * N[q * 64 + b];
+      K[i] += beta * s;
+    }
+    for (int a = threadIdx.x; a < m; a += blockDim.x) {
+      double s = 0.0;
+      for (int q = 0; q < nq; ++q) s += W[q] * Gv[q] * N[q * 64 + a];
+      be[a] += beta * s;
+    }
+  }
+}
+
+void launch_edge_penalty(const Geo &g, const Tables &t, const int *pel, int nel, const int *ptr,
+                         const double *pts, double beta, const int *kmat, double *Kcut,
+                         double *be_all, hipStream_t s) {
+  if (nel <= 0) return;
+  edge_penalty_kernel<<<nel, 256, 0, s>>>(g, t.lm, t.m, pel, ptr, pts, beta, kmat, Kcut, be_all);
+}
+
 __global__ void traction_kernel(Geo g, const double *gxw, const double *vgauss, const int *smap,
                                 int ms, int m, int face, double t0, double t1, double t2,
                                 const uint8_t *state, double *be_all) {

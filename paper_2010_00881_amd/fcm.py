@@ -44,6 +44,8 @@ class Problem(ctypes.Structure):
         ("n_gauss", ctypes.c_int), ("gauss", ctypes.POINTER(ctypes.c_double)),
         ("f_const", ctypes.c_double), ("body_force", ctypes.c_double * 3),
         ("beta", ctypes.c_double), ("surf_n", ctypes.c_int * 2), ("space", ctypes.c_int),
+        ("psi", ctypes.c_double), ("trig_src", ctypes.c_double * 2),
+        ("trig_dir", ctypes.c_double * 2),
     ]
 
 
@@ -206,6 +208,10 @@ class _ProblemData:
         if sp not in ("tensor", "trunk"):
             raise ValueError(f"unknown space {sp!r}")
         P.space = 1 if sp == "trunk" else 0
+        P.psi = float(desc.get("psi", 0.0))
+        for name in ("trig_src", "trig_dir"):
+            v = desc.get(name) or (0.0, 0.0)
+            getattr(P, name)[0], getattr(P, name)[1] = float(v[0]), float(v[1])
         self.struct = P
 
 

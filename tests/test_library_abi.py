@@ -43,7 +43,7 @@ def test_struct_layouts_match_header():
     # 7 fields, then use_graphs, autotune, coarse and coarse_dense_max
     assert ctypes.sizeof(fcm.Options) == 64
     assert ctypes.sizeof(fcm.SolveInfo) == 56
-    assert ctypes.sizeof(fcm.Problem) == 240     # ..., beta, surf_n[2], space
+    assert ctypes.sizeof(fcm.Problem) == 280     # ..., surf_n[2], space, psi, trig_src, trig_dir
     assert ctypes.sizeof(fcm.Stats) == 64
     assert ctypes.sizeof(fcm.ServerOpts) == 16
 
