@@ -241,18 +241,20 @@ def mlhp_bench(args):
     """Multi-level hp sphere problem (8^3 base grid, p = 3, sphere r = 0.35,
     alpha = 1e-10, beta = 1e4, six seeded Gaussian sources) at refinement depth
     --mlhp-k (the paper's configuration uses 3, whose base-node patch inverses
-    need ~700 GB; 1 and 2 fit one GPU): setup + FP64 MG-PCG per seed."""
+    need ~700 GB; 1 and 2 fit one GPU): setup + MG-PCG per seed, in the form
+    --precision (mixed: FP32 copies of the well-conditioned patch inverses)
+    and, unless --no-fp64, in the plain FP64 form beside it."""
     import torch
     import fcm_inputs as fi
     from paper_2010_00881_amd import Solver
     K = args.mlhp_k
     p = args.mlhp_p
 
-    def one(seed):
+    def one(seed, precision):
         d, o = fi.sphere_multilevel(seed, n=8, k=K, p=p)
         d["quad_depth"] = 2
         t = time.perf_counter()
-        s = Solver(d, dict(o, precision="fp64"))
+        s = Solver(d, dict(o, precision=precision))
         x, info = s.pcg()
         torch.cuda.synchronize()
         lat = (time.perf_counter() - t) * 1e3
@@ -261,32 +263,50 @@ def mlhp_bench(args):
         s.close()
         if info["status"] != 0:
             raise RuntimeError(f"seed {seed} did not converge: {info}")
+        print(f"[bench] mlhp seed {seed} {precision}: {lat:.0f} ms (setup "
+              f"{info['t_setup_ms']:.0f}, solve {info['t_solve_ms']:.0f}, {info['iterations']} it, "
+              f"{n} unknowns, {st['n_unique_blocks'] - st['n_fp64_blocks']} FP32 patches)",
+              file=sys.stderr, flush=True)
         return lat, info, st, n
+
+    def timed(precision):
+        t0 = time.perf_counter()
+        res = [one(sd, precision) for sd in range(args.steps)]
+        return res, time.perf_counter() - t0
+
+    def summary(res):
+        lat = [r[0] for r in res]
+        return {"p50_ms": statistics.median(lat),
+                "setup_ms_median": statistics.median(r[1]["t_setup_ms"] for r in res),
+                "solve_ms_median": statistics.median(r[1]["t_solve_ms"] for r in res),
+                "iterations": [r[1]["iterations"] for r in res],
+                "max_true_rel_res": max(r[1]["true_rel_res"] for r in res)}
 
     print(f"[bench] multi-level hp K={K} p={p}: warmup", file=sys.stderr, flush=True)
     for w in range(args.warmup):
-        one(1000 + w)
+        one(1000 + w, args.precision)
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    res = [one(sd) for sd in range(args.steps)]
-    T = time.perf_counter() - t0
-    lat = [r[0] for r in res]
+    res, T = timed(args.precision)
+    st = res[0][2]
     out = {
         "metric": "multi-level hp MG-PCG solves/s (setup + solve)", "value": args.steps / T,
         "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": T * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64",
+        "vs_baseline": None, "dtype": "f32+f64" if args.precision == "mixed" else "f64",
         "data": "synthetic (seeded Gaussian sources, seeds 0..steps-1)",
         "config": {"workload": f"sphere_mlhp_8^3_k{K}_p{p}", "dofs": res[0][3],
-                   "leaves": res[0][2]["n_kept"], "patches": res[0][2]["n_unique_blocks"],
-                   "alpha": 1e-10, "beta": 1e4, "quad_depth": 2, "rtol": 1e-10},
-        "p50_ms": statistics.median(lat),
-        "setup_ms_median": statistics.median(r[1]["t_setup_ms"] for r in res),
-        "solve_ms_median": statistics.median(r[1]["t_solve_ms"] for r in res),
-        "iterations": [r[1]["iterations"] for r in res],
-        "max_true_rel_res": max(r[1]["true_rel_res"] for r in res),
-        "device_bytes": res[0][2]["device_bytes"],
+                   "leaves": st["n_kept"], "patches": st["n_unique_blocks"],
+                   "fp32_patches": st["n_unique_blocks"] - st["n_fp64_blocks"],
+                   "precision": args.precision, "alpha": 1e-10, "beta": 1e4,
+                   "quad_depth": 2, "rtol": 1e-10},
+        "device_bytes": st["device_bytes"],
     }
+    out.update(summary(res))
+    if args.precision == "mixed" and not args.no_fp64:
+        r64, T64 = timed("fp64")
+        out["fp64_form_solves_s"] = args.steps / T64
+        out["fp64_form"] = summary(r64)
+        out["mixed_over_fp64"] = out["value"] / out["fp64_form_solves_s"]
     print(json.dumps(out), flush=True)
     return 0
 

@@ -107,9 +107,9 @@ typedef struct {
   int n_fields;               /* 1 (Poisson) or dim (linear elasticity)          */
   int refine_levels;          /* multi-level hp depth K (Section 2.2): elements cut
                                  by the sphere are bisected recursively K times;
-                                 K > 0 needs Poisson, one ball, FP64 V-cycle and
-                                 patchwise blocks (all functions on the base
-                                 elements around a base node, Section 3.3.1)   */
+                                 K > 0 needs Poisson, one ball and patchwise
+                                 blocks (all functions on the base elements
+                                 around a base node, Section 3.3.1)            */
   int geom;                   /* FCM_GEOM_*                                      */
   int n_balls;                /* holes (BOX_MINUS_BALLS) or 1 (BALL_INTERIOR)    */
   const double *ball_c;       /* [n_balls][dim] centres                          */

@@ -227,10 +227,6 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
       set_error("multi-level hp: the coarse level is solved exactly");
       return FCM_ERR_ARG;
     }
-    if (o->precision != FCM_FP64) {
-      set_error("multi-level hp: the V-cycle runs in FP64 only");
-      return FCM_ERR_ARG;
-    }
     if (o->smoother != FCM_SMOOTH_PATCHWISE) {
       set_error("multi-level hp: patchwise Schwarz blocks only");
       return FCM_ERR_ARG;

@@ -55,6 +55,14 @@ struct MlPatches {                // Schwarz blocks of one multigrid level
   double *pc = nullptr;           // per patch row: the smoother product (gathered per DOF)
   double *inv = nullptr;
   int64_t inv_doubles = 0;
+  // mixed form: FP32 copies of the inverses whose Jacobi-scaled kappa_1 is small
+  // enough (ml_lowprec_kernel)
+  double *scal = nullptr;         // per patch row: Jacobi scaling 1/sqrt(B_ii)
+  double *norm1 = nullptr;        // per patch: ||S B S||_1
+  float *inv32 = nullptr;
+  uint8_t *lo32 = nullptr;        // per patch: 1 = applied from inv32
+  int n32 = 0;
+  int64_t nrows = 0;              // patch rows (padded), the length of pidx
   std::vector<std::pair<int64_t, std::pair<int, int>>> buckets;  // (inv offset, (count, mb))
 };
 
@@ -439,7 +447,8 @@ __global__ __launch_bounds__(256) void ml_integrate_kernel(MlLeafArgs a) {
 
 // sum_j M[j] v[j] over j = lane, lane + 64, ... < n with four independent
 // accumulators (four loads in flight per lane), fixed order
-__device__ inline double ml_row_dot(const double *M, const double *v, int n, int lane) {
+template <typename TM>
+__device__ inline double ml_row_dot(const TM *M, const double *v, int n, int lane) {
   double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   int j = lane;
   for (; j + 192 < n; j += 256) {
@@ -544,7 +553,8 @@ __global__ __launch_bounds__(256) void ml_form_blocks_kernel(
 // [64 c, 64 c + 64) of patch P (grid.y = max rows / 64)
 __global__ __launch_bounds__(256) void ml_smooth_kernel(const int *pm, const int64_t *pinv,
                                                         const int64_t *poff, const int *pidx,
-                                                        const double *inv, const double *r,
+                                                        const double *inv, const float *inv32,
+                                                        const uint8_t *lo32, const double *r,
                                                         double *pc) {
   const int P = blockIdx.x, tid = threadIdx.x;
   const int mb = pm[2 * P], mreal = pm[2 * P + 1];
@@ -554,11 +564,12 @@ __global__ __launch_bounds__(256) void ml_smooth_kernel(const int *pm, const int
   __shared__ double rs[kMlMaxPatch];
   for (int i = tid; i < mb; i += 256) rs[i] = i < mreal ? r[idx[i]] : 0.0;
   __syncthreads();
-  const double *M = inv + pinv[P];
   const int wave = tid >> 6, lane = tid & 63;
   const int row1 = min(mreal, row0 + 64);
+  const bool lo = inv32 && lo32[P];
   for (int i = row0 + wave; i < row1; i += 4) {
-    double s = ml_row_dot(M + (size_t)i * mb, rs, mreal, lane);
+    double s = lo ? ml_row_dot(inv32 + pinv[P] + (size_t)i * mb, rs, mreal, lane)
+                  : ml_row_dot(inv + pinv[P] + (size_t)i * mb, rs, mreal, lane);
     for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
     if (lane == 0) pc[poff[P] + i] = s;
   }
@@ -573,7 +584,9 @@ __global__ __launch_bounds__(256) void ml_smooth_kernel(const int *pm, const int
 // (patch blocks with fictitious leaves).
 __global__ __launch_bounds__(256) void ml_chol_factor_kernel(double *Ball, const int *pm,
                                                              const int64_t *pinv, double *WTall,
-                                                             double *Wall, int *flag) {
+                                                             double *Wall, int *flag,
+                                                             const int64_t *poff, double *scal,
+                                                             double *norm1) {
   const int n = pm[2 * blockIdx.x];
   const int64_t off = pinv[blockIdx.x];
   double *B = Ball + off;
@@ -594,6 +607,25 @@ __global__ __launch_bounds__(256) void ml_chol_factor_kernel(double *Ball, const
     B[e] *= sc[i] * sc[j];
   }
   __syncthreads();
+  if (scal) {
+    // scaling and ||S B S||_1 (largest row sum of the symmetric scaled block)
+    double mx = 0.0;
+    for (int i = tid; i < n; i += 256) {
+      scal[poff[blockIdx.x] + i] = sc[i];
+      const double *row = B + (size_t)i * n;
+      double rs = 0.0;
+      for (int j = 0; j < n; ++j) rs += fabs(row[j]);
+      mx = fmax(mx, rs);
+    }
+    red[tid] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+      __syncthreads();
+    }
+    if (tid == 0) norm1[blockIdx.x] = red[0];
+    __syncthreads();
+  }
   for (int j = 0; j < n; ++j) {
     double part = 0.0;
     for (int k = tid; k < j; k += 256) {
@@ -691,6 +723,42 @@ __global__ __launch_bounds__(256) void ml_gemm_kernel(const double *Aall, const 
       }
 }
 
+// Mixed form: ||(S B S)^{-1}||_1 = max_i sum_j |inv_ij| / (s_i s_j) of each
+// patch inverse (one workgroup per patch, fixed reduction order).  Rounding
+// the entries of an m x m inverse to FP32 moves its smallest eigenvalue by up
+// to about u32 sqrt(m) kappa relative (u32 = 2^-24), so a patch gets an FP32
+// copy, and is applied from it, only where u32 sqrt(m) kappa_1 <= 1e-2 (with
+// blocks of up to 1858 rows the uniform-grid rule kappa_1 <= 1e5 allowed
+// perturbations of 25 % and one seeded solve stalled).
+__global__ __launch_bounds__(256) void ml_lowprec_kernel(const int *pm, const int64_t *pinv,
+                                                         const int64_t *poff, const double *scal,
+                                                         const double *norm1, const double *inv,
+                                                         float *inv32, uint8_t *lo32) {
+  const int P = blockIdx.x, tid = threadIdx.x;
+  const int n = pm[2 * P];
+  const double *M = inv + pinv[P];
+  const double *sc = scal + poff[P];
+  __shared__ double red[256];
+  double mx = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    const double *row = M + (size_t)i * n;
+    double rs = 0.0;
+    for (int j = 0; j < n; ++j) rs += fabs(row[j]) / (sc[i] * sc[j]);
+    mx = fmax(mx, rs);
+  }
+  red[tid] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const bool lo = 0x1p-24 * sqrt((double)n) * norm1[P] * red[0] <= 1e-2;
+  if (tid == 0) lo32[P] = lo ? 1 : 0;
+  if (!lo) return;
+  float *M32 = inv32 + pinv[P];
+  for (size_t e = tid; e < (size_t)n * n; e += 256) M32[e] = (float)M[e];
+}
+
 // ------------------------------------------------------------ vectors
 __global__ void ml_axpby_kernel(int64_t n, double a, const double *x, double b, double *y) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -736,9 +804,11 @@ static int ml_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_
 // symmetric MFMA products per bucket of equal-size blocks.
 static fcm_status ml_spd_inverse(double *inv, int npatch, const int *pm, const int64_t *pinv,
                                  const std::vector<std::pair<int64_t, std::pair<int, int>>> &bk,
-                                 double *wt, double *w, int *flag, hipStream_t s) {
+                                 double *wt, double *w, int *flag, hipStream_t s,
+                                 const int64_t *poff = nullptr, double *scal = nullptr,
+                                 double *norm1 = nullptr) {
   if (npatch <= 0) return FCM_OK;
-  ml_chol_factor_kernel<<<npatch, 256, 0, s>>>(inv, pm, pinv, wt, w, flag);
+  ml_chol_factor_kernel<<<npatch, 256, 0, s>>>(inv, pm, pinv, wt, w, flag, poff, scal, norm1);
   for (const auto &b : bk) {
     const int n = b.second.second, nt = (n + 63) / 64;
     ml_gemm_kernel<<<dim3(nt * nt, b.second.first), 256, 0, s>>>(wt + b.first, w + b.first,
@@ -1112,6 +1182,7 @@ static fcm_status ml_patches(Builder &B, int l, const std::vector<int> &fdof,
     ML_TRY(device_upload(h, &P.pg_ptr, gptr));
     ML_TRY(device_upload(h, &P.pg_slot, gslot));
     ML_TRY(device_alloc(h, &P.pc, pidx.size()));
+    P.nrows = (int64_t)pidx.size();
   }
   ML_TRY(device_upload(h, &P.pidx, pidx));
   ML_TRY(device_upload(h, &P.poff, poff));
@@ -1326,13 +1397,30 @@ fcm_status mlhp_setup(fcm_handle *h) {
   double *s1 = nullptr, *s2 = nullptr;
   ML_TRY(pool_alloc((void **)&s1, scr_need * sizeof(double), h->stream));
   ML_TRY(pool_alloc((void **)&s2, scr_need * sizeof(double), h->stream));
+  const bool mixed = h->opt.precision == FCM_MIXED;
   for (int l = 1; l < S->nlev; ++l) {
     MlPatches &P = S->pl[l];
     if (P.npatch == 0) continue;
+    if (mixed) {
+      ML_TRY(device_alloc(h, &P.scal, (size_t)P.nrows));
+      ML_TRY(device_alloc(h, &P.norm1, (size_t)P.npatch));
+      ML_TRY(device_alloc(h, &P.inv32, (size_t)std::max<int64_t>(1, P.inv_doubles)));
+      ML_TRY(device_alloc(h, &P.lo32, (size_t)P.npatch));
+    }
     ml_form_blocks_kernel<<<P.npatch, 256, 0, h->stream>>>(P.pm, P.pinv, P.plf, P.pair_leaf,
                                                            P.pair_map, P.map, S->leaf, S->koff,
                                                            S->Kl, P.inv);
-    ML_TRY(ml_spd_inverse(P.inv, P.npatch, P.pm, P.pinv, P.buckets, s1, s2, S->flag, h->stream));
+    ML_TRY(ml_spd_inverse(P.inv, P.npatch, P.pm, P.pinv, P.buckets, s1, s2, S->flag, h->stream,
+                          P.poff, P.scal, P.norm1));
+    if (mixed) {
+      ml_lowprec_kernel<<<P.npatch, 256, 0, h->stream>>>(P.pm, P.pinv, P.poff, P.scal, P.norm1,
+                                                         P.inv, P.inv32, P.lo32);
+      std::vector<uint8_t> lo(P.npatch);
+      FCM_HIP(hipMemcpyAsync(lo.data(), P.lo32, P.npatch, hipMemcpyDeviceToHost, h->stream));
+      FCM_HIP(hipStreamSynchronize(h->stream));
+      P.n32 = 0;
+      for (uint8_t v : lo) P.n32 += v;
+    }
   }
   FCM_HIP(hipStreamSynchronize(h->stream));
   pool_free(s1, h->stream);
@@ -1378,12 +1466,16 @@ static void ml_apply(MlhpState *S, int l, const double *x, double *y, hipStream_
   ml_gather_kernel<<<ml_grid(n), 256, 0, s>>>(n, S->lg_ptr, S->lg_slot, S->lc, y);
 }
 
-static void ml_smooth(MlhpState *S, int l, const double *r, double *z, hipStream_t s) {
+// z = M_l^{-1} r; mixed: patches flagged at setup are applied from FP32 copies
+static void ml_smooth(MlhpState *S, int l, const double *r, double *z, hipStream_t s,
+                      bool mixed = false) {
   const int64_t n = S->level_size[l];
   const MlPatches &P = S->pl[l];
+  const bool lo = mixed && P.inv32;
   if (P.npatch > 0)
-    ml_smooth_kernel<<<dim3(P.npatch, (P.max_mb + 63) / 64), 256, 0, s>>>(P.pm, P.pinv, P.poff,
-                                                                          P.pidx, P.inv, r, P.pc);
+    ml_smooth_kernel<<<dim3(P.npatch, (P.max_mb + 63) / 64), 256, 0, s>>>(
+        P.pm, P.pinv, P.poff, P.pidx, P.inv, lo ? P.inv32 : nullptr, lo ? P.lo32 : nullptr, r,
+        P.pc);
   ml_gather_kernel<<<ml_grid(n), 256, 0, s>>>(n, P.pg_ptr, P.pg_slot, P.pc, z);
 }
 
@@ -1405,7 +1497,7 @@ static void ml_vcycle(fcm_handle *h, int l, const double *b, double *x, hipStrea
   hipMemcpyAsync(r, b, n * sizeof(double), hipMemcpyDeviceToDevice, s);
   auto steps = [&](int count) {
     for (int it = 0; it < count; ++it) {
-      ml_smooth(S, l, r, z, s);
+      ml_smooth(S, l, r, z, s, h->opt.precision == FCM_MIXED);
       ml_axpby_kernel<<<ml_grid(n), 256, 0, s>>>(n, w, z, 1.0, x);
       ml_apply(S, l, x, y, s);
       ml_sub_kernel<<<ml_grid(n), 256, 0, s>>>(n, b, y, r);
@@ -1552,9 +1644,13 @@ fcm_status mlhp_stats(const fcm_handle *h, fcm_stats *st) {
   st->n_elements = S->nleaf;
   st->n_kept = S->nleaf;
   st->n_cut = S->n_cut_leaves;
-  int64_t np = 0;
-  for (int l = 1; l < S->nlev; ++l) np += S->pl[l].npatch;
+  int64_t np = 0, n32 = 0;
+  for (int l = 1; l < S->nlev; ++l) {
+    np += S->pl[l].npatch;
+    n32 += S->pl[l].n32;
+  }
   st->n_unique_blocks = np;
+  st->n_fp64_blocks = np - n32;
   st->device_bytes = h->bytes;
   st->coarse_blocks = 1;
   st->coarse_block_size = S->n0;

@@ -166,6 +166,34 @@ def test_mlhp_pcg(name):
     assert err <= _tol(name)
 
 
+@pytest.mark.parametrize("name", list(CASES))
+def test_mlhp_pcg_mixed(name):
+    """Mixed form: patch inverses whose Jacobi-scaled kappa_1 is at most 1e5 are
+    applied from FP32 copies inside the FP64 V-cycle and CG.  Against the
+    oracle's FP64 solve: the iteration count +-1 and the energy-norm distance
+    of the solutions within the FP64 bound."""
+    from paper_2010_00881_amd import Solver
+    s64, D, H = _case(name)
+    d, o = CASES[name]()
+    s = Solver(d, dict(o, precision="mixed"))
+    try:
+        x, info = s.pcg()
+        st = s.stats()
+        xo, it, hist = H.pcg(D.b)
+        x = x.cpu().numpy()
+        e = x - xo
+        err = np.sqrt(e @ (D.A @ e)) / np.sqrt(xo @ (D.A @ xo))
+        print(f"[mlhp] {name} mixed: gpu it {info['iterations']} oracle {it}, energy rel diff "
+              f"{err:.1e}, FP32 patches {st['n_unique_blocks'] - st['n_fp64_blocks']} of "
+              f"{st['n_unique_blocks']}", flush=True)
+        assert info["status"] == 0
+        assert abs(info["iterations"] - it) <= 1
+        assert info["true_rel_res"] <= 1e-9
+        assert err <= _tol(name)
+    finally:
+        s.close()
+
+
 def test_mlhp_c4_base_grid_depth1():
     """The c4 problem (8^3 base grid, p = 3, sphere r = 0.35, alpha = 1e-10,
     beta = 1e4, six Gaussian sources) at refinement depth 1: 31,069 unknowns,

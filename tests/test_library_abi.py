@@ -52,7 +52,6 @@ def test_struct_layouts_match_header():
 @pytest.mark.parametrize("change, opt, msg", [
     ({"dim": 4}, {}, "dim must be 2 or 3"),
     ({"refine_levels": 5}, {}, "refine_levels must be in 0..4"),
-    ({"refine_levels": 1}, {"precision": "mixed"}, "FP64 only"),
     ({"refine_levels": 1}, {"smoother": "elementwise", "omega": 2.0 / 15.0}, "patchwise"),
     ({"refine_levels": 1, "quad_depth": 4}, {}, "quad_depth must be <= 3"),
     ({"refine_levels": 0}, {}, "needs refine_levels > 0"),
