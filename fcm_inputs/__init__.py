@@ -25,6 +25,7 @@ import numpy as np
 GEOM_BOX_MINUS_BALLS = 0   # physical domain = box minus a union of balls (holes)
 GEOM_BALL_INTERIOR = 1     # physical domain = interior of one ball
 GEOM_SQUARE = 2            # physical domain = a rotated square (2D)
+GEOM_POPCORN = 3           # physical domain = the popcorn level set phi <= 0 (3D)
 
 # Boundary-face bits: bit (2*axis + side), side 0 = low face, 1 = high face.
 ALL_FACES_2D = 0b1111
@@ -131,6 +132,20 @@ def rotated_square(psi_deg: float = 0.0, h_inv: int = 8, p: int = 2, smoother: s
     d["name"] = f"rotated_square_psi{psi_deg:g}_h{h_inv}_p{p}"
     o = default_options(2, smoother=smoother)
     o["rtol"] = 1e-9
+    return d, o
+
+
+def popcorn(n: int = 16, p: int = 3, smoother: str = "elementwise", space: str = "tensor"):
+    """The popcorn Poisson problem of Section 4.3 (no random draws): embedding
+    cube (-1, 1)^3 with n cells per axis, physical domain phi <= 0, prescribed
+    solution u = x^3 + x y^2 + y^3 + z^4 + sin(3 (x^2 + y^2)) through its
+    source and the penalty beta = 1e4 on phi = 0, alpha = 1e-6.  The paper's
+    weak-scaling runs use the trunk space at p = 3 and elementwise blocks."""
+    d = _base(3, (n, n, n), p)
+    d.update(lo=[-1.0] * 3, hi=[1.0] * 3, geom=GEOM_POPCORN, ball_c=[], ball_r=[], alpha=1e-6,
+             beta=1e4, dirichlet_faces=0, space=space, surface_rule=(192, 384))
+    d["name"] = f"popcorn_{n}^3_p{p}_{space}"
+    o = default_options(3, smoother=smoother)
     return d, o
 
 

@@ -35,7 +35,8 @@ import numpy as np
 import scipy.sparse as sp
 
 from . import basis
-from .geometry import CUT, PHYS, SQUARE, VOID, alpha_at, classify_box, square_corners, square_frame
+from .geometry import (CUT, PHYS, POPCORN, SQUARE, VOID, alpha_at, classify_box, popcorn_grad,
+                       popcorn_phi, square_corners, square_frame)
 
 
 def trunk_degree(t):
@@ -76,7 +77,52 @@ def source(desc, x):
         f += A * np.exp(-d2 / (w * w))
     if desc.get("trig_src"):
         f += trig(desc, desc["trig_src"], x)
+    if desc["geom"] == POPCORN:
+        f -= popcorn_laplacian(x)
     return f
+
+
+def star_surface_rule(phi, grad, n_mu, n_az, rmax=1.5):
+    """Quadrature points and weights on the surface phi = 0 of a domain that is
+    star-shaped about the origin (reading for the popcorn): directions omega
+    from a Gauss-Legendre rule in cos(theta) times a trapezoid rule in the
+    azimuth, the radius rho(omega) by 60 bisection steps of phi(rho omega) on
+    [0, rmax], weight w_mu (2 pi / n_az) rho^2 |grad phi| / |omega . grad phi|
+    (the surface element of r = rho(omega) written with the level set)."""
+    mu, wmu = basis.gauss(n_mu)
+    az = 2.0 * np.pi * np.arange(n_az) / n_az
+    MU, AZ = np.meshgrid(mu, az, indexing="ij")
+    WMU = np.meshgrid(wmu, az, indexing="ij")[0]
+    st = np.sqrt(1.0 - MU * MU)
+    om = np.stack([(st * np.cos(AZ)).ravel(), (st * np.sin(AZ)).ravel(), MU.ravel()], axis=1)
+    lo = np.zeros(om.shape[0])
+    hi = np.full(om.shape[0], float(rmax))
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        inside = phi(mid[:, None] * om) <= 0.0
+        lo = np.where(inside, mid, lo)
+        hi = np.where(inside, hi, mid)
+    rho = 0.5 * (lo + hi)
+    x = rho[:, None] * om
+    g = grad(x)
+    w = WMU.ravel() * (2.0 * np.pi / n_az) * rho * rho * \
+        np.linalg.norm(g, axis=1) / np.abs(np.sum(om * g, axis=1))
+    return x, w
+
+
+def popcorn_u(x):
+    """The prescribed solution of the popcorn problem (Section 4.3)."""
+    x = np.asarray(x, dtype=np.float64)
+    a, b, c = x[:, 0], x[:, 1], x[:, 2]
+    return a ** 3 + a * b * b + b ** 3 + c ** 4 + np.sin(3.0 * (a * a + b * b))
+
+
+def popcorn_laplacian(x):
+    """Laplacian of popcorn_u; the source is its negative (reading: -Lap u = f)."""
+    x = np.asarray(x, dtype=np.float64)
+    a, b, c = x[:, 0], x[:, 1], x[:, 2]
+    s = a * a + b * b
+    return 8.0 * a + 6.0 * b + 12.0 * c * c + 12.0 * np.cos(3.0 * s) - 36.0 * s * np.sin(3.0 * s)
 
 
 def trig(desc, coef, x):
@@ -123,7 +169,11 @@ class Discretization:
         self._classify()
         self._number_dofs()
         self._kref = None
-        self.penalty = self._edge_points() if self._has_edge_penalty() else {}
+        self.penalty = {}
+        if self._has_edge_penalty():
+            self.penalty = self._edge_points()
+        elif self.desc["geom"] == POPCORN and float(self.desc.get("beta", 0.0)) > 0.0:
+            self.penalty = self._popcorn_surface_points()
         if assemble:
             self.assemble()
 
@@ -374,6 +424,24 @@ class Discretization:
                 px, pw, pg = out.get(cell, (np.zeros((0, 2)), np.zeros(0), np.zeros(0)))
                 out[cell] = (np.vstack([px, x]), np.concatenate([pw, w]), np.concatenate([pg, g]))
         return out
+
+    def _popcorn_surface_points(self):
+        """Quadrature of the penalty term on the popcorn surface phi = 0 (eq.
+        weakform) by star_surface_rule (surface_rule = (n_mu, n_phi)); points go
+        to the element that contains them (floor rule, clamped); Dirichlet
+        data g = u there."""
+        n_mu, n_az = self.desc.get("surface_rule", (192, 384))
+        x, w = star_surface_rule(popcorn_phi, popcorn_grad, int(n_mu), int(n_az))
+        cells = np.clip(np.floor((x - self.lo) / self.h).astype(np.int64), 0, self.n - 1)
+        gu = popcorn_u(x)
+        out = {}
+        for i in np.lexsort(tuple(cells[:, ax] for ax in range(3))):
+            key = tuple(int(c) for c in cells[i])
+            out.setdefault(key, ([], [], []))
+            out[key][0].append(x[i])
+            out[key][1].append(w[i])
+            out[key][2].append(gu[i])
+        return {k: (np.array(v[0]), np.array(v[1]), np.array(v[2])) for k, v in out.items()}
 
     def penalty_system(self, e):
         """beta sum_q w N_a N_b and beta sum_q w g N_a over the element's edge

@@ -1,8 +1,11 @@
 """Indicator function alpha(x) and cell classification (Section 2.1).
 
 The physical domain is the box minus a union of balls ("holes"), the
-interior of a single ball, or (2D) a square of side L centred at c and
-rotated by psi (Section 4.1: the rotated square of the Poisson test).  alpha = 1 in the physical domain and alpha = eps
+interior of a single ball, (2D) a square of side L centred at c and rotated
+by psi (Section 4.1: the rotated square of the Poisson test), or (3D) the
+popcorn level set phi <= 0 of Section 4.3 (boxes classified by phi at the
+centre against a Lipschitz bound of phi over the box, so a box that is not
+provably inside or outside is CUT).  alpha = 1 in the physical domain and alpha = eps
 (the problem's ``alpha``) in the fictitious part (eq. weakform).  Points on a
 sphere count as physical.
 
@@ -19,7 +22,57 @@ from __future__ import annotations
 import numpy as np
 
 VOID, PHYS, CUT = 0, 1, 2
-BOX_MINUS_BALLS, BALL_INTERIOR, SQUARE = 0, 1, 2
+BOX_MINUS_BALLS, BALL_INTERIOR, SQUARE, POPCORN = 0, 1, 2, 3
+
+# Popcorn level set of Section 4.3 (weak scaling example):
+#   phi(x) = |x| - r0 - sum_k A exp(-|x - x_k|^2 / sigma^2),  phi <= 0 physical
+POP_R0, POP_A, POP_SIGMA = 0.6, 3.0, 0.2
+
+
+def popcorn_centres(r0=POP_R0):
+    """The twelve bump centres x_k of the popcorn level set."""
+    c = []
+    for k in range(5):
+        t = 2.0 * k * np.pi / 5.0
+        c.append(r0 / np.sqrt(5.0) * np.array([2.0 * np.cos(t), np.sin(t), 1.0]))
+    for k in range(5, 10):
+        t = (2.0 * (k - 5) - 1.0) * np.pi / 5.0
+        c.append(r0 / np.sqrt(5.0) * np.array([2.0 * np.cos(t), np.sin(t), 1.0]))
+    c.append(np.array([0.0, 0.0, r0]))
+    c.append(np.array([0.0, 0.0, -r0]))
+    return np.array(c)
+
+
+def popcorn_phi(x, A=POP_A):
+    """phi at points x (npts, 3)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.sqrt(np.sum(x * x, axis=1)) - POP_R0
+    for c in popcorn_centres():
+        out -= A * np.exp(-np.sum((x - c) ** 2, axis=1) / POP_SIGMA ** 2)
+    return out
+
+
+def popcorn_grad(x, A=POP_A):
+    """grad phi at points x (npts, 3) (x != 0)."""
+    x = np.asarray(x, dtype=np.float64)
+    g = x / np.sqrt(np.sum(x * x, axis=1))[:, None]
+    for c in popcorn_centres():
+        e = A * np.exp(-np.sum((x - c) ** 2, axis=1) / POP_SIGMA ** 2)
+        g += (2.0 / POP_SIGMA ** 2) * e[:, None] * (x - c)
+    return g
+
+
+def _popcorn_lipschitz(lo, hi, A=POP_A):
+    """Upper bound of |grad phi| on the box: 1 for |x|, and for each bump the
+    largest value of (2A/sigma^2) d exp(-d^2/sigma^2) over the box's distances
+    d to its centre (the function rises up to d = sigma/sqrt(2), then falls)."""
+    L = 1.0
+    dpk = POP_SIGMA / np.sqrt(2.0)
+    for c in popcorn_centres():
+        dmin, dmax = _dist_range(lo, hi, c)
+        d = dmax if dmax <= dpk else (dmin if dmin >= dpk else dpk)
+        L += 2.0 * A / POP_SIGMA ** 2 * d * np.exp(-d * d / POP_SIGMA ** 2)
+    return L
 
 
 def square_frame(desc, x):
@@ -73,6 +126,19 @@ def classify_box(desc, lo, hi) -> int:
         if dmax <= r:
             return PHYS
         return CUT
+    if geom == POPCORN:
+        # phi at the centre against its largest change over the box
+        lo = np.asarray(lo, dtype=np.float64)
+        hi = np.asarray(hi, dtype=np.float64)
+        c = 0.5 * (lo + hi)
+        rad = 0.5 * float(np.sqrt(np.sum((hi - lo) ** 2)))
+        f = float(popcorn_phi(c[None, :])[0])
+        slack = _popcorn_lipschitz(lo, hi) * rad
+        if f - slack > 0.0:
+            return VOID
+        if f + slack <= 0.0:
+            return PHYS
+        return CUT
     if geom == SQUARE:
         # convex square against the box: PHYS if every box corner is inside;
         # VOID if an axis of the box or of the square separates them
@@ -95,6 +161,8 @@ def classify_box(desc, lo, hi) -> int:
 def inside_phys(desc, x):
     """Boolean mask over points x (shape (npts, dim))."""
     x = np.asarray(x, dtype=np.float64)
+    if desc["geom"] == POPCORN:
+        return popcorn_phi(x) <= 0.0
     if desc["geom"] == SQUARE:
         half = 0.5 * float(desc["ball_r"][0])
         xr = square_frame(desc, x)
