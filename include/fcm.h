@@ -72,10 +72,16 @@ typedef enum {
   FCM_ERR_BUSY = -7
 } fcm_status;
 
-/* Physical domain: the box minus balls, the interior of one ball, or (2D,
+/* Physical domain: the box minus balls, the interior of one ball, (2D,
  * Section 4.1) the square of side ball_r[0] centred at ball_c[0] and rotated
- * by psi (counter-clockwise) about its centre.                              */
-enum { FCM_GEOM_BOX_MINUS_BALLS = 0, FCM_GEOM_BALL_INTERIOR = 1, FCM_GEOM_SQUARE = 2 };
+ * by psi (counter-clockwise) about its centre, or (3D, Section 4.3) the
+ * popcorn phi(x) = |x| - 0.6 - sum_k 3 exp(-|x - x_k|^2 / 0.04) <= 0 with the
+ * paper's twelve centres x_k.  The popcorn problem carries its prescribed
+ * solution u = x^3 + x y^2 + y^3 + z^4 + sin(3 (x^2 + y^2)): the source gets
+ * -Lap u added, and with beta > 0 the penalty imposes u on phi = 0 with the
+ * surface rule surf_n along rays from the origin.                          */
+enum { FCM_GEOM_BOX_MINUS_BALLS = 0, FCM_GEOM_BALL_INTERIOR = 1, FCM_GEOM_SQUARE = 2,
+       FCM_GEOM_POPCORN = 3 };
 /* Element basis: the tensor-product integrated Legendre space, or its trunk
  * subspace (Table tab::upperbound, trunk column): the products whose bubble
  * factors' degrees sum to at most p; level q of the p-hierarchy holds the
@@ -130,11 +136,12 @@ typedef struct {
                                  boundary (eq. weakform): u = 0 on the sphere
                                  (refine_levels > 0, BALL_INTERIOR) or u = g on
                                  the edges of the square (FCM_GEOM_SQUARE, g
-                                 from trig_dir); 0 = none                       */
-  int surf_n[2];              /* surface rule of the penalty: Gauss-Legendre
-                                 points in cos(theta) (<= 4096) and trapezoid
-                                 points in phi (<= 8192; 2D: phi only);
-                                 0 = 256 x 512                                   */
+                                 from trig_dir) or u = the prescribed solution
+                                 on the popcorn surface; 0 = none              */
+  int surf_n[2];              /* surface rule of the penalty (sphere, popcorn):
+                                 Gauss-Legendre points in cos(theta) (<= 4096)
+                                 and trapezoid points in phi (<= 8192; 2D: phi
+                                 only); 0 = 256 x 512                            */
   int space;                  /* FCM_SPACE_TENSOR or FCM_SPACE_TRUNK (uniform
                                  grids only)                                   */
   double psi;                 /* FCM_GEOM_SQUARE: rotation in radians            */

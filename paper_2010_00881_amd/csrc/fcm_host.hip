@@ -236,12 +236,13 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
       return FCM_ERR_ARG;
     }
     if (p->p > 3) { set_error("multi-level hp: p must be <= 3"); return FCM_ERR_ARG; }
-  } else if (p->beta != 0.0 && p->geom != FCM_GEOM_SQUARE) {
+  } else if (p->beta != 0.0 && p->geom != FCM_GEOM_SQUARE && p->geom != FCM_GEOM_POPCORN) {
     set_error("beta (sphere penalty) needs refine_levels > 0");
     return FCM_ERR_ARG;
   }
   if (!std::isfinite(p->beta) || p->beta < 0.0) { set_error("invalid beta"); return FCM_ERR_ARG; }
-  if (p->beta > 0.0 && p->geom != FCM_GEOM_BALL_INTERIOR && p->geom != FCM_GEOM_SQUARE) {
+  if (p->beta > 0.0 && p->geom != FCM_GEOM_BALL_INTERIOR && p->geom != FCM_GEOM_SQUARE &&
+      p->geom != FCM_GEOM_POPCORN) {
     set_error("beta (sphere penalty) needs the ball-interior geometry");
     return FCM_ERR_ARG;
   }
@@ -257,7 +258,13 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
       set_error("invalid square rotation or trigonometric data");
       return FCM_ERR_ARG;
     }
-  } else if (p->trig_src[0] != 0.0 || p->trig_dir[0] != 0.0) {
+  } else if (p->geom == FCM_GEOM_POPCORN) {
+    if (p->dim != 3 || p->n_fields != 1 || p->refine_levels != 0 || p->n_balls != 0) {
+      set_error("the popcorn geometry needs a 3D Poisson problem on a uniform grid and no balls");
+      return FCM_ERR_ARG;
+    }
+  }
+  if (p->geom != FCM_GEOM_SQUARE && (p->trig_src[0] != 0.0 || p->trig_dir[0] != 0.0)) {
     set_error("trigonometric source and Dirichlet data need the square geometry");
     return FCM_ERR_ARG;
   }
@@ -275,7 +282,7 @@ static fcm_status validate(const fcm_problem *p, const fcm_options *o) {
     return FCM_ERR_ARG;
   }
   if (p->geom != FCM_GEOM_BOX_MINUS_BALLS && p->geom != FCM_GEOM_BALL_INTERIOR &&
-      p->geom != FCM_GEOM_SQUARE) {
+      p->geom != FCM_GEOM_SQUARE && p->geom != FCM_GEOM_POPCORN) {
     set_error("unknown geometry");
     return FCM_ERR_ARG;
   }
@@ -1147,6 +1154,7 @@ static void edge_penalty_points(const fcm_handle *h, std::vector<int> &pel,
         const double xr = cs * rx + sn * ry, yr = -sn * rx + cs * ry;
         out.push_back(x);
         out.push_back(y);
+        out.push_back(0.0);
         out.push_back(0.5 * gw[q] * (t1 - t0) * len);
         out.push_back(pr.trig_dir[0] * std::cos(pr.trig_dir[1] * xr) *
                       std::sin(pr.trig_dir[1] * yr));
@@ -1159,7 +1167,82 @@ static void edge_penalty_points(const fcm_handle *h, std::vector<int> &pel,
   for (auto &kv : per) {
     pel.push_back(kv.first);
     pts.insert(pts.end(), kv.second.begin(), kv.second.end());
-    ptr.push_back((int)(pts.size() / 4));
+    ptr.push_back((int)(pts.size() / 5));
+  }
+}
+
+// Penalty quadrature on the popcorn surface phi = 0 (FCM_GEOM_POPCORN, beta >
+// 0), the domain read as star-shaped about the origin: directions from a
+// Gauss-Legendre rule in cos(theta) (surf_n[0]) times a trapezoid rule in the
+// azimuth (surf_n[1]); the radius rho of the surface point by 60 bisection
+// steps of phi(rho omega) on [0, 1.5]; weight w_mu (2 pi / n) rho^2 |grad phi|
+// / |omega . grad phi|; a point belongs to the element containing it (floor
+// rule, clamped); Dirichlet data = the prescribed solution.  Same CSR output
+// as edge_penalty_points.
+static void popcorn_penalty_points(const fcm_handle *h, std::vector<int> &pel,
+                                   std::vector<int> &ptr, std::vector<double> &pts) {
+  const Geo &g = h->geo;
+  const fcm_problem &pr = h->prob.pr;
+  const std::vector<double> &cen = h->prob.ball;
+  const int nmu = pr.surf_n[0] > 0 ? pr.surf_n[0] : 256;
+  const int naz = pr.surf_n[1] > 0 ? pr.surf_n[1] : 512;
+  const double s2 = 0.2 * 0.2, pi = 3.14159265358979323846;
+  auto phi = [&](const double *x) {
+    double f = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) - 0.6;
+    for (int k = 0; k < 12; ++k) {
+      const double *c = &cen[4 * k];
+      const double d2 = (x[0] - c[0]) * (x[0] - c[0]) + (x[1] - c[1]) * (x[1] - c[1]) +
+                        (x[2] - c[2]) * (x[2] - c[2]);
+      f -= 3.0 * std::exp(-d2 / s2);
+    }
+    return f;
+  };
+  std::vector<double> mu, wmu;
+  gauss_legendre(nmu, mu, wmu);
+  std::map<int, std::vector<double>> per;
+  for (int i = 0; i < nmu; ++i)
+    for (int j = 0; j < naz; ++j) {
+      const double az = 2.0 * pi * j / naz, st = std::sqrt(1.0 - mu[i] * mu[i]);
+      const double om[3] = {st * std::cos(az), st * std::sin(az), mu[i]};
+      double lo = 0.0, hi = 1.5;
+      for (int it = 0; it < 60; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        const double x[3] = {mid * om[0], mid * om[1], mid * om[2]};
+        if (phi(x) <= 0.0) lo = mid;
+        else hi = mid;
+      }
+      const double rho = 0.5 * (lo + hi);
+      const double x[3] = {rho * om[0], rho * om[1], rho * om[2]};
+      const double nx = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+      double gr[3] = {x[0] / nx, x[1] / nx, x[2] / nx};
+      for (int k = 0; k < 12; ++k) {
+        const double *c = &cen[4 * k];
+        const double d2 = (x[0] - c[0]) * (x[0] - c[0]) + (x[1] - c[1]) * (x[1] - c[1]) +
+                          (x[2] - c[2]) * (x[2] - c[2]);
+        const double e = 3.0 * std::exp(-d2 / s2);
+        for (int ax = 0; ax < 3; ++ax) gr[ax] += 2.0 / s2 * e * (x[ax] - c[ax]);
+      }
+      const double gn = std::sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2]);
+      const double w = wmu[i] * (2.0 * pi / naz) * rho * rho * gn /
+                       std::fabs(om[0] * gr[0] + om[1] * gr[1] + om[2] * gr[2]);
+      int cell[3];
+      for (int ax = 0; ax < 3; ++ax) {
+        const double f = std::floor((x[ax] - g.lo[ax]) / g.h[ax]);
+        cell[ax] = (int)std::min(std::max(f, 0.0), (double)(g.n[ax] - 1));
+      }
+      const double sxy = x[0] * x[0] + x[1] * x[1];
+      const double u = x[0] * x[0] * x[0] + x[0] * x[1] * x[1] + x[1] * x[1] * x[1] +
+                       x[2] * x[2] * x[2] * x[2] + std::sin(3.0 * sxy);
+      std::vector<double> &out = per[cell[0] + g.n[0] * (cell[1] + g.n[1] * cell[2])];
+      out.insert(out.end(), {x[0], x[1], x[2], w, u});
+    }
+  pel.clear();
+  ptr.assign(1, 0);
+  pts.clear();
+  for (auto &kv : per) {
+    pel.push_back(kv.first);
+    pts.insert(pts.end(), kv.second.begin(), kv.second.end());
+    ptr.push_back((int)(pts.size() / 5));
   }
 }
 
@@ -1182,11 +1265,12 @@ static fcm_status do_setup(fcm_handle *h) {
   std::vector<int> pen_el, pen_ptr;
   std::vector<double> pen_pts;
   std::vector<uint8_t> pen(g.E, 0);
-  if (g.geom == FCM_GEOM_SQUARE && pr.beta > 0.0) {
-    edge_penalty_points(h, pen_el, pen_ptr, pen_pts);
+  if ((g.geom == FCM_GEOM_SQUARE || g.geom == FCM_GEOM_POPCORN) && pr.beta > 0.0) {
+    if (g.geom == FCM_GEOM_SQUARE) edge_penalty_points(h, pen_el, pen_ptr, pen_pts);
+    else popcorn_penalty_points(h, pen_el, pen_ptr, pen_pts);
     for (int e : pen_el) {
       if (h->h_state[e] == kVoid) {
-        set_error("edge penalty points in a void element");
+        set_error("boundary penalty points in a void element");
         return FCM_ERR_ARG;
       }
       pen[e] = 1;
@@ -1904,6 +1988,23 @@ fcm_status fcm_setup(const fcm_problem *pr, const fcm_options *op, void *stream,
     for (int ax = 0; ax < 3; ++ax) P.ball.push_back(ax < pr->dim ? pr->ball_c[j * pr->dim + ax] : 0.0);
     P.ball.push_back(pr->ball_r[j]);
   }
+  if (pr->geom == FCM_GEOM_POPCORN) {
+    // the twelve bump centres of the popcorn level set (Section 4.3)
+    const double r0 = 0.6, s5 = r0 / std::sqrt(5.0), pi = 3.14159265358979323846;
+    for (int k = 0; k < 12; ++k) {
+      double c[3];
+      if (k < 10) {
+        const double t = k < 5 ? 2.0 * k * pi / 5.0 : (2.0 * (k - 5) - 1.0) * pi / 5.0;
+        c[0] = s5 * 2.0 * std::cos(t);
+        c[1] = s5 * std::sin(t);
+        c[2] = s5;
+      } else {
+        c[0] = c[1] = 0.0;
+        c[2] = k == 10 ? r0 : -r0;
+      }
+      P.ball.insert(P.ball.end(), {c[0], c[1], c[2], 0.0});
+    }
+  }
   P.gsrc.assign(pr->gauss, pr->gauss + 5 * pr->n_gauss);
   P.tface.assign(pr->traction_face, pr->traction_face + pr->n_traction);
   P.tvec.assign(pr->traction_vec, pr->traction_vec + 3 * pr->n_traction);
@@ -1928,7 +2029,7 @@ fcm_status fcm_setup(const fcm_problem *pr, const fcm_options *op, void *stream,
   }
   g.dir = pr->dirichlet_faces;
   g.geom = pr->geom;
-  g.nballs = pr->n_balls;
+  g.nballs = pr->geom == FCM_GEOM_POPCORN ? 12 : pr->n_balls;
   for (int k = 0; k < 5; ++k) g.sq[k] = 0.0;
   if (g.geom == FCM_GEOM_SQUARE) {
     g.sq[0] = pr->ball_c[0];

@@ -303,9 +303,10 @@ void launch_integrate(const Geo &g, const Tables &t, const fcm_problem &pr, cons
                       hipStream_t s);
 void launch_phys_rhs(const Geo &g, const Tables &t, const fcm_problem &pr, const uint8_t *state,
                      double *be_all, hipStream_t s);
-// Penalty of the Dirichlet data on immersed edges (FCM_GEOM_SQUARE): for the
-// elements pel[0..nel) with points ptr[k]..ptr[k+1] of pts ([x, y, w, g]),
-// K_e += beta sum w N N^T and b_e += beta sum w g N, in point order.
+// Penalty of the Dirichlet data on an immersed boundary (square edges,
+// popcorn surface): for the elements pel[0..nel) with points ptr[k]..ptr[k+1]
+// of pts ([x, y, z, w, g]), K_e += beta sum w N N^T and b_e += beta sum w g N,
+// in point order.
 void launch_edge_penalty(const Geo &g, const Tables &t, const int *pel, int nel, const int *ptr,
                          const double *pts, double beta, const int *kmat, double *Kcut,
                          double *be_all, hipStream_t s);

@@ -67,9 +67,57 @@ __device__ inline int classify_square_dev(const Geo &g, const double *lo, const 
   return kCut;
 }
 
+// Popcorn level set (FCM_GEOM_POPCORN); ball holds the twelve bump centres
+// (x, y, z, unused).
+constexpr double kPopR0 = 0.6, kPopA = 3.0, kPopSigma = 0.2;
+__device__ inline double popcorn_phi_dev(const double *ball, const double *x) {
+  double f = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]) - kPopR0;
+  for (int k = 0; k < 12; ++k) {
+    const double *c = ball + 4 * k;
+    const double d2 = (x[0] - c[0]) * (x[0] - c[0]) + (x[1] - c[1]) * (x[1] - c[1]) +
+                      (x[2] - c[2]) * (x[2] - c[2]);
+    f -= kPopA * exp(-d2 / (kPopSigma * kPopSigma));
+  }
+  return f;
+}
+
+// phi at the box centre against a bound of its change over the box: |grad|x||
+// = 1 plus, per bump, the largest (2A/sigma^2) d exp(-d^2/sigma^2) over the
+// box's distances d to the centre (rising up to sigma/sqrt(2), then falling).
+// kVoid if phi > 0 on the whole box, kPhys if phi <= 0 on it, else kCut.
+__device__ inline int classify_popcorn_dev(const double *ball, const double *lo,
+                                           const double *hi) {
+  double c[3], r2 = 0.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    c[ax] = 0.5 * (lo[ax] + hi[ax]);
+    r2 += (hi[ax] - lo[ax]) * (hi[ax] - lo[ax]);
+  }
+  const double rad = 0.5 * sqrt(r2);
+  const double s2 = kPopSigma * kPopSigma, dpk = kPopSigma / sqrt(2.0);
+  double L = 1.0;
+  for (int k = 0; k < 12; ++k) {
+    const double *b = ball + 4 * k;
+    double dmin2 = 0.0, dmax2 = 0.0;
+    for (int ax = 0; ax < 3; ++ax) {
+      const double nr = fmin(fmax(b[ax], lo[ax]), hi[ax]) - b[ax];
+      dmin2 += nr * nr;
+      const double fa = fmax(fabs(lo[ax] - b[ax]), fabs(hi[ax] - b[ax]));
+      dmax2 += fa * fa;
+    }
+    const double dmin = sqrt(dmin2), dmax = sqrt(dmax2);
+    const double d = dmax <= dpk ? dmax : (dmin >= dpk ? dmin : dpk);
+    L += 2.0 * kPopA / s2 * d * exp(-d * d / s2);
+  }
+  const double f = popcorn_phi_dev(ball, c), slack = L * rad;
+  if (f - slack > 0.0) return kVoid;
+  if (f + slack <= 0.0) return kPhys;
+  return kCut;
+}
+
 __device__ inline int classify_box_dev(const Geo &g, const double *ball, const double *lo,
                                        const double *hi) {
   if (g.geom == FCM_GEOM_SQUARE) return classify_square_dev(g, lo, hi);
+  if (g.geom == FCM_GEOM_POPCORN) return classify_popcorn_dev(ball, lo, hi);
   if (g.geom == FCM_GEOM_BOX_MINUS_BALLS) {
     bool any = false;
     for (int j = 0; j < g.nballs; ++j) {
@@ -105,6 +153,7 @@ __device__ inline int classify_box_dev(const Geo &g, const double *ball, const d
 
 __device__ inline bool inside_phys_dev(const Geo &g, const double *ball, const double *x) {
   if (g.geom == FCM_GEOM_SQUARE) return inside_square_dev(g, x);
+  if (g.geom == FCM_GEOM_POPCORN) return popcorn_phi_dev(ball, x) <= 0.0;
   if (g.geom == FCM_GEOM_BOX_MINUS_BALLS) {
     for (int j = 0; j < g.nballs; ++j) {
       const double *b = ball + 4 * j;
@@ -150,6 +199,12 @@ __device__ inline double source_dev(const Geo &g, const double *gsrc, int ngauss
     double xr[2];
     square_frame_dev(g, x, xr);
     f += g.trig[0] * cos(g.trig[1] * xr[0]) * sin(g.trig[1] * xr[1]);
+  }
+  if (g.geom == FCM_GEOM_POPCORN) {
+    // -Lap of the prescribed solution x^3 + x y^2 + y^3 + z^4 + sin(3 (x^2 + y^2))
+    const double s = x[0] * x[0] + x[1] * x[1];
+    f -= 8.0 * x[0] + 6.0 * x[1] + 12.0 * x[2] * x[2] + 12.0 * cos(3.0 * s) -
+         36.0 * s * sin(3.0 * s);
   }
   for (int k = 0; k < ngauss; ++k) {
     const double *s = gsrc + 5 * k;
@@ -588,8 +643,8 @@ void launch_phys_rhs(const Geo &g, const Tables &t, const fcm_problem &pr, const
 }
 
 // Box-face traction t on face (axis, side): int_face N_a t dA, closed form per mode.
-// Penalty of the Dirichlet data on the square's edges (eq. weakform): one
-// workgroup per element with edge points; the mode values of up to 32
+// Penalty of the Dirichlet data on an immersed boundary (eq. weakform): one
+// workgroup per element with boundary points; the mode values of up to 32
 // points at a time are staged in LDS, then thread (a, b) adds
 // beta sum_q w_q N_a N_b to K_e and thread a adds beta sum_q w_q g_q N_a to
 // b_e, points in their stored order.
@@ -614,7 +669,7 @@ __global__ __launch_bounds__(256) void edge_penalty_kernel(Geo g, const int *lm,
     __syncthreads();
     for (int i = threadIdx.x; i < nq * m; i += blockDim.x) {
       const int q = i / m, a = i % m;
-      const double *pt = pts + 4 * (size_t)(q0 + q);
+      const double *pt = pts + 5 * (size_t)(q0 + q);
       double val = 1.0;
       for (int ax = 0; ax < g.d; ++ax) {
         const double xi = 2.0 * (pt[ax] - (g.lo[ax] + ec[ax] * g.h[ax])) / g.h[ax] - 1.0;
@@ -624,8 +679,8 @@ __global__ __launch_bounds__(256) void edge_penalty_kernel(Geo g, const int *lm,
       }
       N[q * 64 + a] = val;
       if (a == 0) {
-        W[q] = pt[2];
-        Gv[q] = pt[3];
+        W[q] = pt[3];
+        Gv[q] = pt[4];
       }
     }
     __syncthreads();

@@ -87,6 +87,7 @@ def test_popcorn_rays_cross_once_and_points_are_kept():
 def test_solution_converges_in_p():
     errs = []
     pts = np.random.default_rng(0).uniform(-0.3, 0.3, (200, 3))
+    assert np.all(popcorn_phi(pts) < 0.0)          # interior points only
     ut = popcorn_u(pts)
     for p in (2, 3):
         d, o = fi.popcorn(4, p)
