@@ -217,9 +217,10 @@ void launch_pack_tiles(const double *src, int m, int nb, double *d64, float *d32
 // every stored entry is read once and used twice.  Wave w takes the tiles
 // t = w, w + 4, ...; a tile is read contiguously (lane l: row l / 4, columns
 // 4 (l % 4) .. + 3, one 128-bit FP32 or two FP64 loads) and staged in LDS.
-// Every half-wave adds into its own LDS copy of y in a fixed order, and the
-// eight copies are added in a fixed order, so the result is the same on
-// every run.
+// Every wave adds into its own LDS copy of y, its two half-waves one after
+// the other, and the four copies are added in a fixed order, so the result
+// is the same on every run (one copy per wave rather than per half-wave
+// halves the LDS and doubles the workgroups a CU holds).
 // A lane's 4 consecutive entries of a stored tile, kept in the storage type
 // while the load is in flight (converted to FP64 when staged in LDS).
 template <typename T> struct TileRaw;
@@ -258,12 +259,10 @@ constexpr int kGemvPairs = 3;
 template <typename M>
 __device__ inline void tile_sweep(const M *base, int ntiles, const unsigned char *tI,
                                   const unsigned char *tJ, const int *toff, const double *xs,
-                                  double (*tb)[16][17], double *yh0, double *yh1, int wave,
-                                  int lane) {
+                                  double (*tb)[16][17], double *yh, int wave, int lane) {
   const int r = lane >> 2, c0 = (lane & 3) * 4;
   const int half = lane >> 5, i = lane & 15;
   const bool rowpart = (lane & 16) == 0;
-  double *yh = half ? yh1 : yh0;
   const M *lp = base + r * 16 + c0;
   for (int t0 = wave; t0 < ntiles; t0 += 8 * kGemvPairs) {
     TileRaw<M> ta[kGemvPairs], tb2[kGemvPairs];
@@ -286,21 +285,27 @@ __device__ inline void tile_sweep(const M *base, int ntiles, const unsigned char
       }
       __builtin_amdgcn_wave_barrier();
       const int t = tp + 4 * half;
+      int dst = -1;
+      double acc = 0.0;
       if (t < ntiles) {
         const int I = tI[t], J = tJ[t];
-        double acc = 0.0;
         if (rowpart) {
           const double *xJ = xs + 16 * J;
 #pragma unroll
           for (int k = 0; k < 16; ++k) acc += tb[half][i][k] * xJ[k];
-          yh[16 * I + i] += acc;
+          dst = 16 * I + i;
         } else if (I != J) {
           const double *xI = xs + 16 * I;
 #pragma unroll
           for (int k = 0; k < 16; ++k) acc += tb[half][k][i] * xI[k];
-          yh[16 * J + i] += acc;
+          dst = 16 * J + i;
         }
       }
+      // the wave's copy of y: the first half-wave adds, then the second (the
+      // two tiles may share rows), so the order is fixed
+      if (half == 0 && dst >= 0) yh[dst] += acc;
+      __builtin_amdgcn_wave_barrier();
+      if (half == 1 && dst >= 0) yh[dst] += acc;
       __builtin_amdgcn_wave_barrier();
     }
   }
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(256) void patch_gemv_kernel(Geo g, const int *__res
   constexpr int kPad = (kSmallPatchM + 15) / 16 * 16;
   constexpr int kMaxTiles = (kPad / 16) * (kPad / 16 + 1) / 2;
   __shared__ double xs[kPad];
-  __shared__ double yw[8][kPad];
+  __shared__ double yw[4][kPad];
   __shared__ double tbuf[4][2][16][17];
   __shared__ unsigned char tI[kMaxTiles], tJ[kMaxTiles];
   const int u = blockIdx.x;
@@ -325,7 +330,7 @@ __global__ __launch_bounds__(256) void patch_gemv_kernel(Geo g, const int *__res
   const int ntiles = nt * (nt + 1) / 2;
   for (int k = threadIdx.x; k < mp; k += 256) {
     xs[k] = k < m && patch_present(g, pinfo[k], kmask, vc) ? (double)a.x[node + pxoff[k]] : 0.0;
-    for (int w = 0; w < 8; ++w) yw[w][k] = 0.0;
+    for (int w = 0; w < 4; ++w) yw[w][k] = 0.0;
   }
   for (int t = threadIdx.x; t < ntiles; t += 256) {
     int I, J;
@@ -338,26 +343,26 @@ __global__ __launch_bounds__(256) void patch_gemv_kernel(Geo g, const int *__res
   const size_t base = (size_t)u * ntiles * 256;
   const bool lo = a.matU32 && !(a.u64flag && a.u64flag[u]);
   if (lo)
-    tile_sweep<float>(a.matU32 + base, ntiles, tI, tJ, nullptr, xs, tbuf[wave], yw[2 * wave],
-                      yw[2 * wave + 1], wave, lane);
+    tile_sweep<float>(a.matU32 + base, ntiles, tI, tJ, nullptr, xs, tbuf[wave], yw[wave], wave,
+                      lane);
   else
-    tile_sweep<double>(a.matU + base, ntiles, tI, tJ, nullptr, xs, tbuf[wave], yw[2 * wave],
-                       yw[2 * wave + 1], wave, lane);
+    tile_sweep<double>(a.matU + base, ntiles, tI, tJ, nullptr, xs, tbuf[wave], yw[wave], wave,
+                       lane);
   __syncthreads();
   for (int k = threadIdx.x; k < m; k += 256) {
     double y = 0.0;
-    for (int w = 0; w < 8; ++w) y += yw[w][k];
+    for (int w = 0; w < 4; ++w) y += yw[w][k];
     a.Yu[(size_t)u * m + k] = y;
   }
 }
 
 // Unique patches with large blocks (m > kSmallPatchM, e.g. elasticity at
-// p = 3, 4: m = 1029, 2187), whose per-half-wave copies of y would not fit in
+// p = 3, 4: m = 1029, 2187), whose per-wave copies of y would not fit in
 // LDS.  The tile rows are cut into bands of kBandT tiles (256 rows); work item
 // (patch u, band pair a <= b) takes the stored tiles (I, J) with I in band a,
 // J in band b and J >= I, so every stored tile is read by exactly one work
 // item.  Its row sums land in band a and its column sums in band b; the
-// work item keeps both bands of x and eight half-wave copies of both bands of
+// work item keeps both bands of x and one copy per wave of both bands of
 // y in LDS (local tile index i for band a, 16 + j for band b, or j when
 // a = b) and writes the two partial bands to P[u][pair][0..511].
 // patch_band_reduce_kernel then adds, for every row of band c, the partials
@@ -381,7 +386,7 @@ __global__ __launch_bounds__(256) void patch_gemv_band_kernel(Geo g, const int *
                                                               int npairs, double *P) {
   constexpr int R = 16 * kBandT;           // rows per band
   __shared__ double xs[2 * R];
-  __shared__ double yw[8][2 * R];
+  __shared__ double yw[4][2 * R];
   __shared__ double tbuf[4][2][16][17];
   __shared__ unsigned char tI[kBandT * kBandT], tJ[kBandT * kBandT];
   __shared__ int toff[kBandT * kBandT];
@@ -401,7 +406,7 @@ __global__ __launch_bounds__(256) void patch_gemv_band_kernel(Geo g, const int *
     if (row < m && patch_present(g, pinfo[rc], kmask, vc)) v = (double)a.x[node + pxoff[rc]];
     xs[k] = v;
 #pragma unroll
-    for (int w = 0; w < 8; ++w) yw[w][k] = 0.0;
+    for (int w = 0; w < 4; ++w) yw[w][k] = 0.0;
   }
   // the work item's tiles, I-major: a < b all (i, j) of the two bands, a = b
   // the triangle j >= i
@@ -425,17 +430,15 @@ __global__ __launch_bounds__(256) void patch_gemv_band_kernel(Geo g, const int *
   const size_t base = (size_t)u * (nt * (nt + 1) / 2) * 256;
   const bool lo = a.matU32 && !(a.u64flag && a.u64flag[u]);
   if (lo)
-    tile_sweep<float>(a.matU32 + base, ntl, tI, tJ, toff, xs, tbuf[wave], yw[2 * wave],
-                      yw[2 * wave + 1], wave, lane);
+    tile_sweep<float>(a.matU32 + base, ntl, tI, tJ, toff, xs, tbuf[wave], yw[wave], wave, lane);
   else
-    tile_sweep<double>(a.matU + base, ntl, tI, tJ, toff, xs, tbuf[wave], yw[2 * wave],
-                       yw[2 * wave + 1], wave, lane);
+    tile_sweep<double>(a.matU + base, ntl, tI, tJ, toff, xs, tbuf[wave], yw[wave], wave, lane);
   __syncthreads();
   double *Pw = P + ((size_t)u * npairs + pr) * (2 * R);
   for (int k = threadIdx.x; k < 2 * R; k += 256) {
     double y = 0.0;
 #pragma unroll
-    for (int w = 0; w < 8; ++w) y += yw[w][k];
+    for (int w = 0; w < 4; ++w) y += yw[w][k];
     Pw[k] = y;
   }
 }
