@@ -39,8 +39,8 @@ HBM_PEAK_GBS = 8000.0
 # the reading of a 1 GiB elementwise copy); constants of the kernels as
 # profiled, reported as null for any other configuration.
 GEMV_TRAFFIC = {
-    "elasticity": 53.682e9,   # profiles/patch_gemv_band_elast24_p4_traffic.md
-    "poisson": 2.231e9,       # profiles/patch_gemv_cube32_p3_traffic.md
+    "elasticity": 53.639e9,   # profiles/patch_gemv_band_elast24_p4_traffic.md
+    "poisson": 2.230e9,       # profiles/patch_gemv_cube32_p3_traffic.md
 }
 
 
