@@ -575,140 +575,336 @@ __global__ __launch_bounds__(256) void ml_smooth_kernel(const int *pm, const int
   }
 }
 
-// Gram-form inverse of SPD blocks, first stage (one workgroup per block):
-// Jacobi scaling S, left-looking Cholesky S B S = L L^T in place (the current
-// row of L in LDS), then the scaled inverse factor: WT[c][i] = s_c (L^{-1})[i][c]
-// and W = WT^T, so that B^{-1} = S L^{-T} L^{-1} S = WT W (formed by
-// ml_gemm_kernel with a symmetric store).  Unlike an elimination inverse, this
-// stays positive definite when the scaled condition reaches 1e13 and more
-// (patch blocks with fictitious leaves).
-__global__ __launch_bounds__(256) void ml_chol_factor_kernel(double *Ball, const int *pm,
-                                                             const int64_t *pinv, double *WTall,
-                                                             double *Wall, int *flag,
-                                                             const int64_t *poff, double *scal,
-                                                             double *norm1) {
-  const int n = pm[2 * blockIdx.x];
-  const int64_t off = pinv[blockIdx.x];
-  double *B = Ball + off;
-  double *WT = WTall + off;
-  double *W = Wall + off;
-  const int tid = threadIdx.x;
-  __shared__ double sc[kMlMaxPatch];
-  __shared__ double lj[kMlMaxPatch];
-  __shared__ double red[256];
-  for (int i = tid; i < n; i += 256) {
+// Inverses of SPD blocks in Gram form, blocked and batched over a bucket of
+// equal-size blocks (n a multiple of 32, count = gridDim.y):
+//   S = diag(B)^{-1/2},  S B S = U^T U  (upper Cholesky factor, in place),
+//   X = U^{-1}  (upper triangular, into a scratch copy),
+//   B^{-1} = S X X^T S,
+// in blocks of kCB = 64 pivots: the diagonal block of each step is factored
+// (or solved against) in LDS, the O(n^3) parts -- the block-row updates of
+// the left-looking factorisation, the block products of the triangular
+// inverse and the Gram product -- run on v_mfma_f64_16x16x4f64 (lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] and holds D[4j + l/16][l%16] of a 16 x 16 tile).  Unlike an
+// elimination inverse, the Gram form stays positive definite when the scaled
+// condition reaches 1e13 and more (patch blocks with fictitious leaves).
+// Every reduction has a fixed order: the result is bitwise reproducible.
+constexpr int kCB = 64;
+typedef double ml_d4 __attribute__((ext_vector_type(4)));
+
+__global__ void mlc_zero_kernel(double *x, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = 0.0;
+}
+
+// s_i = 1 / sqrt(B_ii) (1 and the flag where B_ii <= 0)
+__global__ void mlc_diag_kernel(const double *Ball, int n, double *sc, int *flag) {
+  const int b = blockIdx.y;
+  const double *B = Ball + (size_t)b * n * n;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const double dg = B[(size_t)i * n + i];
     if (!(dg > 0.0)) atomicOr(flag, 1);
-    sc[i] = dg > 0.0 ? 1.0 / sqrt(dg) : 1.0;
-  }
-  __syncthreads();
-  for (size_t e = tid; e < (size_t)n * n; e += 256) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    B[e] *= sc[i] * sc[j];
-  }
-  __syncthreads();
-  if (scal) {
-    // scaling and ||S B S||_1 (largest row sum of the symmetric scaled block)
-    double mx = 0.0;
-    for (int i = tid; i < n; i += 256) {
-      scal[poff[blockIdx.x] + i] = sc[i];
-      const double *row = B + (size_t)i * n;
-      double rs = 0.0;
-      for (int j = 0; j < n; ++j) rs += fabs(row[j]);
-      mx = fmax(mx, rs);
-    }
-    red[tid] = mx;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
-      __syncthreads();
-    }
-    if (tid == 0) norm1[blockIdx.x] = red[0];
-    __syncthreads();
-  }
-  for (int j = 0; j < n; ++j) {
-    double part = 0.0;
-    for (int k = tid; k < j; k += 256) {
-      const double v = B[(size_t)j * n + k];
-      lj[k] = v;
-      part += v * v;
-    }
-    red[tid] = part;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double dj = B[(size_t)j * n + j] - red[0];
-    if (tid == 0 && !(dj > 0.0)) atomicOr(flag, 1);
-    const double piv = dj > 0.0 ? sqrt(dj) : 1.0;
-    // (the unrolled inner loops keep several loads of a row in flight)
-    for (int i = j + 1 + tid; i < n; i += 256) {
-      const double *row = B + (size_t)i * n;
-      double acc = row[j];
-#pragma unroll 16
-      for (int k = 0; k < j; ++k) acc -= row[k] * lj[k];
-      B[(size_t)i * n + j] = acc / piv;
-    }
-    __syncthreads();
-    if (tid == 0) B[(size_t)j * n + j] = piv;
-    __syncthreads();
-  }
-  // scaled inverse factor, one column c of L^{-1} per thread (row c of WT)
-  for (int c = tid; c < n; c += 256) {
-    double *wt = WT + (size_t)c * n;
-    for (int i = 0; i < c; ++i) wt[i] = 0.0;
-    for (int i = c; i < n; ++i) {
-      const double *row = B + (size_t)i * n;
-      double acc = i == c ? 1.0 : 0.0;
-#pragma unroll 16
-      for (int k = c; k < i; ++k) acc -= row[k] * wt[k];
-      wt[i] = acc / row[i];
-    }
-    for (int i = 0; i < n; ++i) {
-      wt[i] *= sc[c];
-      W[(size_t)i * n + c] = wt[i];
-    }
+    sc[(size_t)b * n + i] = dg > 0.0 ? 1.0 / sqrt(dg) : 1.0;
   }
 }
 
-// C_b = A_b B_b for a batch of n x n row-major matrices (n a multiple of 32)
-// on the FP64 matrix cores: 64 x 64 output tile per workgroup, wave w owns
-// the 32 x 32 quarter (w / 2, w % 2) as 2 x 2 v_mfma_f64_16x16x4f64 tiles
-// (lane l supplies A[l%16][l/16] and B[l/16][l%16], holds D[4j + l/16][l%16]).
-// sym = 1: C is symmetric in exact arithmetic; only tiles on or above the
-// diagonal are computed and every entry (i <= j) is stored at (i, j) and
-// (j, i), so the result is exactly symmetric.
-typedef double ml_d4 __attribute__((ext_vector_type(4)));
+// B <- S B S, one wave per row; with norm1, ||S B S||_1 (the largest absolute
+// row sum of the symmetric scaled block) by atomicMax on the bit pattern
+// (order-preserving for non-negative doubles, so the result does not depend
+// on the order of the rows)
+__global__ void mlc_scale_kernel(double *Ball, int n, const double *sc, double *norm1) {
+  const int b = blockIdx.y;
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (r >= n) return;
+  double *row = Ball + (size_t)b * n * n + (size_t)r * n;
+  const double *s = sc + (size_t)b * n;
+  const double sr = s[r];
+  double sum = 0.0;
+  for (int c = lane; c < n; c += 64) {
+    const double v = row[c] * sr * s[c];
+    row[c] = v;
+    sum += fabs(v);
+  }
+  if (!norm1) return;
+  for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+  if (lane == 0)
+    atomicMax((unsigned long long *)(norm1 + b), (unsigned long long)__double_as_longlong(sum));
+}
 
-__global__ __launch_bounds__(256) void ml_gemm_kernel(const double *Aall, const double *Ball,
-                                                      double *Call, int n, int sym) {
-  const int nt = n / 64 + (n % 64 ? 1 : 0);
-  int ti = blockIdx.x / nt, tj = blockIdx.x % nt;
-  if (sym && ti > tj) return;
-  const size_t off = (size_t)blockIdx.y * n * n;
-  const double *A = Aall + off, *B = Ball + off;
-  double *C = Call + off;
+// Step k0 of the factorisation, diagonal block (one workgroup per block of
+// the bucket): A11 = U11^T U11 in LDS, row by row (left-looking, as the
+// block-row update: each entry of row j is formed once from the rows above
+// it), U11 written over A11.  The diagonal entries are left untouched by the
+// block-row updates: each pivot is formed here from the scaled diagonal
+// entry minus the compensated (Kahan) sum of the squares of its whole column
+// of U above it, since the smallest pivots (scaled conditions of 1e13 and
+// more) are the last bits of that cancellation.  Only upper triangles are
+// read and written; the lower one is never used again.
+__global__ __launch_bounds__(256) void mlc_potrf_kernel(double *Ball, int n, int k0, int *flag) {
+  __shared__ double a[kCB][kCB + 1];
+  __shared__ double part[4][kCB];
+  __shared__ double piv_s;
+  const int b = blockIdx.x, tid = threadIdx.x;
+  double *B = Ball + (size_t)b * n * n;
+  const int kb = min(kCB, n - k0);
+  for (int e = tid; e < kCB * kCB; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    a[i][j] = (i < kb && j < kb && i <= j) ? B[(size_t)(k0 + i) * n + k0 + j] : 0.0;
+  }
+  {
+    // sum_{k < k0} U[k][k0 + j]^2 in four interleaved compensated chains
+    const int j = tid & 63, r = tid >> 6;
+    const int jc = min(j, kb - 1);
+    double s = 0.0, c = 0.0;
+    for (int k = r; k < k0; k += 4) {
+      const double u = B[(size_t)k * n + k0 + jc];
+      const double y = fma(u, u, -c);
+      const double t2 = s + y;
+      c = (t2 - s) - y;
+      s = t2;
+    }
+    part[r][j] = s;
+  }
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    if (tid == 0) {
+      double s = ((part[0][j] + part[1][j]) + part[2][j]) + part[3][j], c = 0.0;
+      for (int k = 0; k < j; ++k) {
+        const double y = fma(a[k][j], a[k][j], -c);
+        const double t2 = s + y;
+        c = (t2 - s) - y;
+        s = t2;
+      }
+      const double dj = a[j][j] - s;
+      if (!(dj > 0.0)) atomicOr(flag, 1);
+      piv_s = dj > 0.0 ? sqrt(dj) : 1.0;
+    }
+    __syncthreads();
+    const double piv = piv_s;
+    if (tid > j && tid < kb) {
+      double v = a[j][tid];
+      for (int k = 0; k < j; ++k) v -= a[k][j] * a[k][tid];
+      a[j][tid] = v / piv;
+    }
+    if (tid == j) a[j][j] = piv;
+    __syncthreads();
+  }
+  for (int e = tid; e < kCB * kCB; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    if (i < kb && j < kb && i <= j) B[(size_t)(k0 + i) * n + k0 + j] = a[i][j];
+  }
+}
+
+// Step k0, panel: workgroup (x, b) forms the columns [k0 + 64 (x + 1), + 64)
+// of U12 = U11^{-T} A12 by forward substitution (U11 in LDS, one column per
+// lane).  A separate launch from mlc_potrf_kernel, which writes U11 over A11.
+__global__ __launch_bounds__(256) void mlc_trsm_kernel(double *Ball, int n, int k0) {
+  __shared__ double a[kCB][kCB + 1];
+  __shared__ double xs[kCB][kCB + 1];
+  const int b = blockIdx.y, tid = threadIdx.x;
+  double *B = Ball + (size_t)b * n * n;
+  const int c0 = k0 + kCB * ((int)blockIdx.x + 1), w = min(kCB, n - c0);
+  // columns past k0 + 64 exist only when the step is 64 wide
+  for (int e = tid; e < kCB * kCB; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    a[i][j] = i <= j ? B[(size_t)(k0 + i) * n + k0 + j] : 0.0;
+    xs[i][j] = j < w ? B[(size_t)(k0 + i) * n + c0 + j] : 0.0;
+  }
+  __syncthreads();
+  if (tid < w) {
+    const int c = tid;
+    for (int t = 0; t < kCB; ++t) {
+      double v = xs[t][c];
+      for (int s = 0; s < t; ++s) v -= a[s][t] * xs[s][c];
+      xs[t][c] = v / a[t][t];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < kCB * kCB; e += 256) {
+    const int t = e >> 6, c = e & 63;
+    if (c < w) B[(size_t)(k0 + t) * n + c0 + c] = xs[t][c];
+  }
+}
+
+// Block row q of the factorisation (left-looking): before its diagonal block
+// is factored, every entry of rows [k0, k0 + 64) above the diagonal (the
+// pivots are formed in mlc_potrf_kernel) takes all its updates at once, A[i][j] - sum_{k < k0} U[k][i] U[k][j], the
+// sum in one matrix-core accumulator over the final rows of U above it, and
+// the entry is rounded once (a right-looking update would store and round it
+// after every earlier block; with scaled conditions of 1e13 and more the
+// small pivots come out of a cancellation that those roundings spoil).
+// Workgroup (x, b): the 64 x 64 tile of columns [k0 + 64 x, + 64), wave w
+// its 32 x 32 quarter (w / 2, w % 2) as 2 x 2 MFMA tiles.  n and k0 are
+// multiples of 32 and 64, so a quarter that starts inside the matrix lies
+// inside it.
+__global__ __launch_bounds__(256) void mlc_rowupdate_kernel(double *Ball, int n, int k0) {
+  const int b = blockIdx.y;
+  double *B = Ball + (size_t)b * n * n;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ln = lane & 15, lq = lane >> 4;
-  const int i0 = ti * 64 + (wave >> 1) * 32, j0 = tj * 64 + (wave & 1) * 32;
-  if (i0 >= n || j0 >= n) return;
-  if (sym && i0 > j0 + 31) return;
+  const int i0 = k0 + (wave >> 1) * 32, j0 = k0 + kCB * (int)blockIdx.x + (wave & 1) * 32;
+  if (i0 >= n || j0 >= n || i0 > j0 + 31) return;
   ml_d4 acc[2][2];
-  for (int u = 0; u < 2; ++u)
-    for (int v = 0; v < 2; ++v) acc[u][v] = ml_d4{0.0, 0.0, 0.0, 0.0};
-  for (int k = 0; k < n; k += 4) {
-    double av[2], bv[2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      av[u] = A[(size_t)(i0 + 16 * u + ln) * n + k + lq];
-      bv[u] = B[(size_t)(k + lq) * n + j0 + 16 * u + ln];
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = ml_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < k0; k += 16) {
+    double av[4][2], bv[4][2];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        av[s][u] = B[(size_t)(k + 4 * s + lq) * n + i0 + 16 * u + ln];
+        bv[s][u] = B[(size_t)(k + 4 * s + lq) * n + j0 + 16 * u + ln];
+      }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][u], bv[s][v], acc[u][v], 0, 0, 0);
+  }
+  double old[2][2][4];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+        old[u][v][jj] = B[(size_t)(i0 + 16 * u + 4 * jj + lq) * n + j0 + 16 * v + ln];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int i = i0 + 16 * u + 4 * jj + lq, j = j0 + 16 * v + ln;
+        if (i < j) B[(size_t)i * n + j] = old[u][v][jj] - acc[u][v][jj];
+      }
+}
+
+// Block column J of X = U^{-1}, solved from the right as in the classic
+// blocked triangular inverse: every block X_rJ satisfies X_rJ U_JJ = R with
+// R = I (r = J) or R = -(sum_{K=r}^{J-1} X_rK U_KJ) (r < J, the sum on the
+// matrix cores from the earlier block columns of X), solved row by row by
+// forward substitution against U_JJ in LDS (one row per lane), so that every
+// block has a small right residual X U - I (as the row-by-row forward
+// substitution U^T x_c = e_c has); multiplying by an explicit inverse of
+// U_JJ instead lets an ill-conditioned U_JJ amplify that residual.  r = J
+// stores the zeros below the diagonal of X_JJ too.
+__global__ __launch_bounds__(256) void mlc_trtri_kernel(const double *Ball, double *Xall, int n,
+                                                        int J) {
+  __shared__ double ua[kCB][kCB + 1];   // U_JJ (identity past the matrix)
+  __shared__ double rs[kCB][kCB + 1];   // right-hand sides, then X_rJ
+  const int r = blockIdx.x, b = blockIdx.y, tid = threadIdx.x;
+  const double *B = Ball + (size_t)b * n * n;
+  double *X = Xall + (size_t)b * n * n;
+  const int c0 = kCB * J, w = min(kCB, n - c0);
+  for (int e = tid; e < kCB * kCB; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    ua[i][j] = (i < w && j < w) ? (i <= j ? B[(size_t)(c0 + i) * n + c0 + j] : 0.0)
+                                : (i == j ? 1.0 : 0.0);
+  }
+  const int wave = tid >> 6, lane = tid & 63;
+  if (r == J) {
+    for (int e = tid; e < kCB * kCB; e += 256) rs[e >> 6][e & 63] = (e >> 6) == (e & 63) ? 1.0 : 0.0;
+  } else {
+    // R = -sum_{k in [64 r, 64 J)} X[i][k] U[k][c] for the 64 rows of block r
+    const int ln = lane & 15, lq = lane >> 4;
+    const int i0 = kCB * r + (wave >> 1) * 32, j0 = c0 + (wave & 1) * 32;
+    ml_d4 acc[2][2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) acc[u][v] = ml_d4{0.0, 0.0, 0.0, 0.0};
+    if (j0 < n) {   // wave-uniform: the right half of a 32-wide last block column is empty
+      for (int k = kCB * r; k < c0; k += 16) {
+        double av[4][2], bv[4][2];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            av[s][u] = X[(size_t)(i0 + 16 * u + ln) * n + k + 4 * s + lq];
+            bv[s][u] = B[(size_t)(k + 4 * s + lq) * n + j0 + 16 * u + ln];
+          }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int v = 0; v < 2; ++v)
+              acc[u][v] =
+                  __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][u], bv[s][v], acc[u][v], 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int v = 0; v < 2; ++v)
-        acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+          rs[(wave >> 1) * 32 + 16 * u + 4 * jj + lq][(wave & 1) * 32 + 16 * v + ln] =
+              -acc[u][v][jj];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // row `lane`: x[c] = (R[c] - sum_{t < c} x[t] U[t][c]) / U[c][c], in place
+    for (int c = 0; c < w; ++c) {
+      double v = rs[lane][c];
+      for (int t = 0; t < c; ++t) v -= rs[lane][t] * ua[t][c];
+      rs[lane][c] = v / ua[c][c];
+    }
+  }
+  __syncthreads();
+  const int rows = r == J ? w : kCB;
+  for (int e = tid; e < kCB * kCB; e += 256) {
+    const int i = e >> 6, c = e & 63;
+    if (i < rows && c < w) X[(size_t)(kCB * r + i) * n + c0 + c] = rs[i][c];
+  }
+}
+
+// B^{-1} = S X X^T S: entry (i, j) = s_i s_j sum_{k >= max(i, j)} X[i][k] X[j][k]
+// (X upper triangular, zero below the diagonal inside its diagonal blocks);
+// 64 x 64 tiles ti <= tj, each value stored at (i, j) and (j, i), so the
+// inverse is exactly symmetric.
+__global__ __launch_bounds__(256) void mlc_gram_kernel(const double *Xall, const double *scall,
+                                                       double *Call, int n, int ntile) {
+  const int b = blockIdx.y;
+  int ti = 0, rem = blockIdx.x;
+  while (rem >= ntile - ti) {
+    rem -= ntile - ti;
+    ++ti;
+  }
+  const int tj = ti + rem;
+  const double *X = Xall + (size_t)b * n * n;
+  const double *sc = scall + (size_t)b * n;
+  double *C = Call + (size_t)b * n * n;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ln = lane & 15, lq = lane >> 4;
+  const int i0 = ti * 64 + (wave >> 1) * 32, j0 = tj * 64 + (wave & 1) * 32;
+  if (i0 >= n || j0 >= n || i0 > j0 + 31) return;
+  ml_d4 acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = ml_d4{0.0, 0.0, 0.0, 0.0};
+  for (int k = tj * 64; k < n; k += 32) {
+    double av[8][2], bv[8][2];
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        av[s][u] = X[(size_t)(i0 + 16 * u + ln) * n + k + 4 * s + lq];
+        bv[s][u] = X[(size_t)(j0 + 16 * u + ln) * n + k + 4 * s + lq];
+      }
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+          acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][u], bv[s][v], acc[u][v], 0, 0, 0);
   }
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -717,9 +913,10 @@ __global__ __launch_bounds__(256) void ml_gemm_kernel(const double *Aall, const 
 #pragma unroll
       for (int jj = 0; jj < 4; ++jj) {
         const int i = i0 + 16 * u + 4 * jj + lq, j = j0 + 16 * v + ln;
-        if (sym && i > j) continue;
-        C[(size_t)i * n + j] = acc[u][v][jj];
-        if (sym) C[(size_t)j * n + i] = acc[u][v][jj];
+        if (i > j) continue;
+        const double val = sc[i] * sc[j] * acc[u][v][jj];
+        C[(size_t)i * n + j] = val;
+        C[(size_t)j * n + i] = val;
       }
 }
 
@@ -798,21 +995,43 @@ __global__ void ml_sum_kernel(int nb, const double *partial, double *out) {
 
 static int ml_grid(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048)); }
 
-// Inverses of the npatch SPD blocks of a level in place as Gram matrices
-// WT W: one factor launch over all blocks (pm: padded size per block, pinv:
-// offset of each block in inv and in the scratch arrays wt, w), then the
-// symmetric MFMA products per bucket of equal-size blocks.
-static fcm_status ml_spd_inverse(double *inv, int npatch, const int *pm, const int64_t *pinv,
+// Inverses of the SPD blocks of a level in place, in Gram form (see the
+// mlc_ kernels above), one launch sequence per bucket (inv offset, (count,
+// size)) of equal-size blocks.  The patches of a bucket are consecutive, so
+// their scalings (scal, by patch row) and norms (norm1, by patch) are
+// consecutive too.  wt: scratch for X (the size of inv); w: scratch for the
+// scalings where scal is null.
+static fcm_status ml_spd_inverse(double *inv,
                                  const std::vector<std::pair<int64_t, std::pair<int, int>>> &bk,
                                  double *wt, double *w, int *flag, hipStream_t s,
-                                 const int64_t *poff = nullptr, double *scal = nullptr,
-                                 double *norm1 = nullptr) {
-  if (npatch <= 0) return FCM_OK;
-  ml_chol_factor_kernel<<<npatch, 256, 0, s>>>(inv, pm, pinv, wt, w, flag, poff, scal, norm1);
-  for (const auto &b : bk) {
-    const int n = b.second.second, nt = (n + 63) / 64;
-    ml_gemm_kernel<<<dim3(nt * nt, b.second.first), 256, 0, s>>>(wt + b.first, w + b.first,
-                                                                 inv + b.first, n, 1);
+                                 double *scal = nullptr, double *norm1 = nullptr) {
+  int64_t soff = 0;
+  int p0 = 0;
+  for (const auto &bkt : bk) {
+    const int cnt = bkt.second.first, n = bkt.second.second;
+    if (n % 32 != 0) {
+      set_error("multi-level hp: block size %d is not a multiple of 32", n);
+      return FCM_ERR_ARG;
+    }
+    double *B = inv + bkt.first, *X = wt + bkt.first;
+    double *sc = scal ? scal + soff : w + bkt.first;
+    double *nrm = norm1 ? norm1 + p0 : nullptr;
+    if (nrm) mlc_zero_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(nrm, cnt);
+    mlc_diag_kernel<<<dim3((n + 255) / 256, cnt), 256, 0, s>>>(B, n, sc, flag);
+    mlc_scale_kernel<<<dim3((n + 3) / 4, cnt), 256, 0, s>>>(B, n, sc, nrm);
+    const int nb = (n + kCB - 1) / kCB;
+    for (int q = 0; q < nb; ++q) {
+      const int k0 = q * kCB, kb = std::min(kCB, n - k0), k1 = k0 + kb;
+      if (q > 0) mlc_rowupdate_kernel<<<dim3(nb - q, cnt), 256, 0, s>>>(B, n, k0);
+      mlc_potrf_kernel<<<cnt, 256, 0, s>>>(B, n, k0, flag);
+      // only the last block row can be 32 high, and it has nothing to its right
+      if (k1 < n) mlc_trsm_kernel<<<dim3(nb - q - 1, cnt), 256, 0, s>>>(B, n, k0);
+    }
+    for (int J = 0; J < nb; ++J)
+      mlc_trtri_kernel<<<dim3(J + 1, cnt), 256, 0, s>>>(B, X, n, J);
+    mlc_gram_kernel<<<dim3(nb * (nb + 1) / 2, cnt), 256, 0, s>>>(X, sc, B, n, nb);
+    soff += (int64_t)cnt * n;
+    p0 += cnt;
   }
   FCM_HIP(hipGetLastError());
   return FCM_OK;
@@ -1367,14 +1586,9 @@ fcm_status mlhp_setup(fcm_handle *h) {
       return FCM_ERR_ARG;
     }
     double *s1 = nullptr, *s2 = nullptr;
-    int *cpm = nullptr;
-    int64_t *cpinv = nullptr;
     ML_TRY(pool_alloc((void **)&s1, nn * sizeof(double), h->stream));
     ML_TRY(pool_alloc((void **)&s2, nn * sizeof(double), h->stream));
-    ML_TRY(device_upload(h, &cpm, std::vector<int>{S->n0p, S->n0}));
-    ML_TRY(device_upload(h, &cpinv, std::vector<int64_t>{0}));
-    ML_TRY(ml_spd_inverse(S->A0, 1, cpm, cpinv, {{0, {1, S->n0p}}}, s1, s2, S->flag,
-                          h->stream));
+    ML_TRY(ml_spd_inverse(S->A0, {{0, {1, S->n0p}}}, s1, s2, S->flag, h->stream));
     FCM_HIP(hipStreamSynchronize(h->stream));
     pool_free(s1, h->stream);
     pool_free(s2, h->stream);
@@ -1410,8 +1624,7 @@ fcm_status mlhp_setup(fcm_handle *h) {
     ml_form_blocks_kernel<<<P.npatch, 256, 0, h->stream>>>(P.pm, P.pinv, P.plf, P.pair_leaf,
                                                            P.pair_map, P.map, S->leaf, S->koff,
                                                            S->Kl, P.inv);
-    ML_TRY(ml_spd_inverse(P.inv, P.npatch, P.pm, P.pinv, P.buckets, s1, s2, S->flag, h->stream,
-                          P.poff, P.scal, P.norm1));
+    ML_TRY(ml_spd_inverse(P.inv, P.buckets, s1, s2, S->flag, h->stream, P.scal, P.norm1));
     if (mixed) {
       ml_lowprec_kernel<<<P.npatch, 256, 0, h->stream>>>(P.pm, P.pinv, P.poff, P.scal, P.norm1,
                                                          P.inv, P.inv32, P.lo32);
@@ -1574,7 +1787,7 @@ fcm_status mlhp_vcycle(fcm_handle *h, const double *r, double *z, hipStream_t s)
   return FCM_OK;
 }
 
-// FP64 CG preconditioned by one V-cycle (Section 4), x0 = 0
+// FP64 CG preconditioned by one V-cycle (Section 4), x0 = 0, flexible beta
 fcm_status mlhp_pcg(fcm_handle *h, const double *b_in, double *x, fcm_solve_info *info,
                     hipStream_t s) {
   MlhpState *S = h->ml;
@@ -1615,9 +1828,13 @@ fcm_status mlhp_pcg(fcm_handle *h, const double *b_in, double *x, fcm_solve_info
         status = FCM_OK;
         break;
       }
+      // flexible (Polak-Ribiere) beta: with patch blocks of scaled condition
+      // ~1e13 the V-cycle applied in floating point is symmetric only to about
+      // 1e-4 relative, and the plain beta then loses the conjugacy it assumes
+      const double rzo = ml_dot(S, n, r, z, s);
       ml_vcycle(h, top, r, z, s);
       const double rz2 = ml_dot(S, n, r, z, s);
-      ml_axpby_kernel<<<ml_grid(n), 256, 0, s>>>(n, 1.0, z, rz2 / rz, p);
+      ml_axpby_kernel<<<ml_grid(n), 256, 0, s>>>(n, 1.0, z, (rz2 - rzo) / rz, p);
       rz = rz2;
     }
   }
