@@ -1170,8 +1170,9 @@ __global__ __launch_bounds__(256) void sweep_panel_kernel(double *Wp, int n, int
 
 // M_IJ -= sum_s R_s,I^T W_s,J = Rst_KI^T Wst_KJ (the stacked rows of the
 // four steps) for I, J outside the outer block K = [k0, k0 + kb); rows of K
-// <- Wp (the swept panel); columns of K <- Wp^T.  Only the upper triangle is computed
-// and every value is stored at (i, j) and (j, i): the swept matrix is
+// <- Wp (the swept panel); columns of K <- Wp^T.  Only the upper triangle is
+// computed and every value is stored at (i, j) and (j, i) (the mirror through
+// LDS, row by row): the swept matrix is
 // symmetric in exact arithmetic, and keeping it exactly symmetric matters for
 // cut-cell blocks whose scaled condition reaches 1e12 or more, where R^T (P R)
 // and its mirror image differ by the pivot-block solve error.  64 x 64 output
@@ -1185,9 +1186,26 @@ typedef double doublex4s __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n, int k0, int kb,
                                                                 const double *Wp,
                                                                 const double *Wst,
-                                                                const double *Rst, int ntile) {
-  const int b = blockIdx.y;
-  int ti = 0, rem = blockIdx.x;
+                                                                const double *Rst, int ntile,
+                                                                int batch) {
+  // Workgroups are dealt to the 8 XCDs round-robin by linear id; in batches
+  // of 8 and more all tiles of a matrix get ids of one residue mod 8, so that
+  // the matrix's row stacks are fetched from HBM into one XCD's L2 (and
+  // reused there by its other tiles) instead of into all eight.  Smaller
+  // batches (single coarse blocks) take the plain order.
+  const int npair = ntile * (ntile + 1) / 2;
+  const int L = blockIdx.x;
+  int b, rem;
+  if (batch >= 8) {
+    const int slot = L >> 3;
+    b = 8 * (slot / npair) + (L & 7);
+    rem = slot % npair;
+  } else {
+    b = L / npair;
+    rem = L % npair;
+  }
+  if (b >= batch) return;
+  int ti = 0;
   while (rem >= ntile - ti) {
     rem -= ntile - ti;
     ++ti;
@@ -1201,7 +1219,11 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ln = lane & 15, lq = lane >> 4;
   const int i0 = ti * 64 + (wave >> 1) * 32, j0 = tj * 64 + (wave & 1) * 32;
-  if (i0 >= n || j0 >= n || i0 > j0 + 31) return;   // whole wave: nothing on or above the diagonal
+  __shared__ double tile[64][65];   // the tile's results, for the mirrored store
+  // a wave with nothing on or above the diagonal (or outside the matrix)
+  // skips the products but joins the barrier before the mirrored store
+  const bool active = !(i0 >= n || j0 >= n || i0 > j0 + 31);
+  if (active) {
   doublex4s acc[2][2];
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -1276,8 +1298,18 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
         const bool inK = (i >= k0 && i < k1) || (j >= k0 && j < k1);
         const double val = inK ? old[u][v][jj] : old[u][v][jj] - acc[u][v][jj];
         M[(size_t)i * n + j] = val;
-        M[(size_t)j * n + i] = val;
+        tile[i - ti * 64][j - tj * 64] = val;
       }
+  }
+  __syncthreads();
+  // the mirror (j, i) of every entry i < j, written along rows of the
+  // transposed tile (a store straight from the MFMA layout would touch 16
+  // rows 32 bytes each)
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int jl = e >> 6, il = e & 63;
+    const int i = ti * 64 + il, j = tj * 64 + jl;
+    if (i < j && j < n) M[(size_t)j * n + i] = tile[il][jl];
+  }
 }
 
 size_t spd_inverse_scratch_doubles(int n, int batch) {
@@ -1306,14 +1338,17 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
   apply_scale_kernel<<<sgrid, 256, 0, s>>>(A, n, scale, 1.0, kappa ? nrm : nullptr);
   const int nt = (n + 63) / 64;
   const int pc_blocks = (int)std::min<size_t>(((size_t)kPB * n + 255) / 256, 1024);
-  const dim3 ugrid(nt * (nt + 1) / 2, batch);
+  // one-dimensional: tile pairs x batch, the batch rounded up to a multiple
+  // of 8 from 8 on (the update kernel maps ids to (matrix, tile) XCD by XCD)
+  const dim3 ugrid((unsigned)(nt * (nt + 1) / 2) *
+                   (unsigned)(batch >= 8 ? (batch + 7) / 8 * 8 : batch));
   if (batch < kTwoLevelBatch || n <= kTwoLevelN) {
     // one trailing update per 32 pivots, straight from the matrix rows
     for (int k0 = 0; k0 < n; k0 += kTB) {
       const int kb = std::min(kTB, n - k0);
       sweep_rows_kernel<<<dim3((n + kTJ - 1) / kTJ, batch), 64, 0, s>>>(
           A + (size_t)k0 * n, (size_t)n * n, n, k0, Wst, Rst, (size_t)kPB * n, flag);
-      sweep_update_mfma_kernel<<<ugrid, 256, 0, s>>>(A, n, k0, kb, Wst, Wst, Rst, nt);
+      sweep_update_mfma_kernel<<<ugrid, 256, 0, s>>>(A, n, k0, kb, Wst, Wst, Rst, nt, batch);
     }
   } else {
     for (int k0 = 0; k0 < n; k0 += kPB) {
@@ -1326,7 +1361,7 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
         sweep_panel_kernel<<<dim3((n + 63) / 64, (kb + 15) / 16, batch), 256, 0, s>>>(
             Wp, n, k0, kb, k0 + t0, Wst + off, Rst + off);
       }
-      sweep_update_mfma_kernel<<<ugrid, 256, 0, s>>>(A, n, k0, kb, Wp, Wst, Rst, nt);
+      sweep_update_mfma_kernel<<<ugrid, 256, 0, s>>>(A, n, k0, kb, Wp, Wst, Rst, nt, batch);
     }
   }
   apply_scale_kernel<<<sgrid, 256, 0, s>>>(A, n, scale, -1.0, kappa ? nrm + batch : nullptr);
