@@ -1312,6 +1312,162 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
   }
 }
 
+// Two-level path, the same update from 128 x 128 tiles (ti <= tj): the
+// stacks' 16-deep chunks of the tile's 128 rows and 128 columns are staged in
+// LDS (double-buffered: the next chunk's loads are in flight while the
+// matrix cores work on the current one) and each wave takes a 64 x 64
+// quadrant as 4 x 4 v_mfma_f64_16x16x4f64 tiles, so that the L2 delivers
+// each operand once per workgroup, with four times the products per byte of
+// the 64 x 64 tiles, whose waves each load their own operands.  Entries,
+// the K rows and columns and the mirrored store are as above; the XCD
+// mapping too.
+constexpr int kUT = 128, kUK = 16, kUS = kUT + 4;
+typedef double doublex4w __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256, 2) void sweep_update_wide_kernel(double *A, int n, int k0,
+                                                                   int kb, const double *Wp,
+                                                                   const double *Wst,
+                                                                   const double *Rst, int ntile,
+                                                                   int batch) {
+  __shared__ double lds[2 * 2 * kUK * kUS];   // [buffer][R | W][k][column]; later two 64 x 65 tiles
+  const int npair = ntile * (ntile + 1) / 2;
+  const int L = blockIdx.x;
+  int b, rem;
+  if (batch >= 8) {
+    const int slot = L >> 3;
+    b = 8 * (slot / npair) + (L & 7);
+    rem = slot % npair;
+  } else {
+    b = L / npair;
+    rem = L % npair;
+  }
+  if (b >= batch) return;   // the whole workgroup
+  int ti = 0;
+  while (rem >= ntile - ti) {
+    rem -= ntile - ti;
+    ++ti;
+  }
+  const int tj = ti + rem;
+  double *M = A + (size_t)b * n * n;
+  const double *Wb = Wp + (size_t)b * kPB * n;
+  const double *Sw = Wst + (size_t)b * kPB * n;
+  const double *Sr = Rst + (size_t)b * kPB * n;
+  const int k1 = k0 + kb;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int ln = lane & 15, lq = lane >> 4;
+  const int I0 = ti * kUT, J0 = tj * kUT;
+  const int qi0 = I0 + (wave >> 1) * 64, qj0 = J0 + (wave & 1) * 64;
+  // a quadrant with nothing on or above the diagonal (or outside the matrix)
+  // skips the products but joins the loads and the barriers
+  const bool active = qi0 < n && qj0 < n && qi0 <= qj0 + 63;
+  // each thread stages one column (tid % 128) of rows tid / 128 + 2 r
+  const int lc = tid & 127, lk = tid >> 7;
+  const int ci = min(I0 + lc, n - 1), cj = min(J0 + lc, n - 1);
+  const double mi = I0 + lc < n ? 1.0 : 0.0, mj = J0 + lc < n ? 1.0 : 0.0;
+  double pr[8], pw[8];
+  // stack rows kb.. up to the next multiple of 32 are the zero rows of a
+  // partial last step
+  auto fetch = [&](int c) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const size_t row = (size_t)(c + lk + 2 * r) * n;
+      pr[r] = Sr[row + ci];
+      pw[r] = Sw[row + cj];
+    }
+  };
+  auto stage = [&](int buf) {
+    double *a = lds + buf * 2 * kUK * kUS, *w = a + kUK * kUS;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      a[(lk + 2 * r) * kUS + lc] = pr[r] * mi;
+      w[(lk + 2 * r) * kUS + lc] = pw[r] * mj;
+    }
+  };
+  doublex4w acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = doublex4w{0.0, 0.0, 0.0, 0.0};
+  const int nk = (kb + 15) & ~15;
+  const int ai = (wave >> 1) * 64 + ln, aj = (wave & 1) * 64 + ln;
+  fetch(0);
+  for (int c = 0; c < nk; c += kUK) {
+    const int buf = (c / kUK) & 1;
+    stage(buf);
+    __syncthreads();
+    if (c + kUK < nk) fetch(c + kUK);
+    if (active) {
+      const double *a = lds + buf * 2 * kUK * kUS, *w = a + kUK * kUS;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int kr = (4 * ks + lq) * kUS;
+        double av[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          av[u] = a[kr + ai + 16 * u];
+          bv[u] = w[kr + aj + 16 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[v], acc[u][v], 0, 0, 0);
+      }
+    }
+  }
+  // direct store of the upper entries; acc keeps the stored values
+  if (active) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double old[4][4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int i = qi0 + 16 * u + 4 * jj + lq, j = qj0 + 16 * v + ln;
+          const bool ok = i < n && j < n && i <= j;
+          const bool ik = i >= k0 && i < k1, jk = j >= k0 && j < k1;
+          const double *src = !ok ? M : ik ? Wb + (size_t)(i - k0) * n + j
+                                        : jk ? Wb + (size_t)(j - k0) * n + i
+                                             : M + (size_t)i * n + j;
+          old[v][jj] = *src;
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int i = qi0 + 16 * u + 4 * jj + lq, j = qj0 + 16 * v + ln;
+          if (i >= n || j >= n || i > j) continue;
+          const bool inK = (i >= k0 && i < k1) || (j >= k0 && j < k1);
+          const double val = inK ? old[v][jj] : old[v][jj] - acc[u][v][jj];
+          M[(size_t)i * n + j] = val;
+          acc[u][v][jj] = val;
+        }
+    }
+  }
+  // mirrored store, two quadrants per round through two 64 x 65 LDS tiles
+#pragma unroll
+  for (int round = 0; round < 2; ++round) {
+    __syncthreads();   // the LDS is free (products done, or the last round's reads)
+    if ((wave >> 1) == round && active) {
+      double *T = lds + (wave & 1) * 64 * 65;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj)
+            T[(16 * u + 4 * jj + lq) * 65 + 16 * v + ln] = acc[u][v][jj];
+    }
+    __syncthreads();
+    for (int e = tid; e < 2 * 64 * 64; e += 256) {
+      const int q = e >> 12, jl = (e >> 6) & 63, il = e & 63;
+      const int i = I0 + 64 * round + il, j = J0 + 64 * q + jl;
+      if (i < j && j < n) M[(size_t)j * n + i] = lds[q * 64 * 65 + il * 65 + jl];
+    }
+  }
+}
+
 size_t spd_inverse_scratch_doubles(int n, int batch) {
   // the panel (Wp) and the stacked rows after (Wst) and before (Rst) each
   // step, kPB x n each; scale; two norms per matrix
@@ -1340,8 +1496,10 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
   const int pc_blocks = (int)std::min<size_t>(((size_t)kPB * n + 255) / 256, 1024);
   // one-dimensional: tile pairs x batch, the batch rounded up to a multiple
   // of 8 from 8 on (the update kernel maps ids to (matrix, tile) XCD by XCD)
-  const dim3 ugrid((unsigned)(nt * (nt + 1) / 2) *
-                   (unsigned)(batch >= 8 ? (batch + 7) / 8 * 8 : batch));
+  const unsigned bgrid = (unsigned)(batch >= 8 ? (batch + 7) / 8 * 8 : batch);
+  const dim3 ugrid((unsigned)(nt * (nt + 1) / 2) * bgrid);
+  const int ntw = (n + kUT - 1) / kUT;
+  const dim3 wgrid((unsigned)(ntw * (ntw + 1) / 2) * bgrid);
   if (batch < kTwoLevelBatch || n <= kTwoLevelN) {
     // one trailing update per 32 pivots, straight from the matrix rows
     for (int k0 = 0; k0 < n; k0 += kTB) {
@@ -1361,7 +1519,7 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
         sweep_panel_kernel<<<dim3((n + 63) / 64, (kb + 15) / 16, batch), 256, 0, s>>>(
             Wp, n, k0, kb, k0 + t0, Wst + off, Rst + off);
       }
-      sweep_update_mfma_kernel<<<ugrid, 256, 0, s>>>(A, n, k0, kb, Wp, Wst, Rst, nt, batch);
+      sweep_update_wide_kernel<<<wgrid, 256, 0, s>>>(A, n, k0, kb, Wp, Wst, Rst, ntw, batch);
     }
   }
   apply_scale_kernel<<<sgrid, 256, 0, s>>>(A, n, scale, -1.0, kappa ? nrm + batch : nullptr);
