@@ -1041,14 +1041,66 @@ __global__ void kappa_product_kernel(const double *nrm, int batch, double *kappa
 }
 
 // Panel of outer block [k0, k0 + kb): Wp = rows k0.. of the matrix (kPB x n
-// per matrix, rows past kb zero).
-__global__ __launch_bounds__(256) void panel_copy_kernel(const double *A, int n, int k0, int kb,
-                                                         double *Wp) {
-  const int b = blockIdx.y;
-  const size_t tot = (size_t)kPB * n;
-  const double *M = A + (size_t)b * n * n + (size_t)k0 * n;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < tot; i += (size_t)gridDim.x * 256)
-    Wp[(size_t)b * tot + i] = i < (size_t)kb * n ? M[i] : 0.0;
+// per matrix, rows past kb zero), read from the upper triangle, the only one
+// kept during the two-level sweep: entry (k0 + t, c) is M[k0 + t][c] for c >= k0 + t and
+// M[c][k0 + t] below the diagonal.  Workgroup (x, b) takes the columns
+// [64 x, + 64): the transposed block M[c][k0 .. k0 + 128) of its columns is
+// read along rows into LDS, so that both reads and the panel's writes run
+// along rows.
+__global__ __launch_bounds__(256) void panel_copy_upper_kernel(const double *A, int n, int k0,
+                                                               int kb, double *Wp) {
+  __shared__ double tr[64][kPB + 1];
+  const int b = blockIdx.y, c0 = 64 * blockIdx.x, tid = threadIdx.x;
+  const double *M = A + (size_t)b * n * n;
+  double *W = Wp + (size_t)b * kPB * n;
+  if (c0 >= k0 + kb - 1) {
+    // every column on or right of the panel's diagonal: rows read directly
+    for (int e = tid; e < kPB * 64; e += 256) {
+      const int tt = e >> 6, c = c0 + (e & 63);
+      if (c < n) W[(size_t)tt * n + c] = tt < kb ? M[(size_t)(k0 + tt) * n + c] : 0.0;
+    }
+    return;
+  }
+  for (int e = tid; e < 64 * kPB; e += 256) {
+    const int cl = e >> 7, tt = e & (kPB - 1);
+    const int c = c0 + cl;
+    tr[cl][tt] = (c < n && tt < kb) ? M[(size_t)c * n + k0 + tt] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < kPB * 64; e += 256) {
+    const int tt = e >> 6, cl = e & 63;
+    const int c = c0 + cl;
+    if (c >= n) continue;
+    double v = 0.0;
+    if (tt < kb) v = c >= k0 + tt ? M[(size_t)(k0 + tt) * n + c] : tr[cl][tt];
+    W[(size_t)tt * n + c] = v;
+  }
+}
+
+// Lower triangle <- upper triangle after the two-level sweep: workgroup
+// (pair, b) copies the 64 x 64 tile (ti, tj), ti <= tj, to (tj, ti) through
+// LDS (both along rows); on diagonal tiles only the entries below the diagonal.
+__global__ __launch_bounds__(256) void mirror_upper_kernel(double *A, int n, int ntile) {
+  __shared__ double tl[64][65];
+  const int b = blockIdx.y, tid = threadIdx.x;
+  int ti = 0, rem = blockIdx.x;
+  while (rem >= ntile - ti) {
+    rem -= ntile - ti;
+    ++ti;
+  }
+  const int tj = ti + rem;
+  double *M = A + (size_t)b * n * n;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int il = e >> 6, jl = e & 63;
+    const int i = 64 * ti + il, j = 64 * tj + jl;
+    tl[il][jl] = (i < n && j < n) ? M[(size_t)i * n + j] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int jl = e >> 6, il = e & 63;
+    const int i = 64 * ti + il, j = 64 * tj + jl;
+    if (i < j && j < n) M[(size_t)j * n + i] = tl[il][jl];
+  }
 }
 
 // Pivot rows of one inner block (kTB pivots, global index k0 of the first):
@@ -1324,6 +1376,7 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
 constexpr int kUT = 128, kUK = 16, kUS = kUT + 4;
 typedef double doublex4w __attribute__((ext_vector_type(4)));
 
+template <bool kMirror>
 __global__ __launch_bounds__(256, 2) void sweep_update_wide_kernel(double *A, int n, int k0,
                                                                    int kb, const double *Wp,
                                                                    const double *Wst,
@@ -1445,6 +1498,7 @@ __global__ __launch_bounds__(256, 2) void sweep_update_wide_kernel(double *A, in
         }
     }
   }
+  if (!kMirror) return;   // the two-level sweep keeps the upper triangle only
   // mirrored store, two quadrants per round through two 64 x 65 LDS tiles
 #pragma unroll
   for (int round = 0; round < 2; ++round) {
@@ -1493,7 +1547,6 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
   const dim3 sgrid((n + 3) / 4, batch);
   apply_scale_kernel<<<sgrid, 256, 0, s>>>(A, n, scale, 1.0, kappa ? nrm : nullptr);
   const int nt = (n + 63) / 64;
-  const int pc_blocks = (int)std::min<size_t>(((size_t)kPB * n + 255) / 256, 1024);
   // one-dimensional: tile pairs x batch, the batch rounded up to a multiple
   // of 8 from 8 on (the update kernel maps ids to (matrix, tile) XCD by XCD)
   const unsigned bgrid = (unsigned)(batch >= 8 ? (batch + 7) / 8 * 8 : batch);
@@ -1509,9 +1562,11 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
       sweep_update_mfma_kernel<<<ugrid, 256, 0, s>>>(A, n, k0, kb, Wst, Wst, Rst, nt, batch);
     }
   } else {
+    // only the upper triangle is kept during the sweep (the panel is read
+    // from it, the update writes it), the lower one is filled at the end
     for (int k0 = 0; k0 < n; k0 += kPB) {
       const int kb = std::min(kPB, n - k0);
-      panel_copy_kernel<<<dim3(pc_blocks, batch), 256, 0, s>>>(A, n, k0, kb, Wp);
+      panel_copy_upper_kernel<<<dim3((n + 63) / 64, batch), 256, 0, s>>>(A, n, k0, kb, Wp);
       for (int t0 = 0; t0 < kb; t0 += kTB) {
         const size_t off = (size_t)t0 * n;
         sweep_rows_kernel<<<dim3((n + kTJ - 1) / kTJ, batch), 64, 0, s>>>(
@@ -1519,8 +1574,10 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
         sweep_panel_kernel<<<dim3((n + 63) / 64, (kb + 15) / 16, batch), 256, 0, s>>>(
             Wp, n, k0, kb, k0 + t0, Wst + off, Rst + off);
       }
-      sweep_update_wide_kernel<<<wgrid, 256, 0, s>>>(A, n, k0, kb, Wp, Wst, Rst, ntw, batch);
+      sweep_update_wide_kernel<false>
+          <<<wgrid, 256, 0, s>>>(A, n, k0, kb, Wp, Wst, Rst, ntw, batch);
     }
+    mirror_upper_kernel<<<dim3(nt * (nt + 1) / 2, batch), 256, 0, s>>>(A, n, nt);
   }
   apply_scale_kernel<<<sgrid, 256, 0, s>>>(A, n, scale, -1.0, kappa ? nrm + batch : nullptr);
   if (kappa) kappa_product_kernel<<<(batch + 255) / 256, 256, 0, s>>>(nrm, batch, kappa);
