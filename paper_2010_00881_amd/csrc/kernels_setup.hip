@@ -1109,15 +1109,21 @@ __global__ __launch_bounds__(256) void mirror_upper_kernel(double *A, int n, int
 // (a private copy, needed for the pivot columns), lanes 32..63 the panel
 // columns [32 J, 32 J + 32), each a column of 32 rows in registers; the wave
 // sweeps them pivot by pivot (product form), the pivot column being
-// broadcast from its lane through LDS.  Rows past n of a partial last block
+// broadcast from its lane's registers (readlane).  Rows past n of a partial last block
 // are identity rows.  It writes the swept rows W and the rows before the
 // sweep R of its panel columns.
 constexpr int kTJ = 32;
 
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 __global__ __launch_bounds__(64) void sweep_rows_kernel(const double *P, size_t pstride, int n,
                                                         int k0, double *W, double *Rg,
                                                         size_t wstride, int *flag) {
-  __shared__ double bc[2][kTB];
   const int J = blockIdx.x, b = blockIdx.y, l = threadIdx.x;
   const double *M = P + (size_t)b * pstride;
   double *Wb = W + (size_t)b * wstride;
@@ -1140,14 +1146,11 @@ __global__ __launch_bounds__(64) void sweep_rows_kernel(const double *P, size_t 
 #pragma unroll
   for (int kk = 0; kk < kTB; ++kk) {
     const int kc = k0 + kk;   // pivot column; lane kk holds it
-    if (l == kk) {
-#pragma unroll
-      for (int r = 0; r < kTB; ++r) bc[kk & 1][r] = x[r];
-    }
-    __syncthreads();
+    // broadcast of lane kk's column straight from its registers (kk is a
+    // constant of the unrolled loop), no LDS round trip and no barrier
     double ck[kTB];
 #pragma unroll
-    for (int r = 0; r < kTB; ++r) ck[r] = bc[kk & 1][r];
+    for (int r = 0; r < kTB; ++r) ck[r] = readlane_f64(x[r], kk);
     const double piv = ck[kk];
     if (l == 0 && J == 0 && kc < n && !(piv > 0.0)) atomicOr(flag, 1);
     const double ip = 1.0 / piv;
