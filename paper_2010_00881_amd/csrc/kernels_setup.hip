@@ -1177,8 +1177,8 @@ __global__ __launch_bounds__(64) void sweep_rows_kernel(const double *P, size_t 
 // staged in LDS, wave w takes rows 16 g + w, + 4, + 8, + 12.  Within the panel's own columns (the K x K block, the pivot tiles
 // of the next steps) only the upper triangle is computed and each value is
 // also stored at its mirror position, so that block stays exactly symmetric
-// (as the trailing update keeps the whole matrix); the mirror targets are
-// entries no thread computes.  Ws, Rs: the step's rows in the stacks
+// (the row sweeps of the next steps read whole panel rows); the mirror
+// targets are entries no thread computes.  Ws, Rs: the step's rows in the stacks
 // (matrix stride kPB n).
 __global__ __launch_bounds__(256) void sweep_panel_kernel(double *Wp, int n, int k0p, int kb,
                                                           int s0, const double *Ws,
