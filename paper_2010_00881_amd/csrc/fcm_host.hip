@@ -1943,6 +1943,18 @@ void fcm_destroy(fcm_handle *h) {
   if (h->co_ready) hipEventDestroy(h->co_ready);
   if (h->own) hipStreamDestroy(h->own);
   pinned_put(h->hscal);
+  // A problem that held more than an eighth of the device leaves the pool
+  // cut into blocks of its own sizes, which the next large setup mostly
+  // cannot use: it would wait while the runtime trims and re-maps the pool
+  // on a failed allocation (seconds at 150 GB).  Such memory goes back now.
+  size_t free_b = 0, total_b = 0;
+  if (h->bytes > 0 && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+      (size_t)h->bytes > total_b / 8) {
+    int dev = 0;
+    hipMemPool_t pool;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess)
+      hipMemPoolTrimTo(pool, 0);
+  }
   delete h->hmg;
   delete h;
 }
