@@ -469,10 +469,9 @@ def main():
     label = (f"cube_voids_elasticity_{n}^3_p4" if kind == "elasticity"
              else f"cube_voids_poisson_{n}^3_p3")
 
-    # The kernel figures come first: the problem they hold and their timing
-    # buffers leave the memory pool cut differently from a solve, and the next
-    # setup pays for that (about 4 s at this size); the warm-up solves after
-    # them leave the pool as the timed solves find it.
+    # The kernel figures come first and the warm-up solves after them, so that
+    # the timed solves follow solves of their own kind (device memory is
+    # handed out from a stream-ordered pool).
     print("[bench] kernel figures on the seed-0 problem", file=sys.stderr, flush=True)
     kf = _kernel_figures(kind, n, args.precision, args.smoother)
     torch.cuda.synchronize()

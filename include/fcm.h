@@ -354,6 +354,9 @@ fcm_status fcm_time_op(fcm_handle *h, int op, int level, int reps, void *stream,
  * to the device's stream-ordered pool in stream order after the work queued
  * on the stream given to fcm_setup(); work the caller queued with this
  * handle on any other stream must have completed (synchronise it first).
+ * A handle that held more than an eighth of the device's memory waits for
+ * its stream and then trims the current device's pool (as fcm_trim_pool),
+ * since the next large setup could not reuse blocks cut to its sizes.
  * NULL is ignored.                                                          */
 void fcm_destroy(fcm_handle *h);
 
