@@ -1948,7 +1948,7 @@ void fcm_destroy(fcm_handle *h) {
   // cannot use: it would wait while the runtime trims and re-maps the pool
   // on a failed allocation (seconds at 150 GB).  Such memory goes back now.
   size_t free_b = 0, total_b = 0;
-  if (h->bytes > 0 && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+  if (h->bytes > ((int64_t)8 << 30) && hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
       (size_t)h->bytes > total_b / 8) {
     int dev = 0;
     hipMemPool_t pool;
