@@ -1373,19 +1373,18 @@ __global__ __launch_bounds__(256) void sweep_update_mfma_kernel(double *A, int n
 // matrix cores work on the current one) and each wave takes a 64 x 64
 // quadrant as 4 x 4 v_mfma_f64_16x16x4f64 tiles, so that the L2 delivers
 // each operand once per workgroup, with four times the products per byte of
-// the 64 x 64 tiles, whose waves each load their own operands.  Entries,
-// the K rows and columns and the mirrored store are as above; the XCD
-// mapping too.
+// the 64 x 64 tiles, whose waves each load their own operands.  Entries and
+// the K rows and columns are as above, the XCD mapping too; only the upper
+// triangle is stored (the two-level sweep reads its panels from it).
 constexpr int kUT = 128, kUK = 16, kUS = kUT + 4;
 typedef double doublex4w __attribute__((ext_vector_type(4)));
 
-template <bool kMirror>
 __global__ __launch_bounds__(256, 2) void sweep_update_wide_kernel(double *A, int n, int k0,
                                                                    int kb, const double *Wp,
                                                                    const double *Wst,
                                                                    const double *Rst, int ntile,
                                                                    int batch) {
-  __shared__ double lds[2 * 2 * kUK * kUS];   // [buffer][R | W][k][column]; later two 64 x 65 tiles
+  __shared__ double lds[2 * 2 * kUK * kUS];   // [buffer][R | W][k][column]
   const int npair = ntile * (ntile + 1) / 2;
   const int L = blockIdx.x;
   int b, rem;
@@ -1471,7 +1470,8 @@ __global__ __launch_bounds__(256, 2) void sweep_update_wide_kernel(double *A, in
       }
     }
   }
-  // direct store of the upper entries; acc keeps the stored values
+  // store of the upper entries (the two-level sweep keeps the upper
+  // triangle only; its lower one is filled once at the end)
   if (active) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -1497,30 +1497,7 @@ __global__ __launch_bounds__(256, 2) void sweep_update_wide_kernel(double *A, in
           const bool inK = (i >= k0 && i < k1) || (j >= k0 && j < k1);
           const double val = inK ? old[v][jj] : old[v][jj] - acc[u][v][jj];
           M[(size_t)i * n + j] = val;
-          acc[u][v][jj] = val;
         }
-    }
-  }
-  if (!kMirror) return;   // the two-level sweep keeps the upper triangle only
-  // mirrored store, two quadrants per round through two 64 x 65 LDS tiles
-#pragma unroll
-  for (int round = 0; round < 2; ++round) {
-    __syncthreads();   // the LDS is free (products done, or the last round's reads)
-    if ((wave >> 1) == round && active) {
-      double *T = lds + (wave & 1) * 64 * 65;
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj)
-            T[(16 * u + 4 * jj + lq) * 65 + 16 * v + ln] = acc[u][v][jj];
-    }
-    __syncthreads();
-    for (int e = tid; e < 2 * 64 * 64; e += 256) {
-      const int q = e >> 12, jl = (e >> 6) & 63, il = e & 63;
-      const int i = I0 + 64 * round + il, j = J0 + 64 * q + jl;
-      if (i < j && j < n) M[(size_t)j * n + i] = lds[q * 64 * 65 + il * 65 + jl];
     }
   }
 }
@@ -1577,8 +1554,7 @@ int spd_inverse_batched(double *A, int n, int batch, double *scratch, int *flag,
         sweep_panel_kernel<<<dim3((n + 63) / 64, (kb + 15) / 16, batch), 256, 0, s>>>(
             Wp, n, k0, kb, k0 + t0, Wst + off, Rst + off);
       }
-      sweep_update_wide_kernel<false>
-          <<<wgrid, 256, 0, s>>>(A, n, k0, kb, Wp, Wst, Rst, ntw, batch);
+      sweep_update_wide_kernel<<<wgrid, 256, 0, s>>>(A, n, k0, kb, Wp, Wst, Rst, ntw, batch);
     }
     mirror_upper_kernel<<<dim3(nt * (nt + 1) / 2, batch), 256, 0, s>>>(A, n, nt);
   }
