@@ -232,9 +232,12 @@ fcm_status fcm_hlevels(const fcm_handle *h, int *count, int *cells);
 /* Test hook for the batched SPD inversion used by the Schwarz blocks and the
  * coarse factorisation: A_dev (device, `batch` row-major n x n FP64 SPD
  * matrices, contiguous) is overwritten by the inverses, computed on `stream`
- * by the Jacobi-scaled Gauss-Jordan sweep.  kappa_dev (device, may be NULL)
- * receives ||A_s||_1 ||A_s^{-1}||_1 of each Jacobi-scaled matrix.  Returns
- * FCM_ERR_NOT_SPD if a pivot was not positive.  Synchronises the stream.    */
+ * by the Jacobi-scaled Gauss-Jordan sweep.  The matrices must be exactly
+ * symmetric: for n > 384 and batch >= 8 the sweep works on the upper
+ * triangle only (the inverse is returned in full).  kappa_dev (device, may
+ * be NULL) receives ||A_s||_1 ||A_s^{-1}||_1 of each Jacobi-scaled matrix.
+ * Returns FCM_ERR_NOT_SPD if a pivot was not positive.  Synchronises the
+ * stream.                                                                   */
 fcm_status fcm_spd_inverse(double *A_dev, int n, int batch, double *kappa_dev,
                            void *stream);
 
